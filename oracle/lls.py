@@ -1,0 +1,242 @@
+"""Steps 2-5 of Algorithm 1 (generic sketching algorithm) and the adjoint.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Steps
+-----
+2. Factor the sketch: S[A b] = Q [R c; 0 rho] by Householder QR without
+   pivoting (the usual QR that the algorithm's factorisation remark allows for
+   full-rank SA; V-hat = I, p = d).  The sign of diag(R) is normalised to be
+   non-negative (a row sign flip of [R c] does not change x).
+3. x_s = R^-1 c; terminate early if ||A x_s - b|| <= tau_a.
+4. LSQR (Paige and Saunders, 1982) on W = A R^-1, started from y_0 = c, i.e.
+   on the residual r_0 = b - A x_s, stopped by (TC-lsqr):
+       ||W^T (W y_k - b)|| / (||W|| ||W y_k - b||) <= tau_r
+   with the LSQR estimates of both norms and the running Frobenius estimate
+   ||B_k||_F of ||W||.
+5. x = R^-1 (c + delta).
+
+Guards (Section 6): a rank check on diag(R), read as relative
+(|r_qq| >= rcond |r_11|), and the perturbed back-solve: when the diagonal
+ratio max|r_ii| / min|r_ii| reaches 1/rcond_thres, every division by r_ii
+becomes a division by r_ii + copysign(perturb, r_ii).
+
+The adjoint solves (A^T A) Z = G by conjugate gradients on the preconditioned
+normal equations R^-T A^T A R^-1 (R Z) = R^-T G with the same R.  With the
+residual r = B - A X and the loss sum(X * G), the gradients are
+grad_B = A Z and grad_A = r Z^T - (A Z) X^T.
+"""
+
+import math
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+# status codes shared in meaning (not in code) with the C interface
+OK, WNOCONV, WEARLY, EINVAL, ERANK = 0, 1, 2, -1, -4
+
+
+def factor(SA_aug, d):
+    """Householder QR of the m x (d+k) sketch; returns (R d x d, c d x k, rho)."""
+    R_aug = np.linalg.qr(SA_aug, mode="r")
+    sgn = np.sign(np.diag(R_aug[:d, :d])).copy()
+    sgn[sgn == 0] = 1.0
+    R = sgn[:, None] * R_aug[:d, :d]
+    c = sgn[:, None] * R_aug[:d, d:]
+    rho = None
+    if R_aug.shape[0] > d:
+        rho = np.linalg.norm(R_aug[d:, d:], axis=0)
+    return np.triu(R), c, rho
+
+
+def rank_ok(R, rcond):
+    dg = np.abs(np.diag(R))
+    return bool(dg.size == 0 or (dg[0] > 0 and np.all(dg >= rcond * dg[0])))
+
+
+def perturbed(R, rcond_thres, perturb):
+    """R with its diagonal moved away from zero when it looks singular."""
+    dg = np.abs(np.diag(R))
+    if perturb > 0 and dg.size and (dg.min() == 0 or dg.max() / dg.min() >= 1.0 / rcond_thres):
+        R = R.copy()
+        i = np.arange(R.shape[0])
+        R[i, i] = R[i, i] + np.copysign(perturb, R[i, i])
+    return R
+
+
+def _matvecs(A):
+    if sp.issparse(A):
+        A = A.tocsr()
+        AT = A.T.tocsr()
+        return (lambda z: A @ z), (lambda u: AT @ u)
+    return (lambda z: A @ z), (lambda u: A.T @ u)
+
+
+def lsqr_precond(A, R, r0, tau_r, it_max):
+    """LSQR on min ||W delta - r0||, W = A R^-1.  Returns delta and a record."""
+    Amul, ATmul = _matvecs(A)
+    Rs = lambda v: sla.solve_triangular(R, v, lower=False)           # R^-1 v
+    RTs = lambda g: sla.solve_triangular(R, g, lower=False, trans="T")  # R^-T g
+    d = R.shape[0]
+    delta = np.zeros(d)
+    beta = float(np.linalg.norm(r0))
+    rec = dict(iters=0, rnorm=beta, arnorm=0.0, anorm=0.0, tc=0.0, converged=True)
+    if beta == 0.0:
+        return delta, rec
+    u = r0 / beta
+    v = RTs(ATmul(u))
+    alpha = float(np.linalg.norm(v))
+    if alpha == 0.0:
+        return delta, rec
+    v = v / alpha
+    h = v.copy()
+    phibar, rhobar, anorm2 = beta, alpha, 0.0
+    rec["converged"] = False
+    for it in range(1, it_max + 1):
+        # bidiagonalisation: beta u = W v - alpha u ; alpha v = W^T u - beta v
+        u = Amul(Rs(v)) - alpha * u
+        beta = float(np.linalg.norm(u))
+        if beta > 0.0:
+            u = u / beta
+        anorm2 += alpha * alpha + beta * beta
+        v = RTs(ATmul(u)) - beta * v
+        alpha = float(np.linalg.norm(v))
+        if alpha > 0.0:
+            v = v / alpha
+        # plane rotation eliminating the subdiagonal beta
+        rho = math.sqrt(rhobar * rhobar + beta * beta)
+        cs, sn = rhobar / rho, beta / rho
+        theta = sn * alpha
+        rhobar = -cs * alpha
+        phi = cs * phibar
+        phibar = sn * phibar
+        delta = delta + (phi / rho) * h
+        h = v - (theta / rho) * h
+        rnorm = phibar
+        arnorm = phibar * alpha * abs(cs)
+        anorm = math.sqrt(anorm2)
+        tc = arnorm / (anorm * rnorm) if rnorm > 0 and anorm > 0 else 0.0
+        rec.update(iters=it, rnorm=rnorm, arnorm=arnorm, anorm=anorm, tc=tc)
+        if rnorm == 0.0 or arnorm == 0.0 or tc <= tau_r:
+            rec["converged"] = True
+            break
+    return delta, rec
+
+
+def solve_with_factor(A, b, R, c, tau_a=1e-8, tau_r=1e-6, it_max=10000):
+    """Steps 3-5 for one right-hand side, given R and c = (Q^T S b)[:d]."""
+    xs = sla.solve_triangular(R, c, lower=False)
+    r0 = b - A @ xs
+    if np.linalg.norm(r0) <= tau_a:
+        return xs, dict(iters=0, status=WEARLY, rnorm=float(np.linalg.norm(r0)),
+                        arnorm=0.0, anorm=0.0, tc=0.0, xs=xs)
+    delta, rec = lsqr_precond(A, R, r0, tau_r, it_max)
+    x = sla.solve_triangular(R, c + delta, lower=False)
+    rec["status"] = OK if rec["converged"] else WNOCONV
+    rec["xs"] = xs
+    return x, rec
+
+
+def default_params(sparse):
+    """Defaults of Section 6 (dense: gamma 1.7, s 1; sparse: gamma 1.4, s 2)."""
+    if sparse:
+        return dict(gamma=1.4, s=2, hadamard=False, tau_a=1e-8, tau_r=1e-6,
+                    it_max=10000, rcond=0.0, rcond_thres=1e-10, perturb=1e-10)
+    return dict(gamma=1.7, s=1, hadamard=True, tau_a=1e-8, tau_r=1e-6,
+                it_max=10000, rcond=1e-12, rcond_thres=1e-10, perturb=0.0)
+
+
+def sketch_size(gamma, d, m=None):
+    return int(m) if m else int(math.ceil(gamma * d - 1e-9))
+
+
+def solve(A, B, seed, sparse=None, **kw):
+    """Algorithm 1 end to end (dense or scipy CSR A, B n x k).
+
+    Returns (X d x k, info dict)."""
+    from . import sketch as sk
+    if sparse is None:
+        sparse = sp.issparse(A)
+    p = default_params(sparse)
+    p.update(kw)
+    n, d = A.shape
+    B2 = np.asarray(B, dtype=np.float64).reshape(n, -1)
+    m = sketch_size(p["gamma"], d, p.get("m"))
+    if n < d or m < d or p["s"] > m:
+        return None, dict(status=EINVAL)
+    if sparse:
+        Ac = A.tocsr()
+        out = sk.sketch_csr(Ac.indptr, Ac.indices, Ac.data, n, d, B2, m, p["s"], seed)
+    else:
+        out = sk.sketch_dense(A, B2, m, p["s"], seed, hadamard=p["hadamard"])
+    R, c, _ = factor(out["SA_aug"], d)
+    if p["rcond"] > 0 and not rank_ok(R, p["rcond"]):
+        return None, dict(status=ERANK, R=R, sketch=out)
+    R = perturbed(R, p["rcond_thres"], p["perturb"])
+    X = np.zeros((d, B2.shape[1]))
+    recs = []
+    for j in range(B2.shape[1]):
+        X[:, j], rec = solve_with_factor(A, B2[:, j], R, c[:, j], p["tau_a"],
+                                         p["tau_r"], p["it_max"])
+        recs.append(rec)
+    if any(r["status"] == WNOCONV for r in recs):
+        status = WNOCONV
+    elif all(r["status"] == WEARLY for r in recs):
+        status = WEARLY
+    else:
+        status = OK
+    return X, dict(status=status, R=R, c=c, m=m, records=recs, sketch=out)
+
+
+def lstsq_direct(A, B):
+    """The plain definition: x* = argmin ||A x - b|| by Householder QR of A."""
+    A = A.toarray() if sp.issparse(A) else np.asarray(A, dtype=np.float64)
+    Q, R = np.linalg.qr(A, mode="reduced")
+    return sla.solve_triangular(R, Q.T @ B, lower=False)
+
+
+def normal_solve_pcg(A, R, G, tol=1e-12, it_max=1000):
+    """Z = (A^T A)^-1 G by CG on R^-T A^T A R^-1 y = R^-T g, z = R^-1 y."""
+    Amul, ATmul = _matvecs(A)
+    G = np.asarray(G, dtype=np.float64).reshape(R.shape[0], -1)
+    Z = np.zeros_like(G)
+    iters = []
+    for j in range(G.shape[1]):
+        Mop = lambda y: sla.solve_triangular(
+            R, ATmul(Amul(sla.solve_triangular(R, y, lower=False))), lower=False, trans="T")
+        rhs = sla.solve_triangular(R, G[:, j], lower=False, trans="T")
+        y = np.zeros_like(rhs)
+        r = rhs.copy()
+        pdir = r.copy()
+        rr = float(r @ r)
+        stop = (tol * float(np.linalg.norm(rhs))) ** 2
+        it = 0
+        while it < it_max and rr > stop:
+            q = Mop(pdir)
+            a = rr / float(pdir @ q)
+            y = y + a * pdir
+            r = r - a * q
+            rr_new = float(r @ r)
+            pdir = r + (rr_new / rr) * pdir
+            rr = rr_new
+            it += 1
+        Z[:, j] = sla.solve_triangular(R, y, lower=False)
+        iters.append(it)
+    return Z, iters
+
+
+def grads_from_Z(A, X, B, Z):
+    """grad_A = (B - A X) Z^T - (A Z) X^T and grad_B = A Z for loss sum(X * G)."""
+    A = np.asarray(A, dtype=np.float64)
+    AZ = A @ Z
+    return (B - A @ X) @ Z.T - AZ @ X.T, AZ
+
+
+def grads_closed_form(A, X, B, G):
+    """Reference gradient from a dense QR of A: Z = R_A^-1 R_A^-T G."""
+    A = np.asarray(A, dtype=np.float64)
+    RA = np.linalg.qr(A, mode="r")
+    Z = sla.solve_triangular(RA, sla.solve_triangular(RA, G, lower=False, trans="T"), lower=False)
+    gA, gB = grads_from_Z(A, X, B, Z)
+    return gA, gB, Z
