@@ -1,0 +1,175 @@
+/*
+ * ski.h -- C interface of the MI355X (gfx950) sketch-and-precondition solver for
+ * overdetermined linear least squares  min_x ||A x - b||_2  (A n x d, n >= d).
+ *
+ * Method: Cartis, Fiala and Shao, "Hashing embeddings of optimal dimension, with
+ * applications to linear least squares", Algorithm 1 (generic sketching
+ * algorithm) with the dense and sparse variants of Section 6:
+ *   ski_sketch  -- Step 1: S [A B], with S = S_h H D for dense A (Definition of
+ *                  HRHT, Section 4.3; Walsh-Hadamard H, rows zero-padded to a
+ *                  power of two n') and S = S_h for sparse A; S_h is an s-hashing
+ *                  matrix (Definition of s-hashing, Section 2.2).
+ *   ski_factor  -- Step 2: Householder QR of the m x (d+k) sketch (no pivoting,
+ *                  V-hat = I, p = d), giving R and c = (Q^T S B)[0:d].
+ *   ski_solve   -- Steps 3-5: x_s = R^-1 c and the early exit on tau_a, LSQR on
+ *                  W = A R^-1 stopped by (TC-lsqr) with tau_r, x = R^-1 y.
+ *                  With op = SKI_OP_NORMAL it solves (A^T A) Z = G instead, by
+ *                  conjugate gradients preconditioned with the same R (the adjoint
+ *                  used for differentiation; not in the paper).
+ *   ski_gradients -- grad_B = A Z and grad_A = (B - A X) Z^T - (A Z) X^T for the
+ *                  loss sum(X .* G) once Z = (A^T A)^-1 G is known.
+ *
+ * Conventions
+ *   - All matrix/vector arguments of ski_sketch/ski_solve/ski_gradients are DEVICE
+ *     pointers; dense matrices are row-major with an explicit leading dimension
+ *     (element (i, j) of an n x d matrix at p[i * ld + j]).
+ *   - `stream` is a hipStream_t (passed as void*); every call is ordered on it.
+ *     ski_sketch and ski_factor are asynchronous; ski_solve returns after LSQR has
+ *     stopped (it reads a small on-device status word every few iterations).
+ *   - Return value: 0 (SKI_OK) on success, > 0 a warning, < 0 an error; the
+ *     message of the last error is available from ski_last_error.  No C++
+ *     exception crosses this interface.
+ *   - A handle may be used from one host thread and one stream at a time.
+ */
+#ifndef SKI_H
+#define SKI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ski_handle_s* ski_handle;
+
+enum ski_status {
+    SKI_OK = 0,
+    SKI_WNOCONV = 1,   /* it_max reached before (TC-lsqr) held; X holds the last iterate */
+    SKI_WEARLY = 2,    /* Step 3 terminated early: ||A x_s - b|| <= tau_a, X = x_s       */
+    SKI_EINVAL = -1,   /* invalid argument (sizes, leading dimensions, NULL pointers)     */
+    SKI_ENOMEM = -2,   /* device allocation failed                                         */
+    SKI_EDEVICE = -3,  /* a HIP call failed                                                */
+    SKI_ERANK = -4,    /* rank guard: some |r_qq| < rcond |r_11| (A looks rank deficient)  */
+    SKI_ESTATE = -5    /* calls out of order (e.g. ski_factor before ski_sketch)           */
+};
+
+enum ski_kind { SKI_DENSE = 0, SKI_CSR = 2 };
+enum ski_prec { SKI_FP64 = 0, SKI_FP32 = 1, SKI_BF16 = 2 };
+enum ski_op { SKI_OP_LLS = 0, SKI_OP_NORMAL = 1 };
+
+/* The data matrix.  Dense: `a` (n x d, row-major, leading dimension lda >= d).
+ * CSR: row_ptr[n+1] (int64, row_ptr[0] = 0), col[nnz] (int32 in [0, d), distinct
+ * within a row), val[nnz].  The caller owns the arrays and must keep them alive
+ * and unmodified from ski_sketch until the last ski_solve/ski_gradients call on
+ * the handle: LSQR streams A directly, the handle keeps pointers, not copies. */
+typedef struct {
+    int64_t n, d;
+    int32_t kind;
+    const double* a;
+    int64_t lda;
+    const int64_t* row_ptr;
+    const int32_t* col;
+    const double* val;
+    int64_t nnz;
+} ski_matrix;
+
+/* Parameters (defaults of Section 6 from ski_params_default).
+ *   gamma, m     sketch rows m = ceil(gamma d) unless m > 0 is given; d <= m.
+ *   s            nonzeros per column of S_h, 1 <= s <= min(m, 32).
+ *   hadamard     1: S = S_h H D (dense only); 0: S = S_h.
+ *   seed         Philox4x64-10 key (seed, 0) for S_h and D.
+ *   sketch_prec  arithmetic/storage of H D A and of the sketch (FP64/FP32/BF16).
+ *   qr_prec      arithmetic of the QR of the sketch (FP64/FP32/BF16 MFMA inputs,
+ *                FP32 accumulation for BF16); R is always used in FP64.
+ *   tau_a        early exit when ||A x_s - b|| <= tau_a (absolute).
+ *   tau_r        (TC-lsqr) tolerance.
+ *   it_max       LSQR iteration limit.
+ *   rcond        rank guard |r_qq| >= rcond |r_11| (0 disables); failure -> SKI_ERANK.
+ *   rcond_thres, perturb  if max|r_ii|/min|r_ii| >= 1/rcond_thres and perturb > 0,
+ *                every division by r_ii becomes a division by r_ii + copysign(perturb, r_ii). */
+typedef struct {
+    double gamma;
+    int64_t m;
+    int32_t s;
+    int32_t hadamard;
+    uint64_t seed;
+    int32_t sketch_prec;
+    int32_t qr_prec;
+    double tau_a;
+    double tau_r;
+    int64_t it_max;
+    double rcond;
+    double rcond_thres;
+    double perturb;
+} ski_params;
+
+/* Per right-hand side result of ski_solve. */
+typedef struct {
+    int64_t iters;      /* LSQR (or CG) iterations taken                              */
+    int32_t status;     /* SKI_OK, SKI_WNOCONV or SKI_WEARLY for this column           */
+    int32_t early_exit; /* 1 if Step 3 terminated                                       */
+    double rnorm;       /* LSQR estimate of ||A x - b|| (CG: ||rhs - M y||)           */
+    double arnorm;      /* LSQR estimate of ||W^T (W y - b)||                          */
+    double wnorm_est;   /* running Frobenius estimate of ||W||                         */
+    double tc;          /* arnorm / (wnorm_est * rnorm), the (TC-lsqr) value           */
+    double cond_est;    /* max|r_ii| / min|r_ii| of the R used                          */
+    float ms_sketch, ms_factor, ms_solve; /* device time of the three calls (ms)       */
+} ski_info;
+
+int ski_create(ski_handle* h);
+int ski_destroy(ski_handle h);
+
+/* Fill *p with the defaults of Section 6 for `kind` (SKI_DENSE: gamma 1.7, s 1,
+ * Hadamard on, rcond 1e-12, no perturbation; SKI_CSR: gamma 1.4, s 2, no Hadamard,
+ * rcond_thres 1e-10, perturb 1e-10; both tau_a 1e-8, tau_r 1e-6, it_max 1e4). */
+void ski_params_default(int32_t kind, ski_params* p);
+
+/* Step 1.  Draws S from (m, s, seed), forms S [A B] (B: n x k, device, leading
+ * dimension ldb >= k; k >= 1) and keeps it in the handle.  Errors: SKI_EINVAL for
+ * n < d, d < 1, m < d, m > n' (dense with Hadamard) or m > n, s out of range, k < 1,
+ * bad leading dimensions, Hadamard requested for CSR; SKI_ENOMEM. */
+int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, int64_t ldb,
+               const ski_params* p, void* stream);
+
+/* Step 2.  Householder QR of the sketch; forms R (FP64, diag(R) >= 0), c, and the
+ * explicit inverse of R used by every later product with R^-1 (any nonsingular P
+ * applied consistently keeps the implicit sketching guarantee).  SKI_ERANK if the
+ * rank guard fails (the handle then holds R but cannot solve). */
+int ski_factor(ski_handle h, void* stream);
+
+/* Steps 3-5 (op = SKI_OP_LLS): B is n x k (ldb), X is d x k (ldx).  The k columns are
+ * solved together but stop independently.  info: host array of k entries, or NULL.
+ * Returns the worst status over the columns (SKI_WNOCONV > SKI_WEARLY > SKI_OK).
+ * op = SKI_OP_NORMAL: B is G (d x k, ldb) and X receives Z = (A^T A)^-1 G; the CG
+ * stops when ||rhs - M y|| <= tau_r ||rhs|| for M = R^-T A^T A R^-1. */
+int ski_solve(ski_handle h, int32_t op, const double* B, int32_t k, int64_t ldb,
+              double* X, int64_t ldx, ski_info* info, void* stream);
+
+/* grad_B = A Z (n x k, ldgb) and grad_A = (B - A X) Z^T - (A Z) X^T (n x d, ldga) for
+ * dense A.  Either output may be NULL.  X, Z: d x k; B: n x k. */
+int ski_gradients(ski_handle h, const double* X, int64_t ldx, const double* B, int64_t ldb,
+                  const double* Z, int64_t ldz, int32_t k, double* grad_A, int64_t ldga,
+                  double* grad_B, int64_t ldgb, void* stream);
+
+const char* ski_last_error(ski_handle h);
+
+/* Test and inspection getters: HOST copies, synchronous.
+ *   dims: n, d, k, m, n' (padded rows, = n without Hadamard), s.
+ *   hash: rows[n'*s] and neg[n'*s] per column in acceptance order; the bucket-sorted
+ *         form bucket_ptr[m+1], src[n'*s] (column index), src_neg[n'*s].  Any pointer
+ *         may be NULL.
+ *   dsign: the diagonal of D as int8 (+1 / -1), n' entries (dense with Hadamard only).
+ *   SA: the sketch m x (d+k) row-major, converted to double.
+ *   R: d x d row-major (upper triangle, zeros below); c: d x k; Rinv: d x d. */
+int ski_get_dims(ski_handle h, int64_t dims[6]);
+int ski_get_hash(ski_handle h, int32_t* rows, int8_t* neg, int64_t* bucket_ptr, int32_t* src,
+                 int8_t* src_neg);
+int ski_get_dsign(ski_handle h, int8_t* dsign);
+int ski_get_SA(ski_handle h, double* SA);
+int ski_get_R(ski_handle h, double* R, double* c, double* Rinv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SKI_H */

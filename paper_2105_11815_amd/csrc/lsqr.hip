@@ -1,0 +1,720 @@
+// Steps 3-5 of Algorithm 1 on the GPU, all in FP64: x_s = R^-1 c with the early exit on
+// ||A x_s - b|| <= tau_a, LSQR (Paige and Saunders) on W = A R^-1 started from y_0 = c,
+// stopped by (TC-lsqr), and x = R^-1 (c + delta); plus CG on the preconditioned normal
+// equations for the adjoint.
+//
+// R^-1 is formed once (blocked triangular inversion on the MFMA GEMM) and kept both
+// row-major and transposed, so z = R^-1 v and R^-T g are triangle-only streaming GEMVs.
+// Any nonsingular P applied consistently as W = A P and x = P y keeps the implicit
+// sketching guarantee, so the explicit inverse is an exact preconditioner.
+//
+// One LSQR iteration for a dense A and one right-hand side reads A once: the fused pass
+// computes u_hat = A z - (alpha/beta) u_hat_old row by row and, with the row still in
+// registers, accumulates g = A^T u_hat into per-workgroup partials that a second kernel
+// sums in a fixed order.  The scalar recurrences run on the device; the host only reads a
+// status word every few iterations.  Every reduction has a fixed order: results are
+// bitwise reproducible run to run.
+#include "ski_internal.h"
+#include "lsqr.h"
+
+namespace ski {
+
+namespace {
+
+constexpr int DB = 64;  // diagonal block of the triangular inversion
+
+// invert the 64 x 64 diagonal blocks of upper-triangular R (diag + diag_add), X row-major d x d
+__global__ __launch_bounds__(DB) void k_trtri_diag(const double* __restrict__ R, int64_t d,
+                                                   const double* __restrict__ diag_add,
+                                                   double* __restrict__ X) {
+    __shared__ double Rs[DB][DB + 1];
+    const int64_t b0 = (int64_t)blockIdx.x * DB;
+    const int nb = (int)std::min<int64_t>(DB, d - b0);
+    const int j = threadIdx.x;  // this thread computes column j of the block inverse
+    for (int i = 0; i < nb; ++i)
+        if (j < nb) {
+            double v = R[(b0 + i) * d + b0 + j];
+            if (i == j && diag_add) v += diag_add[b0 + i];
+            Rs[i][j] = v;
+        }
+    __syncthreads();
+    if (j >= nb) return;
+    double x[DB];
+#pragma unroll
+    for (int i = 0; i < DB; ++i) x[i] = 0;
+    // back substitution R x = e_j
+    for (int i = nb - 1; i >= 0; --i) {
+        double s = (i == j) ? 1.0 : 0.0;
+        for (int t = i + 1; t <= j; ++t) s -= Rs[i][t] * x[t];
+        x[i] = (i <= j) ? s / Rs[i][i] : 0.0;
+    }
+    for (int i = 0; i < nb; ++i) X[(b0 + i) * d + b0 + j] = x[i];
+}
+
+__global__ __launch_bounds__(256) void k_zero_lower_and_transpose(double* __restrict__ X,
+                                                                  int64_t d,
+                                                                  double* __restrict__ XT) {
+    // X: zero the strictly lower triangle; XT = X^T
+    const int64_t i = blockIdx.x;
+    for (int64_t j = threadIdx.x; j < d; j += 256) {
+        double v = j < i ? 0.0 : X[i * d + j];
+        X[i * d + j] = v;
+    }
+    __syncthreads();
+    for (int64_t j = threadIdx.x; j < d; j += 256) XT[j * d + i] = j < i ? 0.0 : X[i * d + j];
+}
+
+__global__ __launch_bounds__(256) void k_fill_f64(double* p, int64_t n, double v) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        p[i] = v;
+}
+
+hipError_t trtri_rec(const double* R, int64_t d, int64_t lo, int64_t hi, double* X, double* tmp,
+                     GemmWs& ws, hipStream_t st) {
+    const int64_t n = hi - lo;
+    if (n <= DB) return hipSuccess;  // diagonal blocks done by k_trtri_diag
+    int64_t mid = lo + ((n / 2 + DB - 1) / DB) * DB;
+    if (mid >= hi) mid = hi - DB;
+    SKI_HIP(trtri_rec(R, d, lo, mid, X, tmp, ws, st));
+    SKI_HIP(trtri_rec(R, d, mid, hi, X, tmp, ws, st));
+    const int64_t n1 = mid - lo, n2 = hi - mid;
+    // X12 = -X11 (R12 X22): tmp = R12 X22 (n1 x n2), then X12 = -X11 tmp
+    SKI_HIP(gemm_f64(false, false, n1, n2, n2, 1.0, R + lo * d + mid, d, X + mid * d + mid, d, 0.0,
+                     tmp, n2, ws, st));
+    SKI_HIP(gemm_f64(false, false, n1, n2, n1, -1.0, X + lo * d + lo, d, tmp, n2, 0.0,
+                     X + lo * d + mid, d, ws, st));
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// triangular GEMV y = s * M x over the triangle only (one wave per row)
+__global__ __launch_bounds__(256) void k_tri_gemv(const double* __restrict__ M, int64_t d, int upper,
+                                                  const double* __restrict__ x, int64_t ldx,
+                                                  double* __restrict__ y, int64_t ldy, double s,
+                                                  const int32_t* __restrict__ done) {
+    if (done && *done) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * 256) >> 6;
+    for (int64_t i = wave; i < d; i += nw) {
+        const int64_t j0 = upper ? i : 0, j1 = upper ? d : i + 1;
+        const double* row = M + i * d;
+        double acc = 0;
+        for (int64_t j = j0 + lane; j < j1; j += 64) acc += row[j] * x[j * ldx];
+        acc = wave_sum(acc);
+        if (lane == 0) y[i * ldy] = s * acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// fused dense pass: u = A z - coef * u_old (in place), g partials and ||u||^2 partials
+template <int CPT>
+__global__ __launch_bounds__(256) void k_lsqr_pass(const double* __restrict__ A, int64_t lda,
+                                                   int64_t n, int64_t d,
+                                                   const double* __restrict__ z,
+                                                   double* __restrict__ u,
+                                                   const LsqrState* __restrict__ stt,
+                                                   int64_t rows_per_wg, double* __restrict__ gpart,
+                                                   double* __restrict__ upart, int use_coef_m1) {
+    if (stt->done) return;
+    __shared__ double red[2][4][2];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const double coef = use_coef_m1 ? -1.0 : stt->coef;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
+    const int64_t r1 = std::min(n, r0 + rows_per_wg);
+    double zr[CPT], g[CPT], a0[CPT], a1[CPT];
+    double uo0 = 0.0, uo1 = 0.0;  // u_old of the pair in flight, read before any write
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        const int64_t c = tid + 256 * q;
+        zr[q] = c < d ? z[c] : 0.0;
+        g[q] = 0.0;
+    }
+    double usq = 0.0;
+    int buf = 0;
+    auto load2 = [&](int64_t r) {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            const int64_t c = tid + 256 * q;
+            a0[q] = (c < d && r < r1) ? A[r * lda + c] : 0.0;
+            a1[q] = (c < d && r + 1 < r1) ? A[(r + 1) * lda + c] : 0.0;
+        }
+        uo0 = r < r1 ? u[r] : 0.0;
+        uo1 = r + 1 < r1 ? u[r + 1] : 0.0;
+    };
+    if (r0 < r1) load2(r0);
+    for (int64_t r = r0; r < r1; r += 2) {
+        double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            p0 += a0[q] * zr[q];
+            p1 += a1[q] * zr[q];
+        }
+        p0 = wave_sum(p0);
+        p1 = wave_sum(p1);
+        if (lane == 0) {
+            red[buf][wv][0] = p0;
+            red[buf][wv][1] = p1;
+        }
+        __syncthreads();
+        const double d0 = (red[buf][0][0] + red[buf][1][0]) + (red[buf][2][0] + red[buf][3][0]);
+        const double d1 = (red[buf][0][1] + red[buf][1][1]) + (red[buf][2][1] + red[buf][3][1]);
+        const double u0 = d0 - coef * uo0;
+        const double u1 = (r + 1 < r1) ? d1 - coef * uo1 : 0.0;
+        double b0[CPT], b1[CPT];
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            b0[q] = a0[q];
+            b1[q] = a1[q];
+        }
+        if (r + 2 < r1) load2(r + 2);
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) g[q] += b0[q] * u0 + b1[q] * u1;
+        if (tid == 0) {
+            u[r] = u0;
+            if (r + 1 < r1) u[r + 1] = u1;
+            usq += u0 * u0 + u1 * u1;
+        }
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        const int64_t c = tid + 256 * q;
+        if (c < d) gpart[(int64_t)blockIdx.x * d + c] = g[q];
+    }
+    if (tid == 0) upart[blockIdx.x] = usq;
+}
+
+// g[c] = sum_g gpart[g][c], in order; beta2 = sum upart
+__global__ __launch_bounds__(256) void k_reduce_pass(const double* __restrict__ gpart,
+                                                     const double* __restrict__ upart, int64_t G,
+                                                     int64_t d, double* __restrict__ g,
+                                                     LsqrState* __restrict__ stt) {
+    if (stt->done) return;
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c < d) {
+        double s = 0;
+        for (int64_t q = 0; q < G; ++q) s += gpart[q * d + c];
+        g[c] = s;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double s = 0;
+        for (int64_t q = 0; q < G; ++q) s += upart[q];
+        stt->beta2 = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// CSR products (k right-hand sides, vectors row-major with leading dimension k)
+// u[i] = (A z)[i] - coef_j u[i]; eight lanes per row; squared-norm partial per workgroup
+__global__ __launch_bounds__(256) void k_spmv_csr(const int64_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ ci,
+                                                  const double* __restrict__ va, int64_t n, int k,
+                                                  const double* __restrict__ z,
+                                                  double* __restrict__ u,
+                                                  const LsqrState* __restrict__ stt,
+                                                  int use_coef_m1, double* __restrict__ upart) {
+    __shared__ double red[32];
+    const int grp = threadIdx.x >> 3, gl = threadIdx.x & 7;
+    const int64_t i = (int64_t)blockIdx.x * 32 + grp;
+    for (int j = 0; j < k; ++j) {
+        const bool act = !stt[j].done;
+        double sq = 0.0;
+        if (act) {
+            double acc = 0.0;
+            if (i < n)
+                for (int64_t e = rp[i] + gl; e < rp[i + 1]; e += 8) acc += va[e] * z[(int64_t)ci[e] * k + j];
+            acc += __shfl_xor(acc, 1, 64);
+            acc += __shfl_xor(acc, 2, 64);
+            acc += __shfl_xor(acc, 4, 64);
+            if (i < n && gl == 0) {
+                const double coef = use_coef_m1 ? -1.0 : stt[j].coef;
+                const double v = acc - coef * u[i * k + j];
+                u[i * k + j] = v;
+                sq = v * v;
+            }
+        }
+        if (gl == 0) red[grp] = sq;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = 0;
+            for (int q = 0; q < 32; ++q) s += red[q];
+            upart[(int64_t)blockIdx.x * k + j] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// g = A^T u through CSR(A^T): one wave per column of A
+__global__ __launch_bounds__(256) void k_spmv_csrT(const int32_t* __restrict__ tp,
+                                                   const int32_t* __restrict__ ti,
+                                                   const double* __restrict__ tv, int64_t d, int k,
+                                                   const double* __restrict__ u,
+                                                   double* __restrict__ g,
+                                                   const LsqrState* __restrict__ stt) {
+    const int lane = threadIdx.x & 63;
+    const int64_t c = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+    if (c >= d) return;
+    for (int j = 0; j < k; ++j) {
+        if (stt[j].done) continue;
+        double acc = 0;
+        for (int64_t e = tp[c] + lane; e < tp[c + 1]; e += 64) acc += tv[e] * u[(int64_t)ti[e] * k + j];
+        acc = wave_sum(acc);
+        if (lane == 0) g[c * k + j] = acc;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_upart(const double* __restrict__ upart, int64_t G,
+                                                      int k, LsqrState* __restrict__ stt) {
+    const int j = threadIdx.x;
+    if (j >= k || stt[j].done) return;
+    double s = 0;
+    for (int64_t q = 0; q < G; ++q) s += upart[q * k + j];
+    stt[j].beta2 = s;
+}
+
+// row index of every stored entry (for CSR(A^T))
+__global__ __launch_bounds__(256) void k_csr_keys(const int64_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ ci, int64_t n,
+                                                  uint64_t* __restrict__ keys) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
+        keys[e] = ((uint64_t)(uint32_t)ci[e] << 32) | (uint64_t)e;
+}
+
+__global__ __launch_bounds__(256) void k_csrT_fill(const int32_t* __restrict__ payload, int64_t nnz,
+                                                   const int64_t* __restrict__ rp, int64_t n,
+                                                   const double* __restrict__ va,
+                                                   int32_t* __restrict__ ti,
+                                                   double* __restrict__ tv) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= nnz) return;
+    const int64_t e = (uint32_t)payload[p];
+    // row of entry e: last i with rp[i] <= e
+    int64_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        int64_t mid = (lo + hi) >> 1;
+        if (rp[mid] <= e)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    ti[p] = (int32_t)lo;
+    tv[p] = va[e];
+}
+
+// ---------------------------------------------------------------------------
+// dense multi-RHS helpers
+// u = t - coef_j u (n x k) and squared-norm partials per column
+__global__ __launch_bounds__(256) void k_combine_u(const double* __restrict__ t,
+                                                   double* __restrict__ u, int64_t n, int k,
+                                                   const LsqrState* __restrict__ stt,
+                                                   int use_coef_m1, double* __restrict__ upart,
+                                                   int64_t rows_per_wg) {
+    __shared__ double red[256];
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg, r1 = std::min(n, r0 + rows_per_wg);
+    // thread layout: column j = tid % k' over k' = min(k, 256) lanes, row stride 256 / k'
+    for (int j0 = 0; j0 < k; j0 += 256) {
+        const int kk = std::min(256, k - j0);
+        const int rstride = 256 / kk;
+        const int j = j0 + threadIdx.x % kk;
+        const int rr = threadIdx.x / kk;
+        double sq = 0;
+        if (threadIdx.x < kk * rstride && !stt[j].done) {
+            const double coef = use_coef_m1 ? -1.0 : stt[j].coef;
+            for (int64_t i = r0 + rr; i < r1; i += rstride) {
+                const double v = t[i * k + j] - coef * u[i * k + j];
+                u[i * k + j] = v;
+                sq += v * v;
+            }
+        }
+        red[threadIdx.x] = sq;
+        __syncthreads();
+        if (threadIdx.x < kk) {
+            double s = 0;
+            for (int q = 0; q < rstride; ++q) s += red[q * kk + threadIdx.x];
+            upart[(int64_t)blockIdx.x * k + j0 + threadIdx.x] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// on-device LSQR scalars, one workgroup per right-hand side j; vectors have stride k
+__device__ double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double s = 0;
+    const int nw = blockDim.x >> 6;
+    for (int q = 0; q < nw; ++q) s += sh[q];
+    return s;
+}
+
+// init: beta_1 u_1 = r_0 (u holds r_0, beta2 = ||r_0||^2), wp = R^-T A^T r_0
+__global__ __launch_bounds__(1024) void k_lsqr_init(LsqrState* __restrict__ stt, int64_t d, int k,
+                                                    const double* __restrict__ wp,
+                                                    double* __restrict__ v, double* __restrict__ h,
+                                                    double* __restrict__ delta, double tau_a) {
+    __shared__ double sh[16];
+    const int j = blockIdx.x;
+    LsqrState& S = stt[j];
+    if (S.done) return;
+    const double beta = sqrt(S.beta2);
+    if (beta <= tau_a) {  // Step 3: early exit with x_s
+        if (threadIdx.x == 0) {
+            S.rnorm = beta;
+            S.done = 1;
+            S.status = SKI_WEARLY;
+            S.early = 1;
+        }
+        return;
+    }
+    double ss = 0;
+    for (int64_t i = threadIdx.x; i < d; i += blockDim.x) {
+        const double w = wp[i * k + j] / beta;
+        ss += w * w;
+    }
+    const double alpha = sqrt(block_sum(ss, sh));
+    for (int64_t i = threadIdx.x; i < d; i += blockDim.x) {
+        const double w = alpha > 0 ? (wp[i * k + j] / beta) / alpha : 0.0;
+        v[i * k + j] = w;
+        h[i * k + j] = w;
+        delta[i * k + j] = 0.0;
+    }
+    if (threadIdx.x == 0) {
+        S.alpha = alpha;
+        S.beta = beta;
+        S.phibar = beta;
+        S.rhobar = alpha;
+        S.anorm2 = 0.0;
+        S.coef = alpha / beta;
+        S.iters = 0;
+        S.arnorm = 0.0;
+        S.tc = 0.0;
+        S.rnorm = beta;
+        if (alpha == 0.0) {  // A^T r_0 = 0: x_s is optimal
+            S.done = 1;
+            S.status = SKI_OK;
+        }
+    }
+}
+
+// one step: u_hat holds W v - alpha u (beta2 = its squared norm), wp = R^-T A^T u_hat
+__global__ __launch_bounds__(1024) void k_lsqr_step(LsqrState* __restrict__ stt, int64_t d, int k,
+                                                    const double* __restrict__ wp,
+                                                    double* __restrict__ v, double* __restrict__ h,
+                                                    double* __restrict__ delta, double tau_r,
+                                                    int64_t it_max) {
+    __shared__ double sh[16];
+    const int j = blockIdx.x;
+    LsqrState& S = stt[j];
+    if (S.done) return;
+    const double beta = sqrt(S.beta2);
+    const double alpha_old = S.alpha;
+    const double rhobar = S.rhobar, phibar = S.phibar, anorm2_old = S.anorm2;
+    const int64_t iters_old = S.iters;
+    const double ib = beta > 0 ? 1.0 / beta : 0.0;
+    double ss = 0;
+    for (int64_t i = threadIdx.x; i < d; i += blockDim.x) {
+        const double w = wp[i * k + j] * ib - beta * v[i * k + j];
+        ss += w * w;
+    }
+    const double alpha = sqrt(block_sum(ss, sh));
+    const double ia = alpha > 0 ? 1.0 / alpha : 0.0;
+    // plane rotation eliminating beta
+    const double rho = sqrt(rhobar * rhobar + beta * beta);
+    const double cs = rhobar / rho, sn = beta / rho;
+    const double theta = sn * alpha;
+    const double phi = cs * phibar;
+    const double t1 = phi / rho, t2 = theta / rho;
+    for (int64_t i = threadIdx.x; i < d; i += blockDim.x) {
+        const double w = wp[i * k + j] * ib - beta * v[i * k + j];
+        const double vn = w * ia;
+        const double hi = h[i * k + j];
+        delta[i * k + j] += t1 * hi;
+        h[i * k + j] = vn - t2 * hi;
+        v[i * k + j] = vn;
+    }
+    if (threadIdx.x == 0) {
+        const double anorm2 = anorm2_old + alpha_old * alpha_old + beta * beta;
+        const double phibar_n = sn * phibar;
+        const double arnorm = phibar_n * alpha * fabs(cs);
+        const double anorm = sqrt(anorm2);
+        const double tc = (phibar_n > 0 && anorm > 0) ? arnorm / (anorm * phibar_n) : 0.0;
+        S.anorm2 = anorm2;
+        S.rhobar = -cs * alpha;
+        S.phibar = phibar_n;
+        S.alpha = alpha;
+        S.beta = beta;
+        S.coef = beta > 0 ? alpha / beta : 0.0;
+        S.rnorm = phibar_n;
+        S.arnorm = arnorm;
+        S.tc = tc;
+        S.iters = iters_old + 1;
+        if (phibar_n == 0.0 || arnorm == 0.0 || tc <= tau_r) {
+            S.done = 1;
+            S.status = SKI_OK;
+        } else if (iters_old + 1 >= it_max) {
+            S.done = 1;
+            S.status = SKI_WNOCONV;
+        }
+    }
+}
+
+// y = c + delta (per column) for the final x = R^-1 y, x_s when the early exit was taken
+__global__ __launch_bounds__(256) void k_final_y(const LsqrState* __restrict__ stt, int64_t d, int k,
+                                                 const double* __restrict__ c,
+                                                 const double* __restrict__ delta,
+                                                 double* __restrict__ y) {
+    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (o >= d * k) return;
+    const int j = (int)(o % k);
+    y[o] = stt[j].early ? c[o] : c[o] + delta[o];
+}
+
+__global__ __launch_bounds__(256) void k_scale_copy(const double* __restrict__ x, int64_t rows,
+                                                    int64_t cols, int64_t ldx, double s,
+                                                    double* __restrict__ y, int64_t ldy) {
+    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (o >= rows * cols) return;
+    const int64_t i = o / cols, j = o - i * cols;
+    y[i * ldy + j] = s * x[i * ldx + j];
+}
+
+// CG scalars on M y = rhs (M = R^-T A^T A R^-1), one workgroup per column
+__global__ __launch_bounds__(1024) void k_cg_init(LsqrState* __restrict__ stt, int64_t d, int k,
+                                                  const double* __restrict__ rhs,
+                                                  double* __restrict__ r, double* __restrict__ p,
+                                                  double* __restrict__ y, double tol) {
+    __shared__ double sh[16];
+    const int j = blockIdx.x;
+    LsqrState& S = stt[j];
+    double ss = 0;
+    for (int64_t i = threadIdx.x; i < d; i += blockDim.x) {
+        const double v = rhs[i * k + j];
+        r[i * k + j] = v;
+        p[i * k + j] = v;
+        y[i * k + j] = 0.0;
+        ss += v * v;
+    }
+    const double rr = block_sum(ss, sh);
+    if (threadIdx.x == 0) {
+        S.rr = rr;
+        S.stop2 = tol * tol * rr;
+        S.iters = 0;
+        S.rnorm = sqrt(rr);
+        S.done = (rr <= S.stop2 || rr == 0.0) ? 1 : 0;
+        S.status = SKI_OK;
+        S.early = 0;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_cg_step(LsqrState* __restrict__ stt, int64_t d, int k,
+                                                  const double* __restrict__ q,
+                                                  double* __restrict__ r, double* __restrict__ p,
+                                                  double* __restrict__ y, int64_t it_max) {
+    __shared__ double sh[16];
+    const int j = blockIdx.x;
+    LsqrState& S = stt[j];
+    if (S.done) return;
+    const double rr_old = S.rr, stop2 = S.stop2;
+    const int64_t iters_old = S.iters;
+    double pq = 0;
+    for (int64_t i = threadIdx.x; i < d; i += blockDim.x) pq += p[i * k + j] * q[i * k + j];
+    pq = block_sum(pq, sh);
+    const double a = rr_old / pq;
+    double ss = 0;
+    for (int64_t i = threadIdx.x; i < d; i += blockDim.x) {
+        y[i * k + j] += a * p[i * k + j];
+        const double rn = r[i * k + j] - a * q[i * k + j];
+        r[i * k + j] = rn;
+        ss += rn * rn;
+    }
+    const double rr_new = block_sum(ss, sh);
+    const double bb = rr_new / rr_old;
+    for (int64_t i = threadIdx.x; i < d; i += blockDim.x) p[i * k + j] = r[i * k + j] + bb * p[i * k + j];
+    if (threadIdx.x == 0) {
+        S.rr = rr_new;
+        S.iters = iters_old + 1;
+        S.rnorm = sqrt(rr_new);
+        if (rr_new <= stop2) {
+            S.done = 1;
+            S.status = SKI_OK;
+        } else if (iters_old + 1 >= it_max) {
+            S.done = 1;
+            S.status = SKI_WNOCONV;
+        }
+    }
+}
+
+__global__ void k_all_done(const LsqrState* __restrict__ stt, int k, int32_t* __restrict__ flag) {
+    int all = 1;
+    for (int j = 0; j < k; ++j) all &= stt[j].done ? 1 : 0;
+    *flag = all;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+hipError_t trtri_upper(const double* R, int64_t d, double* Rinv, double* RinvT,
+                       const double* diag_add, double* tmp, GemmWs& ws, hipStream_t st) {
+    const unsigned nblk = (unsigned)((d + DB - 1) / DB);
+    // the recursion multiplies whole square blocks: the strictly lower part must be zero
+    const int64_t tot = d * d;
+    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)std::min<int64_t>((tot + 255) / 256, 65536)),
+                       dim3(256), 0, st, Rinv, tot, 0.0);
+    SKI_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_trtri_diag, dim3(nblk), dim3(DB), 0, st, R, d, diag_add, Rinv);
+    SKI_HIP(hipGetLastError());
+    // the off-diagonal blocks use R with the same perturbed diagonal only through X11, X22
+    SKI_HIP(trtri_rec(R, d, 0, d, Rinv, tmp, ws, st));
+    hipLaunchKernelGGL(k_zero_lower_and_transpose, dim3((unsigned)d), dim3(256), 0, st, Rinv, d,
+                       RinvT);
+    return hipGetLastError();
+}
+
+hipError_t launch_tri_gemv(const double* M, int64_t d, bool upper, const double* x, int64_t ldx,
+                           double* y, int64_t ldy, double s, const int32_t* done, hipStream_t st) {
+    const unsigned g = (unsigned)std::min<int64_t>((d + 3) / 4, 2048);
+    hipLaunchKernelGGL(k_tri_gemv, dim3(g), dim3(256), 0, st, M, d, upper ? 1 : 0, x, ldx, y, ldy,
+                       s, done);
+    return hipGetLastError();
+}
+
+int lsqr_pass_cpt(int64_t d) {
+    const int64_t c = (d + 255) / 256;
+    if (c <= 1) return 1;
+    if (c <= 2) return 2;
+    if (c <= 4) return 4;
+    if (c <= 8) return 8;
+    if (c <= 16) return 16;
+    if (c <= 24) return 24;
+    if (c <= 32) return 32;
+    return 0;
+}
+
+hipError_t launch_lsqr_pass(const double* A, int64_t lda, int64_t n, int64_t d, const double* z,
+                            double* u, const LsqrState* stt, int64_t G, double* gpart,
+                            double* upart, double* g, LsqrState* stt_w, bool coef_m1,
+                            hipStream_t st) {
+    const int64_t rpw = (((n + G - 1) / G) + 1) / 2 * 2;
+    const int cpt = lsqr_pass_cpt(d);
+#define SKI_PASS(C)                                                                             \
+    hipLaunchKernelGGL((k_lsqr_pass<C>), dim3((unsigned)G), dim3(256), 0, st, A, lda, n, d, z, u, \
+                       stt, rpw, gpart, upart, coef_m1 ? 1 : 0)
+    switch (cpt) {
+        case 1: SKI_PASS(1); break;
+        case 2: SKI_PASS(2); break;
+        case 4: SKI_PASS(4); break;
+        case 8: SKI_PASS(8); break;
+        case 16: SKI_PASS(16); break;
+        case 24: SKI_PASS(24); break;
+        case 32: SKI_PASS(32); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef SKI_PASS
+    SKI_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_reduce_pass, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, st, gpart,
+                       upart, G, d, g, stt_w);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv_csr(const int64_t* rp, const int32_t* ci, const double* va, int64_t n, int k,
+                           const double* z, double* u, LsqrState* stt, bool coef_m1,
+                           double* upart, hipStream_t st) {
+    const int64_t G = (n + 31) / 32;
+    hipLaunchKernelGGL(k_spmv_csr, dim3((unsigned)G), dim3(256), 0, st, rp, ci, va, n, k, z, u, stt,
+                       coef_m1 ? 1 : 0, upart);
+    SKI_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_reduce_upart, dim3(1), dim3(256), 0, st, upart, G, k, stt);
+    return hipGetLastError();
+}
+
+int64_t spmv_csr_groups(int64_t n) { return (n + 31) / 32; }
+
+hipError_t launch_spmv_csrT(const int32_t* tp, const int32_t* ti, const double* tv, int64_t d, int k,
+                            const double* u, double* g, const LsqrState* stt, hipStream_t st) {
+    const unsigned G = (unsigned)((d + 3) / 4);
+    hipLaunchKernelGGL(k_spmv_csrT, dim3(G), dim3(256), 0, st, tp, ti, tv, d, k, u, g, stt);
+    return hipGetLastError();
+}
+
+hipError_t build_csrT(const int64_t* rp, const int32_t* ci, const double* va, int64_t n, int64_t d,
+                      int64_t nnz, uint64_t* keys, uint64_t* keys_tmp, int32_t* table,
+                      int32_t* tp, int32_t* payload, int32_t* ti, double* tv, hipStream_t st) {
+    hipLaunchKernelGGL(k_csr_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, rp, ci, n,
+                       keys);
+    SKI_HIP(hipGetLastError());
+    SKI_HIP(launch_bucket_sort(keys, nnz, d, keys_tmp, table, tp, payload, st));
+    if (nnz > 0)
+        hipLaunchKernelGGL(k_csrT_fill, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, st,
+                           payload, nnz, rp, n, va, ti, tv);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine_u(const double* t, double* u, int64_t n, int k, const LsqrState* stt,
+                            bool coef_m1, double* upart, int64_t G, LsqrState* stt_w,
+                            hipStream_t st) {
+    const int64_t rpw = (n + G - 1) / G;
+    hipLaunchKernelGGL(k_combine_u, dim3((unsigned)G), dim3(256), 0, st, t, u, n, k, stt,
+                       coef_m1 ? 1 : 0, upart, rpw);
+    SKI_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_reduce_upart, dim3(1), dim3(256), 0, st, upart, G, k, stt_w);
+    return hipGetLastError();
+}
+
+hipError_t launch_lsqr_init(LsqrState* stt, int64_t d, int k, const double* wp, double* v,
+                            double* h, double* delta, double tau_a, hipStream_t st) {
+    hipLaunchKernelGGL(k_lsqr_init, dim3((unsigned)k), dim3(1024), 0, st, stt, d, k, wp, v, h, delta,
+                       tau_a);
+    return hipGetLastError();
+}
+
+hipError_t launch_lsqr_step(LsqrState* stt, int64_t d, int k, const double* wp, double* v,
+                            double* h, double* delta, double tau_r, int64_t it_max,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_lsqr_step, dim3((unsigned)k), dim3(1024), 0, st, stt, d, k, wp, v, h, delta,
+                       tau_r, it_max);
+    return hipGetLastError();
+}
+
+hipError_t launch_final_y(const LsqrState* stt, int64_t d, int k, const double* c,
+                          const double* delta, double* y, hipStream_t st) {
+    const int64_t tot = d * k;
+    hipLaunchKernelGGL(k_final_y, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, stt, d, k,
+                       c, delta, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_copy(const double* x, int64_t rows, int64_t cols, int64_t ldx, double s,
+                             double* y, int64_t ldy, hipStream_t st) {
+    const int64_t tot = rows * cols;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scale_copy, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, x, rows,
+                       cols, ldx, s, y, ldy);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_init(LsqrState* stt, int64_t d, int k, const double* rhs, double* r, double* p,
+                          double* y, double tol, hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_init, dim3((unsigned)k), dim3(1024), 0, st, stt, d, k, rhs, r, p, y, tol);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_step(LsqrState* stt, int64_t d, int k, const double* q, double* r, double* p,
+                          double* y, int64_t it_max, hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_step, dim3((unsigned)k), dim3(1024), 0, st, stt, d, k, q, r, p, y,
+                       it_max);
+    return hipGetLastError();
+}
+
+hipError_t launch_all_done(const LsqrState* stt, int k, int32_t* flag, hipStream_t st) {
+    hipLaunchKernelGGL(k_all_done, dim3(1), dim3(1), 0, st, stt, k, flag);
+    return hipGetLastError();
+}
+
+}  // namespace ski

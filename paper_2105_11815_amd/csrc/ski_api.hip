@@ -1,0 +1,776 @@
+// The C interface declared in include/ski.h: handle, device buffers, argument checks and
+// the orchestration of Algorithm 1's steps on one HIP stream.  All arithmetic runs in the
+// kernels of hash.hip, sketch.hip, qr.hip, gemm.hip and lsqr.hip.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "lsqr.h"
+#include "ski_internal.h"
+
+using namespace ski;
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct ski_handle_s {
+    std::string err;
+    // problem description from ski_sketch
+    int32_t kind = SKI_DENSE;
+    int64_t n = 0, d = 0, k = 0, m = 0, npad = 0, ncols_hash = 0;
+    int s = 1;
+    bool had = false;
+    ski_params p{};
+    Prec sprec = Prec::F64, qprec = Prec::F64;
+    const double* A = nullptr;
+    int64_t lda = 0;
+    const int64_t* rp = nullptr;
+    const int32_t* ci = nullptr;
+    const double* va = nullptr;
+    int64_t nnz = 0;
+    const double* Bsk = nullptr;
+    int64_t ldb = 0;
+    bool sketched = false, factored = false;
+    double cond_est = 0.0;
+    // device buffers
+    DevBuf colrows, colneg, bucket_ptr, src, keys, table, dbits, T0, T1, SA;
+    DevBuf R, c, Rinv, RinvT, diag_add, tri_tmp, gemm_ws;
+    DevBuf qr_part, qr_W, qr_T, qr_Y, qr_tau;
+    DevBuf tkeys, tkeys_tmp, ttable, tp, tpay, ti, tv;
+    DevBuf u, t, v, h, delta, z, wp, g, gpart, upart, y, st, flag;
+    DevBuf cg_r, cg_p, cg_q, t2;
+    hipEvent_t ev[6] = {};
+    bool ev_ok = false;
+};
+
+namespace {
+
+int fail(ski_handle h, int code, const std::string& msg) {
+    if (h) h->err = msg;
+    return code;
+}
+
+int hip_fail(ski_handle h, hipError_t e, const char* where) {
+    return fail(h, e == hipErrorOutOfMemory ? SKI_ENOMEM : SKI_EDEVICE,
+                std::string(where) + ": " + hipGetErrorString(e));
+}
+
+hipError_t ensure(DevBuf& b, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (b.bytes >= bytes) return hipSuccess;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        if (e != hipSuccess) return e;
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return e;
+    }
+    b.bytes = bytes;
+    return hipSuccess;
+}
+
+void release(DevBuf& b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+template <typename T>
+T* P(DevBuf& b) {
+    return (T*)b.p;
+}
+
+#define SKI_TRY(h, expr, where)                        \
+    do {                                               \
+        hipError_t e__ = (expr);                       \
+        if (e__ != hipSuccess) return hip_fail(h, e__, where); \
+    } while (0)
+
+size_t elem_bytes(Prec p) { return p == Prec::F64 ? 8 : (p == Prec::F32 ? 4 : 2); }
+
+int64_t next_pow2(int64_t n) {
+    int64_t q = 1;
+    while (q < n) q <<= 1;
+    return q;
+}
+
+constexpr int64_t PASS_WG = 512;  // workgroups of the fused dense LSQR pass
+constexpr int CHECK_EVERY = 8;    // LSQR iterations between status reads
+
+}  // namespace
+
+extern "C" {
+
+int ski_create(ski_handle* h) {
+    if (!h) return SKI_EINVAL;
+    ski_handle_s* x = new (std::nothrow) ski_handle_s();
+    if (!x) return SKI_ENOMEM;
+    bool ok = true;
+    for (auto& e : x->ev) ok = ok && hipEventCreate(&e) == hipSuccess;
+    x->ev_ok = ok;
+    *h = x;
+    return ok ? SKI_OK : SKI_EDEVICE;
+}
+
+int ski_destroy(ski_handle h) {
+    if (!h) return SKI_EINVAL;
+    (void)hipDeviceSynchronize();
+    DevBuf* all[] = {&h->colrows, &h->colneg, &h->bucket_ptr, &h->src, &h->keys, &h->table,
+                     &h->dbits, &h->T0, &h->T1, &h->SA, &h->R, &h->c, &h->Rinv, &h->RinvT,
+                     &h->diag_add, &h->tri_tmp, &h->gemm_ws, &h->qr_part, &h->qr_W, &h->qr_T,
+                     &h->qr_Y, &h->qr_tau, &h->tkeys, &h->tkeys_tmp, &h->ttable, &h->tp,
+                     &h->tpay, &h->ti, &h->tv, &h->u, &h->t, &h->v, &h->h, &h->delta, &h->z,
+                     &h->wp, &h->g, &h->gpart, &h->upart, &h->y, &h->st, &h->flag, &h->cg_r,
+                     &h->cg_p, &h->cg_q, &h->t2};
+    for (DevBuf* b : all) release(*b);
+    if (h->ev_ok)
+        for (auto& e : h->ev) (void)hipEventDestroy(e);
+    delete h;
+    return SKI_OK;
+}
+
+void ski_params_default(int32_t kind, ski_params* p) {
+    if (!p) return;
+    memset(p, 0, sizeof(*p));
+    p->tau_a = 1e-8;
+    p->tau_r = 1e-6;
+    p->it_max = 10000;
+    p->seed = 1;
+    p->sketch_prec = SKI_FP64;
+    p->qr_prec = SKI_FP64;
+    if (kind == SKI_CSR) {
+        p->gamma = 1.4;
+        p->s = 2;
+        p->hadamard = 0;
+        p->rcond = 0.0;
+        p->rcond_thres = 1e-10;
+        p->perturb = 1e-10;
+    } else {
+        p->gamma = 1.7;
+        p->s = 1;
+        p->hadamard = 1;
+        p->rcond = 1e-12;
+        p->rcond_thres = 1e-10;
+        p->perturb = 0.0;
+    }
+}
+
+const char* ski_last_error(ski_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, int64_t ldb,
+               const ski_params* p, void* stream) {
+    if (!h) return SKI_EINVAL;
+    if (!A || !p || !B) return fail(h, SKI_EINVAL, "ski_sketch: NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = A->n, d = A->d;
+    if (d < 1 || n < d) return fail(h, SKI_EINVAL, "ski_sketch: need n >= d >= 1");
+    if (n > ((int64_t)1 << 30)) return fail(h, SKI_EINVAL, "ski_sketch: n above 2^30 rows");
+    if (k < 1 || ldb < k) return fail(h, SKI_EINVAL, "ski_sketch: need k >= 1 and ldb >= k");
+    if (A->kind != SKI_DENSE && A->kind != SKI_CSR)
+        return fail(h, SKI_EINVAL, "ski_sketch: unknown matrix kind");
+    if (A->kind == SKI_DENSE && (!A->a || A->lda < d))
+        return fail(h, SKI_EINVAL, "ski_sketch: dense A needs a and lda >= d");
+    if (A->kind == SKI_CSR && (!A->row_ptr || !A->col || !A->val || A->nnz < 0 ||
+                               A->nnz >= ((int64_t)1 << 31)))
+        return fail(h, SKI_EINVAL, "ski_sketch: CSR A needs row_ptr, col, val, nnz < 2^31");
+    if (A->kind == SKI_CSR && p->hadamard)
+        return fail(h, SKI_EINVAL, "ski_sketch: the Hadamard transform is for dense A only");
+    if (p->s < 1 || p->s > 32) return fail(h, SKI_EINVAL, "ski_sketch: need 1 <= s <= 32");
+    if (p->sketch_prec < 0 || p->sketch_prec > 2 || p->qr_prec < 0 || p->qr_prec > 2)
+        return fail(h, SKI_EINVAL, "ski_sketch: unknown precision");
+    if (!(p->tau_r >= 0) || !(p->tau_a >= 0) || p->it_max < 1)
+        return fail(h, SKI_EINVAL, "ski_sketch: bad tolerances or it_max");
+    int64_t m = p->m > 0 ? p->m : (int64_t)ceil(p->gamma * (double)d - 1e-9);
+    const bool had = (A->kind == SKI_DENSE) && p->hadamard;
+    const int64_t npad = had ? next_pow2(n) : n;
+    if (m < d) return fail(h, SKI_EINVAL, "ski_sketch: need m >= d");
+    if (m > npad) return fail(h, SKI_EINVAL, "ski_sketch: need m <= n (n' with Hadamard)");
+    if (p->s > m) return fail(h, SKI_EINVAL, "ski_sketch: need s <= m");
+    if (m > 12288) return fail(h, SKI_EINVAL, "ski_sketch: m above 12288 is not supported");
+    const int64_t ncols = d + k;
+    Prec sprec = (Prec)p->sketch_prec, qprec = (Prec)p->qr_prec;
+    // the sketch storage follows the QR precision: FP64 QR needs an FP64 sketch
+    if (qprec == Prec::F64) sprec = Prec::F64;
+
+    h->kind = A->kind;
+    h->n = n;
+    h->d = d;
+    h->k = k;
+    h->m = m;
+    h->npad = npad;
+    h->s = p->s;
+    h->had = had;
+    h->p = *p;
+    h->p.m = m;
+    h->sprec = sprec;
+    h->qprec = qprec;
+    h->A = A->a;
+    h->lda = A->lda;
+    h->rp = A->row_ptr;
+    h->ci = A->col;
+    h->va = A->val;
+    h->nnz = A->nnz;
+    h->Bsk = B;
+    h->ldb = ldb;
+    h->sketched = h->factored = false;
+
+    const int64_t nhc = npad;  // hashed columns of S_h
+    h->ncols_hash = nhc;
+    const int64_t nkeys = nhc * p->s;
+    const int64_t nch = hash_num_chunks(nkeys);
+    SKI_TRY(h, ensure(h->colrows, nkeys * 4), "alloc");
+    SKI_TRY(h, ensure(h->colneg, nkeys), "alloc");
+    SKI_TRY(h, ensure(h->bucket_ptr, (m + 1) * 4), "alloc");
+    SKI_TRY(h, ensure(h->src, nkeys * 4), "alloc");
+    SKI_TRY(h, ensure(h->keys, 2 * nch * SORT_CHUNK * 8), "alloc");
+    SKI_TRY(h, ensure(h->table, (size_t)nch * m * 4), "alloc");
+    // SA: FP64 in the FP64 form, FP32 in both mixed forms
+    const size_t sa_e = qprec == Prec::F64 ? 8 : 4;
+    SKI_TRY(h, ensure(h->SA, (size_t)m * ncols * sa_e), "alloc");
+    if (h->ev_ok) (void)hipEventRecord(h->ev[0], st);
+
+    HashBuffers hb;
+    hb.colrows = P<int32_t>(h->colrows);
+    hb.colneg = P<int8_t>(h->colneg);
+    hb.bucket_ptr = P<int32_t>(h->bucket_ptr);
+    hb.src = P<int32_t>(h->src);
+    hb.keys = P<uint64_t>(h->keys);
+    hb.table = P<int32_t>(h->table);
+    SKI_TRY(h, launch_hash_build(nhc, m, p->s, p->seed, hb, st), "hash build");
+
+    // the SA storage type for the gathers: FP64, or FP32 for the mixed forms
+    const Prec gprec = qprec == Prec::F64 ? Prec::F64 : (sprec == Prec::F64 ? Prec::F32 : sprec);
+    if (A->kind == SKI_DENSE && had) {
+        const size_t te = elem_bytes(gprec);
+        SKI_TRY(h, ensure(h->dbits, ((npad + 255) / 256) * 32), "alloc");
+        SKI_TRY(h, ensure(h->T0, (size_t)npad * ncols * te), "alloc");
+        SKI_TRY(h, ensure(h->T1, (size_t)npad * ncols * te), "alloc");
+        SKI_TRY(h, launch_dsign(npad, p->seed, P<uint32_t>(h->dbits), st), "dsign");
+        void* T = nullptr;
+        SKI_TRY(h, launch_wht_sketch_dense(A->a, A->lda, B, ldb, n, d, k, npad,
+                                           P<uint32_t>(h->dbits), h->T0.p, h->T1.p, gprec, &T, st),
+                "wht");
+        const double scale = 1.0 / sqrt((double)npad * (double)p->s);
+        SKI_TRY(h, launch_gather_dense(T, ncols, P<int32_t>(h->bucket_ptr), P<int32_t>(h->src), m,
+                                       scale, gprec, h->SA.p, st),
+                "gather");
+    } else if (A->kind == SKI_DENSE) {
+        const double scale = 1.0 / sqrt((double)p->s);
+        SKI_TRY(h, launch_gather_plain(A->a, A->lda, B, ldb, d, k, P<int32_t>(h->bucket_ptr),
+                                       P<int32_t>(h->src), m, scale,
+                                       qprec == Prec::F64 ? Prec::F64 : Prec::F32, h->SA.p, st),
+                "gather");
+    } else {
+        const double scale = 1.0 / sqrt((double)p->s);
+        SKI_TRY(h, launch_gather_csr(A->row_ptr, A->col, A->val, B, ldb, d, k,
+                                     P<int32_t>(h->bucket_ptr), P<int32_t>(h->src), m, scale,
+                                     qprec == Prec::F64 ? Prec::F64 : Prec::F32, h->SA.p, st),
+                "gather csr");
+        // CSR of A^T for the transposed products of LSQR
+        const int64_t nnz = A->nnz;
+        const int64_t tch = hash_num_chunks(nnz);
+        SKI_TRY(h, ensure(h->tkeys, nnz * 8), "alloc");
+        SKI_TRY(h, ensure(h->tkeys_tmp, tch * SORT_CHUNK * 8), "alloc");
+        SKI_TRY(h, ensure(h->ttable, (size_t)tch * d * 4), "alloc");
+        SKI_TRY(h, ensure(h->tp, (d + 1) * 4), "alloc");
+        SKI_TRY(h, ensure(h->tpay, nnz * 4), "alloc");
+        SKI_TRY(h, ensure(h->ti, nnz * 4), "alloc");
+        SKI_TRY(h, ensure(h->tv, nnz * 8), "alloc");
+        SKI_TRY(h, build_csrT(A->row_ptr, A->col, A->val, n, d, nnz, P<uint64_t>(h->tkeys),
+                              P<uint64_t>(h->tkeys_tmp), P<int32_t>(h->ttable), P<int32_t>(h->tp),
+                              P<int32_t>(h->tpay), P<int32_t>(h->ti), P<double>(h->tv), st),
+                "csr transpose");
+    }
+    if (h->ev_ok) (void)hipEventRecord(h->ev[1], st);
+    h->sketched = true;
+    return SKI_OK;
+}
+
+int ski_factor(ski_handle h, void* stream) {
+    if (!h) return SKI_EINVAL;
+    if (!h->sketched) return fail(h, SKI_ESTATE, "ski_factor: call ski_sketch first");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t m = h->m, d = h->d, k = h->k, ncols = d + k;
+    const size_t e = h->qprec == Prec::F64 ? 8 : 4;
+    size_t gb = 0;
+    const size_t partb = qr_ws_bytes(h->qprec, m, ncols, d, &gb);
+    SKI_TRY(h, ensure(h->qr_part, partb), "alloc");
+    SKI_TRY(h, ensure(h->qr_W, 2 * 64 * ncols * e), "alloc");
+    SKI_TRY(h, ensure(h->qr_T, 64 * 64 * e), "alloc");
+    SKI_TRY(h, ensure(h->qr_Y, 64 * 64 * e), "alloc");
+    SKI_TRY(h, ensure(h->qr_tau, d * e), "alloc");
+    const size_t gws = std::max<size_t>({gb, (size_t)(448 * 64 * 64 + 64 * ncols) * 8,
+                                         (size_t)64 << 20});
+    SKI_TRY(h, ensure(h->gemm_ws, gws), "alloc");
+    SKI_TRY(h, ensure(h->R, d * d * 8), "alloc");
+    SKI_TRY(h, ensure(h->c, d * k * 8), "alloc");
+    SKI_TRY(h, ensure(h->Rinv, d * d * 8), "alloc");
+    SKI_TRY(h, ensure(h->RinvT, d * d * 8), "alloc");
+    SKI_TRY(h, ensure(h->diag_add, d * 8), "alloc");
+    SKI_TRY(h, ensure(h->tri_tmp, ((d + 1) / 2 + 64) * ((d + 1) / 2 + 64) * 8), "alloc");
+    if (h->ev_ok) (void)hipEventRecord(h->ev[2], st);
+    QrWs ws;
+    ws.V = h->qr_part.p;
+    ws.T = h->qr_T.p;
+    ws.W = h->qr_W.p;
+    ws.Y = h->qr_Y.p;
+    ws.ddiag = P<double>(h->qr_tau);
+    ws.g.part = h->gemm_ws.p;
+    ws.g.bytes = h->gemm_ws.bytes;
+    SKI_TRY(h, qr_factor(h->qprec, h->SA.p, m, ncols, d, ws, st), "qr");
+    SKI_TRY(h, launch_extract_Rc(h->qprec, h->SA.p, ncols, d, k, P<double>(h->R), P<double>(h->c),
+                                 st),
+            "extract R");
+    // guards on diag(R): read the diagonal (d values) to the host
+    std::vector<double> Rd(d);
+    SKI_TRY(h, hipMemcpy2DAsync(Rd.data(), sizeof(double), P<double>(h->R), (d + 1) * sizeof(double),
+                                sizeof(double), d, hipMemcpyDeviceToHost, st),
+            "diag copy");
+    SKI_TRY(h, hipStreamSynchronize(st), "sync");
+    double amax = 0, amin = INFINITY;
+    bool finite = true;
+    for (int64_t i = 0; i < d; ++i) {
+        const double a = fabs(Rd[i]);
+        finite = finite && std::isfinite(Rd[i]);
+        amax = std::max(amax, a);
+        amin = std::min(amin, a);
+    }
+    if (!finite) return fail(h, SKI_EINVAL, "ski_factor: non-finite R (non-finite input?)");
+    h->cond_est = amin > 0 ? amax / amin : INFINITY;
+    if (h->p.rcond > 0) {
+        const double r11 = fabs(Rd[0]);
+        for (int64_t i = 0; i < d; ++i)
+            if (!(r11 > 0) || fabs(Rd[i]) < h->p.rcond * r11) {
+                h->factored = false;
+                char buf[160];
+                snprintf(buf, sizeof buf,
+                         "ski_factor: rank guard failed at column %lld (|r_qq| < rcond |r_11|)",
+                         (long long)i);
+                return fail(h, SKI_ERANK, buf);
+            }
+    }
+    std::vector<double> add(d, 0.0);
+    if (h->p.perturb > 0 && h->p.rcond_thres > 0 && h->cond_est >= 1.0 / h->p.rcond_thres)
+        for (int64_t i = 0; i < d; ++i) add[i] = copysign(h->p.perturb, Rd[i]);
+    SKI_TRY(h, hipMemcpyAsync(h->diag_add.p, add.data(), d * 8, hipMemcpyHostToDevice, st),
+            "perturb copy");
+    GemmWs gw;
+    gw.part = h->gemm_ws.p;
+    gw.bytes = h->gemm_ws.bytes;
+    SKI_TRY(h, trtri_upper(P<double>(h->R), d, P<double>(h->Rinv), P<double>(h->RinvT),
+                           P<double>(h->diag_add), P<double>(h->tri_tmp), gw, st),
+            "R inverse");
+    if (h->ev_ok) (void)hipEventRecord(h->ev[3], st);
+    SKI_TRY(h, hipStreamSynchronize(st), "sync");  // add[] lives on this stack frame
+    h->factored = true;
+    return SKI_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// W v products for the multi-RHS dense path through the GEMM
+hipError_t dense_AZ(ski_handle h, const double* Zm, int k, double* out, GemmWs& gw,
+                    hipStream_t st) {
+    return gemm_f64(false, false, h->n, k, h->d, 1.0, h->A, h->lda, Zm, k, 0.0, out, k, gw, st);
+}
+hipError_t dense_ATU(ski_handle h, const double* U, int k, double* out, GemmWs& gw,
+                     hipStream_t st) {
+    return gemm_f64(true, false, h->d, k, h->n, 1.0, h->A, h->lda, U, k, 0.0, out, k, gw, st);
+}
+
+int alloc_solve_ws(ski_handle h, int k) {
+    const int64_t n = h->n, d = h->d;
+    SKI_TRY(h, ensure(h->u, n * k * 8), "alloc");
+    SKI_TRY(h, ensure(h->t, n * k * 8), "alloc");
+    SKI_TRY(h, ensure(h->v, d * k * 8), "alloc");
+    SKI_TRY(h, ensure(h->h, d * k * 8), "alloc");
+    SKI_TRY(h, ensure(h->delta, d * k * 8), "alloc");
+    SKI_TRY(h, ensure(h->z, d * k * 8), "alloc");
+    SKI_TRY(h, ensure(h->wp, d * k * 8), "alloc");
+    SKI_TRY(h, ensure(h->g, d * k * 8), "alloc");
+    SKI_TRY(h, ensure(h->y, d * k * 8), "alloc");
+    SKI_TRY(h, ensure(h->gpart, PASS_WG * d * 8), "alloc");
+    const int64_t G = std::max<int64_t>({PASS_WG, spmv_csr_groups(n), 1});
+    SKI_TRY(h, ensure(h->upart, G * k * 8), "alloc");
+    SKI_TRY(h, ensure(h->st, k * sizeof(LsqrState)), "alloc");
+    SKI_TRY(h, ensure(h->flag, 64), "alloc");
+    return SKI_OK;
+}
+
+// z = R^-1 x (d x k, both leading dimension k)
+hipError_t apply_Rinv(ski_handle h, const double* Mtx, bool upper, const double* x, double* y, int k,
+                      double s, const int32_t* done, GemmWs& gw, hipStream_t st) {
+    if (k == 1) return launch_tri_gemv(Mtx, h->d, upper, x, 1, y, 1, s, done, st);
+    return gemm_f64(false, false, h->d, k, h->d, s, Mtx, h->d, x, k, 0.0, y, k, gw, st);
+}
+
+int read_flag(ski_handle h, int k, hipStream_t st, int32_t* out) {
+    SKI_TRY(h, launch_all_done(P<LsqrState>(h->st), k, P<int32_t>(h->flag), st), "flag");
+    SKI_TRY(h, hipMemcpyAsync(out, h->flag.p, 4, hipMemcpyDeviceToHost, st), "flag copy");
+    SKI_TRY(h, hipStreamSynchronize(st), "sync");
+    return SKI_OK;
+}
+
+int finish_info(ski_handle h, int k, ski_info* info, float ms_solve, bool cg, hipStream_t st) {
+    std::vector<LsqrState> S(k);
+    SKI_TRY(h, hipMemcpyAsync(S.data(), h->st.p, k * sizeof(LsqrState), hipMemcpyDeviceToHost, st),
+            "state copy");
+    SKI_TRY(h, hipStreamSynchronize(st), "sync");
+    float ms_sk = 0, ms_f = 0;
+    if (h->ev_ok) {
+        (void)hipEventElapsedTime(&ms_sk, h->ev[0], h->ev[1]);
+        (void)hipEventElapsedTime(&ms_f, h->ev[2], h->ev[3]);
+    }
+    int worst = SKI_OK;
+    for (int j = 0; j < k; ++j) {
+        const int stj = S[j].done ? S[j].status : SKI_WNOCONV;
+        if (stj == SKI_WNOCONV)
+            worst = SKI_WNOCONV;
+        else if (stj == SKI_WEARLY && worst == SKI_OK)
+            worst = SKI_WEARLY;
+        if (info) {
+            ski_info& I = info[j];
+            I.iters = S[j].iters;
+            I.status = stj;
+            I.early_exit = S[j].early;
+            I.rnorm = S[j].rnorm;
+            I.arnorm = cg ? 0.0 : S[j].arnorm;
+            I.wnorm_est = cg ? 0.0 : sqrt(S[j].anorm2);
+            I.tc = cg ? 0.0 : S[j].tc;
+            I.cond_est = h->cond_est;
+            I.ms_sketch = ms_sk;
+            I.ms_factor = ms_f;
+            I.ms_solve = ms_solve;
+        }
+    }
+    if (worst == SKI_WEARLY && k > 1) {
+        bool all_early = true;
+        for (int j = 0; j < k; ++j) all_early = all_early && S[j].early;
+        if (!all_early) worst = SKI_OK;
+    }
+    return worst;
+}
+
+int solve_lls(ski_handle h, const double* B, int k, int64_t ldb, double* X, int64_t ldx,
+              ski_info* info, hipStream_t st) {
+    const int64_t n = h->n, d = h->d;
+    int rc = alloc_solve_ws(h, k);
+    if (rc != SKI_OK) return rc;
+    GemmWs gw;
+    gw.part = h->gemm_ws.p;
+    gw.bytes = h->gemm_ws.bytes;
+    LsqrState* S = P<LsqrState>(h->st);
+    double *u = P<double>(h->u), *t = P<double>(h->t), *v = P<double>(h->v), *hh = P<double>(h->h);
+    double *dl = P<double>(h->delta), *z = P<double>(h->z), *wp = P<double>(h->wp);
+    double *g = P<double>(h->g), *y = P<double>(h->y);
+    const double* Rinv = P<double>(h->Rinv);
+    const double* RinvT = P<double>(h->RinvT);
+    const double* c = P<double>(h->c);
+    const bool fused = (h->kind == SKI_DENSE && k == 1 && lsqr_pass_cpt(d) > 0);
+    const bool csr = (h->kind == SKI_CSR);
+    hipEvent_t e0 = h->ev[4], e1 = h->ev[5];
+    if (h->ev_ok) (void)hipEventRecord(e0, st);
+    SKI_TRY(h, hipMemsetAsync(S, 0, k * sizeof(LsqrState), st), "state init");
+    // u = B (the residual is formed in place), z = -x_s
+    SKI_TRY(h, launch_scale_copy(B, n, k, ldb, 1.0, u, k, st), "copy b");
+    SKI_TRY(h, apply_Rinv(h, Rinv, true, c, z, k, -1.0, nullptr, gw, st), "x_s");
+    // r_0 = b - A x_s ; g = A^T r_0
+    if (fused) {
+        SKI_TRY(h, launch_lsqr_pass(h->A, h->lda, n, d, z, u, S, PASS_WG, P<double>(h->gpart),
+                                    P<double>(h->upart), g, S, true, st),
+                "pass");
+    } else if (csr) {
+        SKI_TRY(h, launch_spmv_csr(h->rp, h->ci, h->va, n, k, z, u, S, true, P<double>(h->upart), st),
+                "spmv");
+        SKI_TRY(h, launch_spmv_csrT(P<int32_t>(h->tp), P<int32_t>(h->ti), P<double>(h->tv), d, k, u,
+                                    g, S, st),
+                "spmvT");
+    } else {
+        SKI_TRY(h, dense_AZ(h, z, k, t, gw, st), "AZ");
+        SKI_TRY(h, launch_combine_u(t, u, n, k, S, true, P<double>(h->upart), PASS_WG, S, st),
+                "combine");
+        SKI_TRY(h, dense_ATU(h, u, k, g, gw, st), "ATU");
+    }
+    SKI_TRY(h, apply_Rinv(h, RinvT, false, g, wp, k, 1.0, nullptr, gw, st), "R^-T g");
+    SKI_TRY(h, launch_lsqr_init(S, d, k, wp, v, hh, dl, h->p.tau_a, st), "init");
+    const int32_t* done1 = (k == 1) ? &S[0].done : nullptr;
+    int32_t* hflag = nullptr;
+    SKI_TRY(h, hipHostMalloc((void**)&hflag, 4, hipHostMallocDefault), "pinned");
+    int64_t it = 0;
+    int out = SKI_OK;
+    while (true) {
+        int rc2 = read_flag(h, k, st, hflag);
+        if (rc2 != SKI_OK) {
+            out = rc2;
+            break;
+        }
+        if (*hflag || it >= h->p.it_max) break;
+        for (int q = 0; q < CHECK_EVERY && it < h->p.it_max; ++q, ++it) {
+            hipError_t e = apply_Rinv(h, Rinv, true, v, z, k, 1.0, done1, gw, st);
+            if (e == hipSuccess) {
+                if (fused)
+                    e = launch_lsqr_pass(h->A, h->lda, n, d, z, u, S, PASS_WG, P<double>(h->gpart),
+                                         P<double>(h->upart), g, S, false, st);
+                else if (csr) {
+                    e = launch_spmv_csr(h->rp, h->ci, h->va, n, k, z, u, S, false,
+                                        P<double>(h->upart), st);
+                    if (e == hipSuccess)
+                        e = launch_spmv_csrT(P<int32_t>(h->tp), P<int32_t>(h->ti), P<double>(h->tv),
+                                             d, k, u, g, S, st);
+                } else {
+                    e = dense_AZ(h, z, k, t, gw, st);
+                    if (e == hipSuccess)
+                        e = launch_combine_u(t, u, n, k, S, false, P<double>(h->upart), PASS_WG, S,
+                                             st);
+                    if (e == hipSuccess) e = dense_ATU(h, u, k, g, gw, st);
+                }
+            }
+            if (e == hipSuccess) e = apply_Rinv(h, RinvT, false, g, wp, k, 1.0, done1, gw, st);
+            if (e == hipSuccess)
+                e = launch_lsqr_step(S, d, k, wp, v, hh, dl, h->p.tau_r, h->p.it_max, st);
+            if (e != hipSuccess) {
+                out = hip_fail(h, e, "lsqr iteration");
+                break;
+            }
+        }
+        if (out != SKI_OK) break;
+    }
+    (void)hipHostFree(hflag);
+    if (out != SKI_OK) return out;
+    // x = R^-1 (c + delta)
+    SKI_TRY(h, launch_final_y(S, d, k, c, dl, y, st), "final y");
+    if (k == 1) {
+        SKI_TRY(h, launch_tri_gemv(Rinv, d, true, y, 1, X, ldx, 1.0, nullptr, st), "x");
+    } else {
+        SKI_TRY(h, gemm_f64(false, false, d, k, d, 1.0, Rinv, d, y, k, 0.0, X, ldx, gw, st), "x");
+    }
+    float ms = 0;
+    if (h->ev_ok) {
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
+        (void)hipEventElapsedTime(&ms, e0, e1);
+    }
+    return finish_info(h, k, info, ms, false, st);
+}
+
+// Z = (A^T A)^-1 G by CG on R^-T A^T A R^-1 (dense A)
+int solve_normal(ski_handle h, const double* G, int k, int64_t ldg, double* Z, int64_t ldz,
+                 ski_info* info, hipStream_t st) {
+    const int64_t n = h->n, d = h->d;
+    int rc = alloc_solve_ws(h, k);
+    if (rc != SKI_OK) return rc;
+    SKI_TRY(h, ensure(h->cg_r, d * k * 8), "alloc");
+    SKI_TRY(h, ensure(h->cg_p, d * k * 8), "alloc");
+    SKI_TRY(h, ensure(h->cg_q, d * k * 8), "alloc");
+    GemmWs gw;
+    gw.part = h->gemm_ws.p;
+    gw.bytes = h->gemm_ws.bytes;
+    LsqrState* S = P<LsqrState>(h->st);
+    double *t = P<double>(h->t), *z = P<double>(h->z), *g = P<double>(h->g), *y = P<double>(h->y);
+    double *r = P<double>(h->cg_r), *pp = P<double>(h->cg_p), *q = P<double>(h->cg_q);
+    double* wp = P<double>(h->wp);
+    const double* Rinv = P<double>(h->Rinv);
+    const double* RinvT = P<double>(h->RinvT);
+    hipEvent_t e0 = h->ev[4], e1 = h->ev[5];
+    if (h->ev_ok) (void)hipEventRecord(e0, st);
+    SKI_TRY(h, hipMemsetAsync(S, 0, k * sizeof(LsqrState), st), "state init");
+    // rhs = R^-T G (into wp, compact leading dimension k)
+    SKI_TRY(h, launch_scale_copy(G, d, k, ldg, 1.0, g, k, st), "copy g");
+    SKI_TRY(h, gemm_f64(false, false, d, k, d, 1.0, RinvT, d, g, k, 0.0, wp, k, gw, st), "rhs");
+    SKI_TRY(h, launch_cg_init(S, d, k, wp, r, pp, y, h->p.tau_r, st), "cg init");
+    int32_t* hflag = nullptr;
+    SKI_TRY(h, hipHostMalloc((void**)&hflag, 4, hipHostMallocDefault), "pinned");
+    int64_t it = 0;
+    int out = SKI_OK;
+    while (true) {
+        int rc2 = read_flag(h, k, st, hflag);
+        if (rc2 != SKI_OK) {
+            out = rc2;
+            break;
+        }
+        if (*hflag || it >= h->p.it_max) break;
+        for (int s = 0; s < CHECK_EVERY && it < h->p.it_max; ++s, ++it) {
+            hipError_t e = gemm_f64(false, false, d, k, d, 1.0, Rinv, d, pp, k, 0.0, z, k, gw, st);
+            if (e == hipSuccess) e = dense_AZ(h, z, k, t, gw, st);
+            if (e == hipSuccess) e = dense_ATU(h, t, k, g, gw, st);
+            if (e == hipSuccess)
+                e = gemm_f64(false, false, d, k, d, 1.0, RinvT, d, g, k, 0.0, q, k, gw, st);
+            if (e == hipSuccess) e = launch_cg_step(S, d, k, q, r, pp, y, h->p.it_max, st);
+            if (e != hipSuccess) {
+                out = hip_fail(h, e, "cg iteration");
+                break;
+            }
+        }
+        if (out != SKI_OK) break;
+    }
+    (void)hipHostFree(hflag);
+    if (out != SKI_OK) return out;
+    SKI_TRY(h, gemm_f64(false, false, d, k, d, 1.0, Rinv, d, y, k, 0.0, Z, ldz, gw, st), "z");
+    float ms = 0;
+    if (h->ev_ok) {
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
+        (void)hipEventElapsedTime(&ms, e0, e1);
+    }
+    (void)n;
+    return finish_info(h, k, info, ms, true, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ski_solve(ski_handle h, int32_t op, const double* B, int32_t k, int64_t ldb, double* X,
+              int64_t ldx, ski_info* info, void* stream) {
+    if (!h) return SKI_EINVAL;
+    if (!h->factored) return fail(h, SKI_ESTATE, "ski_solve: call ski_sketch and ski_factor first");
+    if (!B || !X) return fail(h, SKI_EINVAL, "ski_solve: NULL B or X");
+    if (k < 1 || ldb < k || ldx < k) return fail(h, SKI_EINVAL, "ski_solve: bad k or leading dims");
+    hipStream_t st = (hipStream_t)stream;
+    if (op == SKI_OP_LLS) {
+        if (k != h->k)
+            return fail(h, SKI_EINVAL,
+                        "ski_solve: B must be the k right-hand sides given to ski_sketch");
+        return solve_lls(h, B, k, ldb, X, ldx, info, st);
+    }
+    if (op == SKI_OP_NORMAL) {
+        if (h->kind != SKI_DENSE) return fail(h, SKI_EINVAL, "ski_solve: NORMAL needs dense A");
+        return solve_normal(h, B, k, ldb, X, ldx, info, st);
+    }
+    return fail(h, SKI_EINVAL, "ski_solve: unknown op");
+}
+
+int ski_gradients(ski_handle h, const double* X, int64_t ldx, const double* B, int64_t ldb,
+                  const double* Z, int64_t ldz, int32_t k, double* grad_A, int64_t ldga,
+                  double* grad_B, int64_t ldgb, void* stream) {
+    if (!h) return SKI_EINVAL;
+    if (!h->sketched) return fail(h, SKI_ESTATE, "ski_gradients: no matrix (call ski_sketch)");
+    if (h->kind != SKI_DENSE) return fail(h, SKI_EINVAL, "ski_gradients: dense A only");
+    if (!X || !B || !Z || k < 1 || ldx < k || ldb < k || ldz < k)
+        return fail(h, SKI_EINVAL, "ski_gradients: bad arguments");
+    if ((grad_A && ldga < h->d) || (grad_B && ldgb < k))
+        return fail(h, SKI_EINVAL, "ski_gradients: bad output leading dimensions");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = h->n, d = h->d;
+    SKI_TRY(h, ensure(h->gemm_ws, (size_t)64 << 20), "alloc");
+    SKI_TRY(h, ensure(h->t, n * k * 8), "alloc");
+    SKI_TRY(h, ensure(h->t2, n * k * 8), "alloc");
+    GemmWs gw;
+    gw.part = h->gemm_ws.p;
+    gw.bytes = h->gemm_ws.bytes;
+    double* AZ = P<double>(h->t);
+    double* Res = P<double>(h->t2);
+    SKI_TRY(h, gemm_f64(false, false, n, k, d, 1.0, h->A, h->lda, Z, ldz, 0.0, AZ, k, gw, st), "AZ");
+    if (grad_B) SKI_TRY(h, launch_scale_copy(AZ, n, k, k, 1.0, grad_B, ldgb, st), "grad_B");
+    if (grad_A) {
+        SKI_TRY(h, launch_scale_copy(B, n, k, ldb, 1.0, Res, k, st), "copy B");
+        SKI_TRY(h, gemm_f64(false, false, n, k, d, -1.0, h->A, h->lda, X, ldx, 1.0, Res, k, gw, st),
+                "residual");
+        SKI_TRY(h, gemm_f64(false, true, n, d, k, 1.0, Res, k, Z, ldz, 0.0, grad_A, ldga, gw, st),
+                "r Z^T");
+        SKI_TRY(h, gemm_f64(false, true, n, d, k, -1.0, AZ, k, X, ldx, 1.0, grad_A, ldga, gw, st),
+                "(AZ) X^T");
+    }
+    return SKI_OK;
+}
+
+int ski_get_dims(ski_handle h, int64_t dims[6]) {
+    if (!h || !dims) return SKI_EINVAL;
+    dims[0] = h->n;
+    dims[1] = h->d;
+    dims[2] = h->k;
+    dims[3] = h->m;
+    dims[4] = h->npad;
+    dims[5] = h->s;
+    return SKI_OK;
+}
+
+int ski_get_hash(ski_handle h, int32_t* rows, int8_t* neg, int64_t* bucket_ptr, int32_t* src,
+                 int8_t* src_neg) {
+    if (!h) return SKI_EINVAL;
+    if (!h->sketched) return fail(h, SKI_ESTATE, "ski_get_hash: nothing sketched");
+    const int64_t nk = h->ncols_hash * h->s;
+    if (hipDeviceSynchronize() != hipSuccess) return fail(h, SKI_EDEVICE, "sync");
+    if (rows && hipMemcpy(rows, h->colrows.p, nk * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(h, SKI_EDEVICE, "copy");
+    if (neg && hipMemcpy(neg, h->colneg.p, nk, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(h, SKI_EDEVICE, "copy");
+    if (bucket_ptr) {
+        std::vector<int32_t> bp(h->m + 1);
+        if (hipMemcpy(bp.data(), h->bucket_ptr.p, (h->m + 1) * 4, hipMemcpyDeviceToHost) !=
+            hipSuccess)
+            return fail(h, SKI_EDEVICE, "copy");
+        for (int64_t i = 0; i <= h->m; ++i) bucket_ptr[i] = bp[i];
+    }
+    if (src || src_neg) {
+        std::vector<int32_t> sv(nk);
+        if (hipMemcpy(sv.data(), h->src.p, nk * 4, hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(h, SKI_EDEVICE, "copy");
+        for (int64_t i = 0; i < nk; ++i) {
+            if (src) src[i] = (int32_t)((uint32_t)sv[i] >> 1);
+            if (src_neg) src_neg[i] = (int8_t)(sv[i] & 1);
+        }
+    }
+    return SKI_OK;
+}
+
+int ski_get_dsign(ski_handle h, int8_t* dsign) {
+    if (!h || !dsign) return SKI_EINVAL;
+    if (!h->sketched || !h->had) return fail(h, SKI_ESTATE, "ski_get_dsign: no Hadamard sketch");
+    std::vector<uint32_t> bits((h->npad + 31) / 32);
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(bits.data(), h->dbits.p, bits.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(h, SKI_EDEVICE, "copy");
+    for (int64_t i = 0; i < h->npad; ++i) dsign[i] = ((bits[i >> 5] >> (i & 31)) & 1u) ? -1 : 1;
+    return SKI_OK;
+}
+
+int ski_get_SA(ski_handle h, double* SA) {
+    if (!h || !SA) return SKI_EINVAL;
+    if (!h->sketched) return fail(h, SKI_ESTATE, "ski_get_SA: nothing sketched");
+    const int64_t cnt = h->m * (h->d + h->k);
+    if (hipDeviceSynchronize() != hipSuccess) return fail(h, SKI_EDEVICE, "sync");
+    if (h->qprec == Prec::F64) {
+        if (hipMemcpy(SA, h->SA.p, cnt * 8, hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(h, SKI_EDEVICE, "copy");
+    } else {
+        std::vector<float> f(cnt);
+        if (hipMemcpy(f.data(), h->SA.p, cnt * 4, hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(h, SKI_EDEVICE, "copy");
+        for (int64_t i = 0; i < cnt; ++i) SA[i] = f[i];
+    }
+    return SKI_OK;
+}
+
+int ski_get_R(ski_handle h, double* R, double* c, double* Rinv) {
+    if (!h) return SKI_EINVAL;
+    if (!h->R.p || !h->sketched) return fail(h, SKI_ESTATE, "ski_get_R: not factored");
+    const int64_t d = h->d;
+    if (hipDeviceSynchronize() != hipSuccess) return fail(h, SKI_EDEVICE, "sync");
+    if (R && hipMemcpy(R, h->R.p, d * d * 8, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(h, SKI_EDEVICE, "copy");
+    if (c && hipMemcpy(c, h->c.p, d * h->k * 8, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(h, SKI_EDEVICE, "copy");
+    if (Rinv && h->factored &&
+        hipMemcpy(Rinv, h->Rinv.p, d * d * 8, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(h, SKI_EDEVICE, "copy");
+    return SKI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,151 @@
+// Internal declarations shared by the HIP sources of the solver library.
+// Host-side launchers are declared here; kernels live in the .hip files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ski.h"
+
+namespace ski {
+
+// ---------------------------------------------------------------------------
+// error plumbing: launchers return hipError_t; the API layer maps it to a status
+#define SKI_HIP(expr)                                   \
+    do {                                                \
+        hipError_t e_ = (expr);                         \
+        if (e_ != hipSuccess) return e_;                \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon et al., SC'11): ten rounds of the 4x64 bijection with the
+// key bumped by the Weyl constants between rounds.
+struct P4 {
+    uint64_t x[4];
+};
+
+__device__ __forceinline__ P4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                             uint64_t k0, uint64_t k1) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += W0;
+            k1 += W1;
+        }
+        uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+        uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    P4 o;
+    o.x[0] = c0;
+    o.x[1] = c1;
+    o.x[2] = c2;
+    o.x[3] = c3;
+    return o;
+}
+
+// ---------------------------------------------------------------------------
+// wave64 reductions (DPP/permute through the compiler's shuffle lowering)
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// storage types for the mixed-precision forms
+__device__ __forceinline__ float to_f(float x) { return x; }
+__device__ __forceinline__ float to_f(double x) { return (float)x; }
+__device__ __forceinline__ float to_f(__hip_bfloat16 x) { return __bfloat162float(x); }
+template <typename T>
+__device__ __forceinline__ T from_f(float x);
+template <>
+__device__ __forceinline__ float from_f<float>(float x) { return x; }
+template <>
+__device__ __forceinline__ double from_f<double>(float x) { return (double)x; }
+template <>
+__device__ __forceinline__ __hip_bfloat16 from_f<__hip_bfloat16>(float x) { return __float2bfloat16(x); }
+
+// ---------------------------------------------------------------------------
+// launchers (all asynchronous on `st`)
+
+// hashing: per-column rows/signs and the bucket-sorted CSR of S_h
+struct HashBuffers {
+    int32_t* colrows = nullptr;   // [ncols*s]
+    int8_t* colneg = nullptr;     // [ncols*s]
+    int32_t* bucket_ptr = nullptr;  // [m+1]
+    int32_t* src = nullptr;       // [ncols*s]  column index | sign bit 31
+    uint64_t* keys = nullptr;     // [nchunks*CHUNK] sorted keys per chunk
+    int32_t* table = nullptr;     // [nchunks*m] per-chunk bucket counts -> bases
+};
+constexpr int SORT_CHUNK = 4096;  // keys sorted per workgroup in LDS
+int64_t hash_num_chunks(int64_t nkeys);
+hipError_t launch_hash_build(int64_t ncols, int64_t m, int s, uint64_t seed, HashBuffers& hb,
+                             hipStream_t st);
+// generic deterministic bucket sort of nkeys (bucket << 32 | payload) keys already in
+// `keys_unsorted` (payloads unique): writes bucket_ptr[nb+1] and out_payload[nkeys]
+hipError_t launch_bucket_sort(const uint64_t* keys_unsorted, int64_t nkeys, int64_t nbuckets,
+                              uint64_t* keys_tmp, int32_t* table, int32_t* bucket_ptr,
+                              int32_t* out_payload, hipStream_t st);
+hipError_t launch_dsign(int64_t npad, uint64_t seed, uint32_t* bits, hipStream_t st);
+
+// Walsh-Hadamard passes and the hashing gathers
+enum class Prec { F64 = 0, F32 = 1, BF16 = 2 };
+hipError_t launch_wht_sketch_dense(const double* A, int64_t lda, const double* B, int64_t ldb,
+                                   int64_t n, int64_t d, int64_t k, int64_t npad,
+                                   const uint32_t* dbits, void* T0, void* T1, Prec prec,
+                                   void** T_out, hipStream_t st);
+hipError_t launch_gather_dense(const void* T, int64_t ncols, const int32_t* bucket_ptr,
+                               const int32_t* src, int64_t m, double scale, Prec prec,
+                               void* SA, hipStream_t st);
+hipError_t launch_gather_plain(const double* A, int64_t lda, const double* B, int64_t ldb,
+                               int64_t d, int64_t k, const int32_t* bucket_ptr,
+                               const int32_t* src, int64_t m, double scale, Prec prec, void* SA,
+                               hipStream_t st);
+hipError_t launch_gather_csr(const int64_t* row_ptr, const int32_t* col, const double* val,
+                             const double* B, int64_t ldb, int64_t d, int64_t k,
+                             const int32_t* bucket_ptr, const int32_t* src, int64_t m,
+                             double scale, Prec prec, void* SA, hipStream_t st);
+
+// GEMM: C[MxN] = alpha op(A) op(B) + beta C, row-major, on MFMA.
+//   T = double (FP64 MFMA), float (FP32 MFMA), or float with bf16 MFMA inputs.
+struct GemmWs {
+    void* part = nullptr;   // split-K partials
+    size_t bytes = 0;
+};
+hipError_t gemm_f64(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
+                    const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                    double* C, int64_t ldc, GemmWs& ws, hipStream_t st, int unitA = 0);
+hipError_t gemm_f32(bool ta, bool tb, int64_t M, int64_t N, int64_t K, float alpha,
+                    const float* A, int64_t lda, const float* B, int64_t ldb, float beta, float* C,
+                    int64_t ldc, bool bf16_inputs, GemmWs& ws, hipStream_t st, int unitA = 0);
+size_t gemm_ws_bytes(int64_t M, int64_t N, int64_t K, size_t elem);
+
+// Householder QR of the m x (d+k) sketch (in place), R into the upper triangle
+struct QrWs {
+    void* V = nullptr;      // explicit Householder vectors, m x nb panel
+    void* T = nullptr;      // nb x nb
+    void* W = nullptr;      // nb x ncols
+    void* Y = nullptr;      // nb x nb
+    double* ddiag = nullptr;
+    GemmWs g;
+};
+hipError_t qr_factor(Prec prec, void* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws,
+                     hipStream_t st);
+size_t qr_ws_bytes(Prec prec, int64_t m, int64_t ncols, int64_t d, size_t* gemm_bytes);
+// copy R (d x d) and c (d x k) out of the factored sketch into FP64, flipping rows so
+// that diag(R) >= 0
+hipError_t launch_extract_Rc(Prec prec, const void* SA, int64_t ldsa, int64_t d, int64_t k,
+                             double* R, double* c, hipStream_t st);
+}  // namespace ski

@@ -1,0 +1,282 @@
+"""GPU parity: the HIP library (through its C interface) against the FP64 CPU oracle on
+the same seeded inputs.  Bit-exact for the integer hashing data; within the stated
+tolerance for floating point."""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+import workloads
+from oracle import lls, sketch as sk
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ski():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2105_11815_amd as P
+    return P
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+# -------------------------------------------------------------------------- sketch
+DENSE_SKETCH_CASES = [
+    # n, d, k, m, s  (ragged n, several WHT passes, several GEMM tiles)
+    (4096, 64, 1, 256, 1),      # the tiny workload shape
+    (3000, 70, 1, 150, 3),      # ragged n, n' = 4096 (passes of 8 + 4 bits)
+    (600, 20, 2, 45, 2),        # n' = 1024 (8 + 2 bits), two right-hand sides
+    (200, 10, 1, 17, 1),        # n' = 256: one pass
+    (33000, 40, 1, 90, 3),      # n' = 65536: two 8-bit passes with skipped zero lines
+]
+
+
+@pytest.mark.parametrize("n,d,k,m,s", DENSE_SKETCH_CASES)
+def test_dense_sketch_bitexact(ski, n, d, k, m, s):
+    _say(f"dense sketch n={n} d={d} k={k} m={m} s={s}")
+    rng = np.random.default_rng(n + d)
+    A = rng.standard_normal((n, d))
+    A[: n // 5] *= 1e3
+    B = rng.standard_normal((n, k))
+    seed = 1234 + n
+    ref = sk.sketch_dense(A, B, m, s, seed)
+    S = ski.Solver()
+    S.sketch(dev(A), dev(B), m=m, s=s, seed=seed, hadamard=True)
+    hsh = S.get_hash()
+    np.testing.assert_array_equal(hsh["rows"], ref["rows"])
+    np.testing.assert_array_equal(hsh["neg"], ref["neg"])
+    np.testing.assert_array_equal(hsh["bucket_ptr"], ref["bucket_ptr"])
+    np.testing.assert_array_equal(hsh["src"], ref["src"])
+    np.testing.assert_array_equal(hsh["src_neg"], ref["src_neg"])
+    np.testing.assert_array_equal(S.get_dsign(), ref["dsign"])
+    SA = S.get_SA()
+    # same butterfly order and bucket order as the oracle: identical bits
+    np.testing.assert_array_equal(SA, ref["SA_aug"])
+    S.close()
+
+
+@pytest.mark.parametrize("n,d,m,s", [(5000, 60, 90, 2), (20000, 300, 450, 2)])
+def test_csr_sketch_bitexact(ski, n, d, m, s):
+    _say(f"csr sketch n={n} d={d} m={m} s={s}")
+    rp, ci, va, b = workloads.sparse_power_law(n=n, d=d, case=3)
+    seed = 77
+    ref = sk.sketch_csr(rp, ci, va, n, d, b, m, s, seed)
+    S = ski.Solver()
+    S.sketch(("csr", dev(rp, torch.int64), dev(ci, torch.int32), dev(va), (n, d)), dev(b),
+             m=m, s=s, seed=seed, hadamard=False)
+    hsh = S.get_hash()
+    np.testing.assert_array_equal(hsh["rows"], ref["rows"])
+    np.testing.assert_array_equal(hsh["src"], ref["src"])
+    np.testing.assert_array_equal(S.get_SA(), ref["SA_aug"])
+    S.close()
+
+
+def test_dense_plain_hashing_matches_oracle(ski):
+    n, d, m, s = 3000, 50, 100, 2
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((n, d))
+    b = rng.standard_normal(n)
+    ref = sk.sketch_dense(A, b, m, s, 9, hadamard=False)
+    S = ski.Solver()
+    S.sketch(dev(A), dev(b), m=m, s=s, seed=9, hadamard=False)
+    np.testing.assert_array_equal(S.get_SA(), ref["SA_aug"])
+    S.close()
+
+
+# -------------------------------------------------------------------------- factor
+@pytest.mark.parametrize("n,d,m,s", [(2000, 64, 110, 3), (6000, 200, 340, 3), (9000, 333, 567, 1)])
+def test_qr_of_sketch_matches_oracle(ski, n, d, m, s):
+    _say(f"qr n={n} d={d} m={m} s={s}")
+    rng = np.random.default_rng(d)
+    A = rng.standard_normal((n, d))
+    A[: n // 5] *= 1e3
+    b = rng.standard_normal(n)
+    ref = sk.sketch_dense(A, b, m, s, 31)
+    Rref, cref, _ = lls.factor(ref["SA_aug"], d)
+    S = ski.Solver()
+    S.sketch(dev(A), dev(b), m=m, s=s, seed=31).factor()
+    R, c, Ri = S.get_R()
+    scale = np.abs(Rref).max()
+    np.testing.assert_allclose(R, Rref, rtol=0, atol=1e-12 * scale * math.sqrt(d))
+    np.testing.assert_allclose(c, cref, rtol=0, atol=1e-12 * np.abs(cref).max() * math.sqrt(d))
+    # explicit inverse: R Rinv = I
+    np.testing.assert_allclose(R @ Ri, np.eye(d), atol=1e-11 * np.linalg.cond(R))
+    S.close()
+
+
+# -------------------------------------------------------------------------- solve
+def _tc_bound(A, R, rec, tau):
+    W = A @ np.linalg.inv(R)
+    sv = np.linalg.svd(W, compute_uv=False)
+    return tau * rec["wnorm_est"] * rec["rnorm"] / sv.min() ** 2 / np.linalg.svd(R, compute_uv=False).min()
+
+
+def test_tiny_workload_x_parity(ski):
+    _say("tiny workload solve")
+    A, b, _ = workloads.tiny()
+    xref_direct = lls.lstsq_direct(A, b)
+    Xo, info_o = lls.solve(A, b, seed=2001, s=1, m=256, tau_r=1e-10)
+    S = ski.Solver()
+    S.sketch(dev(A), dev(b), m=256, s=1, seed=2001, tau_r=1e-10).factor()
+    X, infos, rc = S.solve()
+    x = X[:, 0].cpu().numpy()
+    assert rc == 0 and infos[0]["status"] == 0
+    # same algorithm, same sketch: the iteration counts agree (up to one step of rounding)
+    assert abs(infos[0]["iters"] - info_o["records"][0]["iters"]) <= 1
+    assert np.linalg.norm(x - Xo[:, 0]) <= 1e-10 * np.linalg.norm(Xo[:, 0])
+    assert np.linalg.norm(x - xref_direct) <= 1e-10 * np.linalg.norm(xref_direct)
+    S.close()
+
+
+@pytest.mark.parametrize("tau", [1e-10, 1e-14])
+def test_coherent_dense_x_parity(ski, tau):
+    n, d = 6000, 200
+    _say(f"coherent dense solve n={n} d={d} tau={tau}")
+    A, b = workloads.dense_coherent(n=n, d=d, case=2)
+    xd = lls.lstsq_direct(A, b)
+    S = ski.Solver()
+    S.sketch(dev(A), dev(b), gamma=1.7, s=3, seed=2002, tau_r=tau).factor()
+    X, infos, rc = S.solve()
+    x = X[:, 0].cpu().numpy()
+    assert rc == 0
+    R, _, _ = S.get_R()
+    if tau >= 1e-10:
+        assert np.linalg.norm(x - xd) <= _tc_bound(A, R, infos[0], tau)
+        Xo, io = lls.solve(A, b, seed=2002, s=3, gamma=1.7, tau_r=tau)
+        assert abs(infos[0]["iters"] - io["records"][0]["iters"]) <= 1
+    else:
+        assert np.linalg.norm(x - xd) <= 1e-10 * np.linalg.norm(xd)
+    S.close()
+
+
+def test_sparse_x_parity(ski):
+    n, d = 20000, 300
+    _say(f"sparse solve n={n} d={d}")
+    rp, ci, va, b = workloads.sparse_power_law(n=n, d=d, case=3)
+    A = sp.csr_matrix((va, ci, rp), shape=(n, d))
+    xd = lls.lstsq_direct(A, b)
+    for tau in (1e-10, 1e-14):
+        S = ski.Solver()
+        S.sketch(("csr", dev(rp, torch.int64), dev(ci, torch.int32), dev(va), (n, d)), dev(b),
+                 gamma=1.5, s=2, seed=2003, tau_r=tau).factor()
+        X, infos, rc = S.solve()
+        x = X[:, 0].cpu().numpy()
+        assert rc == 0
+        r = b - A @ x
+        cert = np.linalg.norm(A.T @ r) / (sp.linalg.norm(A) * np.linalg.norm(r))
+        if tau >= 1e-10:
+            assert cert < 1e-9
+        else:
+            assert np.linalg.norm(x - xd) <= 1e-10 * np.linalg.norm(xd)
+        S.close()
+
+
+def test_batched_rhs_and_early_exit(ski):
+    n, d, k = 5000, 120, 5
+    _say(f"batched solve n={n} d={d} k={k}")
+    A, B, G = workloads.batched(n=n, d=d, k=k, case=5)
+    B[:, 2] = A @ np.arange(d) / d  # a consistent column: Step 3 exits early
+    S = ski.Solver()
+    S.sketch(dev(A), dev(B), gamma=1.7, s=3, seed=2005, tau_r=1e-14).factor()
+    X, infos, rc = S.solve()
+    X = X.cpu().numpy()
+    Xd = lls.lstsq_direct(A, B)
+    for j in range(k):
+        assert np.linalg.norm(X[:, j] - Xd[:, j]) <= 1e-10 * np.linalg.norm(Xd[:, j]), j
+    assert infos[2]["early_exit"] == 1 and infos[2]["status"] == 2
+    assert all(infos[j]["status"] == 0 for j in range(k) if j != 2)
+    S.close()
+
+
+def test_iteration_limit_and_rank_guard(ski):
+    from paper_2105_11815_amd import SkiError
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((2000, 40))
+    b = rng.standard_normal(2000)
+    S = ski.Solver()
+    S.sketch(dev(A), dev(b), m=60, s=1, seed=1, tau_r=1e-14, it_max=3).factor()
+    X, infos, rc = S.solve()
+    assert rc == 1 and infos[0]["status"] == 1 and infos[0]["iters"] == 3
+    S.close()
+    A[:, 7] = A[:, 3]
+    S = ski.Solver()
+    S.sketch(dev(A), dev(b), m=60, s=1, seed=1)
+    with pytest.raises(SkiError) as e:
+        S.factor()
+    assert e.value.code == -4
+    S.close()
+
+
+def test_repeat_runs_are_bitwise_identical(ski):
+    A, b = workloads.dense_coherent(n=5000, d=150, case=2)
+    outs = []
+    for _ in range(2):
+        S = ski.Solver()
+        S.sketch(dev(A), dev(b), gamma=1.7, s=3, seed=7, tau_r=1e-10).factor()
+        X, infos, _ = S.solve()
+        outs.append((X.cpu().numpy().copy(), infos[0]["iters"], S.get_R()[0]))
+        S.close()
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][2], outs[1][2])
+    assert outs[0][1] == outs[1][1]
+
+
+# -------------------------------------------------------------------------- adjoint
+def test_adjoint_and_gradients(ski):
+    n, d, k = 3000, 100, 4
+    _say(f"gradients n={n} d={d} k={k}")
+    A, B, G = workloads.batched(n=n, d=d, k=k, case=5)
+    S = ski.Solver()
+    S.sketch(dev(A), dev(B), gamma=1.7, s=3, seed=11, tau_r=1e-14).factor()
+    X, infos, rc = S.solve()
+    Z, zinfo, zrc = S.solve_normal(dev(G))
+    gA, gB = S.gradients(X, dev(B), Z)
+    Xn = X.cpu().numpy()
+    gA_ref, gB_ref, Z_ref = lls.grads_closed_form(A, Xn, B, G)
+    np.testing.assert_allclose(Z.cpu().numpy(), Z_ref, rtol=0, atol=1e-10 * np.abs(Z_ref).max())
+    np.testing.assert_allclose(gB.cpu().numpy(), gB_ref, rtol=0, atol=1e-10 * np.abs(gB_ref).max())
+    np.testing.assert_allclose(gA.cpu().numpy(), gA_ref, rtol=0, atol=1e-10 * np.abs(gA_ref).max())
+    S.close()
+
+
+def test_autograd_function(ski):
+    n, d, k = 2000, 60, 3
+    A, B, G = workloads.batched(n=n, d=d, k=k, case=5)
+    At = dev(A).requires_grad_(True)
+    Bt = dev(B).requires_grad_(True)
+    X = ski.SkiLstsq.apply(At, Bt, dict(gamma=1.7, s=3, seed=3, tau_r=1e-14))
+    (X * dev(G)).sum().backward()
+    gA_ref, gB_ref, _ = lls.grads_closed_form(A, X.detach().cpu().numpy(), B, G)
+    np.testing.assert_allclose(At.grad.cpu().numpy(), gA_ref, atol=1e-10 * np.abs(gA_ref).max())
+    np.testing.assert_allclose(Bt.grad.cpu().numpy(), gB_ref, atol=1e-10 * np.abs(gB_ref).max())
+
+
+# -------------------------------------------------------------------------- mixed precision
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mixed_precision_reaches_fp64_residual(ski, prec):
+    n, d = 8000, 200
+    _say(f"mixed precision {prec}")
+    A, b = workloads.dense_coherent(n=n, d=d, case=2)
+    xd = lls.lstsq_direct(A, b)
+    S = ski.Solver()
+    S.sketch(dev(A), dev(b), gamma=1.7, s=3, seed=4, tau_r=1e-14, sketch_prec=prec,
+             qr_prec=prec, it_max=5000).factor()
+    X, infos, rc = S.solve()
+    x = X[:, 0].cpu().numpy()
+    assert rc == 0
+    assert np.linalg.norm(x - xd) <= 1e-10 * np.linalg.norm(xd)
+    S.close()
