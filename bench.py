@@ -1,0 +1,252 @@
+"""Benchmark of the solver's hot path on one MI355X.
+
+One step = one full solve of Algorithm 1 on the dense 50000 x 4000 workload (coherent:
+20% of rows scaled by 1e3, b ~ N(0,1); hashing s = 3 after the randomised Hadamard
+transform, gamma = 1.7 so m = 6800; Householder QR of the sketch; LSQR on A R^-1 to the
+(TC-lsqr) tolerance 1e-10): ski_sketch + ski_factor + ski_solve with A and b already in
+HBM.  Prints one JSON line on stdout (everything else goes to stderr).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-mixed]
+"""
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "solve time & sketch GB/s at 50000x4000; mixed vs FP64 at equal 1e-10 residual"
+HBM_PEAK_GBPS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_lsqr_pass_dense_50000x4000.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2105_11815_amd", "csrc", "lsqr.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload_dense():
+    import workloads
+    c = workloads.CASES["dense"]
+    A, b = workloads.dense_coherent(n=c["n"], d=c["d"], case=c["case"])
+    return A, b, c
+
+
+def one_solve(P, S, At, bt, **kw):
+    S.sketch(At, bt, **kw).factor()
+    X, infos, rc = S.solve()
+    return X, infos[0], rc
+
+
+def cpu_baseline(A, b, cfg, gpu_iters):
+    """The oracle as it stands, on a bounded sample of the same workload, extrapolated to
+    one full solve: the sketch on 400 of the 4001 columns (the transform and the hashing
+    act column by column, so time scales with the column count), the QR of an m x (d+1)
+    matrix of the workload's shape, and 5 LSQR iterations on the full A, scaled by the
+    GPU's iteration count."""
+    from oracle import lls, sketch as sk
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    n, d, m, s = A.shape[0], A.shape[1], cfg["m"], cfg["s"]
+    cols = 400
+    t0 = time.perf_counter()
+    sk.sketch_dense(A[:, : cols - 1], b, m, s, seed=2002)
+    t_sketch = (time.perf_counter() - t0) * (d + 1) / cols
+    rng = np.random.default_rng(0)
+    SA = rng.standard_normal((m, d + 1))
+    t0 = time.perf_counter()
+    R, c, _ = lls.factor(SA, d)
+    t_qr = time.perf_counter() - t0
+    xs = np.zeros(d)
+    r0 = b - A @ xs
+    its = 5
+    t0 = time.perf_counter()
+    lls.lsqr_precond(A, R, r0, 0.0, its)
+    t_iter = (time.perf_counter() - t0) / its
+    total = t_sketch + t_qr + t_iter * gpu_iters
+    return {
+        "value": 1.0 / total,
+        "unit": "solves/s",
+        "cores": int(cores),
+        "kind": "oracle",
+        "sample": (f"oracle sketch on {cols} of {d + 1} columns (x{(d + 1) / cols:.2f}), "
+                   f"QR of a {m}x{d + 1} matrix, {its} LSQR iterations on the full A "
+                   f"(x{gpu_iters} GPU iterations); extrapolated seconds per solve "
+                   f"{total:.2f} (sketch {t_sketch:.2f}, qr {t_qr:.2f}, "
+                   f"lsqr {t_iter * gpu_iters:.2f})"),
+    }
+
+
+def traffic_for_pass(n_launch_bytes):
+    """HBM bytes per launch of the fused pass from the committed rocprofv3 counter runs,
+    or None when absent or taken on a different version of the kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        if rec.get("kernel_source_sha256") != src:
+            return None
+        return rec["bytes_per_launch"]
+    except Exception:
+        return None
+
+
+def mixed_runs(P, torch, At, bt, base_kw, forms, label):
+    """Time one solve per precision form (after a warm-up solve) and recompute the
+    residual and the optimality certificate ||A^T r|| / (||A||_F ||r||) in FP64."""
+    out, xs = {}, {}
+    for name, kw in forms:
+        S = P.Solver()
+        try:
+            one_solve(P, S, At, bt, **base_kw, **kw)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            X, info, rc = one_solve(P, S, At, bt, **base_kw, **kw)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+        finally:
+            S.close()
+        x = X[:, 0]
+        r = bt - At @ x
+        cert = float((At.T @ r).norm() / (At.norm() * r.norm()))
+        xs[name] = x
+        out[name] = dict(ms=round(ms, 3), iters=int(info["iters"]), status=int(rc),
+                         rnorm=float(r.norm()), optimality=cert,
+                         ms_sketch=round(info["ms_sketch"], 3),
+                         ms_factor=round(info["ms_factor"], 3),
+                         ms_solve=round(info["ms_solve"], 3))
+    if "fp64" in xs:
+        for name in xs:
+            if name != "fp64":
+                out[name]["x_rel_diff_vs_fp64"] = float((xs[name] - xs["fp64"]).norm()
+                                                        / xs["fp64"].norm())
+    log(f"{label}: " + json.dumps(out))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the solver has no multi-GPU path, so --gpus "
+              "must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2105_11815_amd as P
+
+    log("generating the dense 50000x4000 workload ...")
+    A, b, cfg = workload_dense()
+    At = torch.as_tensor(A).to("cuda")
+    bt = torch.as_tensor(b).to("cuda")
+    torch.cuda.synchronize()
+    kw = dict(gamma=cfg["gamma"], m=cfg["m"], s=cfg["s"], seed=2002, tau_r=1e-10,
+              hadamard=True)
+    n, d, k = A.shape[0], A.shape[1], 1
+
+    S = P.Solver()
+    for _ in range(args.warmup):
+        one_solve(P, S, At, bt, **kw)
+    torch.cuda.synchronize()
+    S.set_profiling(True)
+    iters_sum = 0
+    infos = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        X, info, rc = one_solve(P, S, At, bt, **kw)
+        iters_sum += int(info["iters"])
+        infos.append(info)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = S.profile()
+    S.set_profiling(False)
+    S.close()
+    ms_step = wall * 1e3 / args.steps
+    info = infos[-1]
+    log(f"ms/step {ms_step:.3f}  iters {info['iters']}  status {rc}  profile {prof}")
+
+    # correctness of the timed solve (recomputed in FP64)
+    x = X[:, 0]
+    r = bt - At @ x
+    cert = float((At.T @ r).norm() / (At.norm() * r.norm()))
+
+    # sketch bandwidth: A and b read once, SA written once
+    m = cfg["m"]
+    sk_bytes = 8 * n * (d + k) + 8 * m * (d + k)
+    sk_ms = float(np.median([i["ms_sketch"] for i in infos]))
+    sketch_gbps = sk_bytes / (sk_ms * 1e-3) / 1e9
+
+    # roofline of the dominant kernel: the fused LSQR pass (A once, u read and written)
+    pass_ms, pass_cnt = prof["lsqr_pass"]
+    pass_bytes = 8 * n * d + 16 * n
+    pass_avg_ms = pass_ms / max(iters_sum, 1)
+    achieved = pass_bytes / (pass_avg_ms * 1e-3) / 1e9
+    traffic = traffic_for_pass(pass_bytes)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                "traffic": traffic, "kernel": "k_lsqr_pass<16> (fused u = A z - c u, g = A^T u)",
+                "bytes_per_launch": pass_bytes, "avg_launch_ms": round(pass_avg_ms, 5),
+                "launches_timed": pass_cnt, "lsqr_iterations_timed": iters_sum}
+    phases = {kname: {"ms_total": round(v[0], 3), "launches": v[1]}
+              for kname, v in prof.items() if v[1]}
+
+    out = {
+        "metric": METRIC, "value": round(1e3 / ms_step, 4), "unit": "solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "dense 50000x4000, 20% rows x1e3, b~N(0,1); Hadamard + "
+                               "3-hashing, gamma 1.7 (m=6800); Householder QR; LSQR to 1e-10",
+                   "n": n, "d": d, "m": m, "s": cfg["s"], "tau_r": 1e-10},
+        "time_to_solution_ms": round(ms_step, 3),
+        "sketch_GBps": round(sketch_gbps, 1), "sketch_ms": round(sk_ms, 3),
+        "factor_ms": round(float(np.median([i["ms_factor"] for i in infos])), 3),
+        "solve_ms": round(float(np.median([i["ms_solve"] for i in infos])), 3),
+        "lsqr_iters": int(info["iters"]), "optimality_certificate": cert,
+        "rnorm": float(r.norm()), "kernel_ms": phases, "roofline": roofline,
+    }
+
+    if not args.no_mixed:
+        forms = [("fp64", {}), ("fp32", dict(sketch_prec="fp32", qr_prec="fp32")),
+                 ("bf16", dict(sketch_prec="bf16", qr_prec="bf16", it_max=3000))]
+        out["mixed_dense_50000x4000"] = mixed_runs(P, torch, At, bt, kw, forms, "dense")
+        del At, bt
+        torch.cuda.empty_cache()
+        import workloads
+        c4 = workloads.CASES["illcond"]
+        log("generating the ill-conditioned 50000x7000 workload on the GPU ...")
+        A4, b4 = workloads.illcond(n=c4["n"], d=c4["d"], case=c4["case"], device="cuda")
+        torch.cuda.synchronize()
+        kw4 = dict(gamma=c4["gamma"], m=c4["m"], s=c4["s"], seed=2004, tau_r=1e-10,
+                   hadamard=True)
+        out["mixed_illcond_50000x7000"] = mixed_runs(P, torch, A4, b4, kw4, forms, "illcond")
+        del A4, b4
+        torch.cuda.empty_cache()
+
+    if not args.no_cpu:
+        log("timing the CPU oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(A, b, cfg, int(info["iters"]))
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

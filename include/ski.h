@@ -161,6 +161,18 @@ const char* ski_last_error(ski_handle h);
  *   dsign: the diagonal of D as int8 (+1 / -1), n' entries (dense with Hadamard only).
  *   SA: the sketch m x (d+k) row-major, converted to double.
  *   R: d x d row-major (upper triangle, zeros below); c: d x k; Rinv: d x d. */
+/* Kernel timing for measurement (not needed to solve).  ski_set_profiling(h, 1) makes the
+ * library record a HIP event pair on the launch stream around every launch of the kernel
+ * classes below (clearing earlier totals); ski_get_profile returns, per class, the summed
+ * device time in ms and the number of launches since profiling was switched on.
+ * Classes: 0 fused dense LSQR pass, 1 its partial-sum reduction, 2 triangular GEMV with
+ * R^-1 / R^-T, 3 CSR product A z, 4 CSR product A^T u, 5 LSQR scalar step, 6 hashing
+ * (Philox + bucket sort), 7 Walsh-Hadamard passes, 8 hashing gather, 9 whole QR of the
+ * sketch, 10 explicit R^-1.  ms[] and count[] hold SKI_PROF_CLASSES entries. */
+#define SKI_PROF_CLASSES 16
+int ski_set_profiling(ski_handle h, int32_t on);
+int ski_get_profile(ski_handle h, double* ms, int64_t* count);
+
 int ski_get_dims(ski_handle h, int64_t dims[6]);
 int ski_get_hash(ski_handle h, int32_t* rows, int8_t* neg, int64_t* bucket_ptr, int32_t* src,
                  int8_t* src_neg);

@@ -164,6 +164,21 @@ class Solver:
             self._raise(rc, "ski_gradients")
         return gA, gB
 
+    # -- measurement ------------------------------------------------------
+    def set_profiling(self, on=True):
+        rc = self._lib.ski_set_profiling(self._h, 1 if on else 0)
+        if rc != L.SKI_OK:
+            self._raise(rc, "ski_set_profiling")
+
+    def profile(self):
+        """{class name: (total device ms, launches)} since profiling was switched on."""
+        ms = np.zeros(L.PROF_CLASSES)
+        cnt = np.zeros(L.PROF_CLASSES, dtype=np.int64)
+        rc = self._lib.ski_get_profile(self._h, ms.ctypes.data, cnt.ctypes.data)
+        if rc != L.SKI_OK:
+            self._raise(rc, "ski_get_profile")
+        return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(L.PROF_NAMES)}
+
     # -- inspection (host copies) -----------------------------------------
     def dims(self):
         a = np.zeros(6, dtype=np.int64)

@@ -23,6 +23,11 @@ hipError_t launch_lsqr_pass(const double* A, int64_t lda, int64_t n, int64_t d, 
                             double* u, const LsqrState* stt, int64_t G, double* gpart,
                             double* upart, double* g, LsqrState* stt_w, bool coef_m1,
                             hipStream_t st);
+hipError_t launch_pass_kernel(const double* A, int64_t lda, int64_t n, int64_t d, const double* z,
+                              double* u, const LsqrState* stt, int64_t G, double* gpart,
+                              double* upart, bool coef_m1, hipStream_t st);
+hipError_t launch_pass_reduce(const double* gpart, const double* upart, int64_t G, int64_t d,
+                              double* g, LsqrState* stt_w, hipStream_t st);
 hipError_t launch_spmv_csr(const int64_t* rp, const int32_t* ci, const double* va, int64_t n, int k,
                            const double* z, double* u, LsqrState* stt, bool coef_m1,
                            double* upart, hipStream_t st);

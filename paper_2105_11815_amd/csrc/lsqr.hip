@@ -87,22 +87,51 @@ hipError_t trtri_rec(const double* R, int64_t d, int64_t lo, int64_t hi, double*
 }
 
 // ---------------------------------------------------------------------------
-// triangular GEMV y = s * M x over the triangle only (one wave per row)
-__global__ __launch_bounds__(256) void k_tri_gemv(const double* __restrict__ M, int64_t d, int upper,
-                                                  const double* __restrict__ x, int64_t ldx,
-                                                  double* __restrict__ y, int64_t ldy, double s,
-                                                  const int32_t* __restrict__ done) {
+// triangular GEMV y = s * M x over the triangle only: a workgroup of four waves takes the
+// row pair (i, d-1-i), so every workgroup reads d+1 entries; every lane issues its loads
+// for both rows before it adds.
+constexpr int TG = 256;
+__global__ __launch_bounds__(TG) void k_tri_gemv(const double* __restrict__ M, int64_t d, int upper,
+                                                 const double* __restrict__ x, int64_t ldx,
+                                                 double* __restrict__ y, int64_t ldy, double s,
+                                                 const int32_t* __restrict__ done) {
     if (done && *done) return;
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
-    const int64_t nw = ((int64_t)gridDim.x * 256) >> 6;
-    for (int64_t i = wave; i < d; i += nw) {
-        const int64_t j0 = upper ? i : 0, j1 = upper ? d : i + 1;
-        const double* row = M + i * d;
-        double acc = 0;
-        for (int64_t j = j0 + lane; j < j1; j += 64) acc += row[j] * x[j * ldx];
-        acc = wave_sum(acc);
-        if (lane == 0) y[i * ldy] = s * acc;
+    __shared__ double sh[TG / 64][2];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t npairs = (d + 1) / 2;
+    for (int64_t p = blockIdx.x; p < npairs; p += gridDim.x) {
+        const int64_t i0 = p, i1 = d - 1 - p;
+        const bool two = i1 != i0;
+        double acc[2] = {0.0, 0.0};
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            if (t == 1 && !two) break;
+            const int64_t i = t ? i1 : i0;
+            const int64_t j0 = upper ? i : 0, j1 = upper ? d : i + 1;
+            const double* row = M + i * d;
+            double a = 0;
+            int64_t j = j0 + tid;
+            for (; j + 3 * TG < j1; j += 4 * TG) {
+                const double m0 = row[j], m1 = row[j + TG], m2 = row[j + 2 * TG], m3 = row[j + 3 * TG];
+                const double x0 = x[j * ldx], x1 = x[(j + TG) * ldx];
+                const double x2 = x[(j + 2 * TG) * ldx], x3 = x[(j + 3 * TG) * ldx];
+                a += m0 * x0 + m1 * x1 + m2 * x2 + m3 * x3;
+            }
+            for (; j < j1; j += TG) a += row[j] * x[j * ldx];
+            acc[t] = a;
+        }
+        acc[0] = wave_sum(acc[0]);
+        acc[1] = wave_sum(acc[1]);
+        if (lane == 0) {
+            sh[wv][0] = acc[0];
+            sh[wv][1] = acc[1];
+        }
+        __syncthreads();
+        if (tid == 0) {
+            y[i0 * ldy] = s * (((sh[0][0] + sh[1][0]) + sh[2][0]) + sh[3][0]);
+            if (two) y[i1 * ldy] = s * (((sh[0][1] + sh[1][1]) + sh[2][1]) + sh[3][1]);
+        }
+        __syncthreads();
     }
 }
 
@@ -185,22 +214,44 @@ __global__ __launch_bounds__(256) void k_lsqr_pass(const double* __restrict__ A,
     if (tid == 0) upart[blockIdx.x] = usq;
 }
 
-// g[c] = sum_g gpart[g][c], in order; beta2 = sum upart
-__global__ __launch_bounds__(256) void k_reduce_pass(const double* __restrict__ gpart,
-                                                     const double* __restrict__ upart, int64_t G,
-                                                     int64_t d, double* __restrict__ g,
-                                                     LsqrState* __restrict__ stt) {
+// g[c] = sum_g gpart[g][c] and beta2 = sum_g upart[g], each in a fixed order: a
+// workgroup takes 64 columns; its sixteen waves sum a sixteenth of the partials each
+// (the 64 lanes read 64 consecutive columns), then the sixteen sums are added in order.
+// Workgroup 0 also sums the squared-norm partials the same way.
+constexpr int RSL = 16;  // slices of the partials
+__global__ __launch_bounds__(64 * RSL) void k_reduce_pass(const double* __restrict__ gpart,
+                                                          const double* __restrict__ upart,
+                                                          int64_t G, int64_t d,
+                                                          double* __restrict__ g,
+                                                          LsqrState* __restrict__ stt) {
     if (stt->done) return;
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (c < d) {
-        double s = 0;
-        for (int64_t q = 0; q < G; ++q) s += gpart[q * d + c];
-        g[c] = s;
+    __shared__ double part[RSL][64];
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int64_t c = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t g0 = q * G / RSL, g1 = (q + 1) * G / RSL;
+    double s = 0;
+    if (c < d)
+        for (int64_t gq = g0; gq < g1; ++gq) s += gpart[gq * d + c];
+    part[q][lane] = s;
+    __syncthreads();
+    if (q == 0 && c < d) {
+        double t = 0;
+        for (int j = 0; j < RSL; ++j) t += part[j][lane];
+        g[c] = t;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        double s = 0;
-        for (int64_t q = 0; q < G; ++q) s += upart[q];
-        stt->beta2 = s;
+    if (blockIdx.x == 0) {
+        __shared__ double us[64 * RSL];
+        const int t = threadIdx.x;
+        const int64_t u0 = t * G / (64 * RSL), u1 = (t + 1) * G / (64 * RSL);
+        double su = 0;
+        for (int64_t i = u0; i < u1; ++i) su += upart[i];
+        us[t] = su;
+        __syncthreads();
+        for (int off = 32 * RSL; off > 0; off >>= 1) {
+            if (t < off) us[t] = us[t] + us[t + off];
+            __syncthreads();
+        }
+        if (t == 0) stt->beta2 = us[0];
     }
 }
 
@@ -579,8 +630,8 @@ hipError_t trtri_upper(const double* R, int64_t d, double* Rinv, double* RinvT,
 
 hipError_t launch_tri_gemv(const double* M, int64_t d, bool upper, const double* x, int64_t ldx,
                            double* y, int64_t ldy, double s, const int32_t* done, hipStream_t st) {
-    const unsigned g = (unsigned)std::min<int64_t>((d + 3) / 4, 2048);
-    hipLaunchKernelGGL(k_tri_gemv, dim3(g), dim3(256), 0, st, M, d, upper ? 1 : 0, x, ldx, y, ldy,
+    const unsigned g = (unsigned)std::min<int64_t>((d + 1) / 2, 8192);
+    hipLaunchKernelGGL(k_tri_gemv, dim3(g), dim3(TG), 0, st, M, d, upper ? 1 : 0, x, ldx, y, ldy,
                        s, done);
     return hipGetLastError();
 }
@@ -597,10 +648,9 @@ int lsqr_pass_cpt(int64_t d) {
     return 0;
 }
 
-hipError_t launch_lsqr_pass(const double* A, int64_t lda, int64_t n, int64_t d, const double* z,
-                            double* u, const LsqrState* stt, int64_t G, double* gpart,
-                            double* upart, double* g, LsqrState* stt_w, bool coef_m1,
-                            hipStream_t st) {
+hipError_t launch_pass_kernel(const double* A, int64_t lda, int64_t n, int64_t d, const double* z,
+                              double* u, const LsqrState* stt, int64_t G, double* gpart,
+                              double* upart, bool coef_m1, hipStream_t st) {
     const int64_t rpw = (((n + G - 1) / G) + 1) / 2 * 2;
     const int cpt = lsqr_pass_cpt(d);
 #define SKI_PASS(C)                                                                             \
@@ -617,10 +667,22 @@ hipError_t launch_lsqr_pass(const double* A, int64_t lda, int64_t n, int64_t d, 
         default: return hipErrorInvalidValue;
     }
 #undef SKI_PASS
-    SKI_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_reduce_pass, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, st, gpart,
-                       upart, G, d, g, stt_w);
     return hipGetLastError();
+}
+
+hipError_t launch_pass_reduce(const double* gpart, const double* upart, int64_t G, int64_t d,
+                              double* g, LsqrState* stt_w, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_pass, dim3((unsigned)((d + 63) / 64)), dim3(64 * RSL), 0, st,
+                       gpart, upart, G, d, g, stt_w);
+    return hipGetLastError();
+}
+
+hipError_t launch_lsqr_pass(const double* A, int64_t lda, int64_t n, int64_t d, const double* z,
+                            double* u, const LsqrState* stt, int64_t G, double* gpart,
+                            double* upart, double* g, LsqrState* stt_w, bool coef_m1,
+                            hipStream_t st) {
+    SKI_HIP(launch_pass_kernel(A, lda, n, d, z, u, stt, G, gpart, upart, coef_m1, st));
+    return launch_pass_reduce(gpart, upart, G, d, g, stt_w, st);
 }
 
 hipError_t launch_spmv_csr(const int64_t* rp, const int32_t* ci, const double* va, int64_t n, int k,

@@ -1,58 +1,75 @@
-// Step 2 of Algorithm 1: Householder QR (no pivoting) of the m x (d+k) sketch
-// [SA Sb], in place, blocked as in LAPACK's DGEQRF (the factorisation the paper's dense
-// solver uses when A is full rank), so that R sits in the upper triangle and Q^T S b in
-// the last k columns.
+// Step 2 of Algorithm 1: Householder QR (no pivoting) of the m x (d+k) sketch [SA Sb],
+// blocked as in LAPACK's DGEQRF (the factorisation the paper's dense solver uses when A
+// has full rank), giving R in the upper triangle and Q^T S b in the last k columns.
 //
 // Reflectors follow the LAPACK convention: for x = [alpha; x2],
 //   beta = -sign(alpha) ||x||, tau = (beta - alpha)/beta, v = [1; x2/(alpha - beta)],
-// H = I - tau v v^T, and are stored in place below the diagonal (implicit unit diagonal).
-// A block of reflectors H_1 ... H_b = I - V T V^T with T upper triangular (the forward
-// columnwise compact-WY form); applying Q^T to C is C - V T^T V^T C.
+// H = I - tau v v^T; a block H_1 ... H_b = I - V T V^T with T upper triangular (forward,
+// columnwise compact-WY); Q^T C = C - V T^T V^T C.
 //
-// Blocking: outer panels of NB columns.  Inside a panel, leaves of 4 columns are factored
-// by one workgroup with the leaf's rows held in registers (one reduction per column: the
-// squared norm below the diagonal and the column's inner products with the other leaf
-// columns); each leaf's block reflector is applied to the rest of the panel by two small
-// streaming kernels (partial V^T C over row blocks, then a fixed-order sum, T^T and the
-// rank-4 update).  After the panel, T is formed from V^T V and the taus, and the
-// trailing columns (including the right-hand sides) get Q^T through three MFMA GEMMs.
-// Every sum is in a fixed order: the factorisation is deterministic.
+// Layout: the factorisation works on a column-major copy of the sketch (column j holds m
+// contiguous entries), so that a panel's columns stream contiguously.  Reflectors are
+// stored in place below the diagonal with an implicit unit diagonal.
+//
+// Blocking: outer panels of NBP = 64 columns.  Inside a panel, leaves of 4 columns are
+// factored by one workgroup with the leaf's rows in registers (one block reduction per
+// column gives the squared norm below the diagonal and the inner products with the other
+// leaf columns); the leaf's T is formed in the same kernel.  The leaf's block reflector
+// is then applied to each remaining panel column by one workgroup per column (4 inner
+// products, T^T, the rank-4 update).  After a panel, its reflectors are copied out
+// explicitly (V^T, nb x (m - j0)), T is formed from V^T V and the taus, and the trailing
+// columns get Q^T through three MFMA GEMMs on the transposed operands:
+//   W^T = C^T V,  W2^T = W^T T,  C^T -= W2^T V^T.
+// Every sum has a fixed order: the factorisation is deterministic.
 #include "ski_internal.h"
 
 namespace ski {
 
 namespace {
 
-constexpr int NBL = 4;       // leaf width
-constexpr int LT = 512;      // leaf threads
-constexpr int NBP = 64;      // outer panel width
-constexpr int RB = 64;       // rows per workgroup in the narrow kernels
+constexpr int NBL = 4;    // leaf width
+constexpr int LT = 512;   // leaf threads
+constexpr int NBP = 64;   // outer panel width
 
-template <typename T>
-__device__ __forceinline__ T vval(const T* SA, int64_t ld, int64_t r, int64_t c) {
-    // element (r, c) of the explicit reflector block whose origin is at SA
-    if (r < c) return (T)0;
-    if (r == c) return (T)1;
-    return SA[r * ld + c];
+// block reduction of N values over a workgroup of NT threads, in a fixed order
+template <typename T, int N, int NT>
+__device__ __forceinline__ void block_reduce(T (&v)[N], T (*sh)[N], int tid) {
+    const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+    for (int c = 0; c < N; ++c) v[c] = wave_sum(v[c]);
+    if (lane == 0)
+#pragma unroll
+        for (int c = 0; c < N; ++c) sh[wv][c] = v[c];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+        T a = 0;
+        for (int q = 0; q < NT / 64; ++q) a += sh[q][c];
+        v[c] = a;
+    }
 }
 
-// leaf: factor columns [jc, jc+w) (w <= NBL) over rows [jc, m); taus -> tau[jc..]
+// leaf: factor columns [jc, jc+w) over rows [jc, m) of the column-major matrix (ld = m);
+// taus -> tau[jc..], the leaf's T (w x w, row-major, NBL stride) -> Tl
 template <typename T, int RPT>
-__global__ __launch_bounds__(LT) void k_qr_leaf(T* __restrict__ SA, int64_t ld, int64_t m,
-                                                int64_t jc, int w, T* __restrict__ tau) {
+__global__ __launch_bounds__(LT) void k_qr_leaf(T* __restrict__ Ac, int64_t m, int64_t jc, int w,
+                                                T* __restrict__ tau, T* __restrict__ Tl) {
     __shared__ T red[2][LT / 64][NBL];
     __shared__ T rowb[2][NBL];
+    __shared__ T gsh[LT / 64][NBL * NBL];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t mrem = m - jc;
-    T* base = SA + jc * ld + jc;
+    T* base = Ac + jc * m + jc;  // element (r, c) of the leaf at base[c * m + r]
     T P[RPT][NBL];
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
         const int64_t r = tid + (int64_t)LT * u;
 #pragma unroll
-        for (int c = 0; c < NBL; ++c) P[u][c] = (r < mrem && c < w) ? base[r * ld + c] : (T)0;
+        for (int c = 0; c < NBL; ++c) P[u][c] = (r < mrem && c < w) ? base[c * m + r] : (T)0;
     }
-    // fully unrolled over the leaf's columns so that every register-array index is static
+    T taus[NBL];
+#pragma unroll
+    for (int c = 0; c < NBL; ++c) taus[c] = 0;
 #pragma unroll
     for (int jj = 0; jj < NBL; ++jj) {
         if (jj >= w) break;
@@ -101,6 +118,7 @@ __global__ __launch_bounds__(LT) void k_qr_leaf(T* __restrict__ SA, int64_t ld, 
             tj = (beta - alpha) / beta;
             scal = (T)1 / (alpha - beta);
         }
+        taus[jj] = tj;
         T wc[NBL];
 #pragma unroll
         for (int c = 0; c < NBL; ++c) wc[c] = (c > jj) ? rowb[buf][c] + tot[c] * scal : (T)0;
@@ -120,252 +138,353 @@ __global__ __launch_bounds__(LT) void k_qr_leaf(T* __restrict__ SA, int64_t ld, 
                 P[u][jj] = beta;
             }
         }
-        if (tid == 0) tau[jc + jj] = tj;
     }
+    // write back R (upper) and the reflectors (below the diagonal)
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
         const int64_t r = tid + (int64_t)LT * u;
         if (r < mrem)
 #pragma unroll
             for (int c = 0; c < NBL; ++c)
-                if (c < w) base[r * ld + c] = P[u][c];
+                if (c < w) base[c * m + r] = P[u][c];
     }
-}
-
-// partial W_g = V^T C over row block g: V = reflector block at (r0, vc) of width w,
-// C = columns [c0, c0+nc) over rows [r0, m).  part: [G][w][nc]
-template <typename T>
-__global__ __launch_bounds__(256) void k_narrow_partial(const T* __restrict__ SA, int64_t ld,
-                                                        int64_t r0, int64_t m, int64_t vc, int w,
-                                                        int64_t c0, int nc, T* __restrict__ part) {
-    const int64_t g = blockIdx.x;
-    const int64_t rb0 = g * RB, rb1 = std::min<int64_t>(m - r0, rb0 + RB);
-    const T* V = SA + r0 * ld + vc;
-    const T* C = SA + r0 * ld + c0;
-    for (int o = threadIdx.x; o < w * nc; o += 256) {
-        const int a = o / nc, c = o - a * nc;
-        T acc = 0;
-        for (int64_t r = rb0; r < rb1; ++r) acc += vval(V, ld, r, (int64_t)a) * C[r * ld + c];
-        part[(g * w + a) * nc + c] = acc;
+    // leaf T: G = V^T V over the explicit reflectors, then the forward recurrence
+    T g[NBL * NBL];
+#pragma unroll
+    for (int q = 0; q < NBL * NBL; ++q) g[q] = 0;
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+        const int64_t r = tid + (int64_t)LT * u;
+        if (r < mrem) {
+            T v[NBL];
+#pragma unroll
+            for (int c = 0; c < NBL; ++c)
+                v[c] = (c >= w) ? (T)0 : (r < c ? (T)0 : (r == c ? (T)1 : P[u][c]));
+#pragma unroll
+            for (int a = 0; a < NBL; ++a)
+#pragma unroll
+                for (int b = a + 1; b < NBL; ++b) g[a * NBL + b] += v[a] * v[b];
+        }
     }
-}
-
-// W = sum_g part_g (fixed order), W2 = T^T W with T the leaf block (tau-based recurrence
-// rebuilt from the leaf's V: T is passed precomputed in Tl[w][w])
-template <typename T>
-__global__ __launch_bounds__(256) void k_narrow_reduce(const T* __restrict__ part, int64_t G,
-                                                       int w, int nc, const T* __restrict__ Tl,
-                                                       int ldt, T* __restrict__ W2) {
-    __shared__ T Ws[NBL * NBP];
-    for (int o = threadIdx.x; o < w * nc; o += 256) {
-        T s = 0;
-        for (int64_t g = 0; g < G; ++g) s += part[g * w * nc + o];
-        Ws[o] = s;
-    }
+#pragma unroll
+    for (int a = 0; a < NBL; ++a)
+#pragma unroll
+        for (int b = a + 1; b < NBL; ++b) {
+            T t = wave_sum(g[a * NBL + b]);
+            if (lane == 0) gsh[wv][a * NBL + b] = t;
+        }
     __syncthreads();
-    for (int o = threadIdx.x; o < w * nc; o += 256) {
-        const int a = o / nc, c = o - a * nc;
+    if (tid == 0) {
+        T G[NBL * NBL], Tm[NBL * NBL];
+#pragma unroll
+        for (int q = 0; q < NBL * NBL; ++q) {
+            T a = 0;
+            const int qa = q / NBL, qb = q % NBL;
+            if (qa < qb)
+                for (int wq = 0; wq < LT / 64; ++wq) a += gsh[wq][q];
+            G[q] = a;
+            Tm[q] = 0;
+        }
+#pragma unroll
+        for (int i = 0; i < NBL; ++i) {
+            if (i < w) {
+#pragma unroll
+                for (int a = 0; a < NBL; ++a) {
+                    if (a < i) {
+                        T y = 0;
+#pragma unroll
+                        for (int b = 0; b < NBL; ++b)
+                            if (b >= a && b < i) y += Tm[a * NBL + b] * G[b * NBL + i];
+                        Tm[a * NBL + i] = -taus[i] * y;
+                    }
+                }
+                Tm[i * NBL + i] = taus[i];
+                tau[jc + i] = taus[i];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NBL * NBL; ++q) Tl[q] = Tm[q];
+    }
+}
+
+// Q_leaf^T applied to one trailing column per workgroup: c = c0 + blockIdx.x,
+// W = V^T C_c (w values), W2 = T^T W, C_c -= V W2, over rows [jc, m).  The column and
+// the leaf's reflectors stay in registers between the reduction and the update.
+template <typename T, int RPT>
+__global__ __launch_bounds__(LT) void k_narrow_apply(T* __restrict__ Ac, int64_t m, int64_t jc,
+                                                     int w, const T* __restrict__ Tl,
+                                                     int64_t c0) {
+    __shared__ T sh[LT / 64][NBL];
+    const int tid = threadIdx.x;
+    const int64_t mrem = m - jc;
+    const T* V = Ac + jc * m + jc;
+    T* C = Ac + (c0 + blockIdx.x) * m + jc;
+    T cv[RPT], vv[RPT][NBL];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+        const int64_t r = tid + (int64_t)LT * u;
+        const bool ok = r < mrem;
+        cv[u] = ok ? C[r] : (T)0;
+#pragma unroll
+        for (int a = 0; a < NBL; ++a)
+            vv[u][a] = (ok && a < w) ? (r < a ? (T)0 : (r == a ? (T)1 : V[a * m + r])) : (T)0;
+    }
+    T acc[NBL];
+#pragma unroll
+    for (int a = 0; a < NBL; ++a) {
         T s = 0;
-        for (int b = 0; b <= a; ++b) s += Tl[b * ldt + a] * Ws[b * nc + c];
-        W2[o] = s;
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) s += vv[u][a] * cv[u];
+        acc[a] = s;
     }
-}
-
-// C -= V W2 over rows [r0, m)
-template <typename T>
-__global__ __launch_bounds__(256) void k_narrow_update(T* __restrict__ SA, int64_t ld, int64_t r0,
-                                                       int64_t m, int64_t vc, int w, int64_t c0,
-                                                       int nc, const T* __restrict__ W2) {
-    const int64_t rows = m - r0;
-    const T* V = SA + r0 * ld + vc;
-    T* C = SA + r0 * ld + c0;
-    const int64_t total = rows * nc;
-    for (int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x; o < total;
-         o += (int64_t)gridDim.x * 256) {
-        const int64_t r = o / nc;
-        const int c = (int)(o - r * nc);
+    block_reduce<T, NBL, LT>(acc, sh, tid);
+    T w2[NBL];
+#pragma unroll
+    for (int a = 0; a < NBL; ++a) {
         T s = 0;
-        for (int a = 0; a < w; ++a) s += vval(V, ld, r, (int64_t)a) * W2[a * nc + c];
-        C[r * ld + c] -= s;
+#pragma unroll
+        for (int b = 0; b < NBL; ++b)
+            if (b <= a && a < w) s += Tl[b * NBL + a] * acc[b];
+        w2[a] = s;
+    }
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+        const int64_t r = tid + (int64_t)LT * u;
+        if (r < mrem) {
+            T s = 0;
+#pragma unroll
+            for (int a = 0; a < NBL; ++a) s += vv[u][a] * w2[a];
+            C[r] = cv[u] - s;
+        }
     }
 }
 
-// partial Gram matrix of the panel's reflectors: G_g = V^T V over row block g (upper)
+// explicit V^T of a panel: Vt[c][r] = v_c[r] over rows r in [0, mr) from row j0
 template <typename T>
-__global__ __launch_bounds__(256) void k_gram_partial(const T* __restrict__ SA, int64_t ld,
-                                                      int64_t j0, int64_t m, int nb,
-                                                      T* __restrict__ part) {
-    const int64_t g = blockIdx.x;
-    const int64_t rb0 = g * RB, rb1 = std::min<int64_t>(m - j0, rb0 + RB);
-    const T* V = SA + j0 * ld + j0;
-    for (int o = threadIdx.x; o < nb * nb; o += 256) {
-        const int a = o / nb, b = o - a * nb;
-        T acc = 0;
-        if (a < b)
-            for (int64_t r = std::max<int64_t>(rb0, b); r < rb1; ++r)
-                acc += vval(V, ld, r, (int64_t)a) * vval(V, ld, r, (int64_t)b);
-        part[g * nb * nb + o] = acc;
-    }
+__global__ __launch_bounds__(256) void k_make_Vt(const T* __restrict__ Ac, int64_t m, int64_t j0,
+                                                 int nb, T* __restrict__ Vt) {
+    const int64_t mr = m - j0;
+    const int c = blockIdx.y;
+    const T* col = Ac + (j0 + c) * m + j0;
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < mr; r += (int64_t)gridDim.x * 256)
+        Vt[c * mr + r] = r < c ? (T)0 : (r == c ? (T)1 : col[r]);
 }
 
-// T of the panel from G = V^T V and tau: T_ii = tau_i, T[0:i, i] = -tau_i T[0:i,0:i] G[0:i, i]
+// T of a panel from G = V^T V (nb x nb, row-major) and tau, by one wave: lane a owns
+// row a of T; column i needs only rows < i of the columns before it, and a wave's LDS
+// accesses are ordered, so no barrier is needed between columns.
 template <typename T>
-__global__ __launch_bounds__(256) void k_form_T(const T* __restrict__ part, int64_t G, int nb,
-                                                const T* __restrict__ tau, T* __restrict__ Tp) {
+__global__ __launch_bounds__(64) void k_form_T(const T* __restrict__ G, int nb,
+                                               const T* __restrict__ tau, T* __restrict__ Tp) {
     __shared__ T Gs[NBP * NBP];
     __shared__ T Ts[NBP * NBP];
-    for (int o = threadIdx.x; o < nb * nb; o += 256) {
-        T s = 0;
-        for (int64_t g = 0; g < G; ++g) s += part[g * nb * nb + o];
-        Gs[o] = s;
+    const int a = threadIdx.x;
+    for (int o = a; o < nb * nb; o += 64) {
+        Gs[o] = G[o];
         Ts[o] = 0;
     }
     __syncthreads();
     for (int i = 0; i < nb; ++i) {
         const T ti = tau[i];
-        // y = T[0:i,0:i] G[0:i, i]; T[0:i, i] = -ti y
-        if (threadIdx.x < i) {
-            const int a = threadIdx.x;
-            T y = 0;
+        T y = 0;
+        if (a < i)
             for (int b = a; b < i; ++b) y += Ts[a * nb + b] * Gs[b * nb + i];
-            Ts[a * nb + i] = -ti * y;
-        }
-        if (threadIdx.x == 0) Ts[i * nb + i] = ti;
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
+        if (a < i) Ts[a * nb + i] = -ti * y;
+        if (a == i) Ts[i * nb + i] = ti;
+        __builtin_amdgcn_wave_barrier();
     }
-    for (int o = threadIdx.x; o < nb * nb; o += 256) Tp[o] = Ts[o];
+    __syncthreads();
+    for (int o = a; o < nb * nb; o += 64) Tp[o] = Ts[o];
 }
 
-// leaf T (w x w) from the leaf's reflectors, computed the same way on one row-block pass
+// row-major m x n -> column-major (ld m), 64 x 64 tiles through LDS
 template <typename T>
-hipError_t leaf_T(const T* SA, int64_t ld, int64_t jc, int64_t m, int w, const T* tau, T* part,
-                  T* Tl, hipStream_t st) {
-    const int64_t G = (m - jc + RB - 1) / RB;
-    hipLaunchKernelGGL((k_gram_partial<T>), dim3((unsigned)G), dim3(256), 0, st, SA, ld, jc, m, w,
-                       part);
-    hipLaunchKernelGGL((k_form_T<T>), dim3(1), dim3(256), 0, st, part, G, w, tau + jc, Tl);
+__global__ __launch_bounds__(256) void k_to_colmajor(const T* __restrict__ A, int64_t m,
+                                                     int64_t n, T* __restrict__ Ac) {
+    __shared__ T tile[64][65];
+    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int i = ty; i < 64; i += 4) {
+        const int64_t r = r0 + i, c = c0 + tx;
+        if (r < m && c < n) tile[i][tx] = A[r * n + c];
+    }
+    __syncthreads();
+    for (int i = ty; i < 64; i += 4) {
+        const int64_t c = c0 + i, r = r0 + tx;
+        if (r < m && c < n) Ac[c * m + r] = tile[tx][i];
+    }
+}
+
+template <typename T, int RPT>
+void leaf_launch(T* Ac, int64_t m, int64_t jc, int w, T* tau, T* Tl, hipStream_t st) {
+    hipLaunchKernelGGL((k_qr_leaf<T, RPT>), dim3(1), dim3(LT), 0, st, Ac, m, jc, w, tau, Tl);
+}
+
+template <typename T>
+hipError_t launch_leaf(T* Ac, int64_t m, int64_t jc, int w, T* tau, T* Tl, hipStream_t st) {
+    const int64_t rpt = (m - jc + LT - 1) / LT;
+    if (rpt <= 1)
+        leaf_launch<T, 1>(Ac, m, jc, w, tau, Tl, st);
+    else if (rpt <= 2)
+        leaf_launch<T, 2>(Ac, m, jc, w, tau, Tl, st);
+    else if (rpt <= 4)
+        leaf_launch<T, 4>(Ac, m, jc, w, tau, Tl, st);
+    else if (rpt <= 8)
+        leaf_launch<T, 8>(Ac, m, jc, w, tau, Tl, st);
+    else if (rpt <= 12)
+        leaf_launch<T, 12>(Ac, m, jc, w, tau, Tl, st);
+    else if (rpt <= 16)
+        leaf_launch<T, 16>(Ac, m, jc, w, tau, Tl, st);
+    else if (rpt <= 24)
+        leaf_launch<T, 24>(Ac, m, jc, w, tau, Tl, st);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
+template <typename T, int RPT>
+void narrow_launch(T* Ac, int64_t m, int64_t jc, int w, const T* Tl, int nc, hipStream_t st) {
+    hipLaunchKernelGGL((k_narrow_apply<T, RPT>), dim3((unsigned)nc), dim3(LT), 0, st, Ac, m, jc, w,
+                       Tl, jc + w);
+}
+
 template <typename T>
-hipError_t launch_leaf(T* SA, int64_t ld, int64_t m, int64_t jc, int w, T* tau, hipStream_t st) {
-    const int64_t mrem = m - jc;
-    const int64_t rpt = (mrem + LT - 1) / LT;
-#define SKI_LEAF(R)                                                                            \
-    hipLaunchKernelGGL((k_qr_leaf<T, R>), dim3(1), dim3(LT), 0, st, SA, ld, m, jc, w, tau); \
-    return hipGetLastError()
-    if (rpt <= 1) { SKI_LEAF(1); }
-    if (rpt <= 2) { SKI_LEAF(2); }
-    if (rpt <= 4) { SKI_LEAF(4); }
-    if (rpt <= 8) { SKI_LEAF(8); }
-    if (rpt <= 12) { SKI_LEAF(12); }
-    if (rpt <= 16) { SKI_LEAF(16); }
-    if (rpt <= 24) { SKI_LEAF(24); }
-#undef SKI_LEAF
-    return hipErrorInvalidValue;
+hipError_t launch_narrow(T* Ac, int64_t m, int64_t jc, int w, const T* Tl, int nc,
+                         hipStream_t st) {
+    const int64_t rpt = (m - jc + LT - 1) / LT;
+    if (rpt <= 1)
+        narrow_launch<T, 1>(Ac, m, jc, w, Tl, nc, st);
+    else if (rpt <= 2)
+        narrow_launch<T, 2>(Ac, m, jc, w, Tl, nc, st);
+    else if (rpt <= 4)
+        narrow_launch<T, 4>(Ac, m, jc, w, Tl, nc, st);
+    else if (rpt <= 8)
+        narrow_launch<T, 8>(Ac, m, jc, w, Tl, nc, st);
+    else if (rpt <= 12)
+        narrow_launch<T, 12>(Ac, m, jc, w, Tl, nc, st);
+    else if (rpt <= 16)
+        narrow_launch<T, 16>(Ac, m, jc, w, Tl, nc, st);
+    else if (rpt <= 24)
+        narrow_launch<T, 24>(Ac, m, jc, w, Tl, nc, st);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 template <typename T>
 hipError_t gemm_t(bool ta, bool tb, int64_t M, int64_t N, int64_t K, T alpha, const T* A,
                   int64_t lda, const T* B, int64_t ldb, T beta, T* C, int64_t ldc, bool bf16,
-                  GemmWs& ws, hipStream_t st, int unitA) {
+                  GemmWs& ws, hipStream_t st) {
     if constexpr (sizeof(T) == 8)
-        return gemm_f64(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, st, unitA);
+        return gemm_f64(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, st, 0);
     else
-        return gemm_f32(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bf16, ws, st, unitA);
+        return gemm_f32(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bf16, ws, st, 0);
 }
 
 template <typename T>
-hipError_t qr_impl(T* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws, bool bf16,
+hipError_t qr_impl(const T* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws, bool bf16,
                    hipStream_t st) {
-    const int64_t ld = ncols;
-    T* tau = (T*)ws.ddiag;
-    T* Tp = (T*)ws.T;      // NBP x NBP panel T
-    T* Tl = (T*)ws.Y;      // NBL x NBL leaf T
-    T* W = (T*)ws.W;       // NBP x ncols
-    T* W2 = W + (int64_t)NBP * ncols;
-    T* part = (T*)ws.V;    // partial sums of the narrow kernels
+    T* Ac = (T*)ws.Ac;      // column-major working copy, ld = m
+    T* tau = (T*)ws.tau;
+    T* Tl = (T*)ws.Tl;      // NBL x NBL leaf T
+    T* Tp = (T*)ws.Tp;      // NBP x NBP panel T
+    T* G = (T*)ws.G;        // NBP x NBP Gram matrix
+    T* Vt = (T*)ws.Vt;      // NBP x m explicit reflectors of a panel
+    T* Wt = (T*)ws.Wt;      // ncols x NBP
+    T* W2t = (T*)ws.W2t;    // ncols x NBP
+    hipLaunchKernelGGL((k_to_colmajor<T>),
+                       dim3((unsigned)((ncols + 63) / 64), (unsigned)((m + 63) / 64)), dim3(256), 0,
+                       st, SA, m, ncols, Ac);
+    SKI_HIP(hipGetLastError());
     for (int64_t j0 = 0; j0 < d; j0 += NBP) {
         const int nb = (int)std::min<int64_t>(NBP, d - j0);
         for (int jl = 0; jl < nb; jl += NBL) {
             const int64_t jc = j0 + jl;
             const int w = std::min(NBL, nb - jl);
-            SKI_HIP(launch_leaf<T>(SA, ld, m, jc, w, tau, st));
+            SKI_HIP(launch_leaf<T>(Ac, m, jc, w, tau, Tl, st));
             const int nc = nb - jl - w;
-            if (nc > 0) {
-                SKI_HIP(leaf_T<T>(SA, ld, jc, m, w, tau, part, Tl, st));
-                const int64_t G = (m - jc + RB - 1) / RB;
-                hipLaunchKernelGGL((k_narrow_partial<T>), dim3((unsigned)G), dim3(256), 0, st, SA,
-                                   ld, jc, m, jc, w, jc + w, nc, part);
-                hipLaunchKernelGGL((k_narrow_reduce<T>), dim3(1), dim3(256), 0, st, part, G, w, nc,
-                                   Tl, w, W2);
-                const int64_t tot = (m - jc) * nc;
-                const unsigned gu = (unsigned)std::min<int64_t>((tot + 255) / 256, 4096);
-                hipLaunchKernelGGL((k_narrow_update<T>), dim3(gu), dim3(256), 0, st, SA, ld, jc, m,
-                                   jc, w, jc + w, nc, W2);
-                SKI_HIP(hipGetLastError());
-            }
+            if (nc > 0) SKI_HIP(launch_narrow<T>(Ac, m, jc, w, Tl, nc, st));
         }
         const int64_t n_rem = ncols - j0 - nb;
         if (n_rem > 0) {
-            // T of the panel from V^T V
-            const int64_t G = (m - j0 + RB - 1) / RB;
-            hipLaunchKernelGGL((k_gram_partial<T>), dim3((unsigned)G), dim3(256), 0, st, SA, ld, j0,
-                               m, nb, part);
-            hipLaunchKernelGGL((k_form_T<T>), dim3(1), dim3(256), 0, st, part, G, nb, tau + j0, Tp);
-            SKI_HIP(hipGetLastError());
-            const T* V = SA + j0 * ld + j0;
-            T* C = SA + j0 * ld + j0 + nb;
             const int64_t mr = m - j0;
-            // W = V^T C ; W2 = T^T W ; C -= V W2
-            SKI_HIP(gemm_t<T>(true, false, nb, n_rem, mr, (T)1, V, ld, C, ld, (T)0, W, n_rem, bf16,
-                              ws.g, st, 1));
-            SKI_HIP(gemm_t<T>(true, false, nb, n_rem, nb, (T)1, Tp, nb, W, n_rem, (T)0, W2, n_rem,
-                              false, ws.g, st, 0));
-            SKI_HIP(gemm_t<T>(false, false, mr, n_rem, nb, (T)-1, V, ld, W2, n_rem, (T)1, C, ld,
-                              bf16, ws.g, st, 1));
+            hipLaunchKernelGGL((k_make_Vt<T>),
+                               dim3((unsigned)std::min<int64_t>((mr + 255) / 256, 64), (unsigned)nb),
+                               dim3(256), 0, st, Ac, m, j0, nb, Vt);
+            SKI_HIP(hipGetLastError());
+            // G = V^T V (= Vt Vt^T), then T from G and the taus
+            SKI_HIP(gemm_t<T>(false, true, nb, nb, mr, (T)1, Vt, mr, Vt, mr, (T)0, G, nb, false,
+                              ws.g, st));
+            hipLaunchKernelGGL((k_form_T<T>), dim3(1), dim3(64), 0, st, G, nb, tau + j0, Tp);
+            SKI_HIP(hipGetLastError());
+            T* Ct = Ac + (j0 + nb) * m + j0;  // trailing columns as rows, ld = m
+            // W^T = C^T V ; W2^T = W^T T ; C^T -= W2^T V^T
+            SKI_HIP(gemm_t<T>(false, true, n_rem, nb, mr, (T)1, Ct, m, Vt, mr, (T)0, Wt, nb, bf16,
+                              ws.g, st));
+            SKI_HIP(gemm_t<T>(false, false, n_rem, nb, nb, (T)1, Wt, nb, Tp, nb, (T)0, W2t, nb,
+                              false, ws.g, st));
+            SKI_HIP(gemm_t<T>(false, false, n_rem, mr, nb, (T)-1, W2t, nb, Vt, mr, (T)1, Ct, m,
+                              bf16, ws.g, st));
         }
     }
     return hipSuccess;
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_extract_Rc(const T* __restrict__ SA, int64_t ld,
-                                                    int64_t d, int64_t k, double* __restrict__ R,
+__global__ __launch_bounds__(256) void k_extract_Rc(const T* __restrict__ Ac, int64_t m, int64_t d,
+                                                    int64_t k, double* __restrict__ R,
                                                     double* __restrict__ c) {
     const int64_t i = blockIdx.x;
-    const double dg = (double)SA[i * ld + i];
+    const double dg = (double)Ac[i * m + i];
     const double sg = dg < 0 ? -1.0 : 1.0;
     for (int64_t j = threadIdx.x; j < d; j += 256)
-        R[i * d + j] = j < i ? 0.0 : sg * (double)SA[i * ld + j];
-    for (int64_t j = threadIdx.x; j < k; j += 256) c[i * k + j] = sg * (double)SA[i * ld + d + j];
+        R[i * d + j] = j < i ? 0.0 : sg * (double)Ac[j * m + i];
+    for (int64_t j = threadIdx.x; j < k; j += 256) c[i * k + j] = sg * (double)Ac[(d + j) * m + i];
 }
 
 }  // namespace
 
-size_t qr_ws_bytes(Prec prec, int64_t m, int64_t ncols, int64_t d, size_t* gemm_bytes) {
+size_t qr_ws_bytes(Prec prec, int64_t m, int64_t ncols, size_t* gemm_bytes) {
     const size_t e = prec == Prec::F64 ? 8 : 4;
-    const int64_t G = (m + RB - 1) / RB;
-    size_t part = (size_t)G * std::max<int64_t>((int64_t)NBL * NBP, (int64_t)NBP * NBP) * e;
-    // split-K partials of the V^T C product
-    *gemm_bytes = gemm_ws_bytes(NBP, ncols, m, e);
-    return part;
+    *gemm_bytes = gemm_ws_bytes(NBP, NBP, m, e);
+    const size_t pad = 256 * 8;
+    return ((size_t)m * ncols + (size_t)NBP * m + 2 * (size_t)ncols * NBP + NBL * NBL +
+            2 * NBP * NBP + (size_t)ncols) * e + pad;
 }
 
-hipError_t qr_factor(Prec prec, void* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws,
+void qr_ws_carve(Prec prec, void* base, int64_t m, int64_t ncols, QrWs& ws) {
+    const size_t e = prec == Prec::F64 ? 8 : 4;
+    char* p = (char*)base;
+    auto take = [&](size_t count) {
+        void* q = p;
+        p += ((count * e + 255) / 256) * 256;
+        return q;
+    };
+    ws.Ac = take((size_t)m * ncols);
+    ws.Vt = take((size_t)NBP * m);
+    ws.Wt = take((size_t)ncols * NBP);
+    ws.W2t = take((size_t)ncols * NBP);
+    ws.Tl = take(NBL * NBL);
+    ws.Tp = take(NBP * NBP);
+    ws.G = take(NBP * NBP);
+    ws.tau = take((size_t)ncols);
+}
+
+hipError_t qr_factor(Prec prec, const void* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws,
                      hipStream_t st) {
-    if (prec == Prec::F64) return qr_impl<double>((double*)SA, m, ncols, d, ws, false, st);
-    return qr_impl<float>((float*)SA, m, ncols, d, ws, prec == Prec::BF16, st);
+    if (prec == Prec::F64) return qr_impl<double>((const double*)SA, m, ncols, d, ws, false, st);
+    return qr_impl<float>((const float*)SA, m, ncols, d, ws, prec == Prec::BF16, st);
 }
 
-hipError_t launch_extract_Rc(Prec prec, const void* SA, int64_t ldsa, int64_t d, int64_t k,
-                             double* R, double* c, hipStream_t st) {
+hipError_t launch_extract_Rc(Prec prec, const QrWs& ws, int64_t m, int64_t d, int64_t k, double* R,
+                             double* c, hipStream_t st) {
     if (prec == Prec::F64)
         hipLaunchKernelGGL((k_extract_Rc<double>), dim3((unsigned)d), dim3(256), 0, st,
-                           (const double*)SA, ldsa, d, k, R, c);
+                           (const double*)ws.Ac, m, d, k, R, c);
     else
         hipLaunchKernelGGL((k_extract_Rc<float>), dim3((unsigned)d), dim3(256), 0, st,
-                           (const float*)SA, ldsa, d, k, R, c);
+                           (const float*)ws.Ac, m, d, k, R, c);
     return hipGetLastError();
 }
 

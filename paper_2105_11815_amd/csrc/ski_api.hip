@@ -48,9 +48,18 @@ struct ski_handle_s {
     DevBuf qr_part, qr_W, qr_T, qr_Y, qr_tau;
     DevBuf tkeys, tkeys_tmp, ttable, tp, tpay, ti, tv;
     DevBuf u, t, v, h, delta, z, wp, g, gpart, upart, y, st, flag;
-    DevBuf cg_r, cg_p, cg_q, t2;
+    DevBuf cg_r, cg_p, cg_q, t2, dtmp;
+    double* hdiag = nullptr;  // pinned host copy of diag(R)
+    int64_t hdiag_n = 0;
     hipEvent_t ev[6] = {};
     bool ev_ok = false;
+    // kernel-class timing (ski_set_profiling)
+    bool prof = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<std::pair<int, int>> open_pairs;  // (class, index of the start event)
+    size_t pool_used = 0;
+    double prof_ms[SKI_PROF_CLASSES] = {};
+    int64_t prof_cnt[SKI_PROF_CLASSES] = {};
 };
 
 namespace {
@@ -109,6 +118,52 @@ int64_t next_pow2(int64_t n) {
 }
 
 constexpr int64_t PASS_WG = 512;  // workgroups of the fused dense LSQR pass
+
+enum ProfClass {
+    PC_PASS = 0, PC_REDUCE = 1, PC_TRIGEMV = 2, PC_SPMV = 3, PC_SPMVT = 4, PC_STEP = 5,
+    PC_HASH = 6, PC_WHT = 7, PC_GATHER = 8, PC_QR = 9, PC_TRTRI = 10
+};
+
+hipEvent_t pool_event(ski_handle h) {
+    if (h->pool_used == h->pool.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        h->pool.push_back(e);
+    }
+    return h->pool[h->pool_used++];
+}
+
+// bracket the launches between prof_begin and prof_end with an event pair
+void prof_begin(ski_handle h, int cls, hipStream_t st) {
+    if (!h->prof) return;
+    hipEvent_t e = pool_event(h);
+    if (!e) return;
+    (void)hipEventRecord(e, st);
+    h->open_pairs.push_back({cls, (int)h->pool_used - 1});
+}
+void prof_end(ski_handle h, hipStream_t st) {
+    // the end event directly follows its start event in the pool (pairs never nest)
+    if (!h->prof || h->open_pairs.empty()) return;
+    hipEvent_t e = pool_event(h);
+    if (!e) return;
+    (void)hipEventRecord(e, st);
+}
+// sum the recorded pairs (after the stream has been synchronised) and recycle the events
+void prof_collect(ski_handle h) {
+    if (!h->prof) return;
+    for (auto& pr : h->open_pairs) {
+        const int i0 = pr.second;
+        if ((size_t)(i0 + 1) >= h->pool_used) continue;
+        float ms = 0;
+        if (hipEventSynchronize(h->pool[i0 + 1]) == hipSuccess &&
+            hipEventElapsedTime(&ms, h->pool[i0], h->pool[i0 + 1]) == hipSuccess) {
+            h->prof_ms[pr.first] += ms;
+            h->prof_cnt[pr.first] += 1;
+        }
+    }
+    h->open_pairs.clear();
+    h->pool_used = 0;
+}
 constexpr int CHECK_EVERY = 8;    // LSQR iterations between status reads
 
 }  // namespace
@@ -135,10 +190,12 @@ int ski_destroy(ski_handle h) {
                      &h->qr_Y, &h->qr_tau, &h->tkeys, &h->tkeys_tmp, &h->ttable, &h->tp,
                      &h->tpay, &h->ti, &h->tv, &h->u, &h->t, &h->v, &h->h, &h->delta, &h->z,
                      &h->wp, &h->g, &h->gpart, &h->upart, &h->y, &h->st, &h->flag, &h->cg_r,
-                     &h->cg_p, &h->cg_q, &h->t2};
+                     &h->cg_p, &h->cg_q, &h->t2, &h->dtmp};
     for (DevBuf* b : all) release(*b);
     if (h->ev_ok)
         for (auto& e : h->ev) (void)hipEventDestroy(e);
+    for (auto& e : h->pool) (void)hipEventDestroy(e);
+    if (h->hdiag) (void)hipHostFree(h->hdiag);
     delete h;
     return SKI_OK;
 }
@@ -250,7 +307,9 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
     hb.src = P<int32_t>(h->src);
     hb.keys = P<uint64_t>(h->keys);
     hb.table = P<int32_t>(h->table);
+    prof_begin(h, PC_HASH, st);
     SKI_TRY(h, launch_hash_build(nhc, m, p->s, p->seed, hb, st), "hash build");
+    prof_end(h, st);
 
     // the SA storage type for the gathers: FP64, or FP32 for the mixed forms
     const Prec gprec = qprec == Prec::F64 ? Prec::F64 : (sprec == Prec::F64 ? Prec::F32 : sprec);
@@ -259,15 +318,19 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
         SKI_TRY(h, ensure(h->dbits, ((npad + 255) / 256) * 32), "alloc");
         SKI_TRY(h, ensure(h->T0, (size_t)npad * ncols * te), "alloc");
         SKI_TRY(h, ensure(h->T1, (size_t)npad * ncols * te), "alloc");
+        prof_begin(h, PC_WHT, st);
         SKI_TRY(h, launch_dsign(npad, p->seed, P<uint32_t>(h->dbits), st), "dsign");
         void* T = nullptr;
         SKI_TRY(h, launch_wht_sketch_dense(A->a, A->lda, B, ldb, n, d, k, npad,
                                            P<uint32_t>(h->dbits), h->T0.p, h->T1.p, gprec, &T, st),
                 "wht");
+        prof_end(h, st);
         const double scale = 1.0 / sqrt((double)npad * (double)p->s);
+        prof_begin(h, PC_GATHER, st);
         SKI_TRY(h, launch_gather_dense(T, ncols, P<int32_t>(h->bucket_ptr), P<int32_t>(h->src), m,
                                        scale, gprec, h->SA.p, st),
                 "gather");
+        prof_end(h, st);
     } else if (A->kind == SKI_DENSE) {
         const double scale = 1.0 / sqrt((double)p->s);
         SKI_TRY(h, launch_gather_plain(A->a, A->lda, B, ldb, d, k, P<int32_t>(h->bucket_ptr),
@@ -305,16 +368,10 @@ int ski_factor(ski_handle h, void* stream) {
     if (!h->sketched) return fail(h, SKI_ESTATE, "ski_factor: call ski_sketch first");
     hipStream_t st = (hipStream_t)stream;
     const int64_t m = h->m, d = h->d, k = h->k, ncols = d + k;
-    const size_t e = h->qprec == Prec::F64 ? 8 : 4;
     size_t gb = 0;
-    const size_t partb = qr_ws_bytes(h->qprec, m, ncols, d, &gb);
-    SKI_TRY(h, ensure(h->qr_part, partb), "alloc");
-    SKI_TRY(h, ensure(h->qr_W, 2 * 64 * ncols * e), "alloc");
-    SKI_TRY(h, ensure(h->qr_T, 64 * 64 * e), "alloc");
-    SKI_TRY(h, ensure(h->qr_Y, 64 * 64 * e), "alloc");
-    SKI_TRY(h, ensure(h->qr_tau, d * e), "alloc");
-    const size_t gws = std::max<size_t>({gb, (size_t)(448 * 64 * 64 + 64 * ncols) * 8,
-                                         (size_t)64 << 20});
+    const size_t qrb = qr_ws_bytes(h->qprec, m, ncols, &gb);
+    SKI_TRY(h, ensure(h->qr_part, qrb), "alloc");
+    const size_t gws = std::max<size_t>(gb, (size_t)64 << 20);
     SKI_TRY(h, ensure(h->gemm_ws, gws), "alloc");
     SKI_TRY(h, ensure(h->R, d * d * 8), "alloc");
     SKI_TRY(h, ensure(h->c, d * k * 8), "alloc");
@@ -324,23 +381,28 @@ int ski_factor(ski_handle h, void* stream) {
     SKI_TRY(h, ensure(h->tri_tmp, ((d + 1) / 2 + 64) * ((d + 1) / 2 + 64) * 8), "alloc");
     if (h->ev_ok) (void)hipEventRecord(h->ev[2], st);
     QrWs ws;
-    ws.V = h->qr_part.p;
-    ws.T = h->qr_T.p;
-    ws.W = h->qr_W.p;
-    ws.Y = h->qr_Y.p;
-    ws.ddiag = P<double>(h->qr_tau);
+    qr_ws_carve(h->qprec, h->qr_part.p, m, ncols, ws);
     ws.g.part = h->gemm_ws.p;
     ws.g.bytes = h->gemm_ws.bytes;
+    prof_begin(h, PC_QR, st);
     SKI_TRY(h, qr_factor(h->qprec, h->SA.p, m, ncols, d, ws, st), "qr");
-    SKI_TRY(h, launch_extract_Rc(h->qprec, h->SA.p, ncols, d, k, P<double>(h->R), P<double>(h->c),
-                                 st),
+    prof_end(h, st);
+    SKI_TRY(h, launch_extract_Rc(h->qprec, ws, m, d, k, P<double>(h->R), P<double>(h->c), st),
             "extract R");
-    // guards on diag(R): read the diagonal (d values) to the host
-    std::vector<double> Rd(d);
-    SKI_TRY(h, hipMemcpy2DAsync(Rd.data(), sizeof(double), P<double>(h->R), (d + 1) * sizeof(double),
-                                sizeof(double), d, hipMemcpyDeviceToHost, st),
-            "diag copy");
+    // guards on diag(R): gather the diagonal on the device, copy it to pinned host memory
+    SKI_TRY(h, ensure(h->dtmp, d * 8), "alloc");
+    if (h->hdiag_n < d) {
+        if (h->hdiag) (void)hipHostFree(h->hdiag);
+        h->hdiag = nullptr;
+        h->hdiag_n = 0;
+        SKI_TRY(h, hipHostMalloc((void**)&h->hdiag, 2 * d * 8, hipHostMallocDefault), "pinned");
+        h->hdiag_n = d;
+    }
+    SKI_TRY(h, launch_scale_copy(P<double>(h->R), d, 1, d + 1, 1.0, P<double>(h->dtmp), 1, st),
+            "diag gather");
+    SKI_TRY(h, hipMemcpyAsync(h->hdiag, h->dtmp.p, d * 8, hipMemcpyDeviceToHost, st), "diag copy");
     SKI_TRY(h, hipStreamSynchronize(st), "sync");
+    const double* Rd = h->hdiag;
     double amax = 0, amin = INFINITY;
     bool finite = true;
     for (int64_t i = 0; i < d; ++i) {
@@ -356,26 +418,31 @@ int ski_factor(ski_handle h, void* stream) {
         for (int64_t i = 0; i < d; ++i)
             if (!(r11 > 0) || fabs(Rd[i]) < h->p.rcond * r11) {
                 h->factored = false;
-                char buf[160];
+                char buf[200];
                 snprintf(buf, sizeof buf,
-                         "ski_factor: rank guard failed at column %lld (|r_qq| < rcond |r_11|)",
-                         (long long)i);
+                         "rank guard failed at column %lld: |r_qq| = %.3e < rcond |r_11| "
+                         "(r_11 = %.3e)",
+                         (long long)i, fabs(Rd[i]), r11);
                 return fail(h, SKI_ERANK, buf);
             }
     }
-    std::vector<double> add(d, 0.0);
-    if (h->p.perturb > 0 && h->p.rcond_thres > 0 && h->cond_est >= 1.0 / h->p.rcond_thres)
-        for (int64_t i = 0; i < d; ++i) add[i] = copysign(h->p.perturb, Rd[i]);
-    SKI_TRY(h, hipMemcpyAsync(h->diag_add.p, add.data(), d * 8, hipMemcpyHostToDevice, st),
+    double* add = h->hdiag + d;  // pinned
+    const bool pert = h->p.perturb > 0 && h->p.rcond_thres > 0 &&
+                      h->cond_est >= 1.0 / h->p.rcond_thres;
+    for (int64_t i = 0; i < d; ++i) add[i] = pert ? copysign(h->p.perturb, Rd[i]) : 0.0;
+    SKI_TRY(h, hipMemcpyAsync(h->diag_add.p, add, d * 8, hipMemcpyHostToDevice, st),
             "perturb copy");
     GemmWs gw;
     gw.part = h->gemm_ws.p;
     gw.bytes = h->gemm_ws.bytes;
+    prof_begin(h, PC_TRTRI, st);
     SKI_TRY(h, trtri_upper(P<double>(h->R), d, P<double>(h->Rinv), P<double>(h->RinvT),
                            P<double>(h->diag_add), P<double>(h->tri_tmp), gw, st),
             "R inverse");
+    prof_end(h, st);
     if (h->ev_ok) (void)hipEventRecord(h->ev[3], st);
-    SKI_TRY(h, hipStreamSynchronize(st), "sync");  // add[] lives on this stack frame
+    SKI_TRY(h, hipStreamSynchronize(st), "sync");
+    prof_collect(h);
     h->factored = true;
     return SKI_OK;
 }
@@ -420,12 +487,44 @@ hipError_t apply_Rinv(ski_handle h, const double* Mtx, bool upper, const double*
     return gemm_f64(false, false, h->d, k, h->d, s, Mtx, h->d, x, k, 0.0, y, k, gw, st);
 }
 
-int read_flag(ski_handle h, int k, hipStream_t st, int32_t* out) {
-    SKI_TRY(h, launch_all_done(P<LsqrState>(h->st), k, P<int32_t>(h->flag), st), "flag");
-    SKI_TRY(h, hipMemcpyAsync(out, h->flag.p, 4, hipMemcpyDeviceToHost, st), "flag copy");
-    SKI_TRY(h, hipStreamSynchronize(st), "sync");
-    return SKI_OK;
-}
+// Convergence status read back with a one-iteration lag: after iteration i the all-done
+// word is copied to pinned host memory and an event recorded; the host waits on the event
+// of iteration i-1 only, so at most one idle iteration is ever launched.
+struct LagFlag {
+    int32_t* host = nullptr;  // [2]
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    bool stop = false;
+    int init(ski_handle h, int k, hipStream_t st) {
+        (void)k;
+        (void)st;
+        SKI_TRY(h, hipHostMalloc((void**)&host, 2 * sizeof(int32_t), hipHostMallocDefault),
+                "pinned");
+        host[0] = host[1] = 0;
+        for (auto& e : ev) SKI_TRY(h, hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+        return SKI_OK;
+    }
+    int post(ski_handle h, int k, hipStream_t st, int64_t it) {
+        const int slot = (int)(it & 1);
+        SKI_TRY(h, launch_all_done(P<LsqrState>(h->st), k, P<int32_t>(h->flag) + slot, st), "flag");
+        SKI_TRY(h, hipMemcpyAsync(host + slot, P<int32_t>(h->flag) + slot, sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, st),
+                "flag copy");
+        SKI_TRY(h, hipEventRecord(ev[slot], st), "event");
+        return SKI_OK;
+    }
+    // 1 if every column had stopped after iteration it, 0 if not, < 0 on error
+    int wait(ski_handle h, int64_t it) {
+        const int slot = (int)(it & 1);
+        SKI_TRY(h, hipEventSynchronize(ev[slot]), "event sync");
+        return host[slot] ? 1 : 0;
+    }
+    void release() {
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (host) (void)hipHostFree(host);
+        host = nullptr;
+    }
+};
 
 int finish_info(ski_handle h, int k, ski_info* info, float ms_solve, bool cg, hipStream_t st) {
     std::vector<LsqrState> S(k);
@@ -510,29 +609,37 @@ int solve_lls(ski_handle h, const double* B, int k, int64_t ldb, double* X, int6
     SKI_TRY(h, apply_Rinv(h, RinvT, false, g, wp, k, 1.0, nullptr, gw, st), "R^-T g");
     SKI_TRY(h, launch_lsqr_init(S, d, k, wp, v, hh, dl, h->p.tau_a, st), "init");
     const int32_t* done1 = (k == 1) ? &S[0].done : nullptr;
-    int32_t* hflag = nullptr;
-    SKI_TRY(h, hipHostMalloc((void**)&hflag, 4, hipHostMallocDefault), "pinned");
+    LagFlag lf;
+    int out = lf.init(h, k, st);
+    if (out == SKI_OK) out = lf.post(h, k, st, 0);
+    if (out == SKI_OK && lf.wait(h, 0) == 1) lf.stop = true;
     int64_t it = 0;
-    int out = SKI_OK;
-    while (true) {
-        int rc2 = read_flag(h, k, st, hflag);
-        if (rc2 != SKI_OK) {
-            out = rc2;
-            break;
-        }
-        if (*hflag || it >= h->p.it_max) break;
-        for (int q = 0; q < CHECK_EVERY && it < h->p.it_max; ++q, ++it) {
+    while (out == SKI_OK && !lf.stop && it < h->p.it_max) {
+        {
+            prof_begin(h, PC_TRIGEMV, st);
             hipError_t e = apply_Rinv(h, Rinv, true, v, z, k, 1.0, done1, gw, st);
+            prof_end(h, st);
             if (e == hipSuccess) {
-                if (fused)
-                    e = launch_lsqr_pass(h->A, h->lda, n, d, z, u, S, PASS_WG, P<double>(h->gpart),
-                                         P<double>(h->upart), g, S, false, st);
-                else if (csr) {
+                if (fused) {
+                    prof_begin(h, PC_PASS, st);
+                    e = launch_pass_kernel(h->A, h->lda, n, d, z, u, S, PASS_WG,
+                                           P<double>(h->gpart), P<double>(h->upart), false, st);
+                    prof_end(h, st);
+                    prof_begin(h, PC_REDUCE, st);
+                    if (e == hipSuccess)
+                        e = launch_pass_reduce(P<double>(h->gpart), P<double>(h->upart), PASS_WG,
+                                               d, g, S, st);
+                    prof_end(h, st);
+                } else if (csr) {
+                    prof_begin(h, PC_SPMV, st);
                     e = launch_spmv_csr(h->rp, h->ci, h->va, n, k, z, u, S, false,
                                         P<double>(h->upart), st);
+                    prof_end(h, st);
+                    prof_begin(h, PC_SPMVT, st);
                     if (e == hipSuccess)
                         e = launch_spmv_csrT(P<int32_t>(h->tp), P<int32_t>(h->ti), P<double>(h->tv),
                                              d, k, u, g, S, st);
+                    prof_end(h, st);
                 } else {
                     e = dense_AZ(h, z, k, t, gw, st);
                     if (e == hipSuccess)
@@ -541,17 +648,25 @@ int solve_lls(ski_handle h, const double* B, int k, int64_t ldb, double* X, int6
                     if (e == hipSuccess) e = dense_ATU(h, u, k, g, gw, st);
                 }
             }
+            prof_begin(h, PC_TRIGEMV, st);
             if (e == hipSuccess) e = apply_Rinv(h, RinvT, false, g, wp, k, 1.0, done1, gw, st);
+            prof_end(h, st);
+            prof_begin(h, PC_STEP, st);
             if (e == hipSuccess)
                 e = launch_lsqr_step(S, d, k, wp, v, hh, dl, h->p.tau_r, h->p.it_max, st);
+            prof_end(h, st);
             if (e != hipSuccess) {
                 out = hip_fail(h, e, "lsqr iteration");
                 break;
             }
         }
-        if (out != SKI_OK) break;
+        ++it;
+        // status of this iteration is posted now and read one iteration later, so the
+        // device always has the next iteration queued while the host checks
+        out = lf.post(h, k, st, it);
+        if (out == SKI_OK && it >= 2 && lf.wait(h, it - 1) == 1) break;
     }
-    (void)hipHostFree(hflag);
+    lf.release();
     if (out != SKI_OK) return out;
     // x = R^-1 (c + delta)
     SKI_TRY(h, launch_final_y(S, d, k, c, dl, y, st), "final y");
@@ -566,7 +681,9 @@ int solve_lls(ski_handle h, const double* B, int k, int64_t ldb, double* X, int6
         (void)hipEventSynchronize(e1);
         (void)hipEventElapsedTime(&ms, e0, e1);
     }
-    return finish_info(h, k, info, ms, false, st);
+    const int rcf = finish_info(h, k, info, ms, false, st);
+    prof_collect(h);
+    return rcf;
 }
 
 // Z = (A^T A)^-1 G by CG on R^-T A^T A R^-1 (dense A)
@@ -594,32 +711,27 @@ int solve_normal(ski_handle h, const double* G, int k, int64_t ldg, double* Z, i
     SKI_TRY(h, launch_scale_copy(G, d, k, ldg, 1.0, g, k, st), "copy g");
     SKI_TRY(h, gemm_f64(false, false, d, k, d, 1.0, RinvT, d, g, k, 0.0, wp, k, gw, st), "rhs");
     SKI_TRY(h, launch_cg_init(S, d, k, wp, r, pp, y, h->p.tau_r, st), "cg init");
-    int32_t* hflag = nullptr;
-    SKI_TRY(h, hipHostMalloc((void**)&hflag, 4, hipHostMallocDefault), "pinned");
+    LagFlag lf;
+    int out = lf.init(h, k, st);
+    if (out == SKI_OK) out = lf.post(h, k, st, 0);
+    if (out == SKI_OK && lf.wait(h, 0) == 1) lf.stop = true;
     int64_t it = 0;
-    int out = SKI_OK;
-    while (true) {
-        int rc2 = read_flag(h, k, st, hflag);
-        if (rc2 != SKI_OK) {
-            out = rc2;
+    while (out == SKI_OK && !lf.stop && it < h->p.it_max) {
+        hipError_t e = gemm_f64(false, false, d, k, d, 1.0, Rinv, d, pp, k, 0.0, z, k, gw, st);
+        if (e == hipSuccess) e = dense_AZ(h, z, k, t, gw, st);
+        if (e == hipSuccess) e = dense_ATU(h, t, k, g, gw, st);
+        if (e == hipSuccess)
+            e = gemm_f64(false, false, d, k, d, 1.0, RinvT, d, g, k, 0.0, q, k, gw, st);
+        if (e == hipSuccess) e = launch_cg_step(S, d, k, q, r, pp, y, h->p.it_max, st);
+        if (e != hipSuccess) {
+            out = hip_fail(h, e, "cg iteration");
             break;
         }
-        if (*hflag || it >= h->p.it_max) break;
-        for (int s = 0; s < CHECK_EVERY && it < h->p.it_max; ++s, ++it) {
-            hipError_t e = gemm_f64(false, false, d, k, d, 1.0, Rinv, d, pp, k, 0.0, z, k, gw, st);
-            if (e == hipSuccess) e = dense_AZ(h, z, k, t, gw, st);
-            if (e == hipSuccess) e = dense_ATU(h, t, k, g, gw, st);
-            if (e == hipSuccess)
-                e = gemm_f64(false, false, d, k, d, 1.0, RinvT, d, g, k, 0.0, q, k, gw, st);
-            if (e == hipSuccess) e = launch_cg_step(S, d, k, q, r, pp, y, h->p.it_max, st);
-            if (e != hipSuccess) {
-                out = hip_fail(h, e, "cg iteration");
-                break;
-            }
-        }
-        if (out != SKI_OK) break;
+        ++it;
+        out = lf.post(h, k, st, it);
+        if (out == SKI_OK && it >= 2 && lf.wait(h, it - 1) == 1) break;
     }
-    (void)hipHostFree(hflag);
+    lf.release();
     if (out != SKI_OK) return out;
     SKI_TRY(h, gemm_f64(false, false, d, k, d, 1.0, Rinv, d, y, k, 0.0, Z, ldz, gw, st), "z");
     float ms = 0;
@@ -686,6 +798,30 @@ int ski_gradients(ski_handle h, const double* X, int64_t ldx, const double* B, i
                 "r Z^T");
         SKI_TRY(h, gemm_f64(false, true, n, d, k, -1.0, AZ, k, X, ldx, 1.0, grad_A, ldga, gw, st),
                 "(AZ) X^T");
+    }
+    return SKI_OK;
+}
+
+int ski_set_profiling(ski_handle h, int32_t on) {
+    if (!h) return SKI_EINVAL;
+    if (h->prof) {
+        (void)hipDeviceSynchronize();
+        prof_collect(h);
+    }
+    h->prof = on != 0;
+    for (int c = 0; c < SKI_PROF_CLASSES; ++c) {
+        h->prof_ms[c] = 0;
+        h->prof_cnt[c] = 0;
+    }
+    return SKI_OK;
+}
+
+int ski_get_profile(ski_handle h, double* ms, int64_t* count) {
+    if (!h || !ms || !count) return SKI_EINVAL;
+    prof_collect(h);
+    for (int c = 0; c < SKI_PROF_CLASSES; ++c) {
+        ms[c] = h->prof_ms[c];
+        count[c] = h->prof_cnt[c];
     }
     return SKI_OK;
 }

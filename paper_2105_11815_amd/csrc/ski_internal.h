@@ -55,12 +55,39 @@ __device__ __forceinline__ P4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c
 }
 
 // ---------------------------------------------------------------------------
-// wave64 reductions (DPP/permute through the compiler's shuffle lowering)
+// wave64 sum with DPP lane moves (CDNA, gfx9 family): pairs and quads by quad_perm,
+// 16-lane rows by row_ror 4 and 8, then row_bcast 15 and 31 carry the row sums up to
+// lane 63, whose value is broadcast.  The order of the additions is fixed, so the
+// result is the same on every run.  Lanes other than 63 may hold partial garbage
+// before the final broadcast.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+    int lo = __double2loint(x), hi = __double2hiint(x);
+    lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xf, 0xf, false);
+    hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float x) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double lane63(double x) {
+    int lo = __builtin_amdgcn_readlane(__double2loint(x), 63);
+    int hi = __builtin_amdgcn_readlane(__double2hiint(x), 63);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane63(float x) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_move<0xb1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_move<0x4e>(v);   // quad_perm [2,3,0,1]
+    v += dpp_move<0x124>(v);  // row_ror 4
+    v += dpp_move<0x128>(v);  // row_ror 8
+    v += dpp_move<0x142>(v);  // row_bcast 15
+    v += dpp_move<0x143>(v);  // row_bcast 31
+    return lane63(v);
 }
 
 // ---------------------------------------------------------------------------
@@ -132,20 +159,25 @@ hipError_t gemm_f32(bool ta, bool tb, int64_t M, int64_t N, int64_t K, float alp
                     int64_t ldc, bool bf16_inputs, GemmWs& ws, hipStream_t st, int unitA = 0);
 size_t gemm_ws_bytes(int64_t M, int64_t N, int64_t K, size_t elem);
 
-// Householder QR of the m x (d+k) sketch (in place), R into the upper triangle
+// Householder QR of the m x (d+k) sketch on a column-major working copy
 struct QrWs {
-    void* V = nullptr;      // explicit Householder vectors, m x nb panel
-    void* T = nullptr;      // nb x nb
-    void* W = nullptr;      // nb x ncols
-    void* Y = nullptr;      // nb x nb
-    double* ddiag = nullptr;
+    void* Ac = nullptr;   // column-major copy of the sketch (ld = m), factored in place
+    void* Vt = nullptr;   // explicit reflectors of a panel, transposed
+    void* Wt = nullptr;
+    void* W2t = nullptr;
+    void* Tl = nullptr;
+    void* Tp = nullptr;
+    void* G = nullptr;
+    void* tau = nullptr;
     GemmWs g;
 };
-hipError_t qr_factor(Prec prec, void* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws,
+size_t qr_ws_bytes(Prec prec, int64_t m, int64_t ncols, size_t* gemm_bytes);
+void qr_ws_carve(Prec prec, void* base, int64_t m, int64_t ncols, QrWs& ws);
+hipError_t qr_factor(Prec prec, const void* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws,
                      hipStream_t st);
-size_t qr_ws_bytes(Prec prec, int64_t m, int64_t ncols, int64_t d, size_t* gemm_bytes);
-// copy R (d x d) and c (d x k) out of the factored sketch into FP64, flipping rows so
-// that diag(R) >= 0
-hipError_t launch_extract_Rc(Prec prec, const void* SA, int64_t ldsa, int64_t d, int64_t k,
-                             double* R, double* c, hipStream_t st);
+// copy R (d x d) and c (d x k) out of the factored copy into FP64 row-major, flipping
+// rows so that diag(R) >= 0
+hipError_t launch_extract_Rc(Prec prec, const QrWs& ws, int64_t m, int64_t d, int64_t k, double* R,
+                             double* c, hipStream_t st);
+
 }  // namespace ski
