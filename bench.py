@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "solve time & sketch GB/s at 50000x4000; mixed vs FP64 at equal 1e-10 residual"
 HBM_PEAK_GBPS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_lsqr_pass_dense_50000x4000.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lsqr_pass_dense_50000x4000_traffic.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2105_11815_amd", "csrc", "lsqr.hip")
 
 
@@ -88,16 +88,21 @@ def cpu_baseline(A, b, cfg, gpu_iters):
 
 
 def traffic_for_pass(n_launch_bytes):
-    """HBM bytes per launch of the fused pass from the committed rocprofv3 counter runs,
-    or None when absent or taken on a different version of the kernel source."""
+    """HBM bytes per launch of the fused pass from the committed rocprofv3 counter runs
+    (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on the reference copy), or None
+    when absent or taken on a different version of the kernel source."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     try:
-        rec = json.load(open(TRAFFIC_FILE))
+        rec = {}
+        for line in open(TRAFFIC_FILE):
+            if ":" in line and not line.startswith("#"):
+                key, val = line.split(":", 1)
+                rec[key.strip()] = val.strip()
         src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
         if rec.get("kernel_source_sha256") != src:
             return None
-        return rec["bytes_per_launch"]
+        return int(float(rec["bytes_per_launch"]))
     except Exception:
         return None
 
@@ -160,6 +165,18 @@ def main():
               hadamard=True)
     n, d, k = A.shape[0], A.shape[1], 1
 
+    # reference device-to-device copy of A (read and write 8nd bytes): the achievable
+    # streaming rate, and the calibration point for the HBM byte counters
+    ref = torch.empty_like(At)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ref.copy_(At)
+    ev0.record()
+    ref.copy_(At)
+    ev1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 2 * At.numel() * 8 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    del ref
+
     S = P.Solver()
     for _ in range(args.warmup):
         one_solve(P, S, At, bt, **kw)
@@ -221,6 +238,7 @@ def main():
         "solve_ms": round(float(np.median([i["ms_solve"] for i in infos])), 3),
         "lsqr_iters": int(info["iters"]), "optimality_certificate": cert,
         "rnorm": float(r.norm()), "kernel_ms": phases, "roofline": roofline,
+        "copy_GBps_reference": round(copy_gbps, 1),
     }
 
     if not args.no_mixed:

@@ -230,8 +230,17 @@ __global__ __launch_bounds__(64 * RSL) void k_reduce_pass(const double* __restri
     const int64_t c = (int64_t)blockIdx.x * 64 + lane;
     const int64_t g0 = q * G / RSL, g1 = (q + 1) * G / RSL;
     double s = 0;
-    if (c < d)
-        for (int64_t gq = g0; gq < g1; ++gq) s += gpart[gq * d + c];
+    if (c < d) {
+        int64_t gq = g0;
+        for (; gq + 8 <= g1; gq += 8) {
+            double a[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] = gpart[(gq + u) * d + c];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += a[u];
+        }
+        for (; gq < g1; ++gq) s += gpart[gq * d + c];
+    }
     part[q][lane] = s;
     __syncthreads();
     if (q == 0 && c < d) {

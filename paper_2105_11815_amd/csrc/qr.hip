@@ -50,7 +50,8 @@ __device__ __forceinline__ void block_reduce(T (&v)[N], T (*sh)[N], int tid) {
 }
 
 // leaf: factor columns [jc, jc+w) over rows [jc, m) of the column-major matrix (ld = m);
-// taus -> tau[jc..], the leaf's T (w x w, row-major, NBL stride) -> Tl
+// taus -> tau[jc..], the leaf's T (w x w) -> Tl, the leaf's diagonal block of the panel T
+// (row-major, leading dimension NBP)
 template <typename T, int RPT>
 __global__ __launch_bounds__(LT) void k_qr_leaf(T* __restrict__ Ac, int64_t m, int64_t jc, int w,
                                                 T* __restrict__ tau, T* __restrict__ Tl) {
@@ -203,7 +204,10 @@ __global__ __launch_bounds__(LT) void k_qr_leaf(T* __restrict__ Ac, int64_t m, i
             }
         }
 #pragma unroll
-        for (int q = 0; q < NBL * NBL; ++q) Tl[q] = Tm[q];
+        for (int a = 0; a < NBL; ++a)
+#pragma unroll
+            for (int b = 0; b < NBL; ++b)
+                if (a < w && b < w) Tl[a * NBP + b] = Tm[a * NBL + b];
     }
 }
 
@@ -244,7 +248,7 @@ __global__ __launch_bounds__(LT) void k_narrow_apply(T* __restrict__ Ac, int64_t
         T s = 0;
 #pragma unroll
         for (int b = 0; b < NBL; ++b)
-            if (b <= a && a < w) s += Tl[b * NBL + a] * acc[b];
+            if (b <= a && a < w) s += Tl[b * NBP + a] * acc[b];
         w2[a] = s;
     }
 #pragma unroll
@@ -270,32 +274,53 @@ __global__ __launch_bounds__(256) void k_make_Vt(const T* __restrict__ Ac, int64
         Vt[c * mr + r] = r < c ? (T)0 : (r == c ? (T)1 : col[r]);
 }
 
-// T of a panel from G = V^T V (nb x nb, row-major) and tau, by one wave: lane a owns
-// row a of T; column i needs only rows < i of the columns before it, and a wave's LDS
-// accesses are ordered, so no barrier is needed between columns.
+// T of a panel: the leaves left their w x w blocks on the diagonal of Tp (ld NBP); blocks
+// are merged pairwise, level by level, with T12 = -T1 (V1^T V2) T2, where V1^T V2 is the
+// corresponding block of G = V^T V (nb x nb, ld nb).
 template <typename T>
-__global__ __launch_bounds__(64) void k_form_T(const T* __restrict__ G, int nb,
-                                               const T* __restrict__ tau, T* __restrict__ Tp) {
+__global__ __launch_bounds__(256) void k_form_T(const T* __restrict__ G, int nb,
+                                                T* __restrict__ Tp) {
     __shared__ T Gs[NBP * NBP];
     __shared__ T Ts[NBP * NBP];
-    const int a = threadIdx.x;
-    for (int o = a; o < nb * nb; o += 64) {
+    __shared__ T Xs[NBP * NBP];
+    const int tid = threadIdx.x;
+    for (int o = tid; o < nb * nb; o += 256) {
+        const int a = o / nb, b = o - a * nb;
         Gs[o] = G[o];
-        Ts[o] = 0;
+        // keep only the leaves' diagonal blocks
+        Ts[o] = (a / NBL == b / NBL) ? Tp[a * NBP + b] : (T)0;
     }
     __syncthreads();
-    for (int i = 0; i < nb; ++i) {
-        const T ti = tau[i];
-        T y = 0;
-        if (a < i)
-            for (int b = a; b < i; ++b) y += Ts[a * nb + b] * Gs[b * nb + i];
-        __builtin_amdgcn_wave_barrier();
-        if (a < i) Ts[a * nb + i] = -ti * y;
-        if (a == i) Ts[i * nb + i] = ti;
-        __builtin_amdgcn_wave_barrier();
+    for (int bs = NBL; bs < nb; bs *= 2) {
+        // pairs at offsets o = 2 bs q: T1 = [o, o+bs), T2 = [o+bs, min(o+2bs, nb))
+        // X = G12 T2 (bs x n2), then T12 = -T1 X
+        for (int e = tid; e < nb * nb; e += 256) {
+            const int i = e / nb, j = e - i * nb;
+            const int o = (i / (2 * bs)) * 2 * bs;
+            const int o2 = o + bs;
+            if (i < o2 && j >= o2 && j < std::min(o + 2 * bs, nb)) {
+                T x = 0;
+                for (int t = o2; t <= j; ++t) x += Gs[i * nb + t] * Ts[t * nb + j];
+                Xs[e] = x;
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < nb * nb; e += 256) {
+            const int i = e / nb, j = e - i * nb;
+            const int o = (i / (2 * bs)) * 2 * bs;
+            const int o2 = o + bs;
+            if (i < o2 && j >= o2 && j < std::min(o + 2 * bs, nb)) {
+                T y = 0;
+                for (int t = i; t < o2; ++t) y += Ts[i * nb + t] * Xs[t * nb + j];
+                Ts[e] = -y;
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int o = a; o < nb * nb; o += 64) Tp[o] = Ts[o];
+    for (int o = tid; o < nb * nb; o += 256) {
+        const int a = o / nb, b = o - a * nb;
+        Tp[a * NBP + b] = Ts[o];
+    }
 }
 
 // row-major m x n -> column-major (ld m), 64 x 64 tiles through LDS
@@ -382,52 +407,81 @@ hipError_t gemm_t(bool ta, bool tb, int64_t M, int64_t N, int64_t K, T alpha, co
         return gemm_f32(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bf16, ws, st, 0);
 }
 
+// Q^T of one panel (reflectors Vt, nb x (m - j0); T with leading dimension NBP) applied
+// to the columns [c0, c1): W^T = C^T V, W2^T = W^T T, C^T -= W2^T V^T
+template <typename T>
+hipError_t apply_panel(T* Ac, int64_t m, int64_t j0, int nb, const T* Vt, const T* Tp, int64_t c0,
+                       int64_t c1, T* Wt, T* W2t, bool bf16, GemmWs& g, hipStream_t s) {
+    const int64_t n = c1 - c0;
+    if (n <= 0) return hipSuccess;
+    const int64_t mr = m - j0;
+    T* Ct = Ac + c0 * m + j0;  // the columns as rows, ld = m
+    SKI_HIP(gemm_t<T>(false, true, n, nb, mr, (T)1, Ct, m, Vt, mr, (T)0, Wt, nb, bf16, g, s));
+    SKI_HIP(gemm_t<T>(false, false, n, nb, nb, (T)1, Wt, nb, Tp, NBP, (T)0, W2t, nb, false, g, s));
+    SKI_HIP(gemm_t<T>(false, false, n, mr, nb, (T)-1, W2t, nb, Vt, mr, (T)1, Ct, m, bf16, g, s));
+    return hipSuccess;
+}
+
+// Blocked QR with a look-ahead of one panel: after panel p is factored, its reflectors
+// update the next panel's columns on the caller's stream (so panel p+1 can be factored
+// at once) while the remaining columns are updated on a second stream.  Events keep the
+// order of the updates every column receives: Q_1^T, Q_2^T, ... in sequence.
 template <typename T>
 hipError_t qr_impl(const T* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws, bool bf16,
                    hipStream_t st) {
-    T* Ac = (T*)ws.Ac;      // column-major working copy, ld = m
+    T* Ac = (T*)ws.Ac;  // column-major working copy, ld = m
     T* tau = (T*)ws.tau;
-    T* Tl = (T*)ws.Tl;      // NBL x NBL leaf T
-    T* Tp = (T*)ws.Tp;      // NBP x NBP panel T
-    T* G = (T*)ws.G;        // NBP x NBP Gram matrix
-    T* Vt = (T*)ws.Vt;      // NBP x m explicit reflectors of a panel
-    T* Wt = (T*)ws.Wt;      // ncols x NBP
-    T* W2t = (T*)ws.W2t;    // ncols x NBP
+    T* G = (T*)ws.G;    // NBP x NBP Gram matrix
+    T* Tpb[2] = {(T*)ws.Tp, (T*)ws.Tp2};
+    T* Vtb[2] = {(T*)ws.Vt, (T*)ws.Vt2};
+    hipStream_t s2 = ws.st2;
     hipLaunchKernelGGL((k_to_colmajor<T>),
                        dim3((unsigned)((ncols + 63) / 64), (unsigned)((m + 63) / 64)), dim3(256), 0,
                        st, SA, m, ncols, Ac);
     SKI_HIP(hipGetLastError());
-    for (int64_t j0 = 0; j0 < d; j0 += NBP) {
+    int64_t p = 0;
+    bool pending_rest = false;  // a remaining-columns update is queued on s2 (event evE[(p-1)&1])
+    for (int64_t j0 = 0; j0 < d; j0 += NBP, ++p) {
         const int nb = (int)std::min<int64_t>(NBP, d - j0);
+        T* Tp = Tpb[p & 1];
+        T* Vt = Vtb[p & 1];
         for (int jl = 0; jl < nb; jl += NBL) {
             const int64_t jc = j0 + jl;
             const int w = std::min(NBL, nb - jl);
-            SKI_HIP(launch_leaf<T>(Ac, m, jc, w, tau, Tl, st));
+            T* Tdiag = Tp + (int64_t)jl * NBP + jl;  // this leaf's block of the panel T
+            SKI_HIP(launch_leaf<T>(Ac, m, jc, w, tau, Tdiag, st));
             const int nc = nb - jl - w;
-            if (nc > 0) SKI_HIP(launch_narrow<T>(Ac, m, jc, w, Tl, nc, st));
+            if (nc > 0) SKI_HIP(launch_narrow<T>(Ac, m, jc, w, Tdiag, nc, st));
         }
         const int64_t n_rem = ncols - j0 - nb;
-        if (n_rem > 0) {
-            const int64_t mr = m - j0;
-            hipLaunchKernelGGL((k_make_Vt<T>),
-                               dim3((unsigned)std::min<int64_t>((mr + 255) / 256, 64), (unsigned)nb),
-                               dim3(256), 0, st, Ac, m, j0, nb, Vt);
-            SKI_HIP(hipGetLastError());
-            // G = V^T V (= Vt Vt^T), then T from G and the taus
-            SKI_HIP(gemm_t<T>(false, true, nb, nb, mr, (T)1, Vt, mr, Vt, mr, (T)0, G, nb, false,
-                              ws.g, st));
-            hipLaunchKernelGGL((k_form_T<T>), dim3(1), dim3(64), 0, st, G, nb, tau + j0, Tp);
-            SKI_HIP(hipGetLastError());
-            T* Ct = Ac + (j0 + nb) * m + j0;  // trailing columns as rows, ld = m
-            // W^T = C^T V ; W2^T = W^T T ; C^T -= W2^T V^T
-            SKI_HIP(gemm_t<T>(false, true, n_rem, nb, mr, (T)1, Ct, m, Vt, mr, (T)0, Wt, nb, bf16,
-                              ws.g, st));
-            SKI_HIP(gemm_t<T>(false, false, n_rem, nb, nb, (T)1, Wt, nb, Tp, nb, (T)0, W2t, nb,
-                              false, ws.g, st));
-            SKI_HIP(gemm_t<T>(false, false, n_rem, mr, nb, (T)-1, W2t, nb, Vt, mr, (T)1, Ct, m,
-                              bf16, ws.g, st));
+        if (n_rem <= 0) break;
+        const int64_t mr = m - j0;
+        hipLaunchKernelGGL((k_make_Vt<T>),
+                           dim3((unsigned)std::min<int64_t>((mr + 255) / 256, 64), (unsigned)nb),
+                           dim3(256), 0, st, Ac, m, j0, nb, Vt);
+        SKI_HIP(hipGetLastError());
+        // G = V^T V (= Vt Vt^T); T from the leaves' blocks and G
+        SKI_HIP(gemm_t<T>(false, true, nb, nb, mr, (T)1, Vt, mr, Vt, mr, (T)0, G, nb, false, ws.g,
+                          st));
+        hipLaunchKernelGGL((k_form_T<T>), dim3(1), dim3(256), 0, st, G, nb, Tp);
+        SKI_HIP(hipGetLastError());
+        SKI_HIP(hipEventRecord(ws.evF[p & 1], st));
+        const int64_t nx0 = j0 + nb;
+        const int64_t nx1 = std::min<int64_t>(j0 + 2 * NBP, d);  // next panel's columns
+        // the previous panel's remaining-columns update covered the next panel: wait for it
+        if (pending_rest) SKI_HIP(hipStreamWaitEvent(st, ws.evE[(p - 1) & 1], 0));
+        SKI_HIP(apply_panel<T>(Ac, m, j0, nb, Vt, Tp, nx0, nx1, (T*)ws.Wt, (T*)ws.W2t, bf16, ws.g,
+                               st));
+        pending_rest = false;
+        if (nx1 < ncols) {
+            SKI_HIP(hipStreamWaitEvent(s2, ws.evF[p & 1], 0));
+            SKI_HIP(apply_panel<T>(Ac, m, j0, nb, Vt, Tp, nx1, ncols, (T*)ws.Wt2, (T*)ws.W2t2,
+                                   bf16, ws.g2, s2));
+            SKI_HIP(hipEventRecord(ws.evE[p & 1], s2));
+            pending_rest = true;
         }
     }
+    if (pending_rest) SKI_HIP(hipStreamWaitEvent(st, ws.evE[(p - 1) & 1], 0));
     return hipSuccess;
 }
 
@@ -448,9 +502,9 @@ __global__ __launch_bounds__(256) void k_extract_Rc(const T* __restrict__ Ac, in
 size_t qr_ws_bytes(Prec prec, int64_t m, int64_t ncols, size_t* gemm_bytes) {
     const size_t e = prec == Prec::F64 ? 8 : 4;
     *gemm_bytes = gemm_ws_bytes(NBP, NBP, m, e);
-    const size_t pad = 256 * 8;
-    return ((size_t)m * ncols + (size_t)NBP * m + 2 * (size_t)ncols * NBP + NBL * NBL +
-            2 * NBP * NBP + (size_t)ncols) * e + pad;
+    const size_t pad = 16 * 256;
+    return ((size_t)m * ncols + 2 * (size_t)NBP * m + 4 * (size_t)ncols * NBP + 3 * NBP * NBP +
+            (size_t)ncols) * e + pad;
 }
 
 void qr_ws_carve(Prec prec, void* base, int64_t m, int64_t ncols, QrWs& ws) {
@@ -463,10 +517,13 @@ void qr_ws_carve(Prec prec, void* base, int64_t m, int64_t ncols, QrWs& ws) {
     };
     ws.Ac = take((size_t)m * ncols);
     ws.Vt = take((size_t)NBP * m);
+    ws.Vt2 = take((size_t)NBP * m);
     ws.Wt = take((size_t)ncols * NBP);
     ws.W2t = take((size_t)ncols * NBP);
-    ws.Tl = take(NBL * NBL);
+    ws.Wt2 = take((size_t)ncols * NBP);
+    ws.W2t2 = take((size_t)ncols * NBP);
     ws.Tp = take(NBP * NBP);
+    ws.Tp2 = take(NBP * NBP);
     ws.G = take(NBP * NBP);
     ws.tau = take((size_t)ncols);
 }

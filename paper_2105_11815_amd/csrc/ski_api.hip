@@ -48,7 +48,9 @@ struct ski_handle_s {
     DevBuf qr_part, qr_W, qr_T, qr_Y, qr_tau;
     DevBuf tkeys, tkeys_tmp, ttable, tp, tpay, ti, tv;
     DevBuf u, t, v, h, delta, z, wp, g, gpart, upart, y, st, flag;
-    DevBuf cg_r, cg_p, cg_q, t2, dtmp;
+    DevBuf cg_r, cg_p, cg_q, t2, dtmp, gemm_ws2;
+    hipStream_t st2 = nullptr;           // second stream of the QR's look-ahead
+    hipEvent_t qev[4] = {};
     double* hdiag = nullptr;  // pinned host copy of diag(R)
     int64_t hdiag_n = 0;
     hipEvent_t ev[6] = {};
@@ -190,11 +192,14 @@ int ski_destroy(ski_handle h) {
                      &h->qr_Y, &h->qr_tau, &h->tkeys, &h->tkeys_tmp, &h->ttable, &h->tp,
                      &h->tpay, &h->ti, &h->tv, &h->u, &h->t, &h->v, &h->h, &h->delta, &h->z,
                      &h->wp, &h->g, &h->gpart, &h->upart, &h->y, &h->st, &h->flag, &h->cg_r,
-                     &h->cg_p, &h->cg_q, &h->t2, &h->dtmp};
+                     &h->cg_p, &h->cg_q, &h->t2, &h->dtmp, &h->gemm_ws2};
     for (DevBuf* b : all) release(*b);
     if (h->ev_ok)
         for (auto& e : h->ev) (void)hipEventDestroy(e);
     for (auto& e : h->pool) (void)hipEventDestroy(e);
+    for (auto& e : h->qev)
+        if (e) (void)hipEventDestroy(e);
+    if (h->st2) (void)hipStreamDestroy(h->st2);
     if (h->hdiag) (void)hipHostFree(h->hdiag);
     delete h;
     return SKI_OK;
@@ -380,10 +385,23 @@ int ski_factor(ski_handle h, void* stream) {
     SKI_TRY(h, ensure(h->diag_add, d * 8), "alloc");
     SKI_TRY(h, ensure(h->tri_tmp, ((d + 1) / 2 + 64) * ((d + 1) / 2 + 64) * 8), "alloc");
     if (h->ev_ok) (void)hipEventRecord(h->ev[2], st);
+    SKI_TRY(h, ensure(h->gemm_ws2, gws), "alloc");
+    if (!h->st2) {
+        // default priority (no priority argument), non-blocking with respect to stream 0
+        SKI_TRY(h, hipStreamCreateWithFlags(&h->st2, hipStreamNonBlocking), "stream");
+        for (auto& e : h->qev) SKI_TRY(h, hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+    }
     QrWs ws;
     qr_ws_carve(h->qprec, h->qr_part.p, m, ncols, ws);
     ws.g.part = h->gemm_ws.p;
     ws.g.bytes = h->gemm_ws.bytes;
+    ws.g2.part = h->gemm_ws2.p;
+    ws.g2.bytes = h->gemm_ws2.bytes;
+    ws.st2 = h->st2;
+    ws.evF[0] = h->qev[0];
+    ws.evF[1] = h->qev[1];
+    ws.evE[0] = h->qev[2];
+    ws.evE[1] = h->qev[3];
     prof_begin(h, PC_QR, st);
     SKI_TRY(h, qr_factor(h->qprec, h->SA.p, m, ncols, d, ws, st), "qr");
     prof_end(h, st);
