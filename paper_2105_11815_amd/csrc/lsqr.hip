@@ -136,8 +136,26 @@ __global__ __launch_bounds__(TG) void k_tri_gemv(const double* __restrict__ M, i
 }
 
 // ---------------------------------------------------------------------------
-// fused dense pass: u = A z - coef * u_old (in place), g partials and ||u||^2 partials
-template <int CPT>
+// fused dense pass: u = A z - coef * u_old (in place), g partials and ||u||^2 partials.
+// A is streamed once with non-temporal loads (it is not reused before it leaves the
+// caches); with VEC = 2 each lane loads 16-byte column pairs (needs an even lda and a
+// 16-byte aligned A).  One row per step: its dot product is reduced across the
+// workgroup while the next row's loads are in flight; the row stays in registers for
+// g += A[i,:]^T u_i.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
+template <int VEC>
+struct RowT;
+template <>
+struct RowT<1> {
+    using type = double;
+};
+template <>
+struct RowT<2> {
+    using type = dvec2;
+};
+
+template <int CPT, int VEC>
 __global__ __launch_bounds__(256) void k_lsqr_pass(const double* __restrict__ A, int64_t lda,
                                                    int64_t n, int64_t d,
                                                    const double* __restrict__ z,
@@ -146,70 +164,83 @@ __global__ __launch_bounds__(256) void k_lsqr_pass(const double* __restrict__ A,
                                                    int64_t rows_per_wg, double* __restrict__ gpart,
                                                    double* __restrict__ upart, int use_coef_m1) {
     if (stt->done) return;
-    __shared__ double red[2][4][2];
+    using V = typename RowT<VEC>::type;
+    constexpr int H = CPT / VEC;  // vector loads per row per thread
+    __shared__ double red[2][4];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const double coef = use_coef_m1 ? -1.0 : stt->coef;
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
     const int64_t r1 = std::min(n, r0 + rows_per_wg);
-    double zr[CPT], g[CPT], a0[CPT], a1[CPT];
-    double uo0 = 0.0, uo1 = 0.0;  // u_old of the pair in flight, read before any write
+    // thread's columns: VEC consecutive columns starting at VEC * (tid + 256 q), q < H
+    V zr[H], g[H], cur[H], nxt[H];
+    double uo = 0.0, un = 0.0;
 #pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-        const int64_t c = tid + 256 * q;
-        zr[q] = c < d ? z[c] : 0.0;
-        g[q] = 0.0;
+    for (int q = 0; q < H; ++q) {
+        const int64_t c = VEC * (tid + 256 * (int64_t)q);
+        V zv, zero;
+        if constexpr (VEC == 1) {
+            zv = c < d ? z[c] : 0.0;
+            zero = 0.0;
+        } else {
+            zv = dvec2{c < d ? z[c] : 0.0, c + 1 < d ? z[c + 1] : 0.0};
+            zero = dvec2{0.0, 0.0};
+        }
+        zr[q] = zv;
+        g[q] = zero;
     }
+    auto load = [&](V (&dst)[H], double& uu, int64_t r) {
+#pragma unroll
+        for (int q = 0; q < H; ++q) {
+            const int64_t c = VEC * (tid + 256 * (int64_t)q);
+            if constexpr (VEC == 1) {
+                dst[q] = (c < d && r < r1) ? __builtin_nontemporal_load(A + r * lda + c) : 0.0;
+            } else {
+                // d is even on this path, so a pair is either fully inside or fully outside
+                dst[q] = (c < d && r < r1)
+                             ? __builtin_nontemporal_load((const dvec2*)(A + r * lda + c))
+                             : dvec2{0.0, 0.0};
+            }
+        }
+        uu = r < r1 ? u[r] : 0.0;
+    };
     double usq = 0.0;
     int buf = 0;
-    auto load2 = [&](int64_t r) {
+    if (r0 < r1) load(cur, uo, r0);
+    for (int64_t r = r0; r < r1; ++r) {
+        if (r + 1 < r1) load(nxt, un, r + 1);
+        double p = 0.0;
 #pragma unroll
-        for (int q = 0; q < CPT; ++q) {
-            const int64_t c = tid + 256 * q;
-            a0[q] = (c < d && r < r1) ? A[r * lda + c] : 0.0;
-            a1[q] = (c < d && r + 1 < r1) ? A[(r + 1) * lda + c] : 0.0;
+        for (int q = 0; q < H; ++q) {
+            if constexpr (VEC == 1)
+                p += cur[q] * zr[q];
+            else
+                p += cur[q].x * zr[q].x + cur[q].y * zr[q].y;
         }
-        uo0 = r < r1 ? u[r] : 0.0;
-        uo1 = r + 1 < r1 ? u[r + 1] : 0.0;
-    };
-    if (r0 < r1) load2(r0);
-    for (int64_t r = r0; r < r1; r += 2) {
-        double p0 = 0.0, p1 = 0.0;
-#pragma unroll
-        for (int q = 0; q < CPT; ++q) {
-            p0 += a0[q] * zr[q];
-            p1 += a1[q] * zr[q];
-        }
-        p0 = wave_sum(p0);
-        p1 = wave_sum(p1);
-        if (lane == 0) {
-            red[buf][wv][0] = p0;
-            red[buf][wv][1] = p1;
-        }
+        p = wave_sum(p);
+        if (lane == 0) red[buf][wv] = p;
         __syncthreads();
-        const double d0 = (red[buf][0][0] + red[buf][1][0]) + (red[buf][2][0] + red[buf][3][0]);
-        const double d1 = (red[buf][0][1] + red[buf][1][1]) + (red[buf][2][1] + red[buf][3][1]);
-        const double u0 = d0 - coef * uo0;
-        const double u1 = (r + 1 < r1) ? d1 - coef * uo1 : 0.0;
-        double b0[CPT], b1[CPT];
+        const double dt = (red[buf][0] + red[buf][1]) + (red[buf][2] + red[buf][3]);
+        const double u0 = dt - coef * uo;
 #pragma unroll
-        for (int q = 0; q < CPT; ++q) {
-            b0[q] = a0[q];
-            b1[q] = a1[q];
-        }
-        if (r + 2 < r1) load2(r + 2);
-#pragma unroll
-        for (int q = 0; q < CPT; ++q) g[q] += b0[q] * u0 + b1[q] * u1;
+        for (int q = 0; q < H; ++q) g[q] += cur[q] * u0;
         if (tid == 0) {
             u[r] = u0;
-            if (r + 1 < r1) u[r + 1] = u1;
-            usq += u0 * u0 + u1 * u1;
+            usq += u0 * u0;
         }
+#pragma unroll
+        for (int q = 0; q < H; ++q) cur[q] = nxt[q];
+        uo = un;
         buf ^= 1;
     }
 #pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-        const int64_t c = tid + 256 * q;
-        if (c < d) gpart[(int64_t)blockIdx.x * d + c] = g[q];
+    for (int q = 0; q < H; ++q) {
+        const int64_t c = VEC * (tid + 256 * (int64_t)q);
+        if constexpr (VEC == 1) {
+            if (c < d) gpart[(int64_t)blockIdx.x * d + c] = g[q];
+        } else {
+            if (c < d) gpart[(int64_t)blockIdx.x * d + c] = g[q].x;
+            if (c + 1 < d) gpart[(int64_t)blockIdx.x * d + c + 1] = g[q].y;
+        }
     }
     if (tid == 0) upart[blockIdx.x] = usq;
 }
@@ -660,20 +691,33 @@ int lsqr_pass_cpt(int64_t d) {
 hipError_t launch_pass_kernel(const double* A, int64_t lda, int64_t n, int64_t d, const double* z,
                               double* u, const LsqrState* stt, int64_t G, double* gpart,
                               double* upart, bool coef_m1, hipStream_t st) {
-    const int64_t rpw = (((n + G - 1) / G) + 1) / 2 * 2;
+    const int64_t rpw = (n + G - 1) / G;
     const int cpt = lsqr_pass_cpt(d);
-#define SKI_PASS(C)                                                                             \
-    hipLaunchKernelGGL((k_lsqr_pass<C>), dim3((unsigned)G), dim3(256), 0, st, A, lda, n, d, z, u, \
-                       stt, rpw, gpart, upart, coef_m1 ? 1 : 0)
-    switch (cpt) {
-        case 1: SKI_PASS(1); break;
-        case 2: SKI_PASS(2); break;
-        case 4: SKI_PASS(4); break;
-        case 8: SKI_PASS(8); break;
-        case 16: SKI_PASS(16); break;
-        case 24: SKI_PASS(24); break;
-        case 32: SKI_PASS(32); break;
-        default: return hipErrorInvalidValue;
+    const bool vec2 = (lda % 2 == 0) && (d % 2 == 0) && (((uintptr_t)A & 15) == 0) && cpt >= 2;
+#define SKI_PASS(C, VV)                                                                            \
+    hipLaunchKernelGGL((k_lsqr_pass<C, VV>), dim3((unsigned)G), dim3(256), 0, st, A, lda, n, d, z, \
+                       u, stt, rpw, gpart, upart, coef_m1 ? 1 : 0)
+    if (vec2) {
+        switch (cpt) {
+            case 2: SKI_PASS(2, 2); break;
+            case 4: SKI_PASS(4, 2); break;
+            case 8: SKI_PASS(8, 2); break;
+            case 16: SKI_PASS(16, 2); break;
+            case 24: SKI_PASS(24, 2); break;
+            case 32: SKI_PASS(32, 2); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (cpt) {
+            case 1: SKI_PASS(1, 1); break;
+            case 2: SKI_PASS(2, 1); break;
+            case 4: SKI_PASS(4, 1); break;
+            case 8: SKI_PASS(8, 1); break;
+            case 16: SKI_PASS(16, 1); break;
+            case 24: SKI_PASS(24, 1); break;
+            case 32: SKI_PASS(32, 1); break;
+            default: return hipErrorInvalidValue;
+        }
     }
 #undef SKI_PASS
     return hipGetLastError();
