@@ -27,9 +27,10 @@ namespace ski {
 
 namespace {
 
-constexpr int NBL = 4;    // leaf width
-constexpr int LT = 512;   // leaf threads
-constexpr int NBP = 64;   // outer panel width
+constexpr int NBL = 4;     // leaf width
+constexpr int LFT = 512;   // leaf threads
+constexpr int LT = 512;    // threads of the narrow update
+constexpr int NBP = 64;    // outer panel width
 
 // block reduction of N values over a workgroup of NT threads, in a fixed order
 template <typename T, int N, int NT>
@@ -50,21 +51,20 @@ __device__ __forceinline__ void block_reduce(T (&v)[N], T (*sh)[N], int tid) {
 }
 
 // leaf: factor columns [jc, jc+w) over rows [jc, m) of the column-major matrix (ld = m);
-// taus -> tau[jc..], the leaf's T (w x w) -> Tl, the leaf's diagonal block of the panel T
-// (row-major, leading dimension NBP)
+// taus -> tau[jc..], the leaf's T (w x w, zero-padded to NBL x NBL, row-major) -> Tl
 template <typename T, int RPT>
-__global__ __launch_bounds__(LT) void k_qr_leaf(T* __restrict__ Ac, int64_t m, int64_t jc, int w,
+__global__ __launch_bounds__(LFT) void k_qr_leaf(T* __restrict__ Ac, int64_t m, int64_t jc, int w,
                                                 T* __restrict__ tau, T* __restrict__ Tl) {
-    __shared__ T red[2][LT / 64][NBL];
+    __shared__ T red[2][LFT / 64][NBL];
     __shared__ T rowb[2][NBL];
-    __shared__ T gsh[LT / 64][NBL * NBL];
+    __shared__ T gsh[LFT / 64][NBL * NBL];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t mrem = m - jc;
     T* base = Ac + jc * m + jc;  // element (r, c) of the leaf at base[c * m + r]
     T P[RPT][NBL];
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
-        const int64_t r = tid + (int64_t)LT * u;
+        const int64_t r = tid + (int64_t)LFT * u;
 #pragma unroll
         for (int c = 0; c < NBL; ++c) P[u][c] = (r < mrem && c < w) ? base[c * m + r] : (T)0;
     }
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(LT) void k_qr_leaf(T* __restrict__ Ac, int64_t m, i
         for (int c = 0; c < NBL; ++c) s[c] = 0;
 #pragma unroll
         for (int u = 0; u < RPT; ++u) {
-            const int64_t r = tid + (int64_t)LT * u;
+            const int64_t r = tid + (int64_t)LFT * u;
             if (r > jj && r < mrem) {
 #pragma unroll
                 for (int c = 0; c < NBL; ++c)
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(LT) void k_qr_leaf(T* __restrict__ Ac, int64_t m, i
         for (int c = 0; c < NBL; ++c) {
             T a = 0;
             if (c >= jj)
-                for (int q = 0; q < LT / 64; ++q) a += red[buf][q][c];
+                for (int q = 0; q < LFT / 64; ++q) a += red[buf][q][c];
             tot[c] = a;
         }
         const T alpha = rowb[buf][jj];
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(LT) void k_qr_leaf(T* __restrict__ Ac, int64_t m, i
         for (int c = 0; c < NBL; ++c) wc[c] = (c > jj) ? rowb[buf][c] + tot[c] * scal : (T)0;
 #pragma unroll
         for (int u = 0; u < RPT; ++u) {
-            const int64_t r = tid + (int64_t)LT * u;
+            const int64_t r = tid + (int64_t)LFT * u;
             if (r > jj && r < mrem) {
                 const T v = P[u][jj] * scal;
 #pragma unroll
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(LT) void k_qr_leaf(T* __restrict__ Ac, int64_t m, i
     // write back R (upper) and the reflectors (below the diagonal)
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
-        const int64_t r = tid + (int64_t)LT * u;
+        const int64_t r = tid + (int64_t)LFT * u;
         if (r < mrem)
 #pragma unroll
             for (int c = 0; c < NBL; ++c)
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(LT) void k_qr_leaf(T* __restrict__ Ac, int64_t m, i
     for (int q = 0; q < NBL * NBL; ++q) g[q] = 0;
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
-        const int64_t r = tid + (int64_t)LT * u;
+        const int64_t r = tid + (int64_t)LFT * u;
         if (r < mrem) {
             T v[NBL];
 #pragma unroll
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(LT) void k_qr_leaf(T* __restrict__ Ac, int64_t m, i
             T a = 0;
             const int qa = q / NBL, qb = q % NBL;
             if (qa < qb)
-                for (int wq = 0; wq < LT / 64; ++wq) a += gsh[wq][q];
+                for (int wq = 0; wq < LFT / 64; ++wq) a += gsh[wq][q];
             G[q] = a;
             Tm[q] = 0;
         }
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(LT) void k_qr_leaf(T* __restrict__ Ac, int64_t m, i
         for (int a = 0; a < NBL; ++a)
 #pragma unroll
             for (int b = 0; b < NBL; ++b)
-                if (a < w && b < w) Tl[a * NBP + b] = Tm[a * NBL + b];
+                Tl[a * NBL + b] = Tm[a * NBL + b];
     }
 }
 
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(LT) void k_narrow_apply(T* __restrict__ Ac, int64_t
         T s = 0;
 #pragma unroll
         for (int b = 0; b < NBL; ++b)
-            if (b <= a && a < w) s += Tl[b * NBP + a] * acc[b];
+            if (b <= a && a < w) s += Tl[b * NBL + a] * acc[b];
         w2[a] = s;
     }
 #pragma unroll
@@ -263,63 +263,47 @@ __global__ __launch_bounds__(LT) void k_narrow_apply(T* __restrict__ Ac, int64_t
     }
 }
 
-// explicit V^T of a panel: Vt[c][r] = v_c[r] over rows r in [0, mr) from row j0
+// [V^T; C_next^T] of a panel: rows c < nb hold the explicit reflectors v_c (unit diagonal,
+// zeros above), rows nb + c hold the next panel's column nx0 + c, all over the rows
+// [j0, m) of the matrix (leading dimension mr = m - j0)
 template <typename T>
-__global__ __launch_bounds__(256) void k_make_Vt(const T* __restrict__ Ac, int64_t m, int64_t j0,
-                                                 int nb, T* __restrict__ Vt) {
+__global__ __launch_bounds__(256) void k_make_VC(const T* __restrict__ Ac, int64_t m, int64_t j0,
+                                                 int nb, int64_t nx0, T* __restrict__ VC) {
     const int64_t mr = m - j0;
     const int c = blockIdx.y;
-    const T* col = Ac + (j0 + c) * m + j0;
+    const bool isv = c < nb;
+    const T* col = isv ? Ac + (j0 + c) * m + j0 : Ac + (nx0 + (c - nb)) * m + j0;
     for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < mr; r += (int64_t)gridDim.x * 256)
-        Vt[c * mr + r] = r < c ? (T)0 : (r == c ? (T)1 : col[r]);
+        VC[c * mr + r] = isv ? (r < c ? (T)0 : (r == c ? (T)1 : col[r])) : col[r];
 }
 
-// T of a panel: the leaves left their w x w blocks on the diagonal of Tp (ld NBP); blocks
-// are merged pairwise, level by level, with T12 = -T1 (V1^T V2) T2, where V1^T V2 is the
-// corresponding block of G = V^T V (nb x nb, ld nb).
+// W2^T = W^T T for the panel's T without forming T: T^-1 = diag(1/tau) + striu(V^T V), so
+// each row x of W2^T solves x T^-1 = w, i.e. x_j = tau_j (w_j - sum_{i<j} x_i G_ij); a
+// reflector with tau = 0 (the identity) contributes x_j = 0.  One thread per row.
 template <typename T>
-__global__ __launch_bounds__(256) void k_form_T(const T* __restrict__ G, int nb,
-                                                T* __restrict__ Tp) {
+__global__ __launch_bounds__(256) void k_apply_Tinv(const T* __restrict__ Wt, int64_t n, int nb,
+                                                    const T* __restrict__ G, int ldg,
+                                                    const T* __restrict__ tau,
+                                                    T* __restrict__ W2t) {
     __shared__ T Gs[NBP * NBP];
-    __shared__ T Ts[NBP * NBP];
-    __shared__ T Xs[NBP * NBP];
-    const int tid = threadIdx.x;
-    for (int o = tid; o < nb * nb; o += 256) {
-        const int a = o / nb, b = o - a * nb;
-        Gs[o] = G[o];
-        // keep only the leaves' diagonal blocks
-        Ts[o] = (a / NBL == b / NBL) ? Tp[a * NBP + b] : (T)0;
-    }
+    __shared__ T ts[NBP];
+    for (int o = threadIdx.x; o < nb * nb; o += 256) Gs[o] = G[(o / nb) * ldg + (o % nb)];
+    for (int o = threadIdx.x; o < nb; o += 256) ts[o] = tau[o];
     __syncthreads();
-    for (int bs = NBL; bs < nb; bs *= 2) {
-        // pairs at offsets o = 2 bs q: T1 = [o, o+bs), T2 = [o+bs, min(o+2bs, nb))
-        // X = G12 T2 (bs x n2), then T12 = -T1 X
-        for (int e = tid; e < nb * nb; e += 256) {
-            const int i = e / nb, j = e - i * nb;
-            const int o = (i / (2 * bs)) * 2 * bs;
-            const int o2 = o + bs;
-            if (i < o2 && j >= o2 && j < std::min(o + 2 * bs, nb)) {
-                T x = 0;
-                for (int t = o2; t <= j; ++t) x += Gs[i * nb + t] * Ts[t * nb + j];
-                Xs[e] = x;
-            }
+    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (row >= n) return;
+    const T* w = Wt + row * nb;
+    T* x = W2t + row * nb;
+    T xs[NBP];
+#pragma unroll
+    for (int j = 0; j < NBP; ++j) {
+        if (j < nb) {
+            T sacc = w[j];
+#pragma unroll
+            for (int i = 0; i < j; ++i) sacc -= xs[i] * Gs[i * nb + j];
+            xs[j] = ts[j] * sacc;
+            x[j] = xs[j];
         }
-        __syncthreads();
-        for (int e = tid; e < nb * nb; e += 256) {
-            const int i = e / nb, j = e - i * nb;
-            const int o = (i / (2 * bs)) * 2 * bs;
-            const int o2 = o + bs;
-            if (i < o2 && j >= o2 && j < std::min(o + 2 * bs, nb)) {
-                T y = 0;
-                for (int t = i; t < o2; ++t) y += Ts[i * nb + t] * Xs[t * nb + j];
-                Ts[e] = -y;
-            }
-        }
-        __syncthreads();
-    }
-    for (int o = tid; o < nb * nb; o += 256) {
-        const int a = o / nb, b = o - a * nb;
-        Tp[a * NBP + b] = Ts[o];
     }
 }
 
@@ -343,12 +327,12 @@ __global__ __launch_bounds__(256) void k_to_colmajor(const T* __restrict__ A, in
 
 template <typename T, int RPT>
 void leaf_launch(T* Ac, int64_t m, int64_t jc, int w, T* tau, T* Tl, hipStream_t st) {
-    hipLaunchKernelGGL((k_qr_leaf<T, RPT>), dim3(1), dim3(LT), 0, st, Ac, m, jc, w, tau, Tl);
+    hipLaunchKernelGGL((k_qr_leaf<T, RPT>), dim3(1), dim3(LFT), 0, st, Ac, m, jc, w, tau, Tl);
 }
 
 template <typename T>
 hipError_t launch_leaf(T* Ac, int64_t m, int64_t jc, int w, T* tau, T* Tl, hipStream_t st) {
-    const int64_t rpt = (m - jc + LT - 1) / LT;
+    const int64_t rpt = (m - jc + LFT - 1) / LFT;
     if (rpt <= 1)
         leaf_launch<T, 1>(Ac, m, jc, w, tau, Tl, st);
     else if (rpt <= 2)
@@ -407,76 +391,78 @@ hipError_t gemm_t(bool ta, bool tb, int64_t M, int64_t N, int64_t K, T alpha, co
         return gemm_f32(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bf16, ws, st, 0);
 }
 
-// Q^T of one panel (reflectors Vt, nb x (m - j0); T with leading dimension NBP) applied
-// to the columns [c0, c1): W^T = C^T V, W2^T = W^T T, C^T -= W2^T V^T
 template <typename T>
-hipError_t apply_panel(T* Ac, int64_t m, int64_t j0, int nb, const T* Vt, const T* Tp, int64_t c0,
-                       int64_t c1, T* Wt, T* W2t, bool bf16, GemmWs& g, hipStream_t s) {
-    const int64_t n = c1 - c0;
+hipError_t launch_Tinv(const T* Wt, int64_t n, int nb, const T* G, int ldg, const T* tau, T* W2t,
+                       hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    const int64_t mr = m - j0;
-    T* Ct = Ac + c0 * m + j0;  // the columns as rows, ld = m
-    SKI_HIP(gemm_t<T>(false, true, n, nb, mr, (T)1, Ct, m, Vt, mr, (T)0, Wt, nb, bf16, g, s));
-    SKI_HIP(gemm_t<T>(false, false, n, nb, nb, (T)1, Wt, nb, Tp, NBP, (T)0, W2t, nb, false, g, s));
-    SKI_HIP(gemm_t<T>(false, false, n, mr, nb, (T)-1, W2t, nb, Vt, mr, (T)1, Ct, m, bf16, g, s));
-    return hipSuccess;
+    hipLaunchKernelGGL((k_apply_Tinv<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Wt, n,
+                       nb, G, ldg, tau, W2t);
+    return hipGetLastError();
 }
 
-// Blocked QR with a look-ahead of one panel: after panel p is factored, its reflectors
-// update the next panel's columns on the caller's stream (so panel p+1 can be factored
-// at once) while the remaining columns are updated on a second stream.  Events keep the
-// order of the updates every column receives: Q_1^T, Q_2^T, ... in sequence.
+// Blocked QR with a look-ahead of one panel.  After panel p is factored, one GEMM gives
+// both V^T V (for T) and V^T C of the next panel's columns; those columns are updated on
+// the caller's stream, so panel p+1 can be factored at once, while the remaining columns
+// are updated on a second stream.  Events keep the order of the updates that every
+// column receives (Q_1^T, Q_2^T, ... in sequence).
 template <typename T>
 hipError_t qr_impl(const T* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws, bool bf16,
                    hipStream_t st) {
     T* Ac = (T*)ws.Ac;  // column-major working copy, ld = m
     T* tau = (T*)ws.tau;
-    T* G = (T*)ws.G;    // NBP x NBP Gram matrix
-    T* Tpb[2] = {(T*)ws.Tp, (T*)ws.Tp2};
-    T* Vtb[2] = {(T*)ws.Vt, (T*)ws.Vt2};
+    T* Tl = (T*)ws.Tl;
+    T* VCb[2] = {(T*)ws.Vt, (T*)ws.Vt2};  // [V^T; C_next^T], 2 NBP x m each
+    T* GWb[2] = {(T*)ws.Tp, (T*)ws.Tp2};  // [V^T V; W_next^T], 2 NBP x NBP each
     hipStream_t s2 = ws.st2;
     hipLaunchKernelGGL((k_to_colmajor<T>),
                        dim3((unsigned)((ncols + 63) / 64), (unsigned)((m + 63) / 64)), dim3(256), 0,
                        st, SA, m, ncols, Ac);
     SKI_HIP(hipGetLastError());
     int64_t p = 0;
-    bool pending_rest = false;  // a remaining-columns update is queued on s2 (event evE[(p-1)&1])
+    bool pending_rest = false;  // a remaining-columns update is queued on s2
     for (int64_t j0 = 0; j0 < d; j0 += NBP, ++p) {
         const int nb = (int)std::min<int64_t>(NBP, d - j0);
-        T* Tp = Tpb[p & 1];
-        T* Vt = Vtb[p & 1];
+        T* VC = VCb[p & 1];
+        T* GW = GWb[p & 1];
         for (int jl = 0; jl < nb; jl += NBL) {
             const int64_t jc = j0 + jl;
             const int w = std::min(NBL, nb - jl);
-            T* Tdiag = Tp + (int64_t)jl * NBP + jl;  // this leaf's block of the panel T
-            SKI_HIP(launch_leaf<T>(Ac, m, jc, w, tau, Tdiag, st));
+            SKI_HIP(launch_leaf<T>(Ac, m, jc, w, tau, Tl, st));
             const int nc = nb - jl - w;
-            if (nc > 0) SKI_HIP(launch_narrow<T>(Ac, m, jc, w, Tdiag, nc, st));
+            if (nc > 0) SKI_HIP(launch_narrow<T>(Ac, m, jc, w, Tl, nc, st));
         }
-        const int64_t n_rem = ncols - j0 - nb;
-        if (n_rem <= 0) break;
+        if (ncols - j0 - nb <= 0) break;
         const int64_t mr = m - j0;
-        hipLaunchKernelGGL((k_make_Vt<T>),
-                           dim3((unsigned)std::min<int64_t>((mr + 255) / 256, 64), (unsigned)nb),
-                           dim3(256), 0, st, Ac, m, j0, nb, Vt);
-        SKI_HIP(hipGetLastError());
-        // G = V^T V (= Vt Vt^T); T from the leaves' blocks and G
-        SKI_HIP(gemm_t<T>(false, true, nb, nb, mr, (T)1, Vt, mr, Vt, mr, (T)0, G, nb, false, ws.g,
-                          st));
-        hipLaunchKernelGGL((k_form_T<T>), dim3(1), dim3(256), 0, st, G, nb, Tp);
-        SKI_HIP(hipGetLastError());
-        SKI_HIP(hipEventRecord(ws.evF[p & 1], st));
         const int64_t nx0 = j0 + nb;
         const int64_t nx1 = std::min<int64_t>(j0 + 2 * NBP, d);  // next panel's columns
+        const int ncn = (int)std::max<int64_t>(0, nx1 - nx0);
         // the previous panel's remaining-columns update covered the next panel: wait for it
         if (pending_rest) SKI_HIP(hipStreamWaitEvent(st, ws.evE[(p - 1) & 1], 0));
-        SKI_HIP(apply_panel<T>(Ac, m, j0, nb, Vt, Tp, nx0, nx1, (T*)ws.Wt, (T*)ws.W2t, bf16, ws.g,
-                               st));
         pending_rest = false;
+        hipLaunchKernelGGL((k_make_VC<T>),
+                           dim3((unsigned)std::min<int64_t>((mr + 255) / 256, 64),
+                                (unsigned)(nb + ncn)),
+                           dim3(256), 0, st, Ac, m, j0, nb, nx0, VC);
+        SKI_HIP(hipGetLastError());
+        // [V^T V; W_next^T] = [V^T; C_next^T] V
+        SKI_HIP(gemm_t<T>(false, true, nb + ncn, nb, mr, (T)1, VC, mr, VC, mr, (T)0, GW, nb,
+                          false, ws.g, st));
+        SKI_HIP(hipEventRecord(ws.evF[p & 1], st));
+        if (ncn > 0) {
+            T* W2n = (T*)ws.W2t;
+            SKI_HIP(launch_Tinv<T>(GW + (int64_t)nb * nb, ncn, nb, GW, nb, tau + j0, W2n, st));
+            SKI_HIP(gemm_t<T>(false, false, ncn, mr, nb, (T)-1, W2n, nb, VC, mr, (T)1,
+                              Ac + nx0 * m + j0, m, bf16, ws.g, st));
+        }
         if (nx1 < ncols) {
+            const int64_t nrest = ncols - nx1;
+            T* Ct = Ac + nx1 * m + j0;
             SKI_HIP(hipStreamWaitEvent(s2, ws.evF[p & 1], 0));
-            SKI_HIP(apply_panel<T>(Ac, m, j0, nb, Vt, Tp, nx1, ncols, (T*)ws.Wt2, (T*)ws.W2t2,
-                                   bf16, ws.g2, s2));
+            SKI_HIP(gemm_t<T>(false, true, nrest, nb, mr, (T)1, Ct, m, VC, mr, (T)0, (T*)ws.Wt2,
+                              nb, bf16, ws.g2, s2));
+            SKI_HIP(launch_Tinv<T>((T*)ws.Wt2, nrest, nb, GW, nb, tau + j0, (T*)ws.W2t2, s2));
+            SKI_HIP(gemm_t<T>(false, false, nrest, mr, nb, (T)-1, (T*)ws.W2t2, nb, VC, mr, (T)1,
+                              Ct, m, bf16, ws.g2, s2));
             SKI_HIP(hipEventRecord(ws.evE[p & 1], s2));
             pending_rest = true;
         }
@@ -501,10 +487,10 @@ __global__ __launch_bounds__(256) void k_extract_Rc(const T* __restrict__ Ac, in
 
 size_t qr_ws_bytes(Prec prec, int64_t m, int64_t ncols, size_t* gemm_bytes) {
     const size_t e = prec == Prec::F64 ? 8 : 4;
-    *gemm_bytes = gemm_ws_bytes(NBP, NBP, m, e);
+    *gemm_bytes = gemm_ws_bytes(2 * NBP, NBP, m, e);
     const size_t pad = 16 * 256;
-    return ((size_t)m * ncols + 2 * (size_t)NBP * m + 4 * (size_t)ncols * NBP + 3 * NBP * NBP +
-            (size_t)ncols) * e + pad;
+    return ((size_t)m * ncols + 4 * (size_t)NBP * m + 3 * (size_t)ncols * NBP +
+            4 * NBP * NBP + NBL * NBL + (size_t)ncols) * e + pad;
 }
 
 void qr_ws_carve(Prec prec, void* base, int64_t m, int64_t ncols, QrWs& ws) {
@@ -516,15 +502,14 @@ void qr_ws_carve(Prec prec, void* base, int64_t m, int64_t ncols, QrWs& ws) {
         return q;
     };
     ws.Ac = take((size_t)m * ncols);
-    ws.Vt = take((size_t)NBP * m);
-    ws.Vt2 = take((size_t)NBP * m);
-    ws.Wt = take((size_t)ncols * NBP);
-    ws.W2t = take((size_t)ncols * NBP);
-    ws.Wt2 = take((size_t)ncols * NBP);
+    ws.Vt = take(2 * (size_t)NBP * m);   // [V^T; C_next^T], two alternating
+    ws.Vt2 = take(2 * (size_t)NBP * m);
+    ws.W2t = take((size_t)NBP * NBP);    // look-ahead product
+    ws.Wt2 = take((size_t)ncols * NBP);  // remaining-columns products
     ws.W2t2 = take((size_t)ncols * NBP);
-    ws.Tp = take(NBP * NBP);
-    ws.Tp2 = take(NBP * NBP);
-    ws.G = take(NBP * NBP);
+    ws.Tp = take(2 * NBP * NBP);         // [V^T V; W_next^T], two alternating
+    ws.Tp2 = take(2 * NBP * NBP);
+    ws.Tl = take(NBL * NBL);
     ws.tau = take((size_t)ncols);
 }
 

@@ -162,20 +162,20 @@ size_t gemm_ws_bytes(int64_t M, int64_t N, int64_t K, size_t elem);
 // Householder QR of the m x (d+k) sketch on a column-major working copy
 struct QrWs {
     void* Ac = nullptr;   // column-major copy of the sketch (ld = m), factored in place
-    void* Vt = nullptr;   // explicit reflectors of a panel, transposed (two, alternating)
+    void* Vt = nullptr;   // [V^T; C_next^T] of a panel, explicit reflectors (two, alternating)
     void* Vt2 = nullptr;
     void* Wt = nullptr;   // products of the look-ahead update (caller's stream)
     void* W2t = nullptr;
     void* Wt2 = nullptr;  // products of the remaining-columns update (second stream)
     void* W2t2 = nullptr;
-    void* Tp = nullptr;   // panel T (two, alternating)
+    void* Tp = nullptr;   // [V^T V; W_next^T] of a panel (two, alternating)
     void* Tp2 = nullptr;
-    void* G = nullptr;
+    void* Tl = nullptr;   // the current leaf's T
     void* tau = nullptr;
     GemmWs g;             // split-K partials, caller's stream
     GemmWs g2;            // split-K partials, second stream
     hipStream_t st2 = nullptr;
-    hipEvent_t evF[2] = {nullptr, nullptr};  // panel factored (reflectors ready)
+    hipEvent_t evF[2] = {nullptr, nullptr};  // panel's V^T V and reflectors ready
     hipEvent_t evE[2] = {nullptr, nullptr};  // remaining-columns update done
 };
 size_t qr_ws_bytes(Prec prec, int64_t m, int64_t ncols, size_t* gemm_bytes);
