@@ -56,6 +56,7 @@ enum ski_status {
 enum ski_kind { SKI_DENSE = 0, SKI_CSR = 2 };
 enum ski_prec { SKI_FP64 = 0, SKI_FP32 = 1, SKI_BF16 = 2 };
 enum ski_op { SKI_OP_LLS = 0, SKI_OP_NORMAL = 1 };
+enum ski_qr_panel { SKI_QR_AUTO = 0, SKI_QR_HOUSEHOLDER = 1 };
 
 /* The data matrix.  Dense: `a` (n x d, row-major, leading dimension lda >= d).
  * CSR: row_ptr[n+1] (int64, row_ptr[0] = 0), col[nnz] (int32 in [0, d), distinct
@@ -86,7 +87,14 @@ typedef struct {
  *   it_max       LSQR iteration limit.
  *   rcond        rank guard |r_qq| >= rcond |r_11| (0 disables); failure -> SKI_ERANK.
  *   rcond_thres, perturb  if max|r_ii|/min|r_ii| >= 1/rcond_thres and perturb > 0,
- *                every division by r_ii becomes a division by r_ii + copysign(perturb, r_ii). */
+ *                every division by r_ii becomes a division by r_ii + copysign(perturb, r_ii).
+ *   qr_panel     how each 64-column panel of the Householder QR is factored:
+ *                SKI_QR_AUTO (default): CholeskyQR2 of the panel, with the Householder
+ *                vectors reconstructed from its orthonormal factor; if any panel is too
+ *                ill-conditioned for that (checked on the device), the whole factorisation
+ *                is repeated with the column-by-column panel.  SKI_QR_HOUSEHOLDER: the
+ *                column-by-column panel only.  Both give the same R up to rounding.
+ *   reserved     must be 0. */
 typedef struct {
     double gamma;
     int64_t m;
@@ -101,6 +109,8 @@ typedef struct {
     double rcond;
     double rcond_thres;
     double perturb;
+    int32_t qr_panel;
+    int32_t reserved;
 } ski_params;
 
 /* Per right-hand side result of ski_solve. */

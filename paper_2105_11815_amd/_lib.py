@@ -24,7 +24,7 @@ EXPORTED = ["ski_create", "ski_destroy", "ski_params_default", "ski_sketch", "sk
             "ski_get_dsign", "ski_get_SA", "ski_get_R", "ski_set_profiling", "ski_get_profile"]
 PROF_CLASSES = 16
 PROF_NAMES = ["lsqr_pass", "pass_reduce", "tri_gemv", "spmv_csr", "spmv_csrT", "lsqr_step",
-              "hash", "wht", "gather", "qr", "trtri"]
+              "hash", "wht", "gather", "qr", "trtri", "qr_householder"]
 
 
 class SkiMatrix(C.Structure):
@@ -39,7 +39,7 @@ class SkiParams(C.Structure):
                 ("hadamard", C.c_int32), ("seed", C.c_uint64), ("sketch_prec", C.c_int32),
                 ("qr_prec", C.c_int32), ("tau_a", C.c_double), ("tau_r", C.c_double),
                 ("it_max", C.c_int64), ("rcond", C.c_double), ("rcond_thres", C.c_double),
-                ("perturb", C.c_double)]
+                ("perturb", C.c_double), ("qr_panel", C.c_int32), ("reserved", C.c_int32)]
 
 
 class SkiInfo(C.Structure):

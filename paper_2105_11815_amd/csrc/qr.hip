@@ -400,6 +400,18 @@ hipError_t launch_Tinv(const T* Wt, int64_t n, int nb, const T* G, int ldg, cons
     return hipGetLastError();
 }
 
+// W2^T = W^T T for rows x nb products: with the CholeskyQR2 panels T is explicit (a GEMM);
+// the column-by-column panel only leaves the taus, so T^-1 = diag(1/tau) + striu(V^T V)
+// is applied row by row.
+template <typename T>
+hipError_t apply_T(const QrWs& ws, const T* Wt, int64_t rows, int nb, const T* G, const T* tau,
+                   const T* Tp, T* W2t, GemmWs& g, hipStream_t s) {
+    if (ws.cqr_panels)
+        return gemm_t<T>(false, false, rows, nb, nb, (T)1, Wt, nb, Tp, NBP, (T)0, W2t, nb, false,
+                         g, s);
+    return launch_Tinv<T>(Wt, rows, nb, G, nb, tau, W2t, s);
+}
+
 // Blocked QR with a look-ahead of one panel.  After panel p is factored, one GEMM gives
 // both V^T V (for T) and V^T C of the next panel's columns; those columns are updated on
 // the caller's stream, so panel p+1 can be factored at once, while the remaining columns
@@ -418,18 +430,24 @@ hipError_t qr_impl(const T* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws, b
                        dim3((unsigned)((ncols + 63) / 64), (unsigned)((m + 63) / 64)), dim3(256), 0,
                        st, SA, m, ncols, Ac);
     SKI_HIP(hipGetLastError());
+    if (ws.cqr_panels) SKI_HIP(cqr_clear_flag(ws.cqr.flag, st));
     int64_t p = 0;
     bool pending_rest = false;  // a remaining-columns update is queued on s2
     for (int64_t j0 = 0; j0 < d; j0 += NBP, ++p) {
         const int nb = (int)std::min<int64_t>(NBP, d - j0);
         T* VC = VCb[p & 1];
         T* GW = GWb[p & 1];
-        for (int jl = 0; jl < nb; jl += NBL) {
-            const int64_t jc = j0 + jl;
-            const int w = std::min(NBL, nb - jl);
-            SKI_HIP(launch_leaf<T>(Ac, m, jc, w, tau, Tl, st));
-            const int nc = nb - jl - w;
-            if (nc > 0) SKI_HIP(launch_narrow<T>(Ac, m, jc, w, Tl, nc, st));
+        T* Tp = (T*)ws.cqr.Tx + (p & 1) * NBP * NBP;  // the panel's T (CholeskyQR2 panels)
+        if (ws.cqr_panels) {
+            SKI_HIP(cqr_panel<T>(Ac, m, j0, nb, ws.cqr, Tp, st));
+        } else {
+            for (int jl = 0; jl < nb; jl += NBL) {
+                const int64_t jc = j0 + jl;
+                const int w = std::min(NBL, nb - jl);
+                SKI_HIP(launch_leaf<T>(Ac, m, jc, w, tau, Tl, st));
+                const int nc = nb - jl - w;
+                if (nc > 0) SKI_HIP(launch_narrow<T>(Ac, m, jc, w, Tl, nc, st));
+            }
         }
         if (ncols - j0 - nb <= 0) break;
         const int64_t mr = m - j0;
@@ -450,7 +468,8 @@ hipError_t qr_impl(const T* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws, b
         SKI_HIP(hipEventRecord(ws.evF[p & 1], st));
         if (ncn > 0) {
             T* W2n = (T*)ws.W2t;
-            SKI_HIP(launch_Tinv<T>(GW + (int64_t)nb * nb, ncn, nb, GW, nb, tau + j0, W2n, st));
+            SKI_HIP(apply_T<T>(ws, GW + (int64_t)nb * nb, ncn, nb, GW, tau + j0, Tp, W2n, ws.g,
+                               st));
             SKI_HIP(gemm_t<T>(false, false, ncn, mr, nb, (T)-1, W2n, nb, VC, mr, (T)1,
                               Ac + nx0 * m + j0, m, bf16, ws.g, st));
         }
@@ -460,7 +479,8 @@ hipError_t qr_impl(const T* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws, b
             SKI_HIP(hipStreamWaitEvent(s2, ws.evF[p & 1], 0));
             SKI_HIP(gemm_t<T>(false, true, nrest, nb, mr, (T)1, Ct, m, VC, mr, (T)0, (T*)ws.Wt2,
                               nb, bf16, ws.g2, s2));
-            SKI_HIP(launch_Tinv<T>((T*)ws.Wt2, nrest, nb, GW, nb, tau + j0, (T*)ws.W2t2, s2));
+            SKI_HIP(apply_T<T>(ws, (T*)ws.Wt2, nrest, nb, GW, tau + j0, Tp, (T*)ws.W2t2, ws.g2,
+                               s2));
             SKI_HIP(gemm_t<T>(false, false, nrest, mr, nb, (T)-1, (T*)ws.W2t2, nb, VC, mr, (T)1,
                               Ct, m, bf16, ws.g2, s2));
             SKI_HIP(hipEventRecord(ws.evE[p & 1], s2));
@@ -489,8 +509,9 @@ size_t qr_ws_bytes(Prec prec, int64_t m, int64_t ncols, size_t* gemm_bytes) {
     const size_t e = prec == Prec::F64 ? 8 : 4;
     *gemm_bytes = gemm_ws_bytes(2 * NBP, NBP, m, e);
     const size_t pad = 16 * 256;
+    const size_t cqr = (size_t)NBP * m + ((size_t)cqr_num_chunks(m) + 6) * NBP * NBP;
     return ((size_t)m * ncols + 4 * (size_t)NBP * m + 3 * (size_t)ncols * NBP +
-            4 * NBP * NBP + NBL * NBL + (size_t)ncols) * e + pad;
+            4 * NBP * NBP + NBL * NBL + (size_t)ncols + cqr) * e + 12 * 256 + pad;
 }
 
 void qr_ws_carve(Prec prec, void* base, int64_t m, int64_t ncols, QrWs& ws) {
@@ -511,6 +532,15 @@ void qr_ws_carve(Prec prec, void* base, int64_t m, int64_t ncols, QrWs& ws) {
     ws.Tp2 = take(2 * NBP * NBP);
     ws.Tl = take(NBL * NBL);
     ws.tau = take((size_t)ncols);
+    ws.cqr.Q1 = take((size_t)NBP * m);
+    ws.cqr.Gp = take((size_t)cqr_num_chunks(m) * NBP * NBP);
+    ws.cqr.G = take(NBP * NBP);
+    ws.cqr.R1 = take(NBP * NBP);
+    ws.cqr.R1i = take(NBP * NBP);
+    ws.cqr.Mx = take(NBP * NBP);
+    ws.cqr.Tx = take(2 * NBP * NBP);
+    ws.cqr.tau = ws.tau;
+    ws.cqr.flag = (int*)take(1);
 }
 
 hipError_t qr_factor(Prec prec, const void* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws,

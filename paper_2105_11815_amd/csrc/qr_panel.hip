@@ -1,0 +1,584 @@
+// Panel factorisation for the blocked Householder QR of the sketch (Step 2 of
+// Algorithm 1), built from wide kernels instead of a column-by-column chain.
+//
+// A panel P (mr x nb, nb <= 64, column-major inside the working copy) is factored by
+// CholeskyQR2 (Yamamoto, Nakatsukasa, Yanagisawa and Fukaya, 2015):
+//   G1 = P^T P,  R1 = chol(G1),  Q1 = P R1^-1,  G2 = Q1^T Q1,  R2 = chol(G2),
+//   R  = R2 R1,  Q = Q1 R2^-1  (orthonormal to working precision).
+// The Householder form of the same factorisation is then recovered from Q by a LU
+// factorisation with sign-chosen pivots (Ballard, Demmel, Grigori, Jacquelin, Knight and
+// Nguyen, "Reconstructing Householder vectors from tall-skinny QR", 2015):
+//   [I; 0] - Q S = V U',  S = diag(s_k) chosen during the elimination so that every pivot
+//   is 1 + |q_kk| >= 1,
+// which gives the unit lower trapezoidal reflectors V, tau_k = U'_kk, and R_h = S R with
+// P = (I - V T V^T) [R_h; 0].  The result is exactly what the column-by-column panel
+// writes (R_h on and above the diagonal, V below it, the taus), so the trailing updates
+// are unchanged.
+//
+// CholeskyQR2 is accurate only while cond(P) stays well below u^-1/2.  Both Cholesky
+// factorisations check their pivots and the second Gram matrix must be close to the
+// identity; any failure sets a flag that the host reads after the factorisation, which
+// then repeats with the column-by-column Householder panel.
+//
+// Kernels per panel: Gram partials on MFMA over 64-row chunks, their fixed-order
+// reduction, the first Cholesky and R1^-1, Q1 = P R1^-1 with the Gram partials of Q1 (MFMA),
+// the reduction, the second Cholesky with the reconstruction and the panel's T, and
+// V2 = Q1(nb:, :) M (MFMA).  The 64 x 64 factorisations are blocked (8 x 8 diagonal
+// blocks, register-resident on one wavefront; the block row and the trailing update on
+// all 256 threads), and the triangular inverses use recursive doubling, so that each
+// runs in a few dozen barrier steps.  All sums have a fixed order: the result is
+// deterministic.  T = U' V1^-T is written out, so the trailing updates apply it as a
+// GEMM.
+#include "ski_internal.h"
+
+namespace ski {
+
+namespace {
+
+constexpr int PB = 64;       // panel width handled
+constexpr int PP = PB + 1;   // LDS pitch of a PB x PB tile
+constexpr int GR = 64;       // rows per workgroup of the Gram / apply / V2 kernels
+constexpr int TB = 8;        // diagonal block of the tile factorisations
+constexpr int RSL = 16;      // slices of the partial-sum reduction
+
+__device__ __forceinline__ double bcast_lane(double x, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                            __builtin_amdgcn_readlane(__double2loint(x), l));
+}
+__device__ __forceinline__ float bcast_lane(float x, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
+// 16x16x4 MFMA: lane l supplies A[l%16][l/16] and B[l/16][l%16] and holds D[row(r, l)][l%16]
+// in accumulator element r (FP64: row 4r + l/16; FP32: row 4(l/16) + r)
+template <typename T>
+struct MF;
+template <>
+struct MF<double> {
+    typedef double A4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ A4 mma(double a, double b, A4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int r, int l) { return 4 * r + (l >> 4); }
+};
+template <>
+struct MF<float> {
+    typedef float A4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ A4 mma(float a, float b, A4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int r, int l) { return 4 * (l >> 4) + r; }
+};
+
+// rows [r0, r1) of an nb-column column-major block -> sh[GR][PP], zero padded
+template <typename T>
+__device__ __forceinline__ void stage_chunk(const T* __restrict__ P, int64_t ldp, int64_t r0,
+                                            int64_t r1, int nb, T (*sh)[PP], int t) {
+    for (int o = t; o < GR * PB; o += 256) {
+        const int rr = o % GR, c = o / GR;
+        sh[rr][c] = (r0 + rr < r1 && c < nb) ? P[c * ldp + r0 + rr] : (T)0;
+    }
+}
+
+// sh[GR][PP] -> rows [r0, r1), columns < nb of a column-major block
+template <typename T>
+__device__ __forceinline__ void store_chunk(T (*sh)[PP], int64_t r0, int64_t r1, int nb,
+                                            T* __restrict__ P, int64_t ldp, int t) {
+    for (int o = t; o < GR * PB; o += 256) {
+        const int rr = o % GR, c = o / GR;
+        if (r0 + rr < r1 && c < nb) P[c * ldp + r0 + rr] = sh[rr][c];
+    }
+}
+
+// Gram partial sh^T sh (PB x PB) of the staged chunk on MFMA: wave w owns the tile row w
+template <typename T>
+__device__ __forceinline__ void chunk_gram(T (*sh)[PP], T* __restrict__ Gp, int t) {
+    using A4 = typename MF<T>::A4;
+    const int l = t & 63, w = t >> 6, li = l & 15, lk = l >> 4;
+    A4 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = (A4){0, 0, 0, 0};
+#pragma unroll 4
+    for (int s = 0; s < GR / 4; ++s) {
+        const T a = sh[4 * s + lk][16 * w + li];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = MF<T>::mma(a, sh[4 * s + lk][16 * q + li], acc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Gp[(16 * w + MF<T>::row(r, l)) * PB + 16 * q + li] = acc[q][r];
+}
+
+// sh <- sh X for the staged chunk and an upper triangular X (PB x PB in Xs) on MFMA;
+// wave w owns the tile row w.  Synchronises before overwriting sh.
+template <typename T>
+__device__ __forceinline__ void chunk_times_upper(T (*sh)[PP], T (*Xs)[PP], int t) {
+    using A4 = typename MF<T>::A4;
+    const int l = t & 63, w = t >> 6, li = l & 15, lk = l >> 4;
+    A4 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = (A4){0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        for (int s = 0; s < 4 * (q + 1); ++s)  // X(k, 16q + j) = 0 for k >= 16 (q + 1)
+            acc[q] = MF<T>::mma(sh[16 * w + li][4 * s + lk], Xs[4 * s + lk][16 * q + li], acc[q]);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sh[16 * w + MF<T>::row(r, l)][16 * q + li] = acc[q][r];
+    __syncthreads();
+}
+
+// Gram partials: workgroup b sums P^T P over the rows [b GR, (b+1) GR) -> Gp[b] (PB x PB)
+template <typename T>
+__global__ __launch_bounds__(256) void k_cqr_gram(const T* __restrict__ P, int64_t ldp, int64_t mr,
+                                                  int nb, T* __restrict__ Gp) {
+    __shared__ T sh[GR][PP];
+    const int t = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * GR, r1 = std::min<int64_t>(mr, r0 + GR);
+    stage_chunk(P, ldp, r0, r1, nb, sh, t);
+    __syncthreads();
+    chunk_gram(sh, Gp + (int64_t)blockIdx.x * PB * PB, t);
+}
+
+// G = sum of the nch partials: slice q of an entry sums the partials q, q + RSL, ... in
+// ascending order, then the slices are added in ascending order
+template <typename T>
+__global__ __launch_bounds__(256) void k_cqr_reduce(const T* __restrict__ Gp, int nch,
+                                                    T* __restrict__ G) {
+    __shared__ T part[RSL][256 / RSL];
+    constexpr int EPB = 256 / RSL;  // entries per workgroup
+    const int t = threadIdx.x, el = t % EPB, sl = t / EPB;
+    const int e = blockIdx.x * EPB + el;
+    T s = 0;
+#pragma unroll 4
+    for (int c = sl; c < nch; c += RSL) s += Gp[(int64_t)c * PB * PB + e];
+    part[sl][el] = s;
+    __syncthreads();
+    if (t < EPB) {
+        T a = 0;
+#pragma unroll
+        for (int q = 0; q < RSL; ++q) a += part[q][t];
+        G[e] = a;
+    }
+}
+
+// ---------------------------------------------------------------- 64 x 64 tile algorithms
+// All are called by the 256 threads of a workgroup and end synchronised.
+
+// X(i, j) = f(i, j) for every entry, through registers (dst may be read by f)
+template <typename T, typename F>
+__device__ __forceinline__ void tile_eval(T (*dst)[PP], int t, F f) {
+    T v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int o = t + 256 * q;
+        v[q] = f(o / PB, o % PB);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int o = t + 256 * q;
+        dst[o / PB][o % PB] = v[q];
+    }
+    __syncthreads();
+}
+
+// D(i, j) = fin(i, j, sum_k fa(i, k) fb(k, j)) on MFMA: wave w computes the 16-row tile
+// row w; for output tile (w, q) the sum runs over the k-steps [s0, s1) of 4 given by
+// kr(w, q) = (s0, s1) (the caller's triangular structure).  fin may read D.
+template <typename T, typename FA, typename FB, typename KR, typename FIN>
+__device__ __forceinline__ void tile_mma(T (*D)[PP], int t, FA fa, FB fb, KR kr, FIN fin) {
+    using A4 = typename MF<T>::A4;
+    const int l = t & 63, w = t >> 6, li = l & 15, lk = l >> 4;
+    A4 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        acc[q] = (A4){0, 0, 0, 0};
+        const int2 kk = kr(w, q);
+        for (int s = kk.x; s < kk.y; ++s)
+            acc[q] = MF<T>::mma(fa(16 * w + li, 4 * s + lk), fb(4 * s + lk, 16 * q + li), acc[q]);
+    }
+    T v[16];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[4 * q + r] = fin(16 * w + MF<T>::row(r, l), 16 * q + li, acc[q][r]);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) D[16 * w + MF<T>::row(r, l)][16 * q + li] = v[4 * q + r];
+    __syncthreads();
+}
+
+// k-step ranges of products with triangular factors (tile row a, tile column b)
+struct KUpperUpper {  // upper x upper: k in [16a, 16b + 16)
+    __device__ int2 operator()(int a, int b) const {
+        return make_int2(4 * a, b >= a ? 4 * b + 4 : 4 * a);
+    }
+};
+struct KFullUpper {  // full x upper: k in [0, 16b + 16)
+    __device__ int2 operator()(int, int b) const { return make_int2(0, 4 * b + 4); }
+};
+struct KSlice {  // one slice of k for the tiles that meet rows/columns >= lo
+    int k0, k1, lo;
+    bool upper;
+    __device__ int2 operator()(int a, int b) const {
+        const bool on = 16 * a + 15 >= lo && 16 * b + 15 >= lo && (!upper || b >= a);
+        return make_int2(k0 / 4, on ? k1 / 4 : k0 / 4);
+    }
+};
+
+// Cholesky of the symmetric positive definite A (upper triangle read): A <- R upper
+// (A = R^T R), zero lower.  Blocks of TB: the diagonal block on one wavefront in
+// registers, the block row by one thread per column, the trailing update on MFMA.
+// Sets *bad if a pivot is not positive and finite.
+template <typename T>
+__device__ __forceinline__ void tile_chol(T (*A)[PP], int t, int* bad) {
+    for (int k0 = 0; k0 < PB; k0 += TB) {
+        if (t < TB) {  // diagonal block: lane j holds its column
+            T col[TB];
+#pragma unroll
+            for (int i = 0; i < TB; ++i) col[i] = i <= t ? A[k0 + i][k0 + t] : (T)0;
+            bool b = false;
+#pragma unroll
+            for (int k = 0; k < TB; ++k) {
+                const T dkk = bcast_lane(col[k], k);
+                b = b || !(dkk > (T)0) || !isfinite(dkk);
+                const T piv = sqrt(dkk);
+                const T r = t == k ? piv : (t > k ? col[k] / piv : (T)0);
+                col[k] = r;
+#pragma unroll
+                for (int i = k + 1; i < TB; ++i) col[i] -= bcast_lane(r, i) * r;
+            }
+#pragma unroll
+            for (int i = 0; i < TB; ++i) A[k0 + i][k0 + t] = i <= t ? col[i] : (T)0;
+            if (b && t == 0) *bad = 1;
+        }
+        __syncthreads();
+        const int nt = PB - k0 - TB;
+        if (nt == 0) break;
+        if (t < nt) {  // block row: R_kk^-T A(k0 block, c)
+            const int c = k0 + TB + t;
+            T x[TB];
+#pragma unroll
+            for (int i = 0; i < TB; ++i) {
+                T s = A[k0 + i][c];
+#pragma unroll
+                for (int l = 0; l < i; ++l) s -= A[k0 + l][k0 + i] * x[l];
+                x[i] = s / A[k0 + i][k0 + i];
+            }
+#pragma unroll
+            for (int i = 0; i < TB; ++i) A[k0 + i][c] = x[i];
+        }
+        __syncthreads();
+        const int lo = k0 + TB;
+        tile_mma(A, t, [&](int i, int k) { return A[k][i]; }, [&](int k, int j) { return A[k][j]; },
+                 KSlice{k0, k0 + TB, lo, true},
+                 [&](int i, int j, T v) { return (i >= lo && j >= i) ? A[i][j] - v : A[i][j]; });
+    }
+    tile_eval(A, t, [&](int i, int j) { return i <= j ? A[i][j] : (T)0; });
+}
+
+// in-place inverse of the upper triangular A (unit: its diagonal is taken as 1) by
+// recursive doubling: 8 x 8 diagonal blocks by back substitution, 16 x 16 blocks by one
+// level on vector FMAs, then X12 = -X11 (A12 X22) on MFMA for blocks of 32 and 64
+template <typename T>
+__device__ __forceinline__ void tile_trinv(T (*A)[PP], int t, bool unit) {
+    {
+        T x[TB];
+        const int b = t >> 3, j = t & 7, o = TB * b;
+        if (t < PB) {
+#pragma unroll
+            for (int i = TB - 1; i >= 0; --i) {
+                T s = i == j ? (T)1 : (T)0;
+#pragma unroll
+                for (int l = i + 1; l < TB; ++l) s -= A[o + i][o + l] * x[l];
+                x[i] = unit ? s : s / A[o + i][o + i];
+            }
+        }
+        __syncthreads();
+        if (t < PB)
+#pragma unroll
+            for (int i = 0; i < TB; ++i)
+                if (i <= j) A[o + i][o + j] = x[i];
+        __syncthreads();
+    }
+    {
+        // h = 8: four pairs of 8 x 8 blocks, one output of each product per thread
+        const int base = 16 * (t >> 6), i = (t >> 3) & 7, jj = t & 7;
+        T s = 0;
+#pragma unroll
+        for (int l = 0; l <= 7; ++l)
+            if (l <= jj) s += A[base + i][base + 8 + l] * A[base + 8 + l][base + 8 + jj];
+        __syncthreads();
+        A[base + i][base + 8 + jj] = s;
+        __syncthreads();
+        s = 0;
+#pragma unroll
+        for (int l = 0; l <= 7; ++l)
+            if (l >= i) s += A[base + i][base + l] * A[base + l][base + 8 + jj];
+        __syncthreads();
+        A[base + i][base + 8 + jj] = -s;
+        __syncthreads();
+    }
+    // h = 16, 32: the off-diagonal blocks are whole tiles (tile row a, tile column b)
+    for (int h = 16; h < PB; h *= 2) {
+        const int hb = h / 16;  // block size in tiles
+        auto in_pair = [=](int a, int b) {
+            return (a / hb) % 2 == 0 && b / hb == a / hb + 1;
+        };
+        // Y = A12 X22: k over the X22 block
+        tile_mma(A, t, [&](int i, int k) { return A[i][k]; }, [&](int k, int j) { return A[k][j]; },
+                 [=](int a, int b) {
+                     const int s0 = 4 * hb * (b / hb);
+                     return make_int2(s0, in_pair(a, b) ? 4 * b + 4 : s0);
+                 },
+                 [&](int i, int j, T v) { return in_pair(i / 16, j / 16) ? v : A[i][j]; });
+        // X12 = -X11 Y: k over the X11 block
+        tile_mma(A, t, [&](int i, int k) { return A[i][k]; }, [&](int k, int j) { return A[k][j]; },
+                 [=](int a, int b) {
+                     return make_int2(4 * a, in_pair(a, b) ? 4 * hb * (a / hb + 1) : 4 * a);
+                 },
+                 [&](int i, int j, T v) { return in_pair(i / 16, j / 16) ? -v : A[i][j]; });
+    }
+}
+
+// LU without row exchanges of [I - C S] where the sign s_k = -sign(c_kk) is chosen at
+// elimination step k (pivot 1 + |c_kk| >= 1).  The elimination runs on C itself:
+// C <- [multipliers below the diagonal; eliminated C on and above it], sg <- s.
+// Blocks of TB columns: the panel on one wavefront (a row per lane), the block row by one
+// thread per column, the trailing update on MFMA.
+template <typename T>
+__device__ __forceinline__ void tile_lu_signed(T (*C)[PP], T* sg, int t) {
+    for (int k0 = 0; k0 < PB; k0 += TB) {
+        if (t < PB - k0) {
+            const int i = k0 + t;
+            T pr[TB];
+#pragma unroll
+            for (int c = 0; c < TB; ++c) pr[c] = C[i][k0 + c];
+#pragma unroll
+            for (int k = 0; k < TB; ++k) {
+                const T qkk = bcast_lane(pr[k], k);
+                T qk[TB];
+#pragma unroll
+                for (int c = k + 1; c < TB; ++c) qk[c] = bcast_lane(pr[c], k);
+                const T s = qkk >= (T)0 ? (T)-1 : (T)1;
+                const T iu = (T)1 / ((T)1 + fabs(qkk));
+                if (t == 0) sg[k0 + k] = s;
+                if (t > k) {
+                    const T l = -s * pr[k] * iu;
+#pragma unroll
+                    for (int c = k + 1; c < TB; ++c) pr[c] -= l * qk[c];
+                    pr[k] = l;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < TB; ++c) C[i][k0 + c] = pr[c];
+        }
+        __syncthreads();
+        const int nt = PB - k0 - TB;
+        if (nt == 0) break;
+        if (t < nt) {  // block row: L11^-1 C(k0 block, c)
+            const int c = k0 + TB + t;
+            T x[TB];
+#pragma unroll
+            for (int i = 0; i < TB; ++i) {
+                T s = C[k0 + i][c];
+#pragma unroll
+                for (int l = 0; l < i; ++l) s -= C[k0 + i][k0 + l] * x[l];
+                x[i] = s;
+            }
+#pragma unroll
+            for (int i = 0; i < TB; ++i) C[k0 + i][c] = x[i];
+        }
+        __syncthreads();
+        const int lo = k0 + TB;
+        tile_mma(C, t, [&](int i, int k) { return C[i][k]; }, [&](int k, int j) { return C[k][j]; },
+                 KSlice{k0, k0 + TB, lo, false},
+                 [&](int i, int j, T v) { return (i >= lo && j >= lo) ? C[i][j] - v : C[i][j]; });
+    }
+}
+
+// ---------------------------------------------------------------- kernels
+
+// first Cholesky: G (PB x PB, identity beyond nb) -> R1 and R1^-1 (row-major PB x PB)
+template <typename T>
+__global__ __launch_bounds__(256) void k_cqr_chol1(const T* __restrict__ G, int nb,
+                                                   T* __restrict__ R1, T* __restrict__ R1i,
+                                                   int* __restrict__ flag) {
+    __shared__ T A[PB][PP];
+    __shared__ int bad;
+    const int t = threadIdx.x;
+    if (t == 0) bad = 0;
+    for (int o = t; o < PB * PB; o += 256) {
+        const int i = o / PB, j = o % PB;
+        A[i][j] = (i < nb && j < nb) ? G[o] : (i == j ? (T)1 : (T)0);
+    }
+    __syncthreads();
+    tile_chol(A, t, &bad);
+    for (int o = t; o < PB * PB; o += 256) R1[o] = A[o / PB][o % PB];
+    tile_trinv(A, t, false);
+    for (int o = t; o < PB * PB; o += 256) R1i[o] = A[o / PB][o % PB];
+    if (t == 0 && bad) flag[0] = 1;
+}
+
+// Q1 = P R1^-1 over the rows [b GR, (b+1) GR) (column-major, ld ldq) and the Gram partial
+// of those rows of Q1
+template <typename T>
+__global__ __launch_bounds__(256) void k_cqr_apply_gram(const T* __restrict__ P, int64_t ldp,
+                                                        int64_t mr, int nb,
+                                                        const T* __restrict__ Ri,
+                                                        T* __restrict__ Q, int64_t ldq,
+                                                        T* __restrict__ Gp) {
+    __shared__ T Xs[PB][PP];
+    __shared__ T sh[GR][PP];
+    const int t = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * GR, r1 = std::min<int64_t>(mr, r0 + GR);
+    for (int o = t; o < PB * PB; o += 256) Xs[o / PB][o % PB] = Ri[o];
+    stage_chunk(P, ldp, r0, r1, nb, sh, t);
+    __syncthreads();
+    chunk_times_upper(sh, Xs, t);
+    store_chunk(sh, r0, r1, nb, Q, ldq, t);
+    chunk_gram(sh, Gp + (int64_t)blockIdx.x * PB * PB, t);
+}
+
+// Second Cholesky and the Householder reconstruction:
+//   check G2 ~ I, R2 = chol(G2), R = R2 R1, Qt = Q1(0:nb, :) R2^-1,
+//   LU with sign-chosen pivots of [I - Qt S] -> L1 (unit lower), U' (upper), S,
+//   M = -R2^-1 S U'^-1 (for V2 = Q1(nb:, :) M),  T = U' L1^-T.
+// Writes the panel's top block (S R on and above the diagonal, L1 below), tau = diag(U'),
+// M and T (row-major PB x PB).
+template <typename T>
+__global__ __launch_bounds__(256) void k_cqr_chol2(const T* __restrict__ G, int nb,
+                                                   const T* __restrict__ R1,
+                                                   const T* __restrict__ Q, int64_t ldq,
+                                                   T* __restrict__ Pt, int64_t ldp,
+                                                   T* __restrict__ tau, T* __restrict__ Mx,
+                                                   T* __restrict__ Tx, int* __restrict__ flag) {
+    __shared__ T A[PB][PP];  // G2 -> R2 -> R2^-1 -> M
+    __shared__ T B[PB][PP];  // R1 -> R = R2 R1
+    __shared__ T C[PB][PP];  // Q1 top -> Qt -> L1 and the eliminated Qt
+    __shared__ T D[PB][PP];  // R2 copy -> U'^-1 -> L1^-T -> T
+    __shared__ T sg[PB];
+    __shared__ int bad;
+    const int t = threadIdx.x;
+    int off = 0;
+    for (int o = t; o < PB * PB; o += 256) {
+        const int i = o / PB, j = o % PB;
+        const T g = (i < nb && j < nb) ? G[o] : (i == j ? (T)1 : (T)0);
+        A[i][j] = g;
+        // G2 must be close to the identity for the second step to be accurate
+        off |= !(fabs(g - (i == j ? (T)1 : (T)0)) <= (T)0.01);
+        B[i][j] = R1[o];
+        const int r = o % PB, c = o / PB;  // column-major walk of Q1 for coalescing
+        C[r][c] = (r < nb && c < nb) ? Q[c * ldq + r] : (T)0;
+    }
+    if (t == 0) bad = 0;
+    off = __syncthreads_or(off);
+    tile_chol(A, t, &bad);
+    // R = R2 R1 (both upper)
+    tile_mma(B, t, [&](int i, int k) { return A[i][k]; }, [&](int k, int j) { return B[k][j]; },
+             KUpperUpper{}, [](int, int, T v) { return v; });
+    tile_trinv(A, t, false);
+    // Qt = Q1top R2^-1
+    tile_mma(C, t, [&](int i, int k) { return C[i][k]; }, [&](int k, int j) { return A[k][j]; },
+             KFullUpper{}, [](int, int, T v) { return v; });
+    tile_lu_signed(C, sg, t);
+    // U'(k, c) = delta_kc - s_c C(k, c) on and above the diagonal; then U'^-1 in place
+    tile_eval(D, t, [&](int i, int j) {
+        return i <= j ? (i == j ? (T)1 : (T)0) - sg[j] * C[i][j] : (T)0;
+    });
+    tile_trinv(D, t, false);
+    // M = -R2^-1 S U'^-1
+    tile_mma(A, t, [&](int i, int k) { return A[i][k] * sg[k]; },
+             [&](int k, int j) { return D[k][j]; }, KUpperUpper{},
+             [](int, int, T v) { return -v; });
+    // L1^T (unit upper), inverted in place
+    tile_eval(D, t, [&](int i, int j) { return i < j ? C[j][i] : (i == j ? (T)1 : (T)0); });
+    tile_trinv(D, t, true);
+    // T = U' L1^-T with U' from C and the signs
+    tile_mma(D, t,
+             [&](int i, int k) {
+                 return k >= i ? (k == i ? (T)1 : (T)0) - sg[k] * C[i][k] : (T)0;
+             },
+             [&](int k, int j) { return D[k][j]; }, KUpperUpper{},
+             [](int, int, T v) { return v; });
+    for (int o = t; o < PB * PB; o += 256) {
+        const int i = o % PB, c = o / PB;  // column-major walk of the panel's top block
+        if (i < nb && c < nb) Pt[c * ldp + i] = i <= c ? sg[i] * B[i][c] : C[i][c];
+        Mx[o] = A[o / PB][o % PB];
+        Tx[o] = D[o / PB][o % PB];
+    }
+    if (t < nb) tau[t] = (T)1 - sg[t] * C[t][t];
+    if (t == 0 && (bad || off)) flag[0] = 1;
+}
+
+// V2 = Q1(rows, :) M for the rows [nb + b GR, nb + (b+1) GR) of the panel, written into
+// the panel (column-major, ld ldp)
+template <typename T>
+__global__ __launch_bounds__(256) void k_cqr_v2(const T* __restrict__ Q, int64_t ldq, int64_t mr,
+                                                int nb, const T* __restrict__ Mx,
+                                                T* __restrict__ P, int64_t ldp) {
+    __shared__ T Xs[PB][PP];
+    __shared__ T sh[GR][PP];
+    const int t = threadIdx.x;
+    const int64_t r0 = nb + (int64_t)blockIdx.x * GR, r1 = std::min<int64_t>(mr, r0 + GR);
+    for (int o = t; o < PB * PB; o += 256) Xs[o / PB][o % PB] = Mx[o];
+    stage_chunk(Q, ldq, r0, r1, nb, sh, t);
+    __syncthreads();
+    chunk_times_upper(sh, Xs, t);
+    store_chunk(sh, r0, r1, nb, P, ldp, t);
+}
+
+__global__ void k_set_flag(int* flag, int v) {
+    if (threadIdx.x == 0) flag[0] = v;
+}
+
+}  // namespace
+
+int64_t cqr_num_chunks(int64_t m) { return (m + GR - 1) / GR; }
+
+template <typename T>
+hipError_t cqr_panel(T* Ac, int64_t m, int64_t j0, int nb, const CqrWs& w, T* Tout,
+                     hipStream_t st) {
+    if (nb < 1 || nb > PB) return hipErrorInvalidValue;
+    const int64_t mr = m - j0;
+    if (mr < nb) return hipErrorInvalidValue;
+    T* P = Ac + j0 * m + j0;
+    T* Q = (T*)w.Q1;
+    T* Gp = (T*)w.Gp;
+    T* G = (T*)w.G;
+    T* R1 = (T*)w.R1;
+    T* R1i = (T*)w.R1i;
+    const int nch = (int)((mr + GR - 1) / GR);
+    const unsigned nred = PB * PB / (256 / RSL);
+    hipLaunchKernelGGL((k_cqr_gram<T>), dim3(nch), dim3(256), 0, st, P, m, mr, nb, Gp);
+    hipLaunchKernelGGL((k_cqr_reduce<T>), dim3(nred), dim3(256), 0, st, Gp, nch, G);
+    hipLaunchKernelGGL((k_cqr_chol1<T>), dim3(1), dim3(256), 0, st, G, nb, R1, R1i, w.flag);
+    hipLaunchKernelGGL((k_cqr_apply_gram<T>), dim3(nch), dim3(256), 0, st, P, m, mr, nb, R1i, Q,
+                       m, Gp);
+    hipLaunchKernelGGL((k_cqr_reduce<T>), dim3(nred), dim3(256), 0, st, Gp, nch, G);
+    hipLaunchKernelGGL((k_cqr_chol2<T>), dim3(1), dim3(256), 0, st, G, nb, R1, Q, m, P, m,
+                       (T*)w.tau + j0, (T*)w.Mx, Tout, w.flag);
+    const int64_t nv = (mr - nb + GR - 1) / GR;
+    if (nv > 0)
+        hipLaunchKernelGGL((k_cqr_v2<T>), dim3((unsigned)nv), dim3(256), 0, st, Q, m, mr, nb,
+                           (const T*)w.Mx, P, m);
+    return hipGetLastError();
+}
+
+hipError_t cqr_clear_flag(int* flag, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(64), 0, st, flag, 0);
+    return hipGetLastError();
+}
+
+template hipError_t cqr_panel<double>(double*, int64_t, int64_t, int, const CqrWs&, double*,
+                                      hipStream_t);
+template hipError_t cqr_panel<float>(float*, int64_t, int64_t, int, const CqrWs&, float*,
+                                     hipStream_t);
+
+}  // namespace ski

@@ -123,7 +123,7 @@ constexpr int64_t PASS_WG = 512;  // workgroups of the fused dense LSQR pass
 
 enum ProfClass {
     PC_PASS = 0, PC_REDUCE = 1, PC_TRIGEMV = 2, PC_SPMV = 3, PC_SPMVT = 4, PC_STEP = 5,
-    PC_HASH = 6, PC_WHT = 7, PC_GATHER = 8, PC_QR = 9, PC_TRTRI = 10
+    PC_HASH = 6, PC_WHT = 7, PC_GATHER = 8, PC_QR = 9, PC_TRTRI = 10, PC_QR_HH = 11
 };
 
 hipEvent_t pool_event(ski_handle h) {
@@ -252,6 +252,8 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
     if (A->kind == SKI_CSR && p->hadamard)
         return fail(h, SKI_EINVAL, "ski_sketch: the Hadamard transform is for dense A only");
     if (p->s < 1 || p->s > 32) return fail(h, SKI_EINVAL, "ski_sketch: need 1 <= s <= 32");
+    if (p->qr_panel != SKI_QR_AUTO && p->qr_panel != SKI_QR_HOUSEHOLDER)
+        return fail(h, SKI_EINVAL, "ski_sketch: qr_panel must be SKI_QR_AUTO or SKI_QR_HOUSEHOLDER");
     if (p->sketch_prec < 0 || p->sketch_prec > 2 || p->qr_prec < 0 || p->qr_prec > 2)
         return fail(h, SKI_EINVAL, "ski_sketch: unknown precision");
     if (!(p->tau_r >= 0) || !(p->tau_a >= 0) || p->it_max < 1)
@@ -402,24 +404,41 @@ int ski_factor(ski_handle h, void* stream) {
     ws.evF[1] = h->qev[1];
     ws.evE[0] = h->qev[2];
     ws.evE[1] = h->qev[3];
-    prof_begin(h, PC_QR, st);
-    SKI_TRY(h, qr_factor(h->qprec, h->SA.p, m, ncols, d, ws, st), "qr");
-    prof_end(h, st);
-    SKI_TRY(h, launch_extract_Rc(h->qprec, ws, m, d, k, P<double>(h->R), P<double>(h->c), st),
-            "extract R");
-    // guards on diag(R): gather the diagonal on the device, copy it to pinned host memory
     SKI_TRY(h, ensure(h->dtmp, d * 8), "alloc");
     if (h->hdiag_n < d) {
         if (h->hdiag) (void)hipHostFree(h->hdiag);
         h->hdiag = nullptr;
         h->hdiag_n = 0;
-        SKI_TRY(h, hipHostMalloc((void**)&h->hdiag, 2 * d * 8, hipHostMallocDefault), "pinned");
+        // 2d doubles: diag(R), then the perturbation; one more slot for the panel flag
+        SKI_TRY(h, hipHostMalloc((void**)&h->hdiag, (2 * d + 1) * 8, hipHostMallocDefault),
+                "pinned");
         h->hdiag_n = d;
     }
-    SKI_TRY(h, launch_scale_copy(P<double>(h->R), d, 1, d + 1, 1.0, P<double>(h->dtmp), 1, st),
-            "diag gather");
-    SKI_TRY(h, hipMemcpyAsync(h->hdiag, h->dtmp.p, d * 8, hipMemcpyDeviceToHost, st), "diag copy");
-    SKI_TRY(h, hipStreamSynchronize(st), "sync");
+    int* hflag = (int*)(h->hdiag + 2 * d);
+    bool cqr = h->p.qr_panel == SKI_QR_AUTO;
+    for (;;) {
+        ws.cqr_panels = cqr;
+        prof_begin(h, cqr ? PC_QR : PC_QR_HH, st);
+        SKI_TRY(h, qr_factor(h->qprec, h->SA.p, m, ncols, d, ws, st), "qr");
+        prof_end(h, st);
+        SKI_TRY(h, launch_extract_Rc(h->qprec, ws, m, d, k, P<double>(h->R), P<double>(h->c), st),
+                "extract R");
+        // guards on diag(R): gather the diagonal on the device, copy it to pinned host memory
+        SKI_TRY(h, launch_scale_copy(P<double>(h->R), d, 1, d + 1, 1.0, P<double>(h->dtmp), 1, st),
+                "diag gather");
+        SKI_TRY(h, hipMemcpyAsync(h->hdiag, h->dtmp.p, d * 8, hipMemcpyDeviceToHost, st),
+                "diag copy");
+        if (cqr)
+            SKI_TRY(h, hipMemcpyAsync(hflag, ws.cqr.flag, sizeof(int), hipMemcpyDeviceToHost, st),
+                    "flag copy");
+        SKI_TRY(h, hipStreamSynchronize(st), "sync");
+        if (cqr && *hflag != 0) {
+            // a panel was too ill-conditioned for CholeskyQR2: factor again column by column
+            cqr = false;
+            continue;
+        }
+        break;
+    }
     const double* Rd = h->hdiag;
     double amax = 0, amin = INFINITY;
     bool finite = true;

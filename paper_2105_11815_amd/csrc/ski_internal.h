@@ -159,6 +159,24 @@ hipError_t gemm_f32(bool ta, bool tb, int64_t M, int64_t N, int64_t K, float alp
                     int64_t ldc, bool bf16_inputs, GemmWs& ws, hipStream_t st, int unitA = 0);
 size_t gemm_ws_bytes(int64_t M, int64_t N, int64_t K, size_t elem);
 
+// panel factorisation by CholeskyQR2 and Householder reconstruction (qr_panel.hip)
+struct CqrWs {
+    void* Q1 = nullptr;   // m x 64 column-major, the first orthonormalised panel
+    void* Gp = nullptr;   // cqr_num_chunks(m) Gram partials of 64 x 64
+    void* G = nullptr;    // reduced Gram matrix, 64 x 64
+    void* R1 = nullptr;   // first Cholesky factor and its inverse, 64 x 64 each
+    void* R1i = nullptr;
+    void* Mx = nullptr;   // -R2^-1 S U'^-1, 64 x 64
+    void* Tx = nullptr;   // the panels' T (compact WY), two alternating 64 x 64 row-major
+    void* tau = nullptr;  // the QR's taus (indexed by global column)
+    int* flag = nullptr;  // set to 1 when a panel is too ill-conditioned for CholeskyQR2
+};
+int64_t cqr_num_chunks(int64_t m);
+template <typename T>
+hipError_t cqr_panel(T* Ac, int64_t m, int64_t j0, int nb, const CqrWs& w, T* Tout,
+                     hipStream_t st);
+hipError_t cqr_clear_flag(int* flag, hipStream_t st);
+
 // Householder QR of the m x (d+k) sketch on a column-major working copy
 struct QrWs {
     void* Ac = nullptr;   // column-major copy of the sketch (ld = m), factored in place
@@ -172,6 +190,8 @@ struct QrWs {
     void* Tp2 = nullptr;
     void* Tl = nullptr;   // the current leaf's T
     void* tau = nullptr;
+    CqrWs cqr;            // panel factorisation by CholeskyQR2 (when cqr_panels)
+    bool cqr_panels = true;
     GemmWs g;             // split-K partials, caller's stream
     GemmWs g2;            // split-K partials, second stream
     hipStream_t st2 = nullptr;

@@ -98,9 +98,16 @@ def test_dense_plain_hashing_matches_oracle(ski):
 
 
 # -------------------------------------------------------------------------- factor
-@pytest.mark.parametrize("n,d,m,s", [(2000, 64, 110, 3), (6000, 200, 340, 3), (9000, 333, 567, 1)])
-def test_qr_of_sketch_matches_oracle(ski, n, d, m, s):
-    _say(f"qr n={n} d={d} m={m} s={s}")
+QR_CASES = [
+    # n, d, m, s: one full panel; ragged last panel (8 columns, 18 rows below it); three
+    # panels and a ragged one; a square sketch (m = d, no rows below the last panel)
+    (2000, 64, 110, 3), (6000, 200, 210, 3), (9000, 333, 567, 1), (1500, 64, 64, 2)]
+
+
+@pytest.mark.parametrize("panel", ["auto", "householder"])
+@pytest.mark.parametrize("n,d,m,s", QR_CASES)
+def test_qr_of_sketch_matches_oracle(ski, n, d, m, s, panel):
+    _say(f"qr n={n} d={d} m={m} s={s} panel={panel}")
     rng = np.random.default_rng(d)
     A = rng.standard_normal((n, d))
     A[: n // 5] *= 1e3
@@ -108,7 +115,11 @@ def test_qr_of_sketch_matches_oracle(ski, n, d, m, s):
     ref = sk.sketch_dense(A, b, m, s, 31)
     Rref, cref, _ = lls.factor(ref["SA_aug"], d)
     S = ski.Solver()
-    S.sketch(dev(A), dev(b), m=m, s=s, seed=31).factor()
+    S.set_profiling(True)
+    S.sketch(dev(A), dev(b), m=m, s=s, seed=31, qr_panel=0 if panel == "auto" else 1).factor()
+    prof = S.profile()
+    # a well-conditioned sketch never needs the column-by-column fallback
+    assert (prof["qr"][1], prof["qr_householder"][1]) == ((1, 0) if panel == "auto" else (0, 1))
     R, c, Ri = S.get_R()
     scale = np.abs(Rref).max()
     np.testing.assert_allclose(R, Rref, rtol=0, atol=1e-12 * scale * math.sqrt(d))
@@ -116,6 +127,62 @@ def test_qr_of_sketch_matches_oracle(ski, n, d, m, s):
     # explicit inverse: R Rinv = I
     np.testing.assert_allclose(R @ Ri, np.eye(d), atol=1e-11 * np.linalg.cond(R))
     S.close()
+
+
+def test_qr_falls_back_on_an_ill_conditioned_panel(ski):
+    # two nearly equal columns in the first panel: cond(panel) ~ 1e11, beyond what
+    # CholeskyQR2 resolves in FP64; the device check must send the factorisation to the
+    # column-by-column Householder panel.  Past the near-dependent column the rows of R
+    # are determined only to ~1e-5 (for any backward-stable QR, the oracle's included),
+    # so the pins are the leading columns and the Gram identities R^T R = (SA)^T SA and
+    # R^T c = (SA)^T Sb, which every backward-stable QR satisfies to rounding
+    n, d, m, s = 3000, 96, 170, 2
+    _say("qr fallback on an ill-conditioned panel")
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((n, d))
+    A[:, 9] = A[:, 4] + 1e-11 * rng.standard_normal(n)
+    b = rng.standard_normal(n)
+    ref = sk.sketch_dense(A, b, m, s, 13)
+    Rref, cref, _ = lls.factor(ref["SA_aug"], d)
+    S = ski.Solver()
+    S.set_profiling(True)
+    S.sketch(dev(A), dev(b), m=m, s=s, seed=13, rcond=0.0).factor()
+    prof = S.profile()
+    assert prof["qr"][1] == 1 and prof["qr_householder"][1] == 1
+    R, c, _ = S.get_R()
+    scale = np.abs(Rref).max()
+    np.testing.assert_allclose(R[:, :10], Rref[:, :10], rtol=0, atol=1e-12 * scale * math.sqrt(d))
+    SA, Sb = ref["SA_aug"][:, :d], ref["SA_aug"][:, d:]
+    nrm = np.linalg.norm(ref["SA_aug"], axis=0)
+    tol = 1e-13 * math.sqrt(m) * np.outer(nrm, nrm)
+    assert np.all(np.abs(R.T @ R - SA.T @ SA) <= tol[:d, :d])
+    assert np.all(np.abs(R.T @ c - SA.T @ Sb) <= tol[:d, d:])
+    S.close()
+
+
+def test_illconditioned_solve_reaches_the_optimality_bound(ski):
+    # singular values from 1 to 1e-8 (the mixed-precision workload's spectrum at a small
+    # size): x cannot be pinned beyond u cond(A)^2 ||r||; the optimality of the residual can
+    n, d = 6000, 300
+    _say(f"ill-conditioned solve n={n} d={d}")
+    At, bt = workloads.illcond(n=n, d=d, case=4)
+    A, b = At.numpy(), bt.numpy()
+    for panel in (0, 1):
+        S = ski.Solver()
+        S.sketch(dev(A), dev(b), gamma=1.7, s=3, seed=2004, tau_r=1e-10, qr_panel=panel).factor()
+        X, infos, rc = S.solve()
+        x = X[:, 0].cpu().numpy()
+        r = b - A @ x
+        opt = np.linalg.norm(A.T @ r) / (np.linalg.norm(A) * np.linalg.norm(r))
+        # (TC-lsqr) bounds ||W^T r|| with W = A R^-1, so ||A^T r|| <= ||R|| ||W^T r||;
+        # 1e-11 covers the rounding of r = b - A x in FP64 with ||x|| ~ 1e8
+        R = S.get_R()[0]
+        bound = 1e-10 * np.linalg.norm(R, 2) * infos[0]["wnorm_est"] / np.linalg.norm(A) + 1e-11
+        assert rc == 0 and opt <= bound, (panel, rc, opt, bound)
+        xd = lls.lstsq_direct(A, b)
+        rd = b - A @ xd
+        assert abs(np.linalg.norm(r) - np.linalg.norm(rd)) <= 1e-10 * np.linalg.norm(rd)
+        S.close()
 
 
 # -------------------------------------------------------------------------- solve
