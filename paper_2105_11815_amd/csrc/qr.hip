@@ -400,54 +400,32 @@ hipError_t launch_Tinv(const T* Wt, int64_t n, int nb, const T* G, int ldg, cons
     return hipGetLastError();
 }
 
-// W2^T = W^T T for rows x nb products: with the CholeskyQR2 panels T is explicit (a GEMM);
-// the column-by-column panel only leaves the taus, so T^-1 = diag(1/tau) + striu(V^T V)
-// is applied row by row.
+// Column-by-column panels with a look-ahead of one panel.  After panel p is factored, one
+// GEMM gives both V^T V (for T) and V^T C of the next panel's columns; those columns are
+// updated on the caller's stream, so panel p+1 can be factored at once, while the
+// remaining columns are updated on a second stream.  Events keep the order of the updates
+// that every column receives (Q_1^T, Q_2^T, ... in sequence).  T is never formed:
+// W2^T = W^T T is applied through T^-1 = diag(1/tau) + striu(V^T V).
 template <typename T>
-hipError_t apply_T(const QrWs& ws, const T* Wt, int64_t rows, int nb, const T* G, const T* tau,
-                   const T* Tp, T* W2t, GemmWs& g, hipStream_t s) {
-    if (ws.cqr_panels)
-        return gemm_t<T>(false, false, rows, nb, nb, (T)1, Wt, nb, Tp, NBP, (T)0, W2t, nb, false,
-                         g, s);
-    return launch_Tinv<T>(Wt, rows, nb, G, nb, tau, W2t, s);
-}
-
-// Blocked QR with a look-ahead of one panel.  After panel p is factored, one GEMM gives
-// both V^T V (for T) and V^T C of the next panel's columns; those columns are updated on
-// the caller's stream, so panel p+1 can be factored at once, while the remaining columns
-// are updated on a second stream.  Events keep the order of the updates that every
-// column receives (Q_1^T, Q_2^T, ... in sequence).
-template <typename T>
-hipError_t qr_impl(const T* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws, bool bf16,
-                   hipStream_t st) {
-    T* Ac = (T*)ws.Ac;  // column-major working copy, ld = m
+hipError_t qr_impl_hh(T* Ac, int64_t m, int64_t ncols, int64_t d, QrWs& ws, bool bf16,
+                      hipStream_t st) {
     T* tau = (T*)ws.tau;
     T* Tl = (T*)ws.Tl;
     T* VCb[2] = {(T*)ws.Vt, (T*)ws.Vt2};  // [V^T; C_next^T], 2 NBP x m each
     T* GWb[2] = {(T*)ws.Tp, (T*)ws.Tp2};  // [V^T V; W_next^T], 2 NBP x NBP each
     hipStream_t s2 = ws.st2;
-    hipLaunchKernelGGL((k_to_colmajor<T>),
-                       dim3((unsigned)((ncols + 63) / 64), (unsigned)((m + 63) / 64)), dim3(256), 0,
-                       st, SA, m, ncols, Ac);
-    SKI_HIP(hipGetLastError());
-    if (ws.cqr_panels) SKI_HIP(cqr_clear_flag(ws.cqr.flag, st));
     int64_t p = 0;
     bool pending_rest = false;  // a remaining-columns update is queued on s2
     for (int64_t j0 = 0; j0 < d; j0 += NBP, ++p) {
         const int nb = (int)std::min<int64_t>(NBP, d - j0);
         T* VC = VCb[p & 1];
         T* GW = GWb[p & 1];
-        T* Tp = (T*)ws.cqr.Tx + (p & 1) * NBP * NBP;  // the panel's T (CholeskyQR2 panels)
-        if (ws.cqr_panels) {
-            SKI_HIP(cqr_panel<T>(Ac, m, j0, nb, ws.cqr, Tp, st));
-        } else {
-            for (int jl = 0; jl < nb; jl += NBL) {
-                const int64_t jc = j0 + jl;
-                const int w = std::min(NBL, nb - jl);
-                SKI_HIP(launch_leaf<T>(Ac, m, jc, w, tau, Tl, st));
-                const int nc = nb - jl - w;
-                if (nc > 0) SKI_HIP(launch_narrow<T>(Ac, m, jc, w, Tl, nc, st));
-            }
+        for (int jl = 0; jl < nb; jl += NBL) {
+            const int64_t jc = j0 + jl;
+            const int w = std::min(NBL, nb - jl);
+            SKI_HIP(launch_leaf<T>(Ac, m, jc, w, tau, Tl, st));
+            const int nc = nb - jl - w;
+            if (nc > 0) SKI_HIP(launch_narrow<T>(Ac, m, jc, w, Tl, nc, st));
         }
         if (ncols - j0 - nb <= 0) break;
         const int64_t mr = m - j0;
@@ -468,8 +446,7 @@ hipError_t qr_impl(const T* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws, b
         SKI_HIP(hipEventRecord(ws.evF[p & 1], st));
         if (ncn > 0) {
             T* W2n = (T*)ws.W2t;
-            SKI_HIP(apply_T<T>(ws, GW + (int64_t)nb * nb, ncn, nb, GW, tau + j0, Tp, W2n, ws.g,
-                               st));
+            SKI_HIP(launch_Tinv<T>(GW + (int64_t)nb * nb, ncn, nb, GW, nb, tau + j0, W2n, st));
             SKI_HIP(gemm_t<T>(false, false, ncn, mr, nb, (T)-1, W2n, nb, VC, mr, (T)1,
                               Ac + nx0 * m + j0, m, bf16, ws.g, st));
         }
@@ -479,8 +456,7 @@ hipError_t qr_impl(const T* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws, b
             SKI_HIP(hipStreamWaitEvent(s2, ws.evF[p & 1], 0));
             SKI_HIP(gemm_t<T>(false, true, nrest, nb, mr, (T)1, Ct, m, VC, mr, (T)0, (T*)ws.Wt2,
                               nb, bf16, ws.g2, s2));
-            SKI_HIP(apply_T<T>(ws, (T*)ws.Wt2, nrest, nb, GW, tau + j0, Tp, (T*)ws.W2t2, ws.g2,
-                               s2));
+            SKI_HIP(launch_Tinv<T>((T*)ws.Wt2, nrest, nb, GW, nb, tau + j0, (T*)ws.W2t2, s2));
             SKI_HIP(gemm_t<T>(false, false, nrest, mr, nb, (T)-1, (T*)ws.W2t2, nb, VC, mr, (T)1,
                               Ct, m, bf16, ws.g2, s2));
             SKI_HIP(hipEventRecord(ws.evE[p & 1], s2));
@@ -489,6 +465,68 @@ hipError_t qr_impl(const T* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws, b
     }
     if (pending_rest) SKI_HIP(hipStreamWaitEvent(st, ws.evE[(p - 1) & 1], 0));
     return hipSuccess;
+}
+
+// CholeskyQR2 panels.  The look-ahead is fused into the panel kernels: the finished panel
+// p leaves its explicit reflectors V, its T and W = V^T C_{p+1}; the Gram kernel of panel
+// p+1 applies C_{p+1} -= V (T^T W) chunk by chunk before summing its Gram matrix.  The
+// columns beyond panel p+1 get Q_p^T on the second stream (W = C^T V, W T and the rank-nb
+// update as MFMA GEMMs); events keep every column's updates in panel order.
+template <typename T>
+hipError_t qr_impl_cqr(T* Ac, int64_t m, int64_t ncols, int64_t d, QrWs& ws, bool bf16,
+                       hipStream_t st) {
+    T* Vb[2] = {(T*)ws.Vt, (T*)ws.Vt2};  // explicit V of a panel, column-major (ld m - j0)
+    T* Tb[2] = {(T*)ws.cqr.Tx, (T*)ws.cqr.Tx + NBP * NBP};
+    hipStream_t s2 = ws.st2;
+    SKI_HIP(cqr_clear_flag(ws.cqr.flag, st));
+    int64_t p = 0;
+    bool pending_rest = false;  // the previous panel's remaining-columns update is on s2
+    for (int64_t j0 = 0; j0 < d; j0 += NBP, ++p) {
+        const int nb = (int)std::min<int64_t>(NBP, d - j0);
+        const int64_t mr = m - j0;
+        if (p == 0)
+            SKI_HIP(cqr_gram_update<T>(Ac, m, -1, j0, nb, nullptr, nullptr, ws.cqr, st));
+        else
+            SKI_HIP(cqr_gram_update<T>(Ac, m, j0 - NBP, j0, nb, Vb[(p - 1) & 1], Tb[(p - 1) & 1],
+                                       ws.cqr, st));
+        SKI_HIP(cqr_factor_panel<T>(Ac, m, j0, nb, ws.cqr, Tb[p & 1], st));
+        const int64_t nx0 = j0 + nb;
+        const int64_t nx1 = std::min<int64_t>(nx0 + NBP, d);  // next panel's columns
+        const int nbn = (int)std::max<int64_t>(0, nx1 - nx0);
+        // V^T C_next needs the previous panel's update of the next panel's columns
+        if (pending_rest) SKI_HIP(hipStreamWaitEvent(st, ws.evE[(p - 1) & 1], 0));
+        pending_rest = false;
+        SKI_HIP(cqr_finish_panel<T>(Ac, m, j0, nb, nbn, ws.cqr, Vb[p & 1], st));
+        if (nx1 < ncols) {
+            const int64_t nrest = ncols - nx1;
+            T* Ct = Ac + nx1 * m + j0;
+            T* V = Vb[p & 1];
+            SKI_HIP(hipEventRecord(ws.evF[p & 1], st));
+            SKI_HIP(hipStreamWaitEvent(s2, ws.evF[p & 1], 0));
+            SKI_HIP(gemm_t<T>(false, true, nrest, nb, mr, (T)1, Ct, m, V, mr, (T)0, (T*)ws.Wt2, nb,
+                              bf16, ws.g2, s2));
+            SKI_HIP(gemm_t<T>(false, false, nrest, nb, nb, (T)1, (T*)ws.Wt2, nb, Tb[p & 1], NBP,
+                              (T)0, (T*)ws.W2t2, nb, false, ws.g2, s2));
+            SKI_HIP(gemm_t<T>(false, false, nrest, mr, nb, (T)-1, (T*)ws.W2t2, nb, V, mr, (T)1,
+                              Ct, m, bf16, ws.g2, s2));
+            SKI_HIP(hipEventRecord(ws.evE[p & 1], s2));
+            pending_rest = true;
+        }
+    }
+    if (pending_rest) SKI_HIP(hipStreamWaitEvent(st, ws.evE[(p - 1) & 1], 0));
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t qr_impl(const T* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws, bool bf16,
+                   hipStream_t st) {
+    T* Ac = (T*)ws.Ac;  // column-major working copy, ld = m
+    hipLaunchKernelGGL((k_to_colmajor<T>),
+                       dim3((unsigned)((ncols + 63) / 64), (unsigned)((m + 63) / 64)), dim3(256), 0,
+                       st, SA, m, ncols, Ac);
+    SKI_HIP(hipGetLastError());
+    if (ws.cqr_panels) return qr_impl_cqr<T>(Ac, m, ncols, d, ws, bf16, st);
+    return qr_impl_hh<T>(Ac, m, ncols, d, ws, bf16, st);
 }
 
 template <typename T>
@@ -509,9 +547,9 @@ size_t qr_ws_bytes(Prec prec, int64_t m, int64_t ncols, size_t* gemm_bytes) {
     const size_t e = prec == Prec::F64 ? 8 : 4;
     *gemm_bytes = gemm_ws_bytes(2 * NBP, NBP, m, e);
     const size_t pad = 16 * 256;
-    const size_t cqr = (size_t)NBP * m + ((size_t)cqr_num_chunks(m) + 6) * NBP * NBP;
+    const size_t cqr = (size_t)NBP * m + ((size_t)cqr_num_chunks(m) + 7) * NBP * NBP;
     return ((size_t)m * ncols + 4 * (size_t)NBP * m + 3 * (size_t)ncols * NBP +
-            4 * NBP * NBP + NBL * NBL + (size_t)ncols + cqr) * e + 12 * 256 + pad;
+            4 * NBP * NBP + NBL * NBL + (size_t)ncols + cqr) * e + 14 * 256 + pad;
 }
 
 void qr_ws_carve(Prec prec, void* base, int64_t m, int64_t ncols, QrWs& ws) {
@@ -539,6 +577,7 @@ void qr_ws_carve(Prec prec, void* base, int64_t m, int64_t ncols, QrWs& ws) {
     ws.cqr.R1i = take(NBP * NBP);
     ws.cqr.Mx = take(NBP * NBP);
     ws.cqr.Tx = take(2 * NBP * NBP);
+    ws.cqr.W = take(NBP * NBP);
     ws.cqr.tau = ws.tau;
     ws.cqr.flag = (int*)take(1);
 }

@@ -40,6 +40,15 @@ constexpr int PP = PB + 1;   // LDS pitch of a PB x PB tile
 constexpr int GR = 64;       // rows per workgroup of the Gram / apply / V2 kernels
 constexpr int TB = 8;        // diagonal block of the tile factorisations
 constexpr int RSL = 16;      // slices of the partial-sum reduction
+constexpr double EPS_SERIES = 1e-8;  // |G2 - I| below which R2 comes from the series
+
+// compiler ordering point for LDS traffic between the lanes of one wavefront (a wavefront
+// executes its LDS instructions in order)
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __device__ __forceinline__ double bcast_lane(double x, int l) {
     return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
@@ -47,6 +56,37 @@ __device__ __forceinline__ double bcast_lane(double x, int l) {
 }
 __device__ __forceinline__ float bcast_lane(float x, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
+// 1/sqrt(x) and 1/x for x > 0: the hardware estimate refined by two Newton steps (each
+// doubles the number of correct bits), accurate to a few units in the last place
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-x * y, y, 1.0);  // 1 - x y^2
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+__device__ __forceinline__ float rsqrt_nr(float x) {
+    float y = __builtin_amdgcn_rsqf(x);
+    const float e = fmaf(-x * y, y, 1.0f);
+    return fmaf(0.5f * y, e, y);
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-x, y, 1.0);  // 1 - x y
+        y = fma(y, e, y);
+    }
+    return y;
+}
+__device__ __forceinline__ float rcp_nr(float x) {
+    float y = __builtin_amdgcn_rcpf(x);
+    const float e = fmaf(-x, y, 1.0f);
+    return fmaf(y, e, y);
 }
 
 // 16x16x4 MFMA: lane l supplies A[l%16][l/16] and B[l/16][l%16] and holds D[row(r, l)][l%16]
@@ -90,9 +130,9 @@ __device__ __forceinline__ void store_chunk(T (*sh)[PP], int64_t r0, int64_t r1,
     }
 }
 
-// Gram partial sh^T sh (PB x PB) of the staged chunk on MFMA: wave w owns the tile row w
+// X^T Y (PB x PB) of two staged chunks on MFMA -> Gp: wave w owns the tile row w
 template <typename T>
-__device__ __forceinline__ void chunk_gram(T (*sh)[PP], T* __restrict__ Gp, int t) {
+__device__ __forceinline__ void chunk_atb(T (*X)[PP], T (*Y)[PP], T* __restrict__ Gp, int t) {
     using A4 = typename MF<T>::A4;
     const int l = t & 63, w = t >> 6, li = l & 15, lk = l >> 4;
     A4 acc[4];
@@ -100,14 +140,19 @@ __device__ __forceinline__ void chunk_gram(T (*sh)[PP], T* __restrict__ Gp, int 
     for (int q = 0; q < 4; ++q) acc[q] = (A4){0, 0, 0, 0};
 #pragma unroll 4
     for (int s = 0; s < GR / 4; ++s) {
-        const T a = sh[4 * s + lk][16 * w + li];
+        const T a = X[4 * s + lk][16 * w + li];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = MF<T>::mma(a, sh[4 * s + lk][16 * q + li], acc[q]);
+        for (int q = 0; q < 4; ++q) acc[q] = MF<T>::mma(a, Y[4 * s + lk][16 * q + li], acc[q]);
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int r = 0; r < 4; ++r) Gp[(16 * w + MF<T>::row(r, l)) * PB + 16 * q + li] = acc[q][r];
+}
+
+template <typename T>
+__device__ __forceinline__ void chunk_gram(T (*sh)[PP], T* __restrict__ Gp, int t) {
+    chunk_atb(sh, sh, Gp, t);
 }
 
 // sh <- sh X for the staged chunk and an upper triangular X (PB x PB in Xs) on MFMA;
@@ -188,7 +233,9 @@ __device__ __forceinline__ void tile_eval(T (*dst)[PP], int t, F f) {
 
 // D(i, j) = fin(i, j, sum_k fa(i, k) fb(k, j)) on MFMA: wave w computes the 16-row tile
 // row w; for output tile (w, q) the sum runs over the k-steps [s0, s1) of 4 given by
-// kr(w, q) = (s0, s1) (the caller's triangular structure).  fin may read D.
+// kr(w, q) = (s0, s1).  The ranges must not depend on w: the k-loop is then the same on
+// every wavefront, which the compiler pipelines (triangular factors are stored with
+// explicit zeros, so a full x upper range is also right for upper x upper).  fin may read D.
 template <typename T, typename FA, typename FB, typename KR, typename FIN>
 __device__ __forceinline__ void tile_mma(T (*D)[PP], int t, FA fa, FB fb, KR kr, FIN fin) {
     using A4 = typename MF<T>::A4;
@@ -198,8 +245,8 @@ __device__ __forceinline__ void tile_mma(T (*D)[PP], int t, FA fa, FB fb, KR kr,
     for (int q = 0; q < 4; ++q) {
         acc[q] = (A4){0, 0, 0, 0};
         const int2 kk = kr(w, q);
-        for (int s = kk.x; s < kk.y; ++s)
-            acc[q] = MF<T>::mma(fa(16 * w + li, 4 * s + lk), fb(4 * s + lk, 16 * q + li), acc[q]);
+        for (int u = kk.x; u < kk.y; ++u)
+            acc[q] = MF<T>::mma(fa(16 * w + li, 4 * u + lk), fb(4 * u + lk, 16 * q + li), acc[q]);
     }
     T v[16];
 #pragma unroll
@@ -215,69 +262,59 @@ __device__ __forceinline__ void tile_mma(T (*D)[PP], int t, FA fa, FB fb, KR kr,
 }
 
 // k-step ranges of products with triangular factors (tile row a, tile column b)
-struct KUpperUpper {  // upper x upper: k in [16a, 16b + 16)
-    __device__ int2 operator()(int a, int b) const {
-        return make_int2(4 * a, b >= a ? 4 * b + 4 : 4 * a);
-    }
-};
 struct KFullUpper {  // full x upper: k in [0, 16b + 16)
     __device__ int2 operator()(int, int b) const { return make_int2(0, 4 * b + 4); }
 };
-struct KSlice {  // one slice of k for the tiles that meet rows/columns >= lo
-    int k0, k1, lo;
-    bool upper;
-    __device__ int2 operator()(int a, int b) const {
-        const bool on = 16 * a + 15 >= lo && 16 * b + 15 >= lo && (!upper || b >= a);
-        return make_int2(k0 / 4, on ? k1 / 4 : k0 / 4);
-    }
+struct KSlice {  // one slice [k0, k1) of k for every tile (the caller masks in fin)
+    int k0, k1;
+    __device__ int2 operator()(int, int) const { return make_int2(k0 / 4, k1 / 4); }
+};
+struct KFull {
+    __device__ int2 operator()(int, int) const { return make_int2(0, PB / 4); }
+};
+struct KLowerFull {  // lower x full: k in [0, 16a + 16)
+    __device__ int2 operator()(int a, int) const { return make_int2(0, 4 * a + 4); }
 };
 
 // Cholesky of the symmetric positive definite A (upper triangle read): A <- R upper
-// (A = R^T R), zero lower.  Blocks of TB: the diagonal block on one wavefront in
-// registers, the block row by one thread per column, the trailing update on MFMA.
-// Sets *bad if a pivot is not positive and finite.
+// (A = R^T R), zero lower.  Blocks of TB rows: wavefront 0 eliminates the block row in
+// registers (lane c holds rows k0..k0+TB-1 of column k0 + c, so the diagonal block and the
+// block row R_kk^-T A(k0 block, :) come out of the same sweep), then the trailing update
+// runs on MFMA.  Sets *bad if a pivot is not positive and finite.
 template <typename T>
 __device__ __forceinline__ void tile_chol(T (*A)[PP], int t, int* bad) {
     for (int k0 = 0; k0 < PB; k0 += TB) {
-        if (t < TB) {  // diagonal block: lane j holds its column
+        if (t < PB - k0) {
+            const int c = k0 + t;
             T col[TB];
 #pragma unroll
-            for (int i = 0; i < TB; ++i) col[i] = i <= t ? A[k0 + i][k0 + t] : (T)0;
+            for (int i = 0; i < TB; ++i) col[i] = i <= t ? A[k0 + i][c] : (T)0;
             bool b = false;
 #pragma unroll
             for (int k = 0; k < TB; ++k) {
+                // row k of the block before scaling: the pivot and a_{k, k0+i}, i > k
                 const T dkk = bcast_lane(col[k], k);
+                T aki[TB];
+#pragma unroll
+                for (int i = k + 1; i < TB; ++i) aki[i] = bcast_lane(col[k], i);
                 b = b || !(dkk > (T)0) || !isfinite(dkk);
-                const T piv = sqrt(dkk);
-                const T r = t == k ? piv : (t > k ? col[k] / piv : (T)0);
-                col[k] = r;
+                const T ip = rsqrt_nr(dkk), id = ip * ip;  // 1/sqrt(d), 1/d
+                // a_ij -= r_ki r_kj = a_ki a_kj / d
+                const T ck = col[k] * id;
 #pragma unroll
-                for (int i = k + 1; i < TB; ++i) col[i] -= bcast_lane(r, i) * r;
+                for (int i = k + 1; i < TB; ++i) col[i] -= aki[i] * ck;
+                col[k] = t == k ? dkk * ip : (t > k ? col[k] * ip : (T)0);
             }
+            // entries below the diagonal block's diagonal are cleared at the end
 #pragma unroll
-            for (int i = 0; i < TB; ++i) A[k0 + i][k0 + t] = i <= t ? col[i] : (T)0;
+            for (int i = 0; i < TB; ++i) A[k0 + i][c] = col[i];
             if (b && t == 0) *bad = 1;
         }
         __syncthreads();
-        const int nt = PB - k0 - TB;
-        if (nt == 0) break;
-        if (t < nt) {  // block row: R_kk^-T A(k0 block, c)
-            const int c = k0 + TB + t;
-            T x[TB];
-#pragma unroll
-            for (int i = 0; i < TB; ++i) {
-                T s = A[k0 + i][c];
-#pragma unroll
-                for (int l = 0; l < i; ++l) s -= A[k0 + l][k0 + i] * x[l];
-                x[i] = s / A[k0 + i][k0 + i];
-            }
-#pragma unroll
-            for (int i = 0; i < TB; ++i) A[k0 + i][c] = x[i];
-        }
-        __syncthreads();
+        if (k0 + TB == PB) break;
         const int lo = k0 + TB;
         tile_mma(A, t, [&](int i, int k) { return A[k][i]; }, [&](int k, int j) { return A[k][j]; },
-                 KSlice{k0, k0 + TB, lo, true},
+                 KSlice{k0, k0 + TB},
                  [&](int i, int j, T v) { return (i >= lo && j >= i) ? A[i][j] - v : A[i][j]; });
     }
     tile_eval(A, t, [&](int i, int j) { return i <= j ? A[i][j] : (T)0; });
@@ -292,12 +329,15 @@ __device__ __forceinline__ void tile_trinv(T (*A)[PP], int t, bool unit) {
         T x[TB];
         const int b = t >> 3, j = t & 7, o = TB * b;
         if (t < PB) {
+            T inv[TB];  // reciprocals of the diagonal, off the substitution's dependency chain
+#pragma unroll
+            for (int i = 0; i < TB; ++i) inv[i] = unit ? (T)1 : (T)1 / A[o + i][o + i];
 #pragma unroll
             for (int i = TB - 1; i >= 0; --i) {
                 T s = i == j ? (T)1 : (T)0;
 #pragma unroll
                 for (int l = i + 1; l < TB; ++l) s -= A[o + i][o + l] * x[l];
-                x[i] = unit ? s : s / A[o + i][o + i];
+                x[i] = s * inv[i];
             }
         }
         __syncthreads();
@@ -333,16 +373,15 @@ __device__ __forceinline__ void tile_trinv(T (*A)[PP], int t, bool unit) {
         };
         // Y = A12 X22: k over the X22 block
         tile_mma(A, t, [&](int i, int k) { return A[i][k]; }, [&](int k, int j) { return A[k][j]; },
-                 [=](int a, int b) {
+                 [=](int, int b) {
                      const int s0 = 4 * hb * (b / hb);
-                     return make_int2(s0, in_pair(a, b) ? 4 * b + 4 : s0);
+                     return make_int2(s0, in_pair(0, b) || in_pair(2, b) ? 4 * b + 4 : s0);
                  },
                  [&](int i, int j, T v) { return in_pair(i / 16, j / 16) ? v : A[i][j]; });
-        // X12 = -X11 Y: k over the X11 block
-        tile_mma(A, t, [&](int i, int k) { return A[i][k]; }, [&](int k, int j) { return A[k][j]; },
-                 [=](int a, int b) {
-                     return make_int2(4 * a, in_pair(a, b) ? 4 * hb * (a / hb + 1) : 4 * a);
-                 },
+        // X12 = -X11 Y: k over the X11 block (rows of Y), the same block as the row i
+        tile_mma(A, t, [&](int i, int k) { return k / h == i / h ? A[i][k] : (T)0; },
+                 [&](int k, int j) { return A[k][j]; },
+                 [=](int, int b) { return make_int2(0, in_pair(0, b) || in_pair(2, b) ? 4 * b : 0); },
                  [&](int i, int j, T v) { return in_pair(i / 16, j / 16) ? -v : A[i][j]; });
     }
 }
@@ -350,55 +389,57 @@ __device__ __forceinline__ void tile_trinv(T (*A)[PP], int t, bool unit) {
 // LU without row exchanges of [I - C S] where the sign s_k = -sign(c_kk) is chosen at
 // elimination step k (pivot 1 + |c_kk| >= 1).  The elimination runs on C itself:
 // C <- [multipliers below the diagonal; eliminated C on and above it], sg <- s.
-// Blocks of TB columns: the panel on one wavefront (a row per lane), the block row by one
-// thread per column, the trailing update on MFMA.
+// Blocks of TB columns on wavefront 0: the panel with one row per lane, then the block row
+// L11^-1 C(k0 block, :) with one column per lane; the trailing update on MFMA.
 template <typename T>
 __device__ __forceinline__ void tile_lu_signed(T (*C)[PP], T* sg, int t) {
     for (int k0 = 0; k0 < PB; k0 += TB) {
-        if (t < PB - k0) {
-            const int i = k0 + t;
-            T pr[TB];
-#pragma unroll
-            for (int c = 0; c < TB; ++c) pr[c] = C[i][k0 + c];
-#pragma unroll
-            for (int k = 0; k < TB; ++k) {
-                const T qkk = bcast_lane(pr[k], k);
-                T qk[TB];
-#pragma unroll
-                for (int c = k + 1; c < TB; ++c) qk[c] = bcast_lane(pr[c], k);
-                const T s = qkk >= (T)0 ? (T)-1 : (T)1;
-                const T iu = (T)1 / ((T)1 + fabs(qkk));
-                if (t == 0) sg[k0 + k] = s;
-                if (t > k) {
-                    const T l = -s * pr[k] * iu;
-#pragma unroll
-                    for (int c = k + 1; c < TB; ++c) pr[c] -= l * qk[c];
-                    pr[k] = l;
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < TB; ++c) C[i][k0 + c] = pr[c];
-        }
-        __syncthreads();
         const int nt = PB - k0 - TB;
-        if (nt == 0) break;
-        if (t < nt) {  // block row: L11^-1 C(k0 block, c)
-            const int c = k0 + TB + t;
-            T x[TB];
+        if (t < 64) {
+            if (t < PB - k0) {
+                const int i = k0 + t;
+                T pr[TB];
 #pragma unroll
-            for (int i = 0; i < TB; ++i) {
-                T s = C[k0 + i][c];
+                for (int c = 0; c < TB; ++c) pr[c] = C[i][k0 + c];
 #pragma unroll
-                for (int l = 0; l < i; ++l) s -= C[k0 + i][k0 + l] * x[l];
-                x[i] = s;
+                for (int k = 0; k < TB; ++k) {
+                    const T qkk = bcast_lane(pr[k], k);
+                    T qk[TB];
+#pragma unroll
+                    for (int c = k + 1; c < TB; ++c) qk[c] = bcast_lane(pr[c], k);
+                    const T s = qkk >= (T)0 ? (T)-1 : (T)1;
+                    const T iu = rcp_nr((T)1 + fabs(qkk));
+                    if (t == 0) sg[k0 + k] = s;
+                    if (t > k) {
+                        const T l = -s * pr[k] * iu;
+#pragma unroll
+                        for (int c = k + 1; c < TB; ++c) pr[c] -= l * qk[c];
+                        pr[k] = l;
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < TB; ++c) C[i][k0 + c] = pr[c];
             }
+            wave_sync();
+            if (t < nt) {
+                const int c = k0 + TB + t;
+                T x[TB];
 #pragma unroll
-            for (int i = 0; i < TB; ++i) C[k0 + i][c] = x[i];
+                for (int i = 0; i < TB; ++i) {
+                    T s = C[k0 + i][c];
+#pragma unroll
+                    for (int l = 0; l < i; ++l) s -= C[k0 + i][k0 + l] * x[l];
+                    x[i] = s;
+                }
+#pragma unroll
+                for (int i = 0; i < TB; ++i) C[k0 + i][c] = x[i];
+            }
         }
         __syncthreads();
+        if (nt == 0) break;
         const int lo = k0 + TB;
         tile_mma(C, t, [&](int i, int k) { return C[i][k]; }, [&](int k, int j) { return C[k][j]; },
-                 KSlice{k0, k0 + TB, lo, false},
+                 KSlice{k0, k0 + TB},
                  [&](int i, int j, T v) { return (i >= lo && j >= lo) ? C[i][j] - v : C[i][j]; });
     }
 }
@@ -466,24 +507,49 @@ __global__ __launch_bounds__(256) void k_cqr_chol2(const T* __restrict__ G, int 
     __shared__ T sg[PB];
     __shared__ int bad;
     const int t = threadIdx.x;
-    int off = 0;
+    int off = 0, big = 0;
     for (int o = t; o < PB * PB; o += 256) {
         const int i = o / PB, j = o % PB;
         const T g = (i < nb && j < nb) ? G[o] : (i == j ? (T)1 : (T)0);
         A[i][j] = g;
         // G2 must be close to the identity for the second step to be accurate
-        off |= !(fabs(g - (i == j ? (T)1 : (T)0)) <= (T)0.01);
+        const T e = fabs(g - (i == j ? (T)1 : (T)0));
+        off |= !(e <= (T)0.01);
+        big |= !(e <= (T)EPS_SERIES);
         B[i][j] = R1[o];
         const int r = o % PB, c = o / PB;  // column-major walk of Q1 for coalescing
         C[r][c] = (r < nb && c < nb) ? Q[c * ldq + r] : (T)0;
     }
     if (t == 0) bad = 0;
     off = __syncthreads_or(off);
-    tile_chol(A, t, &bad);
-    // R = R2 R1 (both upper)
-    tile_mma(B, t, [&](int i, int k) { return A[i][k]; }, [&](int k, int j) { return B[k][j]; },
-             KUpperUpper{}, [](int, int, T v) { return v; });
-    tile_trinv(A, t, false);
+    big = __syncthreads_or(big);
+    if (big) {
+        tile_chol(A, t, &bad);
+        // R = R2 R1 (both upper)
+        tile_mma(B, t, [&](int i, int k) { return A[i][k]; }, [&](int k, int j) { return B[k][j]; },
+                 KFullUpper{}, [](int, int, T v) { return v; });
+        tile_trinv(A, t, false);
+    } else {
+        // G2 = I + E with |E| <= EPS_SERIES: R2 = I + F where F + F^T + F^T F = E is solved
+        // by two steps of F <- up(E - F^T F) (up: strict upper part plus half the diagonal),
+        // and R2^-1 = I - F + F^2; both are exact to O(|E|^3), far below rounding
+        auto up = [](int i, int j, T x) { return i < j ? x : (i == j ? x * (T)0.5 : (T)0); };
+        tile_eval(D, t, [&](int i, int j) { return up(i, j, A[i][j] - (i == j ? (T)1 : (T)0)); });
+        tile_mma(A, t, [&](int i, int k) { return D[k][i]; }, [&](int k, int j) { return D[k][j]; },
+                 KFull{}, [&](int i, int j, T v) {
+                     return (i == j ? (T)1 : (T)0) +
+                            up(i, j, A[i][j] - (i == j ? (T)1 : (T)0) - v);
+                 });
+        // R = R2 R1 (both upper)
+        tile_mma(B, t, [&](int i, int k) { return A[i][k]; }, [&](int k, int j) { return B[k][j]; },
+                 KFullUpper{}, [](int, int, T v) { return v; });
+        // R2^-1 = I - F + F F with F = R2 - I
+        tile_mma(A, t, [&](int i, int k) { return A[i][k] - (i == k ? (T)1 : (T)0); },
+                 [&](int k, int j) { return A[k][j] - (k == j ? (T)1 : (T)0); }, KFullUpper{},
+                 [&](int i, int j, T v) {
+                     return (i == j ? (T)1 : (T)0) - (A[i][j] - (i == j ? (T)1 : (T)0)) + v;
+                 });
+    }
     // Qt = Q1top R2^-1
     tile_mma(C, t, [&](int i, int k) { return C[i][k]; }, [&](int k, int j) { return A[k][j]; },
              KFullUpper{}, [](int, int, T v) { return v; });
@@ -495,43 +561,98 @@ __global__ __launch_bounds__(256) void k_cqr_chol2(const T* __restrict__ G, int 
     tile_trinv(D, t, false);
     // M = -R2^-1 S U'^-1
     tile_mma(A, t, [&](int i, int k) { return A[i][k] * sg[k]; },
-             [&](int k, int j) { return D[k][j]; }, KUpperUpper{},
+             [&](int k, int j) { return D[k][j]; }, KFullUpper{},
              [](int, int, T v) { return -v; });
-    // L1^T (unit upper), inverted in place
+    for (int o = t; o < PB * PB; o += 256) Mx[o] = A[o / PB][o % PB];
+    // L1^T (unit upper), inverted in place; U' again (into A)
     tile_eval(D, t, [&](int i, int j) { return i < j ? C[j][i] : (i == j ? (T)1 : (T)0); });
+    tile_eval(A, t, [&](int i, int j) {
+        return i <= j ? (i == j ? (T)1 : (T)0) - sg[j] * C[i][j] : (T)0;
+    });
     tile_trinv(D, t, true);
-    // T = U' L1^-T with U' from C and the signs
-    tile_mma(D, t,
-             [&](int i, int k) {
-                 return k >= i ? (k == i ? (T)1 : (T)0) - sg[k] * C[i][k] : (T)0;
-             },
-             [&](int k, int j) { return D[k][j]; }, KUpperUpper{},
-             [](int, int, T v) { return v; });
+    // T = U' L1^-T
+    tile_mma(D, t, [&](int i, int k) { return A[i][k]; }, [&](int k, int j) { return D[k][j]; },
+             KFullUpper{}, [](int, int, T v) { return v; });
     for (int o = t; o < PB * PB; o += 256) {
         const int i = o % PB, c = o / PB;  // column-major walk of the panel's top block
         if (i < nb && c < nb) Pt[c * ldp + i] = i <= c ? sg[i] * B[i][c] : C[i][c];
-        Mx[o] = A[o / PB][o % PB];
         Tx[o] = D[o / PB][o % PB];
     }
     if (t < nb) tau[t] = (T)1 - sg[t] * C[t][t];
     if (t == 0 && (bad || off)) flag[0] = 1;
 }
 
-// V2 = Q1(rows, :) M for the rows [nb + b GR, nb + (b+1) GR) of the panel, written into
-// the panel (column-major, ld ldp)
+// Gram partials of panel p after the previous panel's block reflector (V, T; rows [jq, m))
+// is applied to it: with W = V^T C (reduced beforehand) and Y = T^T W,
+//   C <- C - V Y  over the rows [jq, m),
+// written back (rows [jq, j0) are rows of R), and the Gram partials of the updated rows
+// [j0, m) (the panel to factor).  Chunk b covers the rows [jq + b GR, jq + (b+1) GR); its
+// Gram partial goes to Gp[b - 1] (chunk 0 is the block of R rows).
 template <typename T>
-__global__ __launch_bounds__(256) void k_cqr_v2(const T* __restrict__ Q, int64_t ldq, int64_t mr,
-                                                int nb, const T* __restrict__ Mx,
-                                                T* __restrict__ P, int64_t ldp) {
-    __shared__ T Xs[PB][PP];
-    __shared__ T sh[GR][PP];
+__global__ __launch_bounds__(256) void k_cqr_update_gram(T* __restrict__ Ac, int64_t m, int64_t jq,
+                                                         int64_t j0, int nb,
+                                                         const T* __restrict__ V,
+                                                         const T* __restrict__ Tq,
+                                                         const T* __restrict__ W,
+                                                         T* __restrict__ Gp) {
+    __shared__ T Ys[PB][PP];
+    __shared__ T Vs[PB][PP];
+    __shared__ T Cs[PB][PP];
     const int t = threadIdx.x;
-    const int64_t r0 = nb + (int64_t)blockIdx.x * GR, r1 = std::min<int64_t>(mr, r0 + GR);
-    for (int o = t; o < PB * PB; o += 256) Xs[o / PB][o % PB] = Mx[o];
-    stage_chunk(Q, ldq, r0, r1, nb, sh, t);
+    const int64_t mq = m - jq;
+    const int64_t r0 = (int64_t)blockIdx.x * GR, r1 = std::min<int64_t>(mq, r0 + GR);
+    for (int o = t; o < PB * PB; o += 256) {
+        Vs[o / PB][o % PB] = Tq[o];
+        Cs[o / PB][o % PB] = W[o];
+    }
     __syncthreads();
-    chunk_times_upper(sh, Xs, t);
-    store_chunk(sh, r0, r1, nb, P, ldp, t);
+    // Y = T^T W (T upper)
+    tile_mma(Ys, t, [&](int i, int k) { return Vs[k][i]; }, [&](int k, int j) { return Cs[k][j]; },
+             KLowerFull{}, [](int, int, T v) { return v; });
+    stage_chunk(V, mq, r0, r1, PB, Vs, t);
+    stage_chunk(Ac + j0 * m + jq, m, r0, r1, nb, Cs, t);
+    __syncthreads();
+    tile_mma(Cs, t, [&](int i, int k) { return Vs[i][k]; }, [&](int k, int j) { return Ys[k][j]; },
+             KFull{}, [&](int i, int j, T v) { return Cs[i][j] - v; });
+    store_chunk(Cs, r0, r1, nb, Ac + j0 * m + jq, m, t);
+    if (blockIdx.x > 0) chunk_gram(Cs, Gp + (int64_t)(blockIdx.x - 1) * PB * PB, t);
+}
+
+// The panel's reflectors: V2 = Q1 M below the top block, L1 (unit lower) in it.  Chunk b
+// covers the panel rows [b GR, (b+1) GR): V2 rows go into the panel, the explicit V (unit
+// diagonal, zeros above) into Vout (column-major, ld mr), and with a next panel of nbn
+// columns the partial products V^T C_next of those rows into Gp[b].
+template <typename T>
+__global__ __launch_bounds__(256) void k_cqr_v2x(const T* __restrict__ Q, int64_t ldq, int64_t mr,
+                                                 int nb, const T* __restrict__ Mx,
+                                                 T* __restrict__ P, int64_t ldp,
+                                                 T* __restrict__ Vout, int nbn,
+                                                 T* __restrict__ Gp) {
+    __shared__ T Ms[PB][PP];
+    __shared__ T Qs[PB][PP];
+    __shared__ T Cs[PB][PP];
+    const int t = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * GR, r1 = std::min<int64_t>(mr, r0 + GR);
+    for (int o = t; o < PB * PB; o += 256) Ms[o / PB][o % PB] = Mx[o];
+    stage_chunk(Q, ldq, r0, r1, nb, Qs, t);
+    if (nbn > 0) stage_chunk(P + (int64_t)nb * ldp, ldp, r0, r1, nbn, Cs, t);
+    __syncthreads();
+    tile_mma(Qs, t, [&](int i, int k) { return Qs[i][k]; }, [&](int k, int j) { return Ms[k][j]; },
+             KFullUpper{}, [&](int i, int j, T v) {
+                 const int64_t r = r0 + i;
+                 if (r >= r1 || j >= nb) return (T)0;
+                 if (r < nb) return r == j ? (T)1 : (r > j ? P[j * ldp + r] : (T)0);
+                 return v;
+             });
+    for (int o = t; o < GR * PB; o += 256) {
+        const int rr = o % GR, c = o / GR;
+        const int64_t r = r0 + rr;
+        if (r < r1 && c < nb) {
+            if (r >= nb) P[c * ldp + r] = Qs[rr][c];
+            Vout[c * mr + r] = Qs[rr][c];
+        }
+    }
+    if (nbn > 0) chunk_atb(Qs, Cs, Gp + (int64_t)blockIdx.x * PB * PB, t);
 }
 
 __global__ void k_set_flag(int* flag, int v) {
@@ -543,8 +664,28 @@ __global__ void k_set_flag(int* flag, int v) {
 int64_t cqr_num_chunks(int64_t m) { return (m + GR - 1) / GR; }
 
 template <typename T>
-hipError_t cqr_panel(T* Ac, int64_t m, int64_t j0, int nb, const CqrWs& w, T* Tout,
-                     hipStream_t st) {
+hipError_t cqr_gram_update(T* Ac, int64_t m, int64_t jq, int64_t j0, int nb, const T* V,
+                           const T* Tq, const CqrWs& w, hipStream_t st) {
+    if (nb < 1 || nb > PB || m - j0 < nb) return hipErrorInvalidValue;
+    const int64_t mr = m - j0;
+    const int nch = (int)((mr + GR - 1) / GR);
+    const unsigned nred = PB * PB / (256 / RSL);
+    if (jq < 0) {
+        hipLaunchKernelGGL((k_cqr_gram<T>), dim3(nch), dim3(256), 0, st, Ac + j0 * m + j0, m, mr,
+                           nb, (T*)w.Gp);
+    } else {
+        if (j0 - jq != PB) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_cqr_update_gram<T>), dim3(nch + 1), dim3(256), 0, st, Ac, m, jq, j0,
+                           nb, V, Tq, (const T*)w.W, (T*)w.Gp);
+    }
+    hipLaunchKernelGGL((k_cqr_reduce<T>), dim3(nred), dim3(256), 0, st, (const T*)w.Gp, nch,
+                       (T*)w.G);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t cqr_factor_panel(T* Ac, int64_t m, int64_t j0, int nb, const CqrWs& w, T* Tout,
+                            hipStream_t st) {
     if (nb < 1 || nb > PB) return hipErrorInvalidValue;
     const int64_t mr = m - j0;
     if (mr < nb) return hipErrorInvalidValue;
@@ -556,18 +697,26 @@ hipError_t cqr_panel(T* Ac, int64_t m, int64_t j0, int nb, const CqrWs& w, T* To
     T* R1i = (T*)w.R1i;
     const int nch = (int)((mr + GR - 1) / GR);
     const unsigned nred = PB * PB / (256 / RSL);
-    hipLaunchKernelGGL((k_cqr_gram<T>), dim3(nch), dim3(256), 0, st, P, m, mr, nb, Gp);
-    hipLaunchKernelGGL((k_cqr_reduce<T>), dim3(nred), dim3(256), 0, st, Gp, nch, G);
     hipLaunchKernelGGL((k_cqr_chol1<T>), dim3(1), dim3(256), 0, st, G, nb, R1, R1i, w.flag);
     hipLaunchKernelGGL((k_cqr_apply_gram<T>), dim3(nch), dim3(256), 0, st, P, m, mr, nb, R1i, Q,
                        m, Gp);
     hipLaunchKernelGGL((k_cqr_reduce<T>), dim3(nred), dim3(256), 0, st, Gp, nch, G);
     hipLaunchKernelGGL((k_cqr_chol2<T>), dim3(1), dim3(256), 0, st, G, nb, R1, Q, m, P, m,
                        (T*)w.tau + j0, (T*)w.Mx, Tout, w.flag);
-    const int64_t nv = (mr - nb + GR - 1) / GR;
-    if (nv > 0)
-        hipLaunchKernelGGL((k_cqr_v2<T>), dim3((unsigned)nv), dim3(256), 0, st, Q, m, mr, nb,
-                           (const T*)w.Mx, P, m);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t cqr_finish_panel(T* Ac, int64_t m, int64_t j0, int nb, int nbn, const CqrWs& w,
+                            T* Vout, hipStream_t st) {
+    if (nb < 1 || nb > PB || nbn < 0 || nbn > PB) return hipErrorInvalidValue;
+    const int64_t mr = m - j0;
+    const int nch = (int)((mr + GR - 1) / GR);
+    hipLaunchKernelGGL((k_cqr_v2x<T>), dim3(nch), dim3(256), 0, st, (const T*)w.Q1, m, mr, nb,
+                       (const T*)w.Mx, Ac + j0 * m + j0, m, Vout, nbn, (T*)w.Gp);
+    if (nbn > 0)
+        hipLaunchKernelGGL((k_cqr_reduce<T>), dim3(PB * PB / (256 / RSL)), dim3(256), 0, st,
+                           (const T*)w.Gp, nch, (T*)w.W);
     return hipGetLastError();
 }
 
@@ -576,9 +725,15 @@ hipError_t cqr_clear_flag(int* flag, hipStream_t st) {
     return hipGetLastError();
 }
 
-template hipError_t cqr_panel<double>(double*, int64_t, int64_t, int, const CqrWs&, double*,
-                                      hipStream_t);
-template hipError_t cqr_panel<float>(float*, int64_t, int64_t, int, const CqrWs&, float*,
-                                     hipStream_t);
+#define SKI_CQR_INST(T)                                                                     \
+    template hipError_t cqr_gram_update<T>(T*, int64_t, int64_t, int64_t, int, const T*,     \
+                                           const T*, const CqrWs&, hipStream_t);             \
+    template hipError_t cqr_factor_panel<T>(T*, int64_t, int64_t, int, const CqrWs&, T*,      \
+                                            hipStream_t);                                    \
+    template hipError_t cqr_finish_panel<T>(T*, int64_t, int64_t, int, int, const CqrWs&, T*, \
+                                            hipStream_t);
+SKI_CQR_INST(double)
+SKI_CQR_INST(float)
+#undef SKI_CQR_INST
 
 }  // namespace ski

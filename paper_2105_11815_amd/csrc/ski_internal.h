@@ -168,13 +168,27 @@ struct CqrWs {
     void* R1i = nullptr;
     void* Mx = nullptr;   // -R2^-1 S U'^-1, 64 x 64
     void* Tx = nullptr;   // the panels' T (compact WY), two alternating 64 x 64 row-major
+    void* W = nullptr;    // V^T C_next of the last finished panel, 64 x 64
     void* tau = nullptr;  // the QR's taus (indexed by global column)
     int* flag = nullptr;  // set to 1 when a panel is too ill-conditioned for CholeskyQR2
 };
 int64_t cqr_num_chunks(int64_t m);
+// Gram matrix of the panel [j0, j0+nb) into w.G; with jq >= 0 the previous panel's block
+// reflector (explicit V over the rows [jq, m), column-major; T; w.W = V^T C) is applied to
+// the panel's columns first
 template <typename T>
-hipError_t cqr_panel(T* Ac, int64_t m, int64_t j0, int nb, const CqrWs& w, T* Tout,
-                     hipStream_t st);
+hipError_t cqr_gram_update(T* Ac, int64_t m, int64_t jq, int64_t j0, int nb, const T* V,
+                           const T* Tq, const CqrWs& w, hipStream_t st);
+// CholeskyQR2 and the reconstruction of the panel: R and the reflectors' top block in place,
+// the taus, M and the panel's T into Tout
+template <typename T>
+hipError_t cqr_factor_panel(T* Ac, int64_t m, int64_t j0, int nb, const CqrWs& w, T* Tout,
+                            hipStream_t st);
+// the rest of the reflectors in place, the explicit V (column-major, ld m - j0) into Vout,
+// and with a next panel of nbn columns w.W = V^T C_next
+template <typename T>
+hipError_t cqr_finish_panel(T* Ac, int64_t m, int64_t j0, int nb, int nbn, const CqrWs& w,
+                            T* Vout, hipStream_t st);
 hipError_t cqr_clear_flag(int* flag, hipStream_t st);
 
 // Householder QR of the m x (d+k) sketch on a column-major working copy
