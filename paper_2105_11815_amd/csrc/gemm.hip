@@ -62,7 +62,8 @@ __global__ __launch_bounds__(GTHR) void k_gemm(int64_t M, int64_t N, int64_t K, 
                                                const typename MT<MD>::T* __restrict__ B,
                                                int64_t ldb, typename MT<MD>::T beta,
                                                typename MT<MD>::T* __restrict__ C, int64_t ldc,
-                                               typename MT<MD>::T* __restrict__ part, int unitA) {
+                                               typename MT<MD>::T* __restrict__ part, int unitA,
+                                               int tri) {
     using T = typename MT<MD>::T;
     using Acc = typename MT<MD>::Acc;
     __shared__ T As[BK][BM + PAD];
@@ -73,8 +74,12 @@ __global__ __launch_bounds__(GTHR) void k_gemm(int64_t M, int64_t N, int64_t K, 
     const int wave = tid >> 6;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
-    const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
-    const int64_t kend = std::min(K, kbeg + kchunk);
+    int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+    int64_t kend = std::min(K, kbeg + kchunk);
+    // triangular operands: A(i, k) = 0 for k < i, B(k, j) = 0 for k > j (m0, n0 are
+    // multiples of BK, so the slices stay aligned)
+    if (tri & GEMM_A_UPPER) kbeg = std::max(kbeg, m0);
+    if (tri & GEMM_B_UPPER) kend = std::min(kend, n0 + BN);
 
     Acc acc[2][2];
 #pragma unroll
@@ -238,7 +243,7 @@ template <Mode MD>
 hipError_t gemm_impl(bool ta, bool tb, int64_t M, int64_t N, int64_t K, typename MT<MD>::T alpha,
                      const typename MT<MD>::T* A, int64_t lda, const typename MT<MD>::T* B,
                      int64_t ldb, typename MT<MD>::T beta, typename MT<MD>::T* C, int64_t ldc,
-                     GemmWs& ws, hipStream_t st, int unitA) {
+                     GemmWs& ws, hipStream_t st, int unitA, int tri) {
     using T = typename MT<MD>::T;
     if (M <= 0 || N <= 0) return hipSuccess;
     int splits = choose_splits(M, N, K);
@@ -253,7 +258,7 @@ hipError_t gemm_impl(bool ta, bool tb, int64_t M, int64_t N, int64_t K, typename
     if (K <= 0) kchunk = 0;
 #define SKI_GEMM_LAUNCH(TA_, TB_)                                                              \
     hipLaunchKernelGGL((k_gemm<MD, TA_, TB_>), grid, dim3(GTHR), 0, st, M, N, K, kchunk, alpha, \
-                       A, lda, B, ldb, beta, C, ldc, part, unitA)
+                       A, lda, B, ldb, beta, C, ldc, part, unitA, tri)
     if (!ta && !tb)
         SKI_GEMM_LAUNCH(false, false);
     else if (ta && !tb)
@@ -282,9 +287,9 @@ size_t gemm_ws_bytes(int64_t M, int64_t N, int64_t K, size_t elem) {
 
 hipError_t gemm_f64(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
                     const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
-                    double* C, int64_t ldc, GemmWs& ws, hipStream_t st, int unitA) {
+                    double* C, int64_t ldc, GemmWs& ws, hipStream_t st, int unitA, int tri) {
     return gemm_impl<Mode::F64>(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, st,
-                                unitA);
+                                unitA, tri);
 }
 
 hipError_t gemm_f32(bool ta, bool tb, int64_t M, int64_t N, int64_t K, float alpha,
@@ -292,9 +297,9 @@ hipError_t gemm_f32(bool ta, bool tb, int64_t M, int64_t N, int64_t K, float alp
                     int64_t ldc, bool bf16_inputs, GemmWs& ws, hipStream_t st, int unitA) {
     if (bf16_inputs)
         return gemm_impl<Mode::BF16>(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, st,
-                                     unitA);
+                                     unitA, 0);
     return gemm_impl<Mode::F32>(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, st,
-                                unitA);
+                                unitA, 0);
 }
 
 }  // namespace ski

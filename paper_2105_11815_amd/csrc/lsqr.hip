@@ -16,6 +16,7 @@
 // bitwise reproducible run to run.
 #include "ski_internal.h"
 #include "lsqr.h"
+#include "tile64.h"
 
 namespace ski {
 
@@ -23,45 +24,55 @@ namespace {
 
 constexpr int DB = 64;  // diagonal block of the triangular inversion
 
-// invert the 64 x 64 diagonal blocks of upper-triangular R (diag + diag_add), X row-major d x d
-__global__ __launch_bounds__(DB) void k_trtri_diag(const double* __restrict__ R, int64_t d,
-                                                   const double* __restrict__ diag_add,
-                                                   double* __restrict__ X) {
-    __shared__ double Rs[DB][DB + 1];
+// invert the 64 x 64 diagonal blocks of upper-triangular R (diag + diag_add) into X (row-major
+// d x d): one workgroup per block, recursive doubling on the block in LDS; a partial last
+// block is padded with the identity
+__global__ __launch_bounds__(256) void k_trtri_diag(const double* __restrict__ R, int64_t d,
+                                                    const double* __restrict__ diag_add,
+                                                    double* __restrict__ X) {
+    using namespace tile;
+    __shared__ double Rs[PB][PP];
+    const int t = threadIdx.x;
     const int64_t b0 = (int64_t)blockIdx.x * DB;
     const int nb = (int)std::min<int64_t>(DB, d - b0);
-    const int j = threadIdx.x;  // this thread computes column j of the block inverse
-    for (int i = 0; i < nb; ++i)
-        if (j < nb) {
-            double v = R[(b0 + i) * d + b0 + j];
+    for (int o = t; o < PB * PB; o += 256) {
+        const int i = o / PB, j = o % PB;
+        double v = i == j ? 1.0 : 0.0;
+        if (i < nb && j < nb && i <= j) {
+            v = R[(b0 + i) * d + b0 + j];
             if (i == j && diag_add) v += diag_add[b0 + i];
-            Rs[i][j] = v;
         }
-    __syncthreads();
-    if (j >= nb) return;
-    double x[DB];
-#pragma unroll
-    for (int i = 0; i < DB; ++i) x[i] = 0;
-    // back substitution R x = e_j
-    for (int i = nb - 1; i >= 0; --i) {
-        double s = (i == j) ? 1.0 : 0.0;
-        for (int t = i + 1; t <= j; ++t) s -= Rs[i][t] * x[t];
-        x[i] = (i <= j) ? s / Rs[i][i] : 0.0;
+        Rs[i][j] = v;
     }
-    for (int i = 0; i < nb; ++i) X[(b0 + i) * d + b0 + j] = x[i];
+    __syncthreads();
+    tile_trinv(Rs, t, false);
+    for (int o = t; o < PB * PB; o += 256) {
+        const int i = o / PB, j = o % PB;
+        if (i < nb && j < nb) X[(b0 + i) * d + b0 + j] = i <= j ? Rs[i][j] : 0.0;
+    }
 }
 
+// X: zero the strictly lower triangle; XT = X^T; 64 x 64 tiles through LDS so that both
+// the reads and the transposed writes are row-contiguous
 __global__ __launch_bounds__(256) void k_zero_lower_and_transpose(double* __restrict__ X,
                                                                   int64_t d,
                                                                   double* __restrict__ XT) {
-    // X: zero the strictly lower triangle; XT = X^T
-    const int64_t i = blockIdx.x;
-    for (int64_t j = threadIdx.x; j < d; j += 256) {
-        double v = j < i ? 0.0 : X[i * d + j];
-        X[i * d + j] = v;
+    __shared__ double tl[64][65];
+    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int i = ty; i < 64; i += 4) {
+        const int64_t r = r0 + i, c = c0 + tx;
+        if (r < d && c < d) {
+            const double v = c < r ? 0.0 : X[r * d + c];
+            X[r * d + c] = v;
+            tl[i][tx] = v;
+        }
     }
     __syncthreads();
-    for (int64_t j = threadIdx.x; j < d; j += 256) XT[j * d + i] = j < i ? 0.0 : X[i * d + j];
+    for (int i = ty; i < 64; i += 4) {
+        const int64_t c = c0 + i, r = r0 + tx;
+        if (r < d && c < d) XT[c * d + r] = tl[tx][i];
+    }
 }
 
 __global__ __launch_bounds__(256) void k_fill_f64(double* p, int64_t n, double v) {
@@ -79,10 +90,11 @@ hipError_t trtri_rec(const double* R, int64_t d, int64_t lo, int64_t hi, double*
     SKI_HIP(trtri_rec(R, d, mid, hi, X, tmp, ws, st));
     const int64_t n1 = mid - lo, n2 = hi - mid;
     // X12 = -X11 (R12 X22): tmp = R12 X22 (n1 x n2), then X12 = -X11 tmp
+    // (X22 and X11 are upper triangular: the GEMMs skip their zero blocks)
     SKI_HIP(gemm_f64(false, false, n1, n2, n2, 1.0, R + lo * d + mid, d, X + mid * d + mid, d, 0.0,
-                     tmp, n2, ws, st));
+                     tmp, n2, ws, st, 0, GEMM_B_UPPER));
     SKI_HIP(gemm_f64(false, false, n1, n2, n1, -1.0, X + lo * d + lo, d, tmp, n2, 0.0,
-                     X + lo * d + mid, d, ws, st));
+                     X + lo * d + mid, d, ws, st, 0, GEMM_A_UPPER));
     return hipSuccess;
 }
 
@@ -659,11 +671,11 @@ hipError_t trtri_upper(const double* R, int64_t d, double* Rinv, double* RinvT,
     hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)std::min<int64_t>((tot + 255) / 256, 65536)),
                        dim3(256), 0, st, Rinv, tot, 0.0);
     SKI_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_trtri_diag, dim3(nblk), dim3(DB), 0, st, R, d, diag_add, Rinv);
+    hipLaunchKernelGGL(k_trtri_diag, dim3(nblk), dim3(256), 0, st, R, d, diag_add, Rinv);
     SKI_HIP(hipGetLastError());
     // the off-diagonal blocks use R with the same perturbed diagonal only through X11, X22
     SKI_HIP(trtri_rec(R, d, 0, d, Rinv, tmp, ws, st));
-    hipLaunchKernelGGL(k_zero_lower_and_transpose, dim3((unsigned)d), dim3(256), 0, st, Rinv, d,
+    hipLaunchKernelGGL(k_zero_lower_and_transpose, dim3(nblk, nblk), dim3(256), 0, st, Rinv, d,
                        RinvT);
     return hipGetLastError();
 }

@@ -151,9 +151,13 @@ struct GemmWs {
     void* part = nullptr;   // split-K partials
     size_t bytes = 0;
 };
+// tri: GEMM_A_UPPER when op(A) is upper triangular (A(i, k) = 0 for k < i), GEMM_B_UPPER
+// when op(B) is (B(k, j) = 0 for k > j); each output tile then skips the zero part of K
+enum { GEMM_A_UPPER = 1, GEMM_B_UPPER = 2 };
 hipError_t gemm_f64(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
                     const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
-                    double* C, int64_t ldc, GemmWs& ws, hipStream_t st, int unitA = 0);
+                    double* C, int64_t ldc, GemmWs& ws, hipStream_t st, int unitA = 0,
+                    int tri = 0);
 hipError_t gemm_f32(bool ta, bool tb, int64_t M, int64_t N, int64_t K, float alpha,
                     const float* A, int64_t lda, const float* B, int64_t ldb, float beta, float* C,
                     int64_t ldc, bool bf16_inputs, GemmWs& ws, hipStream_t st, int unitA = 0);
