@@ -24,7 +24,7 @@ EXPORTED = ["ski_create", "ski_destroy", "ski_params_default", "ski_sketch", "sk
             "ski_get_dsign", "ski_get_SA", "ski_get_R", "ski_set_profiling", "ski_get_profile"]
 PROF_CLASSES = 16
 PROF_NAMES = ["lsqr_pass", "pass_reduce", "tri_gemv", "spmv_csr", "spmv_csrT", "lsqr_step",
-              "hash", "wht", "gather", "qr", "trtri", "qr_householder"]
+              "hash", "wht_gather", "gather", "qr", "trtri", "qr_householder"]
 
 
 class SkiMatrix(C.Structure):

@@ -20,6 +20,8 @@
 // a sequential sum in that order.
 #include "ski_internal.h"
 
+#include <type_traits>
+
 namespace ski {
 
 namespace {
@@ -44,6 +46,21 @@ __device__ __forceinline__ TAcc load_as(const TIn* p) {
         return to_f(*p);
 }
 
+// the data matrix is read once per sketch: non-temporal loads keep it from displacing the
+// slab buffer in the caches
+template <typename TIn, typename TAcc>
+__device__ __forceinline__ TAcc load_in(const TIn* p) {
+    if constexpr (std::is_same<TIn, double>::value) {
+        const double x = __builtin_nontemporal_load(p);
+        if constexpr (sizeof(TAcc) == 8)
+            return x;
+        else
+            return (TAcc)x;
+    } else {
+        return load_as<TIn, TAcc>(p);
+    }
+}
+
 template <typename TAcc, typename TOut>
 __device__ __forceinline__ TOut store_as(TAcc v) {
     if constexpr (sizeof(TAcc) == 8)
@@ -54,14 +71,15 @@ __device__ __forceinline__ TOut store_as(TAcc v) {
 
 // One 256-point pass over row bits [p, p+8).
 template <typename TIn, typename TOut, typename TAcc>
-__global__ __launch_bounds__(WT) void k_wht256(const TIn* __restrict__ in, int64_t ld_in,
+__global__ __launch_bounds__(WT) void k_wht256(const TIn* in, int64_t ld_in,
                                                int64_t rows_valid, int64_t ncols_src,
-                                               TOut* __restrict__ out, int64_t ld_out,
+                                               TOut* out, int64_t ld_out,
                                                int64_t out_col0, int p, int skip_zero_lines,
-                                               const uint32_t* __restrict__ dbits) {
+                                               const uint32_t* __restrict__ dbits, int64_t nct) {
     __shared__ TAcc lds[256 * (WC + 1)];
-    const int64_t line = blockIdx.x;
-    const int64_t col = (int64_t)blockIdx.y * WC + (threadIdx.x & (WC - 1));
+    // the column tiles of one line are consecutive workgroups: together they read whole rows
+    const int64_t line = (int64_t)blockIdx.x / nct;
+    const int64_t col = ((int64_t)blockIdx.x % nct) * WC + (threadIdx.x & (WC - 1));
     const int q = threadIdx.x >> 4;  // 0..15
     const int c = threadIdx.x & (WC - 1);
     if (skip_zero_lines && line_row(line, p, 8, 0) >= rows_valid) return;  // p == 0 here
@@ -72,7 +90,7 @@ __global__ __launch_bounds__(WT) void k_wht256(const TIn* __restrict__ in, int64
         int64_t row = line_row(line, p, 8, 16 * q + i);
         TAcc x = 0;
         if (colok && row < rows_valid) {
-            x = load_as<TIn, TAcc>(in + row * ld_in + col);
+            x = load_in<TIn, TAcc>(in + row * ld_in + col);
             if (dbits && dneg(dbits, row)) x = -x;
         }
         v[i] = x;
@@ -113,17 +131,20 @@ __global__ __launch_bounds__(WT) void k_wht256(const TIn* __restrict__ in, int64
 }
 
 // A pass over R < 8 bits: 256/2^R lines of 2^R points per tile, stages in LDS.
+// Both passes may run in place (in == out): a workgroup reads all of its points before it
+// writes any, and workgroups own disjoint points.
 template <typename TIn, typename TOut, typename TAcc>
-__global__ __launch_bounds__(WT) void k_wht_small(const TIn* __restrict__ in, int64_t ld_in,
+__global__ __launch_bounds__(WT) void k_wht_small(const TIn* in, int64_t ld_in,
                                                   int64_t rows_valid, int64_t ncols_src,
-                                                  TOut* __restrict__ out, int64_t ld_out,
+                                                  TOut* out, int64_t ld_out,
                                                   int64_t out_col0, int p, int R,
                                                   int64_t nlines, int skip_zero_lines,
-                                                  const uint32_t* __restrict__ dbits) {
+                                                  const uint32_t* __restrict__ dbits,
+                                                  int64_t nct) {
     __shared__ TAcc lds[256 * (WC + 1)];
     const int lpt = 256 >> R;  // lines per tile
-    const int64_t line0 = (int64_t)blockIdx.x * lpt;
-    const int64_t col = (int64_t)blockIdx.y * WC + (threadIdx.x & (WC - 1));
+    const int64_t line0 = ((int64_t)blockIdx.x / nct) * lpt;
+    const int64_t col = ((int64_t)blockIdx.x % nct) * WC + (threadIdx.x & (WC - 1));
     const int q = threadIdx.x >> 4;
     const int c = threadIdx.x & (WC - 1);
     const bool colok = col < ncols_src;
@@ -136,7 +157,7 @@ __global__ __launch_bounds__(WT) void k_wht_small(const TIn* __restrict__ in, in
         if (line < nlines) {
             int64_t row = line_row(line, p, R, e & pmask);
             if (colok && row < rows_valid) {
-                x = load_as<TIn, TAcc>(in + row * ld_in + col);
+                x = load_in<TIn, TAcc>(in + row * ld_in + col);
                 if (dbits && dneg(dbits, row)) x = -x;
             }
         }
@@ -171,62 +192,20 @@ hipError_t run_pass(const TIn* in, int64_t ld_in, int64_t rows_valid, int64_t nc
                     const uint32_t* dbits, hipStream_t st) {
     const int64_t nlines = npad >> R;
     dim3 blk(WT);
-    const unsigned gy = (unsigned)((ncols_src + WC - 1) / WC);
-    if (gy == 0) return hipSuccess;
+    const int64_t nct = (ncols_src + WC - 1) / WC;
+    if (nct == 0) return hipSuccess;
     if (R == 8) {
-        hipLaunchKernelGGL((k_wht256<TIn, TOut, TAcc>), dim3((unsigned)nlines, gy), blk, 0, st, in,
-                           ld_in, rows_valid, ncols_src, out, ld_out, out_col0, p, skip ? 1 : 0,
-                           dbits);
+        hipLaunchKernelGGL((k_wht256<TIn, TOut, TAcc>), dim3((unsigned)(nlines * nct)), blk, 0, st,
+                           in, ld_in, rows_valid, ncols_src, out, ld_out, out_col0, p,
+                           skip ? 1 : 0, dbits, nct);
     } else {
         const int lpt = 256 >> R;
-        const unsigned gx = (unsigned)((nlines + lpt - 1) / lpt);
-        hipLaunchKernelGGL((k_wht_small<TIn, TOut, TAcc>), dim3(gx, gy), blk, 0, st, in, ld_in,
-                           rows_valid, ncols_src, out, ld_out, out_col0, p, R, nlines,
-                           skip ? 1 : 0, dbits);
+        const int64_t ntl = (nlines + lpt - 1) / lpt;
+        hipLaunchKernelGGL((k_wht_small<TIn, TOut, TAcc>), dim3((unsigned)(ntl * nct)), blk, 0, st,
+                           in, ld_in, rows_valid, ncols_src, out, ld_out, out_col0, p, R, nlines,
+                           skip ? 1 : 0, dbits, nct);
     }
     return hipGetLastError();
-}
-
-template <typename TS, typename TAcc>
-hipError_t wht_all(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t n, int64_t d,
-                   int64_t k, int64_t npad, const uint32_t* dbits, TS* T0, TS* T1, void** T_out,
-                   hipStream_t st) {
-    int L = 0;
-    while (((int64_t)1 << L) < npad) ++L;
-    const int64_t w = d + k;
-    int p = 0;
-    TS* cur_out = T0;
-    TS* cur_in = nullptr;
-    int64_t valid = n;
-    bool first = true;
-    if (L == 0) {  // n' = 1: T = D [A B]
-        SKI_HIP((run_pass<double, TS, TAcc>(A, lda, n, d, T0, w, 0, 1, 0, 0, false, dbits, st)));
-        SKI_HIP((run_pass<double, TS, TAcc>(B, ldb, n, k, T0, w, d, 1, 0, 0, false, dbits, st)));
-        *T_out = T0;
-        return hipSuccess;
-    }
-    while (p < L) {
-        const int R = std::min(8, L - p);
-        const bool last = (p + R == L);
-        const bool skip = first && !last;
-        if (first) {
-            SKI_HIP((run_pass<double, TS, TAcc>(A, lda, valid, d, cur_out, w, 0, npad, p, R, skip,
-                                                dbits, st)));
-            SKI_HIP((run_pass<double, TS, TAcc>(B, ldb, valid, k, cur_out, w, d, npad, p, R, skip,
-                                                dbits, st)));
-            valid = last ? npad : std::min(npad, ((n + (1 << R) - 1) >> R) << R);
-        } else {
-            SKI_HIP((run_pass<TS, TS, TAcc>(cur_in, w, valid, w, cur_out, w, 0, npad, p, R, false,
-                                            nullptr, st)));
-            valid = npad;
-        }
-        first = false;
-        p += R;
-        cur_in = cur_out;
-        cur_out = (cur_out == T0) ? T1 : T0;
-    }
-    *T_out = cur_in;
-    return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------
@@ -240,7 +219,7 @@ __global__ __launch_bounds__(GT) void k_gather_dense(const TX* __restrict__ X, i
                                                      int64_t ldb, int64_t k,
                                                      const int32_t* __restrict__ ptr,
                                                      const int32_t* __restrict__ src, double scale,
-                                                     TOut* __restrict__ out) {
+                                                     TOut* __restrict__ out, int64_t ldo) {
     const int64_t j = blockIdx.x;
     const int64_t ncol = ncx + k;
     const int64_t c0 = (int64_t)blockIdx.y * (GT * GU) + threadIdx.x;
@@ -248,20 +227,38 @@ __global__ __launch_bounds__(GT) void k_gather_dense(const TX* __restrict__ X, i
     TAcc acc[GU];
 #pragma unroll
     for (int u = 0; u < GU; ++u) acc[u] = 0;
-    for (int32_t pp = p0; pp < p1; ++pp) {
-        const int32_t e = src[pp];
+    auto value = [&](int32_t e, int64_t c) -> TAcc {
         const int64_t r = (int64_t)((uint32_t)e >> 1);
-        const bool neg = e & 1;
+        if (c < ncx) return load_as<TX, TAcc>(X + r * ldx + c);
+        return (TAcc)Bx[r * ldb + (c - ncx)];
+    };
+    // four bucket entries at a time: their loads are issued together, the sums still run
+    // in bucket order
+    int32_t pp = p0;
+    for (; pp + 4 <= p1; pp += 4) {
+        int32_t e[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) e[q] = src[pp + q];
 #pragma unroll
         for (int u = 0; u < GU; ++u) {
             const int64_t c = c0 + (int64_t)u * GT;
             if (c < ncol) {
-                TAcc x;
-                if (c < ncx)
-                    x = load_as<TX, TAcc>(X + r * ldx + c);
-                else
-                    x = (TAcc)Bx[r * ldb + (c - ncx)];
-                acc[u] = neg ? acc[u] - x : acc[u] + x;
+                TAcc x[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) x[q] = value(e[q], c);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[u] = (e[q] & 1) ? acc[u] - x[q] : acc[u] + x[q];
+            }
+        }
+    }
+    for (; pp < p1; ++pp) {
+        const int32_t e = src[pp];
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+            const int64_t c = c0 + (int64_t)u * GT;
+            if (c < ncol) {
+                const TAcc x = value(e, c);
+                acc[u] = (e & 1) ? acc[u] - x : acc[u] + x;
             }
         }
     }
@@ -270,9 +267,9 @@ __global__ __launch_bounds__(GT) void k_gather_dense(const TX* __restrict__ X, i
         const int64_t c = c0 + (int64_t)u * GT;
         if (c < ncol) {
             if constexpr (sizeof(TAcc) == 8)
-                out[j * ncol + c] = (TOut)(acc[u] * scale);
+                out[j * ldo + c] = (TOut)(acc[u] * scale);
             else
-                out[j * ncol + c] = from_f<TOut>(acc[u] * (float)scale);
+                out[j * ldo + c] = from_f<TOut>(acc[u] * (float)scale);
         }
     }
 }
@@ -331,48 +328,86 @@ __global__ __launch_bounds__(64) void k_gather_csr(const int64_t* __restrict__ r
 
 }  // namespace
 
-hipError_t launch_wht_sketch_dense(const double* A, int64_t lda, const double* B, int64_t ldb,
-                                   int64_t n, int64_t d, int64_t k, int64_t npad,
-                                   const uint32_t* dbits, void* T0, void* T1, Prec prec,
-                                   void** T_out, hipStream_t st) {
-    switch (prec) {
-        case Prec::F64:
-            return wht_all<double, double>(A, lda, B, ldb, n, d, k, npad, dbits, (double*)T0,
-                                           (double*)T1, T_out, st);
-        case Prec::F32:
-            return wht_all<float, float>(A, lda, B, ldb, n, d, k, npad, dbits, (float*)T0,
-                                         (float*)T1, T_out, st);
-        case Prec::BF16:
-            return wht_all<__hip_bfloat16, float>(A, lda, B, ldb, n, d, k, npad, dbits,
-                                                  (__hip_bfloat16*)T0, (__hip_bfloat16*)T1, T_out,
-                                                  st);
+namespace {
+
+// Dense sketch by column slabs: for each slab of sc columns of [A B], the first pass
+// reads A and B (with the signs D) into the slab buffer T (npad x sc, row-major), the later
+// passes run in place, and the gather sums the slab's rows into SA's columns.  A slab
+// buffer of ~128 MB stays in the 256 MB last-level cache between its passes, so HBM
+// carries little more than A once and SA once.  Rows of T that the first pass skips (no
+// row < n in their line) lie beyond the rows the later passes read.
+template <typename TS, typename TAcc, typename TOut>
+hipError_t sketch_slabs(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t n,
+                        int64_t d, int64_t k, int64_t npad, const uint32_t* dbits, TS* T,
+                        int64_t sc, const int32_t* bucket_ptr, const int32_t* src, int64_t m,
+                        double scale, TOut* SA, hipStream_t st) {
+    int L = 0;
+    while (((int64_t)1 << L) < npad) ++L;
+    const int64_t w = d + k;
+    for (int64_t c0 = 0; c0 < w; c0 += sc) {
+        const int64_t c1 = std::min(w, c0 + sc), cw = c1 - c0;
+        const int64_t a1 = std::min(c1, d), b0 = std::max(c0, d);
+        int p = 0;
+        int64_t valid = n;
+        bool first = true;
+        do {
+            const int R = std::min(8, L - p);
+            const bool last = (p + R >= L);
+            if (first) {
+                const bool skip = R > 0 && !last;
+                if (a1 > c0)
+                    SKI_HIP((run_pass<double, TS, TAcc>(A + c0, lda, valid, a1 - c0, T, sc, 0, npad,
+                                                        p, R, skip, dbits, st)));
+                if (c1 > b0)
+                    SKI_HIP((run_pass<double, TS, TAcc>(B + (b0 - d), ldb, valid, c1 - b0, T, sc,
+                                                        b0 - c0, npad, p, R, skip, dbits, st)));
+                valid = last ? npad : std::min(npad, ((n + (1 << R) - 1) >> R) << R);
+            } else {
+                SKI_HIP((run_pass<TS, TS, TAcc>(T, sc, valid, cw, T, sc, 0, npad, p, R, false,
+                                                nullptr, st)));
+                valid = npad;
+            }
+            first = false;
+            p += R;
+        } while (p < L);
+        dim3 grid((unsigned)m, (unsigned)((cw + GT * GU - 1) / (GT * GU)));
+        hipLaunchKernelGGL((k_gather_dense<TS, TAcc, TOut>), grid, dim3(GT), 0, st, T, sc, cw,
+                           nullptr, 0, 0, bucket_ptr, src, scale, SA + c0, w);
+        SKI_HIP(hipGetLastError());
     }
-    return hipErrorInvalidValue;
+    return hipSuccess;
 }
 
-// SA storage: FP64 for the FP64 form, FP32 for both mixed forms (the QR works in FP32)
-hipError_t launch_gather_dense(const void* T, int64_t ncols, const int32_t* bucket_ptr,
-                               const int32_t* src, int64_t m, double scale, Prec prec, void* SA,
-                               hipStream_t st) {
-    dim3 grid((unsigned)m, (unsigned)((ncols + GT * GU - 1) / (GT * GU)));
+}  // namespace
+
+int64_t sketch_slab_cols(int64_t npad, int64_t ncols, Prec prec) {
+    const int64_t te = prec == Prec::F64 ? 8 : (prec == Prec::F32 ? 4 : 2);
+    int64_t sc = ((int64_t)128 << 20) / (npad * te);  // ~128 MB of slab
+    sc = std::max<int64_t>(WC, sc / WC * WC);
+    return std::min(sc, ncols);
+}
+
+hipError_t launch_sketch_dense(const double* A, int64_t lda, const double* B, int64_t ldb,
+                               int64_t n, int64_t d, int64_t k, int64_t npad,
+                               const uint32_t* dbits, void* T, int64_t sc,
+                               const int32_t* bucket_ptr, const int32_t* src, int64_t m,
+                               double scale, Prec prec, void* SA, hipStream_t st) {
     switch (prec) {
         case Prec::F64:
-            hipLaunchKernelGGL((k_gather_dense<double, double, double>), grid, dim3(GT), 0, st,
-                               (const double*)T, ncols, ncols, nullptr, 0, 0, bucket_ptr, src,
-                               scale, (double*)SA);
-            break;
+            return sketch_slabs<double, double, double>(A, lda, B, ldb, n, d, k, npad, dbits,
+                                                        (double*)T, sc, bucket_ptr, src, m, scale,
+                                                        (double*)SA, st);
         case Prec::F32:
-            hipLaunchKernelGGL((k_gather_dense<float, float, float>), grid, dim3(GT), 0, st,
-                               (const float*)T, ncols, ncols, nullptr, 0, 0, bucket_ptr, src,
-                               scale, (float*)SA);
-            break;
+            return sketch_slabs<float, float, float>(A, lda, B, ldb, n, d, k, npad, dbits,
+                                                     (float*)T, sc, bucket_ptr, src, m, scale,
+                                                     (float*)SA, st);
         case Prec::BF16:
-            hipLaunchKernelGGL((k_gather_dense<__hip_bfloat16, float, float>), grid, dim3(GT), 0,
-                               st, (const __hip_bfloat16*)T, ncols, ncols, nullptr, 0, 0,
-                               bucket_ptr, src, scale, (float*)SA);
-            break;
+            return sketch_slabs<__hip_bfloat16, float, float>(A, lda, B, ldb, n, d, k, npad,
+                                                              dbits, (__hip_bfloat16*)T, sc,
+                                                              bucket_ptr, src, m, scale,
+                                                              (float*)SA, st);
     }
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_gather_plain(const double* A, int64_t lda, const double* B, int64_t ldb,
@@ -383,10 +418,10 @@ hipError_t launch_gather_plain(const double* A, int64_t lda, const double* B, in
     dim3 grid((unsigned)m, (unsigned)((ncols + GT * GU - 1) / (GT * GU)));
     if (prec == Prec::F64)
         hipLaunchKernelGGL((k_gather_dense<double, double, double>), grid, dim3(GT), 0, st, A, lda,
-                           d, B, ldb, k, bucket_ptr, src, scale, (double*)SA);
+                           d, B, ldb, k, bucket_ptr, src, scale, (double*)SA, ncols);
     else
         hipLaunchKernelGGL((k_gather_dense<double, float, float>), grid, dim3(GT), 0, st, A, lda, d,
-                           B, ldb, k, bucket_ptr, src, scale, (float*)SA);
+                           B, ldb, k, bucket_ptr, src, scale, (float*)SA, ncols);
     return hipGetLastError();
 }
 

@@ -43,7 +43,7 @@ struct ski_handle_s {
     bool sketched = false, factored = false;
     double cond_est = 0.0;
     // device buffers
-    DevBuf colrows, colneg, bucket_ptr, src, keys, table, dbits, T0, T1, SA;
+    DevBuf colrows, colneg, bucket_ptr, src, keys, table, dbits, T0, SA;
     DevBuf R, c, Rinv, RinvT, diag_add, tri_tmp, gemm_ws;
     DevBuf qr_part, qr_W, qr_T, qr_Y, qr_tau;
     DevBuf tkeys, tkeys_tmp, ttable, tp, tpay, ti, tv;
@@ -187,7 +187,7 @@ int ski_destroy(ski_handle h) {
     if (!h) return SKI_EINVAL;
     (void)hipDeviceSynchronize();
     DevBuf* all[] = {&h->colrows, &h->colneg, &h->bucket_ptr, &h->src, &h->keys, &h->table,
-                     &h->dbits, &h->T0, &h->T1, &h->SA, &h->R, &h->c, &h->Rinv, &h->RinvT,
+                     &h->dbits, &h->T0, &h->SA, &h->R, &h->c, &h->Rinv, &h->RinvT,
                      &h->diag_add, &h->tri_tmp, &h->gemm_ws, &h->qr_part, &h->qr_W, &h->qr_T,
                      &h->qr_Y, &h->qr_tau, &h->tkeys, &h->tkeys_tmp, &h->ttable, &h->tp,
                      &h->tpay, &h->ti, &h->tv, &h->u, &h->t, &h->v, &h->h, &h->delta, &h->z,
@@ -323,20 +323,15 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
     if (A->kind == SKI_DENSE && had) {
         const size_t te = elem_bytes(gprec);
         SKI_TRY(h, ensure(h->dbits, ((npad + 255) / 256) * 32), "alloc");
-        SKI_TRY(h, ensure(h->T0, (size_t)npad * ncols * te), "alloc");
-        SKI_TRY(h, ensure(h->T1, (size_t)npad * ncols * te), "alloc");
+        const int64_t sc = sketch_slab_cols(npad, ncols, gprec);
+        SKI_TRY(h, ensure(h->T0, (size_t)npad * sc * te), "alloc");
         prof_begin(h, PC_WHT, st);
         SKI_TRY(h, launch_dsign(npad, p->seed, P<uint32_t>(h->dbits), st), "dsign");
-        void* T = nullptr;
-        SKI_TRY(h, launch_wht_sketch_dense(A->a, A->lda, B, ldb, n, d, k, npad,
-                                           P<uint32_t>(h->dbits), h->T0.p, h->T1.p, gprec, &T, st),
-                "wht");
-        prof_end(h, st);
         const double scale = 1.0 / sqrt((double)npad * (double)p->s);
-        prof_begin(h, PC_GATHER, st);
-        SKI_TRY(h, launch_gather_dense(T, ncols, P<int32_t>(h->bucket_ptr), P<int32_t>(h->src), m,
-                                       scale, gprec, h->SA.p, st),
-                "gather");
+        SKI_TRY(h, launch_sketch_dense(A->a, A->lda, B, ldb, n, d, k, npad, P<uint32_t>(h->dbits),
+                                       h->T0.p, sc, P<int32_t>(h->bucket_ptr), P<int32_t>(h->src),
+                                       m, scale, gprec, h->SA.p, st),
+                "sketch");
         prof_end(h, st);
     } else if (A->kind == SKI_DENSE) {
         const double scale = 1.0 / sqrt((double)p->s);

@@ -129,13 +129,14 @@ hipError_t launch_dsign(int64_t npad, uint64_t seed, uint32_t* bits, hipStream_t
 
 // Walsh-Hadamard passes and the hashing gathers
 enum class Prec { F64 = 0, F32 = 1, BF16 = 2 };
-hipError_t launch_wht_sketch_dense(const double* A, int64_t lda, const double* B, int64_t ldb,
-                                   int64_t n, int64_t d, int64_t k, int64_t npad,
-                                   const uint32_t* dbits, void* T0, void* T1, Prec prec,
-                                   void** T_out, hipStream_t st);
-hipError_t launch_gather_dense(const void* T, int64_t ncols, const int32_t* bucket_ptr,
-                               const int32_t* src, int64_t m, double scale, Prec prec,
-                               void* SA, hipStream_t st);
+// dense sketch with the Hadamard row mix, by column slabs of sc columns through the slab
+// buffer T (npad x sc elements of the storage type), into SA (m x (d+k))
+int64_t sketch_slab_cols(int64_t npad, int64_t ncols, Prec prec);
+hipError_t launch_sketch_dense(const double* A, int64_t lda, const double* B, int64_t ldb,
+                               int64_t n, int64_t d, int64_t k, int64_t npad,
+                               const uint32_t* dbits, void* T, int64_t sc,
+                               const int32_t* bucket_ptr, const int32_t* src, int64_t m,
+                               double scale, Prec prec, void* SA, hipStream_t st);
 hipError_t launch_gather_plain(const double* A, int64_t lda, const double* B, int64_t ldb,
                                int64_t d, int64_t k, const int32_t* bucket_ptr,
                                const int32_t* src, int64_t m, double scale, Prec prec, void* SA,
