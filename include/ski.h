@@ -177,10 +177,16 @@ const char* ski_last_error(ski_handle h);
  * device time in ms and the number of launches since profiling was switched on.
  * Classes: 0 fused dense LSQR pass, 1 its partial-sum reduction, 2 triangular GEMV with
  * R^-1 / R^-T, 3 CSR product A z, 4 CSR product A^T u, 5 LSQR scalar step, 6 hashing
- * (Philox + bucket sort), 7 Walsh-Hadamard passes, 8 hashing gather, 9 whole QR of the
- * sketch, 10 explicit R^-1.  ms[] and count[] hold SKI_PROF_CLASSES entries. */
+ * (Philox + bucket sort), 7 dense sketch with the Hadamard mix (transform passes and
+ * hashing gather, by column slabs), 8 hashing gather without the Hadamard mix (dense or
+ * CSR), 9 whole QR of the sketch with CholeskyQR2 panels, 10 explicit R^-1, 11 whole QR
+ * with column-by-column Householder panels.  ms[] and count[] hold SKI_PROF_CLASSES
+ * entries.  ski_set_profiling(h, 1) times every class; ski_set_profiling_mask times only
+ * the classes whose bit is set (bit c for class c; 0 switches profiling off), which keeps
+ * the event records out of the other launches. */
 #define SKI_PROF_CLASSES 16
 int ski_set_profiling(ski_handle h, int32_t on);
+int ski_set_profiling_mask(ski_handle h, uint32_t mask);
 int ski_get_profile(ski_handle h, double* ms, int64_t* count);
 
 int ski_get_dims(ski_handle h, int64_t dims[6]);

@@ -21,7 +21,8 @@ STATUS_NAMES = {0: "OK", 1: "WNOCONV", 2: "WEARLY", -1: "EINVAL", -2: "ENOMEM",
 
 EXPORTED = ["ski_create", "ski_destroy", "ski_params_default", "ski_sketch", "ski_factor",
             "ski_solve", "ski_gradients", "ski_last_error", "ski_get_dims", "ski_get_hash",
-            "ski_get_dsign", "ski_get_SA", "ski_get_R", "ski_set_profiling", "ski_get_profile"]
+            "ski_get_dsign", "ski_get_SA", "ski_get_R", "ski_set_profiling",
+            "ski_set_profiling_mask", "ski_get_profile"]
 PROF_CLASSES = 16
 PROF_NAMES = ["lsqr_pass", "pass_reduce", "tri_gemv", "spmv_csr", "spmv_csrT", "lsqr_step",
               "hash", "wht_gather", "gather", "qr", "trtri", "qr_householder"]
@@ -83,6 +84,7 @@ def load():
     lib.ski_get_SA.argtypes = [H, P]
     lib.ski_get_R.argtypes = [H, P, P, P]
     lib.ski_set_profiling.argtypes = [H, i32]
+    lib.ski_set_profiling_mask.argtypes = [H, C.c_uint32]
     lib.ski_get_profile.argtypes = [H, P, P]
     for name in EXPORTED:
         if name not in ("ski_params_default", "ski_last_error"):

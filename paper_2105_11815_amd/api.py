@@ -165,8 +165,15 @@ class Solver:
         return gA, gB
 
     # -- measurement ------------------------------------------------------
-    def set_profiling(self, on=True):
-        rc = self._lib.ski_set_profiling(self._h, 1 if on else 0)
+    def set_profiling(self, on=True, classes=None):
+        """Time every kernel class (on), none (off), or only the named classes."""
+        if classes is None:
+            rc = self._lib.ski_set_profiling(self._h, 1 if on else 0)
+        else:
+            mask = 0
+            for name in classes:
+                mask |= 1 << L.PROF_NAMES.index(name)
+            rc = self._lib.ski_set_profiling_mask(self._h, mask if on else 0)
         if rc != L.SKI_OK:
             self._raise(rc, "ski_set_profiling")
 

@@ -44,7 +44,7 @@ hipError_t launch_lsqr_init(LsqrState* stt, int64_t d, int k, const double* wp, 
                             double* h, double* delta, double tau_a, hipStream_t st);
 hipError_t launch_lsqr_step(LsqrState* stt, int64_t d, int k, const double* wp, double* v,
                             double* h, double* delta, double tau_r, int64_t it_max,
-                            hipStream_t st);
+                            int32_t* hflag, hipStream_t st);  // hflag: status word when k == 1
 hipError_t launch_final_y(const LsqrState* stt, int64_t d, int k, const double* c,
                           const double* delta, double* y, hipStream_t st);
 hipError_t launch_scale_copy(const double* x, int64_t rows, int64_t cols, int64_t ldx, double s,
@@ -53,6 +53,7 @@ hipError_t launch_cg_init(LsqrState* stt, int64_t d, int k, const double* rhs, d
                           double* y, double tol, hipStream_t st);
 hipError_t launch_cg_step(LsqrState* stt, int64_t d, int k, const double* q, double* r, double* p,
                           double* y, int64_t it_max, hipStream_t st);
+// flag <- 1 if every column has stopped (flag may be host memory mapped for the device)
 hipError_t launch_all_done(const LsqrState* stt, int k, int32_t* flag, hipStream_t st);
 
 }  // namespace ski

@@ -511,11 +511,14 @@ __global__ __launch_bounds__(1024) void k_lsqr_step(LsqrState* __restrict__ stt,
                                                     const double* __restrict__ wp,
                                                     double* __restrict__ v, double* __restrict__ h,
                                                     double* __restrict__ delta, double tau_r,
-                                                    int64_t it_max) {
+                                                    int64_t it_max, int32_t* hflag) {
     __shared__ double sh[16];
     const int j = blockIdx.x;
     LsqrState& S = stt[j];
-    if (S.done) return;
+    if (S.done) {
+        if (hflag && threadIdx.x == 0) *hflag = 1;
+        return;
+    }
     const double beta = sqrt(S.beta2);
     const double alpha_old = S.alpha;
     const double rhobar = S.rhobar, phibar = S.phibar, anorm2_old = S.anorm2;
@@ -565,6 +568,8 @@ __global__ __launch_bounds__(1024) void k_lsqr_step(LsqrState* __restrict__ stt,
             S.done = 1;
             S.status = SKI_WNOCONV;
         }
+        // one right-hand side: this workgroup's state is the whole status word
+        if (hflag) *hflag = S.done;
     }
 }
 
@@ -803,9 +808,9 @@ hipError_t launch_lsqr_init(LsqrState* stt, int64_t d, int k, const double* wp, 
 
 hipError_t launch_lsqr_step(LsqrState* stt, int64_t d, int k, const double* wp, double* v,
                             double* h, double* delta, double tau_r, int64_t it_max,
-                            hipStream_t st) {
+                            int32_t* hflag, hipStream_t st) {
     hipLaunchKernelGGL(k_lsqr_step, dim3((unsigned)k), dim3(1024), 0, st, stt, d, k, wp, v, h, delta,
-                       tau_r, it_max);
+                       tau_r, it_max, k == 1 ? hflag : nullptr);
     return hipGetLastError();
 }
 

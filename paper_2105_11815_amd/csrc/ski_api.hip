@@ -47,7 +47,7 @@ struct ski_handle_s {
     DevBuf R, c, Rinv, RinvT, diag_add, tri_tmp, gemm_ws;
     DevBuf qr_part, qr_W, qr_T, qr_Y, qr_tau;
     DevBuf tkeys, tkeys_tmp, ttable, tp, tpay, ti, tv;
-    DevBuf u, t, v, h, delta, z, wp, g, gpart, upart, y, st, flag;
+    DevBuf u, t, v, h, delta, z, wp, g, gpart, upart, y, st;
     DevBuf cg_r, cg_p, cg_q, t2, dtmp, gemm_ws2;
     hipStream_t st2 = nullptr;           // second stream of the QR's look-ahead
     hipEvent_t qev[4] = {};
@@ -60,6 +60,8 @@ struct ski_handle_s {
     std::vector<hipEvent_t> pool;
     std::vector<std::pair<int, int>> open_pairs;  // (class, index of the start event)
     size_t pool_used = 0;
+    uint32_t prof_mask = 0;      // classes timed (bit c: class c)
+    bool prof_recording = false;  // the last prof_begin recorded a start event
     double prof_ms[SKI_PROF_CLASSES] = {};
     int64_t prof_cnt[SKI_PROF_CLASSES] = {};
 };
@@ -137,15 +139,18 @@ hipEvent_t pool_event(ski_handle h) {
 
 // bracket the launches between prof_begin and prof_end with an event pair
 void prof_begin(ski_handle h, int cls, hipStream_t st) {
-    if (!h->prof) return;
+    h->prof_recording = false;
+    if (!h->prof || !((h->prof_mask >> cls) & 1u)) return;
     hipEvent_t e = pool_event(h);
     if (!e) return;
     (void)hipEventRecord(e, st);
     h->open_pairs.push_back({cls, (int)h->pool_used - 1});
+    h->prof_recording = true;
 }
 void prof_end(ski_handle h, hipStream_t st) {
     // the end event directly follows its start event in the pool (pairs never nest)
-    if (!h->prof || h->open_pairs.empty()) return;
+    if (!h->prof_recording) return;
+    h->prof_recording = false;
     hipEvent_t e = pool_event(h);
     if (!e) return;
     (void)hipEventRecord(e, st);
@@ -191,7 +196,7 @@ int ski_destroy(ski_handle h) {
                      &h->diag_add, &h->tri_tmp, &h->gemm_ws, &h->qr_part, &h->qr_W, &h->qr_T,
                      &h->qr_Y, &h->qr_tau, &h->tkeys, &h->tkeys_tmp, &h->ttable, &h->tp,
                      &h->tpay, &h->ti, &h->tv, &h->u, &h->t, &h->v, &h->h, &h->delta, &h->z,
-                     &h->wp, &h->g, &h->gpart, &h->upart, &h->y, &h->st, &h->flag, &h->cg_r,
+                     &h->wp, &h->g, &h->gpart, &h->upart, &h->y, &h->st, &h->cg_r,
                      &h->cg_p, &h->cg_q, &h->t2, &h->dtmp, &h->gemm_ws2};
     for (DevBuf* b : all) release(*b);
     if (h->ev_ok)
@@ -508,7 +513,6 @@ int alloc_solve_ws(ski_handle h, int k) {
     const int64_t G = std::max<int64_t>({PASS_WG, spmv_csr_groups(n), 1});
     SKI_TRY(h, ensure(h->upart, G * k * 8), "alloc");
     SKI_TRY(h, ensure(h->st, k * sizeof(LsqrState)), "alloc");
-    SKI_TRY(h, ensure(h->flag, 64), "alloc");
     return SKI_OK;
 }
 
@@ -522,25 +526,34 @@ hipError_t apply_Rinv(ski_handle h, const double* Mtx, bool upper, const double*
 // Convergence status read back with a one-iteration lag: after iteration i the all-done
 // word is copied to pinned host memory and an event recorded; the host waits on the event
 // of iteration i-1 only, so at most one idle iteration is ever launched.
+// The host learns that the iterations have stopped through a status word in pinned host
+// memory mapped for the device: the iteration's last kernel writes it (the scalar step
+// itself for one right-hand side, else a one-thread kernel), an event marks the
+// iteration, and the host reads the word one iteration later, so the device always has
+// the next iteration queued.
 struct LagFlag {
-    int32_t* host = nullptr;  // [2]
+    volatile int32_t* host = nullptr;  // [2], one slot per iteration parity
+    int32_t* dev = nullptr;            // the same words, device address
     hipEvent_t ev[2] = {nullptr, nullptr};
     bool stop = false;
-    int init(ski_handle h, int k, hipStream_t st) {
-        (void)k;
-        (void)st;
-        SKI_TRY(h, hipHostMalloc((void**)&host, 2 * sizeof(int32_t), hipHostMallocDefault),
+    int init(ski_handle h) {
+        int32_t* p = nullptr;
+        SKI_TRY(h, hipHostMalloc((void**)&p, 2 * sizeof(int32_t),
+                                 hipHostMallocMapped | hipHostMallocCoherent),
                 "pinned");
+        host = p;
         host[0] = host[1] = 0;
+        SKI_TRY(h, hipHostGetDevicePointer((void**)&dev, p, 0), "device pointer");
         for (auto& e : ev) SKI_TRY(h, hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
         return SKI_OK;
     }
-    int post(ski_handle h, int k, hipStream_t st, int64_t it) {
+    // the slot that the step kernel of iteration it (counted from 1) writes
+    int32_t* slot_dev(int64_t it) const { return dev + (it & 1); }
+    // written: the iteration's step kernel already wrote the slot
+    int post(ski_handle h, int k, hipStream_t st, int64_t it, bool written) {
         const int slot = (int)(it & 1);
-        SKI_TRY(h, launch_all_done(P<LsqrState>(h->st), k, P<int32_t>(h->flag) + slot, st), "flag");
-        SKI_TRY(h, hipMemcpyAsync(host + slot, P<int32_t>(h->flag) + slot, sizeof(int32_t),
-                                  hipMemcpyDeviceToHost, st),
-                "flag copy");
+        if (!written)
+            SKI_TRY(h, launch_all_done(P<LsqrState>(h->st), k, dev + slot, st), "flag");
         SKI_TRY(h, hipEventRecord(ev[slot], st), "event");
         return SKI_OK;
     }
@@ -553,7 +566,7 @@ struct LagFlag {
     void release() {
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
-        if (host) (void)hipHostFree(host);
+        if (host) (void)hipHostFree((void*)host);
         host = nullptr;
     }
 };
@@ -642,8 +655,8 @@ int solve_lls(ski_handle h, const double* B, int k, int64_t ldb, double* X, int6
     SKI_TRY(h, launch_lsqr_init(S, d, k, wp, v, hh, dl, h->p.tau_a, st), "init");
     const int32_t* done1 = (k == 1) ? &S[0].done : nullptr;
     LagFlag lf;
-    int out = lf.init(h, k, st);
-    if (out == SKI_OK) out = lf.post(h, k, st, 0);
+    int out = lf.init(h);
+    if (out == SKI_OK) out = lf.post(h, k, st, 0, false);
     if (out == SKI_OK && lf.wait(h, 0) == 1) lf.stop = true;
     int64_t it = 0;
     while (out == SKI_OK && !lf.stop && it < h->p.it_max) {
@@ -685,7 +698,8 @@ int solve_lls(ski_handle h, const double* B, int k, int64_t ldb, double* X, int6
             prof_end(h, st);
             prof_begin(h, PC_STEP, st);
             if (e == hipSuccess)
-                e = launch_lsqr_step(S, d, k, wp, v, hh, dl, h->p.tau_r, h->p.it_max, st);
+                e = launch_lsqr_step(S, d, k, wp, v, hh, dl, h->p.tau_r, h->p.it_max,
+                                     lf.slot_dev(it + 1), st);
             prof_end(h, st);
             if (e != hipSuccess) {
                 out = hip_fail(h, e, "lsqr iteration");
@@ -695,7 +709,7 @@ int solve_lls(ski_handle h, const double* B, int k, int64_t ldb, double* X, int6
         ++it;
         // status of this iteration is posted now and read one iteration later, so the
         // device always has the next iteration queued while the host checks
-        out = lf.post(h, k, st, it);
+        out = lf.post(h, k, st, it, k == 1);
         if (out == SKI_OK && it >= 2 && lf.wait(h, it - 1) == 1) break;
     }
     lf.release();
@@ -744,8 +758,8 @@ int solve_normal(ski_handle h, const double* G, int k, int64_t ldg, double* Z, i
     SKI_TRY(h, gemm_f64(false, false, d, k, d, 1.0, RinvT, d, g, k, 0.0, wp, k, gw, st), "rhs");
     SKI_TRY(h, launch_cg_init(S, d, k, wp, r, pp, y, h->p.tau_r, st), "cg init");
     LagFlag lf;
-    int out = lf.init(h, k, st);
-    if (out == SKI_OK) out = lf.post(h, k, st, 0);
+    int out = lf.init(h);
+    if (out == SKI_OK) out = lf.post(h, k, st, 0, false);
     if (out == SKI_OK && lf.wait(h, 0) == 1) lf.stop = true;
     int64_t it = 0;
     while (out == SKI_OK && !lf.stop && it < h->p.it_max) {
@@ -760,7 +774,7 @@ int solve_normal(ski_handle h, const double* G, int k, int64_t ldg, double* Z, i
             break;
         }
         ++it;
-        out = lf.post(h, k, st, it);
+        out = lf.post(h, k, st, it, false);
         if (out == SKI_OK && it >= 2 && lf.wait(h, it - 1) == 1) break;
     }
     lf.release();
@@ -835,12 +849,17 @@ int ski_gradients(ski_handle h, const double* X, int64_t ldx, const double* B, i
 }
 
 int ski_set_profiling(ski_handle h, int32_t on) {
+    return ski_set_profiling_mask(h, on ? 0xffffffffu : 0u);
+}
+
+int ski_set_profiling_mask(ski_handle h, uint32_t mask) {
     if (!h) return SKI_EINVAL;
     if (h->prof) {
         (void)hipDeviceSynchronize();
         prof_collect(h);
     }
-    h->prof = on != 0;
+    h->prof = mask != 0;
+    h->prof_mask = mask;
     for (int c = 0; c < SKI_PROF_CLASSES; ++c) {
         h->prof_ms[c] = 0;
         h->prof_cnt[c] = 0;
