@@ -115,6 +115,52 @@ def traffic_for_pass(n_launch_bytes):
         return None
 
 
+def sparse_run(P, torch):
+    """The sparse 200000 x 5000 workload (CSR, power-law rows): a warm-up solve, the median
+    of three timed solves, the optimality certificate recomputed in FP64 on the host, and a
+    per-class breakdown from one more (profiled) solve."""
+    import scipy.sparse as sp
+    import workloads
+    c = workloads.CASES["sparse"]
+    n, d = c["n"], c["d"]
+    rp, ci, va, b = workloads.sparse_power_law(n=n, d=d, case=c["case"])
+    dev = lambda a, t: torch.as_tensor(a).to(device="cuda", dtype=t)
+    Acsr = ("csr", dev(rp, torch.int64), dev(ci, torch.int32), dev(va, torch.float64), (n, d))
+    bt = dev(b, torch.float64)
+    kw = dict(m=c["m"], s=c["s"], seed=2003, tau_r=1e-10, hadamard=False)
+    S = P.Solver()
+    one_solve(P, S, Acsr, bt, **kw)
+    torch.cuda.synchronize()
+    times, infos = [], []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        X, info, rc = one_solve(P, S, Acsr, bt, **kw)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+        infos.append(info)
+    S.set_profiling(True)
+    one_solve(P, S, Acsr, bt, **kw)
+    torch.cuda.synchronize()
+    prof = S.profile()
+    S.set_profiling(False)
+    S.close()
+    A = sp.csr_matrix((va, ci, rp), shape=(n, d))
+    x = X[:, 0].cpu().numpy()
+    r = b - A @ x
+    cert = float(np.linalg.norm(A.T @ r) / (sp.linalg.norm(A) * np.linalg.norm(r)))
+    info = infos[-1]
+    return {"workload": f"sparse {n}x{d} CSR, nnz {int(rp[-1])}, power-law rows (mean 10, max 500) "
+                        f"+ 1e-6 identity rows, b = 1; 2-hashing, m {c['m']}; Householder QR; "
+                        "LSQR with CSR products to 1e-10",
+            "ms_median": round(float(np.median(times)), 3), "ms_all": [round(t, 3) for t in times],
+            "iters": int(info["iters"]), "status": rc, "optimality": cert,
+            "ms_sketch": round(float(info["ms_sketch"]), 3),
+            "ms_factor": round(float(info["ms_factor"]), 3),
+            "ms_solve": round(float(info["ms_solve"]), 3),
+            "kernel_ms": {k: {"ms_total": round(v[0], 3), "launches": v[1]}
+                          for k, v in prof.items() if v[1]}}
+
+
 def mixed_runs(P, torch, At, bt, base_kw, forms, label):
     """Time one solve per precision form (after a warm-up solve) and recompute the
     residual and the optimality certificate ||A^T r|| / (||A||_F ||r||) in FP64."""
@@ -155,6 +201,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-sparse", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the solver has no multi-GPU path, so --gpus "
@@ -256,6 +303,11 @@ def main():
         "rnorm": float(r.norm()), "kernel_ms": phases, "roofline": roofline,
         "copy_GBps_reference": round(copy_gbps, 1),
     }
+
+    if not args.no_sparse:
+        log("sparse 200000x5000 workload ...")
+        out["sparse_200000x5000"] = sparse_run(P, torch)
+        torch.cuda.empty_cache()
 
     if not args.no_mixed:
         forms = [("fp64", {}), ("fp32", dict(sketch_prec="fp32", qr_prec="fp32")),

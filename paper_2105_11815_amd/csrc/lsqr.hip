@@ -367,13 +367,25 @@ __global__ __launch_bounds__(256) void k_spmv_csrT(const int32_t* __restrict__ t
     }
 }
 
-__global__ __launch_bounds__(256) void k_reduce_upart(const double* __restrict__ upart, int64_t G,
-                                                      int k, LsqrState* __restrict__ stt) {
-    const int j = threadIdx.x;
-    if (j >= k || stt[j].done) return;
+// beta2_j = sum of the G partials of column j: one workgroup per column; thread t sums
+// the partials t, t + 1024, ... in order, then the wave sums and the 16 wave totals are
+// added in a fixed order
+__global__ __launch_bounds__(1024) void k_reduce_upart(const double* __restrict__ upart, int64_t G,
+                                                       int k, LsqrState* __restrict__ stt) {
+    __shared__ double sh[16];
+    const int j = blockIdx.x;
+    if (stt[j].done) return;
     double s = 0;
-    for (int64_t q = 0; q < G; ++q) s += upart[q * k + j];
-    stt[j].beta2 = s;
+    for (int64_t q = threadIdx.x; q < G; q += 1024) s += upart[q * k + j];
+    s = wave_sum(s);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) sh[wv] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0;
+        for (int q = 0; q < 16; ++q) t += sh[q];
+        stt[j].beta2 = t;
+    }
 }
 
 // row index of every stored entry (for CSR(A^T))
@@ -762,7 +774,7 @@ hipError_t launch_spmv_csr(const int64_t* rp, const int32_t* ci, const double* v
     hipLaunchKernelGGL(k_spmv_csr, dim3((unsigned)G), dim3(256), 0, st, rp, ci, va, n, k, z, u, stt,
                        coef_m1 ? 1 : 0, upart);
     SKI_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_reduce_upart, dim3(1), dim3(256), 0, st, upart, G, k, stt);
+    hipLaunchKernelGGL(k_reduce_upart, dim3((unsigned)k), dim3(1024), 0, st, upart, G, k, stt);
     return hipGetLastError();
 }
 
@@ -795,7 +807,7 @@ hipError_t launch_combine_u(const double* t, double* u, int64_t n, int k, const 
     hipLaunchKernelGGL(k_combine_u, dim3((unsigned)G), dim3(256), 0, st, t, u, n, k, stt,
                        coef_m1 ? 1 : 0, upart, rpw);
     SKI_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_reduce_upart, dim3(1), dim3(256), 0, st, upart, G, k, stt_w);
+    hipLaunchKernelGGL(k_reduce_upart, dim3((unsigned)k), dim3(1024), 0, st, upart, G, k, stt_w);
     return hipGetLastError();
 }
 

@@ -252,6 +252,67 @@ def test_sparse_x_parity(ski):
         S.close()
 
 
+# -------------------------------------------------------------------------- full sizes
+def test_full_size_dense_matches_the_direct_solution(ski):
+    # the dense 50000 x 4000 workload with the benchmark's sketch (gamma 1.7, m 6800, s 3,
+    # seed 2002); x* from the oracle's direct QR solve (tests/golden/make_dense_xstar.py)
+    import os
+    c = workloads.CASES["dense"]
+    _say(f"full-size dense n={c['n']} d={c['d']}")
+    A, b = workloads.dense_coherent(n=c["n"], d=c["d"], case=c["case"])
+    xs = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "dense_50000x4000_xstar.txt"))
+    At, bt = dev(A), dev(b)
+    # run to stagnation: x equals x* to the stated 1e-10 relative
+    S = ski.Solver()
+    S.sketch(At, bt, m=c["m"], s=c["s"], seed=2002, tau_r=1e-14, it_max=400).factor()
+    X, infos, rc = S.solve()
+    x = X[:, 0].cpu().numpy()
+    assert rc in (0, 1)
+    assert np.linalg.norm(x - xs) <= 1e-10 * np.linalg.norm(xs)
+    S.close()
+    # the benchmark's tolerance 1e-10: (TC-lsqr) bounds the optimality of the residual,
+    # ||A^T r|| <= ||R|| ||W^T r|| <= ||R||_F tau wnorm ||r||, with rounding of r beside it
+    S = ski.Solver()
+    S.sketch(At, bt, m=c["m"], s=c["s"], seed=2002, tau_r=1e-10).factor()
+    X, infos, rc = S.solve()
+    x = X[:, 0].cpu().numpy()
+    r = b - A @ x
+    cert = np.linalg.norm(A.T @ r) / (np.linalg.norm(A) * np.linalg.norm(r))
+    R = S.get_R()[0]
+    bound = 1e-10 * np.linalg.norm(R) * infos[0]["wnorm_est"] / np.linalg.norm(A) + 1e-13
+    _say(f"  tau 1e-10: iters {infos[0]['iters']} certificate {cert:.3e} (bound {bound:.3e}) "
+         f"x error {np.linalg.norm(x - xs) / np.linalg.norm(xs):.3e}")
+    assert rc == 0 and cert <= bound
+    assert abs(np.linalg.norm(r) - np.linalg.norm(b - A @ xs)) <= 1e-12 * np.linalg.norm(r)
+    S.close()
+
+
+def test_full_size_sparse_optimality(ski):
+    # the sparse 200000 x 5000 workload with the sketch of the sparse solver (gamma 1.5,
+    # m 7500, s 2, no Hadamard): a dense direct solve is out of reach, so the pin is the
+    # optimality certificate recomputed in FP64 against the bound (TC-lsqr) implies
+    c = workloads.CASES["sparse"]
+    n, d = c["n"], c["d"]
+    _say(f"full-size sparse n={n} d={d}")
+    rp, ci, va, b = workloads.sparse_power_law(n=n, d=d, case=c["case"])
+    A = sp.csr_matrix((va, ci, rp), shape=(n, d))
+    S = ski.Solver()
+    S.sketch(("csr", dev(rp, torch.int64), dev(ci, torch.int32), dev(va), (n, d)), dev(b),
+             m=c["m"], s=c["s"], seed=2003, tau_r=1e-10).factor()
+    X, infos, rc = S.solve()
+    x = X[:, 0].cpu().numpy()
+    r = b - A @ x
+    anorm = sp.linalg.norm(A)
+    cert = np.linalg.norm(A.T @ r) / (anorm * np.linalg.norm(r))
+    R = S.get_R()[0]
+    bound = 1e-10 * np.linalg.norm(R) * infos[0]["wnorm_est"] / anorm + 1e-13
+    _say(f"  iters {infos[0]['iters']} certificate {cert:.3e} (bound {bound:.3e})")
+    assert rc == 0 and cert <= bound
+    # LSQR's residual estimate matches the recomputed residual
+    assert abs(infos[0]["rnorm"] - np.linalg.norm(r)) <= 1e-8 * np.linalg.norm(r)
+    S.close()
+
+
 def test_batched_rhs_and_early_exit(ski):
     n, d, k = 5000, 120, 5
     _say(f"batched solve n={n} d={d} k={k}")

@@ -1,6 +1,7 @@
 """Pins of the oracle's Steps 2-5 of Algorithm 1 and of its adjoint (no GPU)."""
 
 import math
+import os
 
 import numpy as np
 import pytest
@@ -248,3 +249,17 @@ def test_gradients_closed_form_and_adjoint_solve():
         fd = ((Xp - Xm) * G).sum() / (2 * h)
         an = (gA * dA).sum() + (gB * dB).sum()
         assert abs(fd - an) <= 1e-6 * max(1.0, abs(an))
+
+
+def test_stored_dense_reference_solves_the_normal_equations():
+    # the stored x* of the dense 50000 x 4000 workload (tests/golden/make_dense_xstar.py)
+    # must satisfy A^T (b - A x*) = 0 to rounding: the definition of the least-squares
+    # solution, checked on a freshly generated A
+    path = os.path.join(os.path.dirname(__file__), "golden", "dense_50000x4000_xstar.txt")
+    xs = np.loadtxt(path)
+    c = workloads.CASES["dense"]
+    A, b = workloads.dense_coherent(n=c["n"], d=c["d"], case=c["case"])
+    r = b - A @ xs
+    cert = np.linalg.norm(A.T @ r) / (np.linalg.norm(A) * np.linalg.norm(r))
+    assert xs.shape == (c["d"],)
+    assert cert < 1e-13
