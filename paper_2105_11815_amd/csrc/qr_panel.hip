@@ -40,6 +40,7 @@ using namespace tile;
 constexpr int GR = 64;       // rows per workgroup of the Gram / apply / V2 kernels
 constexpr int RSL = 16;      // slices of the partial-sum reduction
 constexpr double EPS_SERIES = 1e-8;  // |G2 - I| below which R2 comes from the series
+constexpr double EPS_FIRST = 1e-11;  // ... from its first-order term alone
 
 // rows [r0, r1) of an nb-column column-major block -> sh[GR][PP], zero padded
 template <typename T>
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(256) void k_cqr_chol2(const T* __restrict__ G, int 
     __shared__ T sg[PB];
     __shared__ int bad;
     const int t = threadIdx.x;
-    int off = 0, big = 0;
+    int off = 0, big = 0, second = 0;
     for (int o = t; o < PB * PB; o += 256) {
         const int i = o / PB, j = o % PB;
         const T g = (i < nb && j < nb) ? G[o] : (i == j ? (T)1 : (T)0);
@@ -213,6 +214,7 @@ __global__ __launch_bounds__(256) void k_cqr_chol2(const T* __restrict__ G, int 
         const T e = fabs(g - (i == j ? (T)1 : (T)0));
         off |= !(e <= (T)0.01);
         big |= !(e <= (T)EPS_SERIES);
+        second |= !(e <= (T)EPS_FIRST);
         B[i][j] = R1[o];
         const int r = o % PB, c = o / PB;  // column-major walk of Q1 for coalescing
         C[r][c] = (r < nb && c < nb) ? Q[c * ldq + r] : (T)0;
@@ -220,7 +222,19 @@ __global__ __launch_bounds__(256) void k_cqr_chol2(const T* __restrict__ G, int 
     if (t == 0) bad = 0;
     off = __syncthreads_or(off);
     big = __syncthreads_or(big);
-    if (big) {
+    second = __syncthreads_or(second);
+    if (!second) {
+        // |G2 - I| <= EPS_FIRST: to first order R2 = I + F, R2^-1 = I - F with
+        // F = up(G2 - I); the neglected terms are O(|G2 - I|^2), below 1e-18
+        tile_eval(D, t, [&](int i, int j) {
+            const T e = A[i][j] - (i == j ? (T)1 : (T)0);
+            return i < j ? e : (i == j ? e * (T)0.5 : (T)0);
+        });
+        // R = R1 + F R1
+        tile_mma(B, t, [&](int i, int k) { return D[i][k]; }, [&](int k, int j) { return B[k][j]; },
+                 KFullUpper{}, [&](int i, int j, T v) { return B[i][j] + v; });
+        tile_eval(A, t, [&](int i, int j) { return (i == j ? (T)1 : (T)0) - D[i][j]; });
+    } else if (big) {
         tile_chol(A, t, &bad);
         // R = R2 R1 (both upper)
         tile_mma(B, t, [&](int i, int k) { return A[i][k]; }, [&](int k, int j) { return B[k][j]; },

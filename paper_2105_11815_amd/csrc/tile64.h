@@ -12,7 +12,8 @@ namespace tile {
 
 constexpr int PB = 64;       // tile size
 constexpr int PP = PB + 1;   // LDS pitch of a PB x PB tile
-constexpr int TB = 8;        // diagonal block of the tile factorisations
+constexpr int TB = 16;       // diagonal block of the Cholesky and LU factorisations
+constexpr int TI = 8;        // diagonal block of the triangular inverse (8 x 8, 64 threads)
 
 // compiler ordering point for LDS traffic between the lanes of one wavefront (a wavefront
 // executes its LDS instructions in order)
@@ -197,24 +198,24 @@ __device__ __forceinline__ void tile_chol(T (*A)[PP], int t, int* bad) {
 template <typename T>
 __device__ __forceinline__ void tile_trinv(T (*A)[PP], int t, bool unit) {
     {
-        T x[TB];
-        const int b = t >> 3, j = t & 7, o = TB * b;
+        T x[TI];
+        const int b = t >> 3, j = t & 7, o = TI * b;
         if (t < PB) {
-            T inv[TB];  // reciprocals of the diagonal, off the substitution's dependency chain
+            T inv[TI];  // reciprocals of the diagonal, off the substitution's dependency chain
 #pragma unroll
-            for (int i = 0; i < TB; ++i) inv[i] = unit ? (T)1 : (T)1 / A[o + i][o + i];
+            for (int i = 0; i < TI; ++i) inv[i] = unit ? (T)1 : (T)1 / A[o + i][o + i];
 #pragma unroll
-            for (int i = TB - 1; i >= 0; --i) {
+            for (int i = TI - 1; i >= 0; --i) {
                 T s = i == j ? (T)1 : (T)0;
 #pragma unroll
-                for (int l = i + 1; l < TB; ++l) s -= A[o + i][o + l] * x[l];
+                for (int l = i + 1; l < TI; ++l) s -= A[o + i][o + l] * x[l];
                 x[i] = s * inv[i];
             }
         }
         __syncthreads();
         if (t < PB)
 #pragma unroll
-            for (int i = 0; i < TB; ++i)
+            for (int i = 0; i < TI; ++i)
                 if (i <= j) A[o + i][o + j] = x[i];
         __syncthreads();
     }
