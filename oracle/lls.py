@@ -25,6 +25,15 @@ The adjoint solves (A^T A) Z = G by conjugate gradients on the preconditioned
 normal equations R^-T A^T A R^-1 (R Z) = R^-T G with the same R.  With the
 residual r = B - A X and the loss sum(X * G), the gradients are
 grad_B = A Z and grad_A = r Z^T - (A Z) X^T.
+
+Rank-deficient input (Step 2 in the form S A V-hat = Q R, Section 6, parameter
+rcond): a column-pivoted QR of SA, truncated to its leading p x p block R11.
+The oracle pivots greedily (LAPACK's xGEQP3, largest remaining column norm
+first) in place of the randomised pivoting of R-CPQR; both choose a valid
+column set, and the quantities that parity compares (p, the residual, and the
+solution on a given column set) do not depend on which.  V_1 holds the first
+p pivots J, so x_s = V_1 R11^-1 Q_1^T S b, W = A V_1 R11^-1 = A_J R11^-1 and
+x = V_1 R11^-1 y vanishes outside J.
 """
 
 import math
@@ -53,6 +62,56 @@ def factor(SA_aug, d):
 def rank_ok(R, rcond):
     dg = np.abs(np.diag(R))
     return bool(dg.size == 0 or (dg[0] > 0 and np.all(dg >= rcond * dg[0])))
+
+
+def rank_count(R, rcond):
+    """p = the number of leading diagonal entries with |r_qq| >= rcond |r_11|.
+
+    Reading of Section 6 (parameter rcond): the threshold is taken relative to
+    |r_11|, and R11 ends at the first diagonal entry below it, so that R11 is
+    never ill-conditioned by a small pivot in its middle.  Greedy pivoting
+    gives a non-increasing |diag(R)|, where this is the largest such q."""
+    dg = np.abs(np.diag(R))
+    if dg.size == 0 or not dg[0] > 0:
+        return 0
+    bad = np.flatnonzero(~(dg >= rcond * dg[0]))
+    return int(bad[0]) if bad.size else int(dg.size)
+
+
+def factor_pivoted(SA_aug, d, rcond):
+    """Step 2 with column pivoting: S A P = Q R, truncated to R11 (p x p).
+
+    Returns (R11, c = (Q_1^T S b) p x k, perm d, p, diag(R) of the full
+    factorisation).  perm[:p] are the columns that V_1 selects.  Signs are
+    normalised so that diag(R11) >= 0."""
+    SA = np.asarray(SA_aug[:, :d], dtype=np.float64)
+    SB = np.asarray(SA_aug[:, d:], dtype=np.float64)
+    Q, R, perm = sla.qr(SA, mode="economic", pivoting=True)
+    p = rank_count(R, rcond)
+    sgn = np.sign(np.diag(R)[:p]).copy()
+    sgn[sgn == 0] = 1.0
+    R11 = np.triu(sgn[:, None] * R[:p, :p])
+    c = sgn[:, None] * (Q[:, :p].T @ SB)
+    return R11, c, np.asarray(perm, dtype=np.int64), p, np.diag(R).copy()
+
+
+def solve_pivoted_with_factor(A, b, R11, c, J, tau_a=1e-8, tau_r=1e-6, it_max=10000):
+    """Steps 3-5 with V_1 = the columns J: LSQR on W = A_J R11^-1.
+
+    Returns x (d, zero outside J) and the record of the one right-hand side."""
+    d = A.shape[1]
+    x = np.zeros(d)
+    if len(J) == 0:
+        r = np.asarray(b, dtype=np.float64)
+        return x, dict(iters=0, status=OK, rnorm=float(np.linalg.norm(r)), arnorm=0.0,
+                       anorm=0.0, tc=0.0, xs=x.copy())
+    AJ = A[:, J]
+    xJ, rec = solve_with_factor(AJ, b, R11, c, tau_a, tau_r, it_max)
+    x[J] = xJ
+    xs = np.zeros(d)
+    xs[J] = rec["xs"]
+    rec["xs"] = xs
+    return x, rec
 
 
 def perturbed(R, rcond_thres, perturb):
@@ -170,23 +229,34 @@ def solve(A, B, seed, sparse=None, **kw):
         out = sk.sketch_csr(Ac.indptr, Ac.indices, Ac.data, n, d, B2, m, p["s"], seed)
     else:
         out = sk.sketch_dense(A, B2, m, p["s"], seed, hadamard=p["hadamard"])
-    R, c, _ = factor(out["SA_aug"], d)
-    if p["rcond"] > 0 and not rank_ok(R, p["rcond"]):
-        return None, dict(status=ERANK, R=R, sketch=out)
-    R = perturbed(R, p["rcond_thres"], p["perturb"])
     X = np.zeros((d, B2.shape[1]))
     recs = []
-    for j in range(B2.shape[1]):
-        X[:, j], rec = solve_with_factor(A, B2[:, j], R, c[:, j], p["tau_a"],
-                                         p["tau_r"], p["it_max"])
-        recs.append(rec)
+    extra = {}
+    if p.get("pivoting"):
+        R, c, perm, rank, dg = factor_pivoted(out["SA_aug"], d, p["rcond"])
+        R = perturbed(R, p["rcond_thres"], p["perturb"])
+        J = perm[:rank]
+        extra = dict(perm=perm, p=rank, J=J, diag_full=dg)
+        for j in range(B2.shape[1]):
+            X[:, j], rec = solve_pivoted_with_factor(A, B2[:, j], R, c[:, j], J, p["tau_a"],
+                                                     p["tau_r"], p["it_max"])
+            recs.append(rec)
+    else:
+        R, c, _ = factor(out["SA_aug"], d)
+        if p["rcond"] > 0 and not rank_ok(R, p["rcond"]):
+            return None, dict(status=ERANK, R=R, sketch=out)
+        R = perturbed(R, p["rcond_thres"], p["perturb"])
+        for j in range(B2.shape[1]):
+            X[:, j], rec = solve_with_factor(A, B2[:, j], R, c[:, j], p["tau_a"],
+                                             p["tau_r"], p["it_max"])
+            recs.append(rec)
     if any(r["status"] == WNOCONV for r in recs):
         status = WNOCONV
     elif all(r["status"] == WEARLY for r in recs):
         status = WEARLY
     else:
         status = OK
-    return X, dict(status=status, R=R, c=c, m=m, records=recs, sketch=out)
+    return X, dict(status=status, R=R, c=c, m=m, records=recs, sketch=out, **extra)
 
 
 def lstsq_direct(A, B):
@@ -194,6 +264,17 @@ def lstsq_direct(A, B):
     A = A.toarray() if sp.issparse(A) else np.asarray(A, dtype=np.float64)
     Q, R = np.linalg.qr(A, mode="reduced")
     return sla.solve_triangular(R, Q.T @ B, lower=False)
+
+
+def basic_solution(A, b, J):
+    """The plain definition on a column set J: x_J = argmin ||A_J z - b|| (A_J of full
+    column rank), x = 0 outside J, by Householder QR of A_J."""
+    A = A.toarray() if sp.issparse(A) else np.asarray(A, dtype=np.float64)
+    x = np.zeros(A.shape[1])
+    J = np.asarray(J, dtype=np.int64)
+    if J.size:
+        x[J] = lstsq_direct(A[:, J], b)
+    return x
 
 
 def normal_solve_pcg(A, R, G, tol=1e-12, it_max=1000):

@@ -21,6 +21,13 @@ Recipes (host numpy Generator(PCG64(1000 + case)) unless stated):
             10^(-8 i/(d-1)) and U, V from QR of Gaussian matrices; b = 1.
 * batched   20000 x 1000 dense N(0,1) with 32 right-hand sides B ~ N(0,1) and
             a loss weight G ~ N(0,1) (d x 32).
+* rankdef   50000 x 4000 dense of rank 3500: 3500 independent N(0,1) columns
+            and 500 dependent ones, a third each of zero columns, exact copies
+            of an independent column and combinations of three independent
+            columns with N(0,1) weights, all shuffled; rows 0 .. 0.2n-1 scaled
+            by 1e3 as in `dense`; b ~ N(0,1); Hadamard, s = 3, gamma = 1.7.
+            Stands in for the paper's rank-deficient test matrices (Table 2),
+            which come from the Florida collection.
 
 Every generator takes (n, d) so that the same recipe runs at test sizes.
 """
@@ -33,6 +40,7 @@ CASES = {
     "sparse": dict(n=200000, d=5000, s=2, gamma=1.5, m=7500, hadamard=False, case=3),
     "illcond": dict(n=50000, d=7000, s=3, gamma=1.7, m=11900, hadamard=True, case=4),
     "batched": dict(n=20000, d=1000, s=3, gamma=1.7, m=1700, hadamard=True, case=5, k=32),
+    "rankdef": dict(n=50000, d=4000, rank=3500, s=3, gamma=1.7, m=6800, hadamard=True, case=6),
 }
 
 POWER_LAW_ALPHA = 1.6725
@@ -131,3 +139,30 @@ def batched(n=20000, d=1000, k=32, case=5):
     B = rng.standard_normal((n, k))
     G = rng.standard_normal((d, k))
     return A, B, G
+
+
+def rank_deficient(n=50000, d=4000, rank=3500, case=6, frac=0.2, scale=1e3):
+    """Dense A of rank `rank` (the recipe `rankdef` above) and b.
+
+    Returns (A, b, independent) where `independent` lists the columns of A that
+    are the independent Gaussian ones."""
+    rng = rng_for(case)
+    base = rng.standard_normal((n, rank))
+    base[: int(frac * n)] *= scale
+    ndep = d - rank
+    nz = ndep // 3
+    ncp = ndep // 3
+    ncb = ndep - nz - ncp
+    A = np.empty((n, d))
+    A[:, :rank] = base
+    A[:, rank:rank + nz] = 0.0
+    A[:, rank + nz:rank + nz + ncp] = base[:, rng.integers(0, rank, ncp)]
+    idx = rng.integers(0, rank, (ncb, 3))
+    w = rng.standard_normal((ncb, 3))
+    for j in range(ncb):
+        A[:, rank + nz + ncp + j] = base[:, idx[j]] @ w[j]
+    del base
+    order = rng.permutation(d)
+    A = np.ascontiguousarray(A[:, order])  # column j of A is column order[j] above
+    b = rng.standard_normal(n)
+    return A, b, np.flatnonzero(order < rank)
