@@ -56,7 +56,7 @@ enum ski_status {
 enum ski_kind { SKI_DENSE = 0, SKI_CSR = 2 };
 enum ski_prec { SKI_FP64 = 0, SKI_FP32 = 1, SKI_BF16 = 2 };
 enum ski_op { SKI_OP_LLS = 0, SKI_OP_NORMAL = 1 };
-enum ski_qr_panel { SKI_QR_AUTO = 0, SKI_QR_HOUSEHOLDER = 1 };
+enum ski_qr_panel { SKI_QR_AUTO = 0, SKI_QR_HOUSEHOLDER = 1, SKI_QR_PIVOTED = 2 };
 
 /* The data matrix.  Dense: `a` (n x d, row-major, leading dimension lda >= d).
  * CSR: row_ptr[n+1] (int64, row_ptr[0] = 0), col[nnz] (int32 in [0, d), distinct
@@ -94,6 +94,17 @@ typedef struct {
  *                ill-conditioned for that (checked on the device), the whole factorisation
  *                is repeated with the column-by-column panel.  SKI_QR_HOUSEHOLDER: the
  *                column-by-column panel only.  Both give the same R up to rounding.
+ *                SKI_QR_PIVOTED: the rank-revealing form of Step 2, S A V-hat = Q R with
+ *                V-hat a column permutation (Section 6: randomised column-pivoted QR,
+ *                parameter rcond).  Each panel's 64 pivots are chosen by greedy column
+ *                pivoting on a 72-row random sketch of the trailing columns (a
+ *                tournament over groups of 512 columns), the panel is factored by
+ *                Householder columns in FP64, and the sketch is updated from R_12.
+ *                The rank p is the number of leading diagonal entries with
+ *                |r_qq| >= rcond |r_11| (with rcond = 0: the leading non-zero ones);
+ *                R_11 is the leading p x p block, V_1 the first p pivots J, and Steps
+ *                3-5 use W = A V_1 R_11^-1, so x is zero outside J.  Needs qr_prec =
+ *                SKI_FP64; the rank guard (SKI_ERANK) does not apply.
  *   reserved     must be 0. */
 typedef struct {
     double gamma;
@@ -144,7 +155,9 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
 /* Step 2.  Householder QR of the sketch; forms R (FP64, diag(R) >= 0), c, and the
  * explicit inverse of R used by every later product with R^-1 (any nonsingular P
  * applied consistently keeps the implicit sketching guarantee).  SKI_ERANK if the
- * rank guard fails (the handle then holds R but cannot solve). */
+ * rank guard fails (the handle then holds R but cannot solve).  With qr_panel =
+ * SKI_QR_PIVOTED: the column-pivoted factorisation and its truncation to R_11
+ * (p x p, p from rcond); p = 0 (a numerically zero A) gives x = 0. */
 int ski_factor(ski_handle h, void* stream);
 
 /* Steps 3-5 (op = SKI_OP_LLS): B is n x k (ldb), X is d x k (ldx).  The k columns are
@@ -156,7 +169,9 @@ int ski_solve(ski_handle h, int32_t op, const double* B, int32_t k, int64_t ldb,
               double* X, int64_t ldx, ski_info* info, void* stream);
 
 /* grad_B = A Z (n x k, ldgb) and grad_A = (B - A X) Z^T - (A Z) X^T (n x d, ldga) for
- * dense A.  Either output may be NULL.  X, Z: d x k; B: n x k. */
+ * dense A.  Either output may be NULL.  X, Z: d x k; B: n x k.  After a pivoted factor
+ * SKI_OP_NORMAL gives Z = V_1 (A_J^T A_J)^-1 G_J (zero outside the kept columns J), the
+ * adjoint of the solution on J with J held fixed. */
 int ski_gradients(ski_handle h, const double* X, int64_t ldx, const double* B, int64_t ldb,
                   const double* Z, int64_t ldz, int32_t k, double* grad_A, int64_t ldga,
                   double* grad_B, int64_t ldgb, void* stream);
@@ -170,7 +185,8 @@ const char* ski_last_error(ski_handle h);
  *         may be NULL.
  *   dsign: the diagonal of D as int8 (+1 / -1), n' entries (dense with Hadamard only).
  *   SA: the sketch m x (d+k) row-major, converted to double.
- *   R: d x d row-major (upper triangle, zeros below); c: d x k; Rinv: d x d. */
+ *   R: d x d row-major (upper triangle, zeros below); c: d x k; Rinv: d x d (after a
+ *      pivoted factor: R of the permuted sketch S A P, and Rinv = R_11^-1, p x p). */
 /* Kernel timing for measurement (not needed to solve).  ski_set_profiling(h, 1) makes the
  * library record a HIP event pair on the launch stream around every launch of the kernel
  * classes below (clearing earlier totals); ski_get_profile returns, per class, the summed
@@ -180,7 +196,8 @@ const char* ski_last_error(ski_handle h);
  * (Philox + bucket sort), 7 dense sketch with the Hadamard mix (transform passes and
  * hashing gather, by column slabs), 8 hashing gather without the Hadamard mix (dense or
  * CSR), 9 whole QR of the sketch with CholeskyQR2 panels, 10 explicit R^-1, 11 whole QR
- * with column-by-column Householder panels.  ms[] and count[] hold SKI_PROF_CLASSES
+ * with column-by-column Householder panels, 12 whole column-pivoted QR (pivot sketch,
+ * selection, moves, panels, updates).  ms[] and count[] hold SKI_PROF_CLASSES
  * entries.  ski_set_profiling(h, 1) times every class; ski_set_profiling_mask times only
  * the classes whose bit is set (bit c for class c; 0 switches profiling off), which keeps
  * the event records out of the other launches. */
@@ -195,6 +212,10 @@ int ski_get_hash(ski_handle h, int32_t* rows, int8_t* neg, int64_t* bucket_ptr, 
 int ski_get_dsign(ski_handle h, int8_t* dsign);
 int ski_get_SA(ski_handle h, double* SA);
 int ski_get_R(ski_handle h, double* R, double* c, double* Rinv);
+/* After ski_factor: perm[d] (position j of the factorisation holds column perm[j] of A;
+ * the identity without pivoting) and the rank p (d without pivoting).  Either pointer
+ * may be NULL.  SKI_ESTATE before a successful ski_factor. */
+int ski_get_pivots(ski_handle h, int32_t* perm, int64_t* rank);
 
 #ifdef __cplusplus
 }

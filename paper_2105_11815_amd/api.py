@@ -14,6 +14,8 @@ import torch
 from . import _lib as L
 
 _PREC = {"fp64": L.SKI_FP64, "fp32": L.SKI_FP32, "bf16": L.SKI_BF16}
+_PANEL = {"auto": L.SKI_QR_AUTO, "householder": L.SKI_QR_HOUSEHOLDER,
+          "pivoted": L.SKI_QR_PIVOTED}
 
 
 class SkiError(RuntimeError):
@@ -45,6 +47,8 @@ def params(kind="dense", **kw):
     for key, val in kw.items():
         if key in ("sketch_prec", "qr_prec") and isinstance(val, str):
             val = _PREC[val]
+        if key == "qr_panel" and isinstance(val, str):
+            val = _PANEL[val]
         if key == "hadamard":
             val = int(bool(val))
         if not hasattr(p, key):
@@ -228,14 +232,29 @@ class Solver:
         return out
 
     def get_R(self):
+        """(R d x d, c d x k, R^-1); after a pivoted factor R^-1 is R_11^-1 (p x p)."""
         dm = self.dims()
         R = np.zeros((dm["d"], dm["d"]))
         c = np.zeros((dm["d"], dm["k"]))
-        Ri = np.zeros((dm["d"], dm["d"]))
+        Ri = np.zeros(dm["d"] * dm["d"])
         rc = self._lib.ski_get_R(self._h, R.ctypes.data, c.ctypes.data, Ri.ctypes.data)
         if rc != L.SKI_OK:
             self._raise(rc, "ski_get_R")
-        return R, c, Ri
+        try:
+            p = self.get_pivots()[1]
+        except SkiError:
+            p = dm["d"]
+        return R, c, Ri[: p * p].reshape(p, p)
+
+    def get_pivots(self):
+        """(perm: position j holds column perm[j] of A, rank p) of the last factor."""
+        d = self.dims()["d"]
+        perm = np.zeros(d, dtype=np.int32)
+        rank = np.zeros(1, dtype=np.int64)
+        rc = self._lib.ski_get_pivots(self._h, perm.ctypes.data, rank.ctypes.data)
+        if rc != L.SKI_OK:
+            self._raise(rc, "ski_get_pivots")
+        return perm.astype(np.int64), int(rank[0])
 
 
 def lstsq(A, B, **kw):

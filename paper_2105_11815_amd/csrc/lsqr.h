@@ -16,8 +16,17 @@ struct LsqrState {
 
 hipError_t trtri_upper(const double* R, int64_t d, double* Rinv, double* RinvT,
                        const double* diag_add, double* tmp, GemmWs& ws, hipStream_t st);
+// y = s M x over the triangle of the d x d M; with perm, an upper product writes row i to
+// y[perm[i]] and a lower one reads x[perm[j]]
 hipError_t launch_tri_gemv(const double* M, int64_t d, bool upper, const double* x, int64_t ldx,
-                           double* y, int64_t ldy, double s, const int32_t* done, hipStream_t st);
+                           double* y, int64_t ldy, double s, const int32_t* done, hipStream_t st,
+                           const int32_t* perm = nullptr);
+// scatter dst[perm[i], :] = src[i, :] or gather dst[i, :] = src[perm[i], :]
+hipError_t launch_permute_rows(const double* src, int64_t lds, double* dst, int64_t ldd,
+                               const int32_t* perm, int64_t rows, int64_t cols, bool scatter,
+                               hipStream_t st);
+hipError_t launch_fill_rows(double* y, int64_t rows, int64_t cols, int64_t ldy, double v,
+                            hipStream_t st);
 int lsqr_pass_cpt(int64_t d);
 hipError_t launch_lsqr_pass(const double* A, int64_t lda, int64_t n, int64_t d, const double* z,
                             double* u, const LsqrState* stt, int64_t G, double* gpart,

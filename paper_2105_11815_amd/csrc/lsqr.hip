@@ -101,13 +101,18 @@ hipError_t trtri_rec(const double* R, int64_t d, int64_t lo, int64_t hi, double*
 // ---------------------------------------------------------------------------
 // triangular GEMV y = s * M x over the triangle only: a workgroup of four waves takes the
 // row pair (i, d-1-i), so every workgroup reads d+1 entries; every lane issues its loads
-// for both rows before it adds.
+// for both rows before it adds.  With PERM (a column-pivoted factor), the upper product
+// scatters its output to y[perm[i]] and the lower one gathers its input from x[perm[j]].
 constexpr int TG = 256;
+template <bool PERM>
 __global__ __launch_bounds__(TG) void k_tri_gemv(const double* __restrict__ M, int64_t d, int upper,
                                                  const double* __restrict__ x, int64_t ldx,
                                                  double* __restrict__ y, int64_t ldy, double s,
-                                                 const int32_t* __restrict__ done) {
+                                                 const int32_t* __restrict__ done,
+                                                 const int32_t* __restrict__ perm) {
     if (done && *done) return;
+    auto xi = [&](int64_t j) -> int64_t { return (PERM && !upper) ? (int64_t)perm[j] : j; };
+    auto yi = [&](int64_t i) -> int64_t { return (PERM && upper) ? (int64_t)perm[i] : i; };
     __shared__ double sh[TG / 64][2];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t npairs = (d + 1) / 2;
@@ -125,11 +130,11 @@ __global__ __launch_bounds__(TG) void k_tri_gemv(const double* __restrict__ M, i
             int64_t j = j0 + tid;
             for (; j + 3 * TG < j1; j += 4 * TG) {
                 const double m0 = row[j], m1 = row[j + TG], m2 = row[j + 2 * TG], m3 = row[j + 3 * TG];
-                const double x0 = x[j * ldx], x1 = x[(j + TG) * ldx];
-                const double x2 = x[(j + 2 * TG) * ldx], x3 = x[(j + 3 * TG) * ldx];
+                const double x0 = x[xi(j) * ldx], x1 = x[xi(j + TG) * ldx];
+                const double x2 = x[xi(j + 2 * TG) * ldx], x3 = x[xi(j + 3 * TG) * ldx];
                 a += m0 * x0 + m1 * x1 + m2 * x2 + m3 * x3;
             }
-            for (; j < j1; j += TG) a += row[j] * x[j * ldx];
+            for (; j < j1; j += TG) a += row[j] * x[xi(j) * ldx];
             acc[t] = a;
         }
         acc[0] = wave_sum(acc[0]);
@@ -140,8 +145,8 @@ __global__ __launch_bounds__(TG) void k_tri_gemv(const double* __restrict__ M, i
         }
         __syncthreads();
         if (tid == 0) {
-            y[i0 * ldy] = s * (((sh[0][0] + sh[1][0]) + sh[2][0]) + sh[3][0]);
-            if (two) y[i1 * ldy] = s * (((sh[0][1] + sh[1][1]) + sh[2][1]) + sh[3][1]);
+            y[yi(i0) * ldy] = s * (((sh[0][0] + sh[1][0]) + sh[2][0]) + sh[3][0]);
+            if (two) y[yi(i1) * ldy] = s * (((sh[0][1] + sh[1][1]) + sh[2][1]) + sh[3][1]);
         }
         __syncthreads();
     }
@@ -596,6 +601,29 @@ __global__ __launch_bounds__(256) void k_final_y(const LsqrState* __restrict__ s
     y[o] = stt[j].early ? c[o] : c[o] + delta[o];
 }
 
+// rows through a permutation: scatter dst[perm[i]] = src[i] or gather dst[i] = src[perm[i]]
+// (rows x cols, row-major with the given leading dimensions)
+__global__ __launch_bounds__(256) void k_permute_rows(const double* __restrict__ src, int64_t lds,
+                                                      double* __restrict__ dst, int64_t ldd,
+                                                      const int32_t* __restrict__ perm,
+                                                      int64_t rows, int64_t cols, int scatter) {
+    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (o >= rows * cols) return;
+    const int64_t i = o / cols, j = o - i * cols;
+    if (scatter)
+        dst[(int64_t)perm[i] * ldd + j] = src[i * lds + j];
+    else
+        dst[i * ldd + j] = src[(int64_t)perm[i] * lds + j];
+}
+
+__global__ __launch_bounds__(256) void k_fill_rows(double* __restrict__ y, int64_t rows,
+                                                   int64_t cols, int64_t ldy, double v) {
+    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (o >= rows * cols) return;
+    const int64_t i = o / cols, j = o - i * cols;
+    y[i * ldy + j] = v;
+}
+
 __global__ __launch_bounds__(256) void k_scale_copy(const double* __restrict__ x, int64_t rows,
                                                     int64_t cols, int64_t ldx, double s,
                                                     double* __restrict__ y, int64_t ldy) {
@@ -698,10 +726,35 @@ hipError_t trtri_upper(const double* R, int64_t d, double* Rinv, double* RinvT,
 }
 
 hipError_t launch_tri_gemv(const double* M, int64_t d, bool upper, const double* x, int64_t ldx,
-                           double* y, int64_t ldy, double s, const int32_t* done, hipStream_t st) {
+                           double* y, int64_t ldy, double s, const int32_t* done, hipStream_t st,
+                           const int32_t* perm) {
+    if (d <= 0) return hipSuccess;
     const unsigned g = (unsigned)std::min<int64_t>((d + 1) / 2, 8192);
-    hipLaunchKernelGGL(k_tri_gemv, dim3(g), dim3(TG), 0, st, M, d, upper ? 1 : 0, x, ldx, y, ldy,
-                       s, done);
+    if (perm)
+        hipLaunchKernelGGL(k_tri_gemv<true>, dim3(g), dim3(TG), 0, st, M, d, upper ? 1 : 0, x, ldx,
+                           y, ldy, s, done, perm);
+    else
+        hipLaunchKernelGGL(k_tri_gemv<false>, dim3(g), dim3(TG), 0, st, M, d, upper ? 1 : 0, x,
+                           ldx, y, ldy, s, done, perm);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute_rows(const double* src, int64_t lds, double* dst, int64_t ldd,
+                               const int32_t* perm, int64_t rows, int64_t cols, bool scatter,
+                               hipStream_t st) {
+    const int64_t tot = rows * cols;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_permute_rows, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, src,
+                       lds, dst, ldd, perm, rows, cols, scatter ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_rows(double* y, int64_t rows, int64_t cols, int64_t ldy, double v,
+                            hipStream_t st) {
+    const int64_t tot = rows * cols;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_rows, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, y, rows,
+                       cols, ldy, v);
     return hipGetLastError();
 }
 
@@ -829,6 +882,7 @@ hipError_t launch_lsqr_step(LsqrState* stt, int64_t d, int k, const double* wp, 
 hipError_t launch_final_y(const LsqrState* stt, int64_t d, int k, const double* c,
                           const double* delta, double* y, hipStream_t st) {
     const int64_t tot = d * k;
+    if (tot <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_final_y, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, stt, d, k,
                        c, delta, y);
     return hipGetLastError();

@@ -517,6 +517,50 @@ hipError_t qr_impl_cqr(T* Ac, int64_t m, int64_t ncols, int64_t d, QrWs& ws, boo
     return hipSuccess;
 }
 
+// Column-pivoted panels (FP64): before each panel its pivots are chosen on the sketch of
+// the trailing columns and moved to the front; the panel is factored column by column;
+// the whole trailing matrix (with the ride-along columns) gets Q^T at once, because the
+// next panel's pivots depend on the updated R_12 through the sketch update.
+hipError_t qr_impl_pivoted(double* Ac, int64_t m, int64_t ncols, int64_t d, QrWs& ws, PivWs& pw,
+                           uint64_t seed, hipStream_t st) {
+    using T = double;
+    T* tau = (T*)ws.tau;
+    T* Tl = (T*)ws.Tl;
+    T* VC = (T*)ws.Vt;
+    T* GW = (T*)ws.Tp;
+    SKI_HIP(piv_init(Ac, m, d, seed, pw, ws.g, st));
+    for (int64_t j0 = 0; j0 < d; j0 += NBP) {
+        const int nb = (int)std::min<int64_t>(NBP, d - j0);
+        SKI_HIP(piv_select(j0, d, nb, pw, st));
+        SKI_HIP(piv_apply(Ac, m, j0, nb, pw, st));
+        for (int jl = 0; jl < nb; jl += NBL) {
+            const int64_t jc = j0 + jl;
+            const int w = std::min(NBL, nb - jl);
+            SKI_HIP(launch_leaf<T>(Ac, m, jc, w, tau, Tl, st));
+            const int nc = nb - jl - w;
+            if (nc > 0) SKI_HIP(launch_narrow<T>(Ac, m, jc, w, Tl, nc, st));
+        }
+        const int64_t nrest = ncols - j0 - nb;
+        if (nrest <= 0) break;
+        const int64_t mr = m - j0;
+        hipLaunchKernelGGL((k_make_VC<T>),
+                           dim3((unsigned)std::min<int64_t>((mr + 255) / 256, 64), (unsigned)nb),
+                           dim3(256), 0, st, Ac, m, j0, nb, j0 + nb, VC);
+        SKI_HIP(hipGetLastError());
+        // V^T V for T, then W = C^T V, W2 = W T, C -= V W2^T over every remaining column
+        SKI_HIP(gemm_t<T>(false, true, nb, nb, mr, (T)1, VC, mr, VC, mr, (T)0, GW, nb, false,
+                          ws.g, st));
+        T* Ct = Ac + (j0 + nb) * m + j0;
+        SKI_HIP(gemm_t<T>(false, true, nrest, nb, mr, (T)1, Ct, m, VC, mr, (T)0, (T*)ws.Wt2, nb,
+                          false, ws.g, st));
+        SKI_HIP(launch_Tinv<T>((T*)ws.Wt2, nrest, nb, GW, nb, tau + j0, (T*)ws.W2t2, st));
+        SKI_HIP(gemm_t<T>(false, false, nrest, mr, nb, (T)-1, (T*)ws.W2t2, nb, VC, mr, (T)1, Ct,
+                          m, false, ws.g, st));
+        SKI_HIP(piv_update_sketch(Ac, m, j0, nb, d, pw, ws.g, st));
+    }
+    return hipSuccess;
+}
+
 template <typename T>
 hipError_t qr_impl(const T* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws, bool bf16,
                    hipStream_t st) {
@@ -586,6 +630,16 @@ hipError_t qr_factor(Prec prec, const void* SA, int64_t m, int64_t ncols, int64_
                      hipStream_t st) {
     if (prec == Prec::F64) return qr_impl<double>((const double*)SA, m, ncols, d, ws, false, st);
     return qr_impl<float>((const float*)SA, m, ncols, d, ws, prec == Prec::BF16, st);
+}
+
+hipError_t qr_factor_pivoted(const double* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws,
+                             PivWs& pw, uint64_t seed, hipStream_t st) {
+    double* Ac = (double*)ws.Ac;
+    hipLaunchKernelGGL((k_to_colmajor<double>),
+                       dim3((unsigned)((ncols + 63) / 64), (unsigned)((m + 63) / 64)), dim3(256), 0,
+                       st, SA, m, ncols, Ac);
+    SKI_HIP(hipGetLastError());
+    return qr_impl_pivoted(Ac, m, ncols, d, ws, pw, seed, st);
 }
 
 hipError_t launch_extract_Rc(Prec prec, const QrWs& ws, int64_t m, int64_t d, int64_t k, double* R,

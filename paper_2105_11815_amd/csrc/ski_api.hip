@@ -49,6 +49,10 @@ struct ski_handle_s {
     DevBuf tkeys, tkeys_tmp, ttable, tp, tpay, ti, tv;
     DevBuf u, t, v, h, delta, z, wp, g, gpart, upart, y, st;
     DevBuf cg_r, cg_p, cg_q, t2, dtmp, gemm_ws2;
+    // column-pivoted factor: workspace, the permutation, compact R_11, p x k staging
+    DevBuf piv_part, pivd, Rc, ptmp;
+    int64_t rank = 0;      // p: columns kept (d without pivoting)
+    bool pivoted = false;  // the last ski_factor pivoted
     hipStream_t st2 = nullptr;           // second stream of the QR's look-ahead
     hipEvent_t qev[4] = {};
     double* hdiag = nullptr;  // pinned host copy of diag(R)
@@ -125,7 +129,8 @@ constexpr int64_t PASS_WG = 512;  // workgroups of the fused dense LSQR pass
 
 enum ProfClass {
     PC_PASS = 0, PC_REDUCE = 1, PC_TRIGEMV = 2, PC_SPMV = 3, PC_SPMVT = 4, PC_STEP = 5,
-    PC_HASH = 6, PC_WHT = 7, PC_GATHER = 8, PC_QR = 9, PC_TRTRI = 10, PC_QR_HH = 11
+    PC_HASH = 6, PC_WHT = 7, PC_GATHER = 8, PC_QR = 9, PC_TRTRI = 10, PC_QR_HH = 11,
+    PC_QR_PIV = 12
 };
 
 hipEvent_t pool_event(ski_handle h) {
@@ -197,7 +202,8 @@ int ski_destroy(ski_handle h) {
                      &h->qr_Y, &h->qr_tau, &h->tkeys, &h->tkeys_tmp, &h->ttable, &h->tp,
                      &h->tpay, &h->ti, &h->tv, &h->u, &h->t, &h->v, &h->h, &h->delta, &h->z,
                      &h->wp, &h->g, &h->gpart, &h->upart, &h->y, &h->st, &h->cg_r,
-                     &h->cg_p, &h->cg_q, &h->t2, &h->dtmp, &h->gemm_ws2};
+                     &h->cg_p, &h->cg_q, &h->t2, &h->dtmp, &h->gemm_ws2,
+                     &h->piv_part, &h->pivd, &h->Rc, &h->ptmp};
     for (DevBuf* b : all) release(*b);
     if (h->ev_ok)
         for (auto& e : h->ev) (void)hipEventDestroy(e);
@@ -257,8 +263,12 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
     if (A->kind == SKI_CSR && p->hadamard)
         return fail(h, SKI_EINVAL, "ski_sketch: the Hadamard transform is for dense A only");
     if (p->s < 1 || p->s > 32) return fail(h, SKI_EINVAL, "ski_sketch: need 1 <= s <= 32");
-    if (p->qr_panel != SKI_QR_AUTO && p->qr_panel != SKI_QR_HOUSEHOLDER)
-        return fail(h, SKI_EINVAL, "ski_sketch: qr_panel must be SKI_QR_AUTO or SKI_QR_HOUSEHOLDER");
+    if (p->qr_panel != SKI_QR_AUTO && p->qr_panel != SKI_QR_HOUSEHOLDER &&
+        p->qr_panel != SKI_QR_PIVOTED)
+        return fail(h, SKI_EINVAL,
+                    "ski_sketch: qr_panel must be SKI_QR_AUTO, SKI_QR_HOUSEHOLDER or SKI_QR_PIVOTED");
+    if (p->qr_panel == SKI_QR_PIVOTED && p->qr_prec != SKI_FP64)
+        return fail(h, SKI_EINVAL, "ski_sketch: SKI_QR_PIVOTED needs qr_prec = SKI_FP64");
     if (p->sketch_prec < 0 || p->sketch_prec > 2 || p->qr_prec < 0 || p->qr_prec > 2)
         return fail(h, SKI_EINVAL, "ski_sketch: unknown precision");
     if (!(p->tau_r >= 0) || !(p->tau_a >= 0) || p->it_max < 1)
@@ -415,8 +425,31 @@ int ski_factor(ski_handle h, void* stream) {
         h->hdiag_n = d;
     }
     int* hflag = (int*)(h->hdiag + 2 * d);
+    const bool piv = h->p.qr_panel == SKI_QR_PIVOTED;
+    h->pivoted = false;
+    h->rank = d;
+    if (piv) {
+        SKI_TRY(h, ensure(h->piv_part, piv_ws_bytes(m, d)), "alloc");
+        SKI_TRY(h, ensure(h->pivd, d * 4), "alloc");
+        SKI_TRY(h, ensure(h->Rc, d * d * 8), "alloc");
+        PivWs pw;
+        piv_ws_carve(h->piv_part.p, m, d, pw);
+        prof_begin(h, PC_QR_PIV, st);
+        SKI_TRY(h, qr_factor_pivoted((const double*)h->SA.p, m, ncols, d, ws, pw, h->p.seed, st),
+                "pivoted qr");
+        prof_end(h, st);
+        SKI_TRY(h, launch_extract_Rc(h->qprec, ws, m, d, k, P<double>(h->R), P<double>(h->c), st),
+                "extract R");
+        SKI_TRY(h, launch_scale_copy(P<double>(h->R), d, 1, d + 1, 1.0, P<double>(h->dtmp), 1, st),
+                "diag gather");
+        SKI_TRY(h, hipMemcpyAsync(h->hdiag, h->dtmp.p, d * 8, hipMemcpyDeviceToHost, st),
+                "diag copy");
+        SKI_TRY(h, hipMemcpyAsync(h->pivd.p, pw.perm, d * 4, hipMemcpyDeviceToDevice, st),
+                "perm copy");
+        SKI_TRY(h, hipStreamSynchronize(st), "sync");
+    }
     bool cqr = h->p.qr_panel == SKI_QR_AUTO;
-    for (;;) {
+    for (; !piv;) {
         ws.cqr_panels = cqr;
         prof_begin(h, cqr ? PC_QR : PC_QR_HH, st);
         SKI_TRY(h, qr_factor(h->qprec, h->SA.p, m, ncols, d, ws, st), "qr");
@@ -440,17 +473,28 @@ int ski_factor(ski_handle h, void* stream) {
         break;
     }
     const double* Rd = h->hdiag;
-    double amax = 0, amin = INFINITY;
     bool finite = true;
-    for (int64_t i = 0; i < d; ++i) {
+    for (int64_t i = 0; i < d; ++i) finite = finite && std::isfinite(Rd[i]);
+    if (!finite) return fail(h, SKI_EINVAL, "ski_factor: non-finite R (non-finite input?)");
+    if (piv) {
+        // p = the leading diagonal entries with |r_qq| >= rcond |r_11| (all non-zero ones
+        // when rcond = 0): R_11 ends at the first entry below the threshold
+        const double r11 = fabs(Rd[0]);
+        const double thr = h->p.rcond > 0 ? h->p.rcond * r11 : 0.0;
+        int64_t p = 0;
+        if (r11 > 0)
+            while (p < d && fabs(Rd[p]) > 0 && fabs(Rd[p]) >= thr) ++p;
+        h->rank = p;
+    }
+    const int64_t dp = h->rank;
+    double amax = 0, amin = INFINITY;
+    for (int64_t i = 0; i < dp; ++i) {
         const double a = fabs(Rd[i]);
-        finite = finite && std::isfinite(Rd[i]);
         amax = std::max(amax, a);
         amin = std::min(amin, a);
     }
-    if (!finite) return fail(h, SKI_EINVAL, "ski_factor: non-finite R (non-finite input?)");
     h->cond_est = amin > 0 ? amax / amin : INFINITY;
-    if (h->p.rcond > 0) {
+    if (!piv && h->p.rcond > 0) {
         const double r11 = fabs(Rd[0]);
         for (int64_t i = 0; i < d; ++i)
             if (!(r11 > 0) || fabs(Rd[i]) < h->p.rcond * r11) {
@@ -466,17 +510,27 @@ int ski_factor(ski_handle h, void* stream) {
     double* add = h->hdiag + d;  // pinned
     const bool pert = h->p.perturb > 0 && h->p.rcond_thres > 0 &&
                       h->cond_est >= 1.0 / h->p.rcond_thres;
-    for (int64_t i = 0; i < d; ++i) add[i] = pert ? copysign(h->p.perturb, Rd[i]) : 0.0;
-    SKI_TRY(h, hipMemcpyAsync(h->diag_add.p, add, d * 8, hipMemcpyHostToDevice, st),
-            "perturb copy");
+    for (int64_t i = 0; i < dp; ++i) add[i] = pert ? copysign(h->p.perturb, Rd[i]) : 0.0;
+    if (dp > 0)
+        SKI_TRY(h, hipMemcpyAsync(h->diag_add.p, add, dp * 8, hipMemcpyHostToDevice, st),
+                "perturb copy");
     GemmWs gw;
     gw.part = h->gemm_ws.p;
     gw.bytes = h->gemm_ws.bytes;
+    // R_11 (the leading p x p block; all of R without pivoting) and its inverse
+    const double* R11 = P<double>(h->R);
+    if (piv) {
+        SKI_TRY(h, launch_scale_copy(P<double>(h->R), dp, dp, d, 1.0, P<double>(h->Rc), dp, st),
+                "R11 copy");
+        R11 = P<double>(h->Rc);
+    }
     prof_begin(h, PC_TRTRI, st);
-    SKI_TRY(h, trtri_upper(P<double>(h->R), d, P<double>(h->Rinv), P<double>(h->RinvT),
-                           P<double>(h->diag_add), P<double>(h->tri_tmp), gw, st),
-            "R inverse");
+    if (dp > 0)
+        SKI_TRY(h, trtri_upper(R11, dp, P<double>(h->Rinv), P<double>(h->RinvT),
+                               P<double>(h->diag_add), P<double>(h->tri_tmp), gw, st),
+                "R inverse");
     prof_end(h, st);
+    h->pivoted = piv;
     if (h->ev_ok) (void)hipEventRecord(h->ev[3], st);
     SKI_TRY(h, hipStreamSynchronize(st), "sync");
     prof_collect(h);
@@ -513,14 +567,29 @@ int alloc_solve_ws(ski_handle h, int k) {
     const int64_t G = std::max<int64_t>({PASS_WG, spmv_csr_groups(n), 1});
     SKI_TRY(h, ensure(h->upart, G * k * 8), "alloc");
     SKI_TRY(h, ensure(h->st, k * sizeof(LsqrState)), "alloc");
+    if (h->pivoted) SKI_TRY(h, ensure(h->ptmp, d * k * 8), "alloc");
     return SKI_OK;
 }
 
-// z = R^-1 x (d x k, both leading dimension k)
+// y = s R_11^-1 x (upper, Mtx = R_11^-1) or y = s R_11^-T x (Mtx = R_11^-T), leading
+// dimension k.  Without pivoting both are d x k.  With pivoting (p = rank columns kept),
+// the upper product takes a compact p x k x and scatters row i of the result to row
+// perm[i] of the d x k y (whose other rows the caller keeps at zero); the transposed
+// product gathers rows perm[i] of the d x k x and writes a compact p x k y.
 hipError_t apply_Rinv(ski_handle h, const double* Mtx, bool upper, const double* x, double* y, int k,
                       double s, const int32_t* done, GemmWs& gw, hipStream_t st) {
-    if (k == 1) return launch_tri_gemv(Mtx, h->d, upper, x, 1, y, 1, s, done, st);
-    return gemm_f64(false, false, h->d, k, h->d, s, Mtx, h->d, x, k, 0.0, y, k, gw, st);
+    const int64_t dp = h->rank;
+    if (dp <= 0) return hipSuccess;
+    const int32_t* perm = h->pivoted ? (const int32_t*)h->pivd.p : nullptr;
+    if (k == 1) return launch_tri_gemv(Mtx, dp, upper, x, 1, y, 1, s, done, st, perm);
+    if (!perm) return gemm_f64(false, false, dp, k, dp, s, Mtx, dp, x, k, 0.0, y, k, gw, st);
+    double* t = (double*)h->ptmp.p;
+    if (upper) {
+        SKI_HIP(gemm_f64(false, false, dp, k, dp, s, Mtx, dp, x, k, 0.0, t, k, gw, st));
+        return launch_permute_rows(t, k, y, k, perm, dp, k, true, st);
+    }
+    SKI_HIP(launch_permute_rows(x, k, t, k, perm, dp, k, false, st));
+    return gemm_f64(false, false, dp, k, dp, s, Mtx, dp, t, k, 0.0, y, k, gw, st);
 }
 
 // Convergence status read back with a one-iteration lag: after iteration i the all-done
@@ -630,7 +699,10 @@ int solve_lls(ski_handle h, const double* B, int k, int64_t ldb, double* X, int6
     const bool csr = (h->kind == SKI_CSR);
     hipEvent_t e0 = h->ev[4], e1 = h->ev[5];
     if (h->ev_ok) (void)hipEventRecord(e0, st);
+    const int64_t dp = h->rank;  // the LSQR vectors v, h, delta, y live in R^p
     SKI_TRY(h, hipMemsetAsync(S, 0, k * sizeof(LsqrState), st), "state init");
+    // with pivoting z = V_1 (...) is zero outside the kept columns
+    if (h->pivoted) SKI_TRY(h, launch_fill_rows(z, d, k, k, 0.0, st), "zero z");
     // u = B (the residual is formed in place), z = -x_s
     SKI_TRY(h, launch_scale_copy(B, n, k, ldb, 1.0, u, k, st), "copy b");
     SKI_TRY(h, apply_Rinv(h, Rinv, true, c, z, k, -1.0, nullptr, gw, st), "x_s");
@@ -652,7 +724,7 @@ int solve_lls(ski_handle h, const double* B, int k, int64_t ldb, double* X, int6
         SKI_TRY(h, dense_ATU(h, u, k, g, gw, st), "ATU");
     }
     SKI_TRY(h, apply_Rinv(h, RinvT, false, g, wp, k, 1.0, nullptr, gw, st), "R^-T g");
-    SKI_TRY(h, launch_lsqr_init(S, d, k, wp, v, hh, dl, h->p.tau_a, st), "init");
+    SKI_TRY(h, launch_lsqr_init(S, dp, k, wp, v, hh, dl, h->p.tau_a, st), "init");
     const int32_t* done1 = (k == 1) ? &S[0].done : nullptr;
     LagFlag lf;
     int out = lf.init(h);
@@ -698,7 +770,7 @@ int solve_lls(ski_handle h, const double* B, int k, int64_t ldb, double* X, int6
             prof_end(h, st);
             prof_begin(h, PC_STEP, st);
             if (e == hipSuccess)
-                e = launch_lsqr_step(S, d, k, wp, v, hh, dl, h->p.tau_r, h->p.it_max,
+                e = launch_lsqr_step(S, dp, k, wp, v, hh, dl, h->p.tau_r, h->p.it_max,
                                      lf.slot_dev(it + 1), st);
             prof_end(h, st);
             if (e != hipSuccess) {
@@ -714,9 +786,23 @@ int solve_lls(ski_handle h, const double* B, int k, int64_t ldb, double* X, int6
     }
     lf.release();
     if (out != SKI_OK) return out;
-    // x = R^-1 (c + delta)
-    SKI_TRY(h, launch_final_y(S, d, k, c, dl, y, st), "final y");
-    if (k == 1) {
+    // x = R^-1 (c + delta); with pivoting x = V_1 R_11^-1 (c + delta), zero elsewhere
+    SKI_TRY(h, launch_final_y(S, dp, k, c, dl, y, st), "final y");
+    if (h->pivoted) {
+        SKI_TRY(h, launch_fill_rows(X, d, k, ldx, 0.0, st), "zero x");
+        if (k == 1) {
+            SKI_TRY(h, launch_tri_gemv(Rinv, dp, true, y, 1, X, ldx, 1.0, nullptr, st,
+                                       P<int32_t>(h->pivd)),
+                    "x");
+        } else if (dp > 0) {
+            SKI_TRY(h, gemm_f64(false, false, dp, k, dp, 1.0, Rinv, dp, y, k, 0.0,
+                                P<double>(h->ptmp), k, gw, st),
+                    "x");
+            SKI_TRY(h, launch_permute_rows(P<double>(h->ptmp), k, X, ldx, P<int32_t>(h->pivd), dp,
+                                           k, true, st),
+                    "x scatter");
+        }
+    } else if (k == 1) {
         SKI_TRY(h, launch_tri_gemv(Rinv, d, true, y, 1, X, ldx, 1.0, nullptr, st), "x");
     } else {
         SKI_TRY(h, gemm_f64(false, false, d, k, d, 1.0, Rinv, d, y, k, 0.0, X, ldx, gw, st), "x");
@@ -752,23 +838,24 @@ int solve_normal(ski_handle h, const double* G, int k, int64_t ldg, double* Z, i
     const double* RinvT = P<double>(h->RinvT);
     hipEvent_t e0 = h->ev[4], e1 = h->ev[5];
     if (h->ev_ok) (void)hipEventRecord(e0, st);
+    const int64_t dp = h->rank;  // CG runs in R^p (p = d without pivoting)
     SKI_TRY(h, hipMemsetAsync(S, 0, k * sizeof(LsqrState), st), "state init");
+    if (h->pivoted) SKI_TRY(h, launch_fill_rows(z, d, k, k, 0.0, st), "zero z");
     // rhs = R^-T G (into wp, compact leading dimension k)
     SKI_TRY(h, launch_scale_copy(G, d, k, ldg, 1.0, g, k, st), "copy g");
-    SKI_TRY(h, gemm_f64(false, false, d, k, d, 1.0, RinvT, d, g, k, 0.0, wp, k, gw, st), "rhs");
-    SKI_TRY(h, launch_cg_init(S, d, k, wp, r, pp, y, h->p.tau_r, st), "cg init");
+    SKI_TRY(h, apply_Rinv(h, RinvT, false, g, wp, k, 1.0, nullptr, gw, st), "rhs");
+    SKI_TRY(h, launch_cg_init(S, dp, k, wp, r, pp, y, h->p.tau_r, st), "cg init");
     LagFlag lf;
     int out = lf.init(h);
     if (out == SKI_OK) out = lf.post(h, k, st, 0, false);
     if (out == SKI_OK && lf.wait(h, 0) == 1) lf.stop = true;
     int64_t it = 0;
     while (out == SKI_OK && !lf.stop && it < h->p.it_max) {
-        hipError_t e = gemm_f64(false, false, d, k, d, 1.0, Rinv, d, pp, k, 0.0, z, k, gw, st);
+        hipError_t e = apply_Rinv(h, Rinv, true, pp, z, k, 1.0, nullptr, gw, st);
         if (e == hipSuccess) e = dense_AZ(h, z, k, t, gw, st);
         if (e == hipSuccess) e = dense_ATU(h, t, k, g, gw, st);
-        if (e == hipSuccess)
-            e = gemm_f64(false, false, d, k, d, 1.0, RinvT, d, g, k, 0.0, q, k, gw, st);
-        if (e == hipSuccess) e = launch_cg_step(S, d, k, q, r, pp, y, h->p.it_max, st);
+        if (e == hipSuccess) e = apply_Rinv(h, RinvT, false, g, q, k, 1.0, nullptr, gw, st);
+        if (e == hipSuccess) e = launch_cg_step(S, dp, k, q, r, pp, y, h->p.it_max, st);
         if (e != hipSuccess) {
             out = hip_fail(h, e, "cg iteration");
             break;
@@ -779,7 +866,19 @@ int solve_normal(ski_handle h, const double* G, int k, int64_t ldg, double* Z, i
     }
     lf.release();
     if (out != SKI_OK) return out;
-    SKI_TRY(h, gemm_f64(false, false, d, k, d, 1.0, Rinv, d, y, k, 0.0, Z, ldz, gw, st), "z");
+    if (h->pivoted) {
+        SKI_TRY(h, launch_fill_rows(Z, d, k, ldz, 0.0, st), "zero Z");
+        if (dp > 0) {
+            SKI_TRY(h, gemm_f64(false, false, dp, k, dp, 1.0, Rinv, dp, y, k, 0.0,
+                                P<double>(h->ptmp), k, gw, st),
+                    "z");
+            SKI_TRY(h, launch_permute_rows(P<double>(h->ptmp), k, Z, ldz, P<int32_t>(h->pivd), dp,
+                                           k, true, st),
+                    "z scatter");
+        }
+    } else {
+        SKI_TRY(h, gemm_f64(false, false, d, k, d, 1.0, Rinv, d, y, k, 0.0, Z, ldz, gw, st), "z");
+    }
     float ms = 0;
     if (h->ev_ok) {
         (void)hipEventRecord(e1, st);
@@ -954,9 +1053,26 @@ int ski_get_R(ski_handle h, double* R, double* c, double* Rinv) {
         return fail(h, SKI_EDEVICE, "copy");
     if (c && hipMemcpy(c, h->c.p, d * h->k * 8, hipMemcpyDeviceToHost) != hipSuccess)
         return fail(h, SKI_EDEVICE, "copy");
-    if (Rinv && h->factored &&
-        hipMemcpy(Rinv, h->Rinv.p, d * d * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    if (Rinv && h->factored && h->rank > 0 &&
+        hipMemcpy(Rinv, h->Rinv.p, h->rank * h->rank * 8, hipMemcpyDeviceToHost) != hipSuccess)
         return fail(h, SKI_EDEVICE, "copy");
+    return SKI_OK;
+}
+
+int ski_get_pivots(ski_handle h, int32_t* perm, int64_t* rank) {
+    if (!h) return SKI_EINVAL;
+    if (!h->factored) return fail(h, SKI_ESTATE, "ski_get_pivots: not factored");
+    const int64_t d = h->d;
+    if (rank) *rank = h->rank;
+    if (perm) {
+        if (h->pivoted) {
+            if (hipDeviceSynchronize() != hipSuccess ||
+                hipMemcpy(perm, h->pivd.p, d * 4, hipMemcpyDeviceToHost) != hipSuccess)
+                return fail(h, SKI_EDEVICE, "copy");
+        } else {
+            for (int64_t j = 0; j < d; ++j) perm[j] = (int32_t)j;
+        }
+    }
     return SKI_OK;
 }
 

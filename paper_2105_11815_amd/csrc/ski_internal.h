@@ -196,6 +196,36 @@ hipError_t cqr_finish_panel(T* Ac, int64_t m, int64_t j0, int nb, int nbn, const
                             T* Vout, hipStream_t st);
 hipError_t cqr_clear_flag(int* flag, hipStream_t st);
 
+// column pivoting on a sketch of the trailing columns (rcpqr.hip)
+constexpr int PIV_YL = 72;  // rows of the pivot sketch: panel width + 8
+struct PivWs {
+    double* Om = nullptr;        // PIV_YL x m random signs
+    double* Yt = nullptr;        // the pivot sketch, transposed: row j = sketch of column j
+    double* Bt = nullptr;        // 64 x PIV_YL, R_11^-T Y_1^T of the last panel
+    int32_t* cand[2] = {};       // tournament winners per group, 64 slots each
+    int32_t* cnt[2] = {};        // winners per group
+    int32_t* sel = nullptr;      // the panel's pivots (positions), in the order chosen
+    double* nu = nullptr;        // remaining sketch norm at each choice
+    int32_t* mv = nullptr;       // column moves: sources, destinations, count
+    double* tA = nullptr;        // staging of the moved columns, 128 x m
+    double* tY = nullptr;        // staging of their sketch rows
+    int32_t* tP = nullptr;       // staging of their permutation entries
+    int32_t* perm = nullptr;     // perm[j] = column of A now at position j
+};
+int64_t piv_groups(int64_t d);
+size_t piv_ws_bytes(int64_t m, int64_t d);
+void piv_ws_carve(void* base, int64_t m, int64_t d, PivWs& w);
+// Omega, the sketch Y^T = (S A)^T Omega^T of the column-major Ac and perm = identity
+hipError_t piv_init(double* Ac, int64_t m, int64_t d, uint64_t seed, PivWs& w, GemmWs& g,
+                    hipStream_t st);
+// nb pivots among the positions j0 .. d-1 into w.sel
+hipError_t piv_select(int64_t j0, int64_t d, int nb, PivWs& w, hipStream_t st);
+// move the pivots to positions j0 .. j0+nb-1 (columns of Ac, sketch rows, perm)
+hipError_t piv_apply(double* Ac, int64_t m, int64_t j0, int nb, PivWs& w, hipStream_t st);
+// Y_2 <- Y_2 - (Y_1 R_11^-1) R_12 after the panel at j0 and its trailing update
+hipError_t piv_update_sketch(const double* Ac, int64_t m, int64_t j0, int nb, int64_t d,
+                             PivWs& w, GemmWs& g, hipStream_t st);
+
 // Householder QR of the m x (d+k) sketch on a column-major working copy
 struct QrWs {
     void* Ac = nullptr;   // column-major copy of the sketch (ld = m), factored in place
@@ -221,6 +251,10 @@ size_t qr_ws_bytes(Prec prec, int64_t m, int64_t ncols, size_t* gemm_bytes);
 void qr_ws_carve(Prec prec, void* base, int64_t m, int64_t ncols, QrWs& ws);
 hipError_t qr_factor(Prec prec, const void* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws,
                      hipStream_t st);
+// FP64 QR with column pivoting of the first d columns (the last ncols - d ride along):
+// Householder panels, pivots chosen on the sketch of rcpqr.hip; the permutation in pw.perm
+hipError_t qr_factor_pivoted(const double* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws,
+                             PivWs& pw, uint64_t seed, hipStream_t st);
 // copy R (d x d) and c (d x k) out of the factored copy into FP64 row-major, flipping
 // rows so that diag(R) >= 0
 hipError_t launch_extract_Rc(Prec prec, const QrWs& ws, int64_t m, int64_t d, int64_t k, double* R,
