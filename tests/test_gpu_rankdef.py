@@ -173,7 +173,9 @@ def test_pivoted_multiple_rhs_and_adjoint(ski):
 def test_pivoted_sparse_parity(ski):
     _say("pivoted, CSR 6000 x 200 rank 160")
     A, b, _ = workloads.rank_deficient(6000, 200, 160, case=11)
-    A[np.abs(A) < 0.8] = 0.0  # sparsify; the dependent columns stay dependent
+    # sparsify: copies and zero columns stay dependent (the combinations do not, so the
+    # rank is taken from the SVD of the sparsified matrix)
+    A[np.abs(A) < 0.8] = 0.0
     Acsr = sp.csr_matrix(A)
     n, d = A.shape
     r = np.linalg.matrix_rank(A)
@@ -202,3 +204,35 @@ def test_pivoted_rejects_mixed_precision(ski):
     with pytest.raises(ski.SkiError):
         S.sketch(dev(A), dev(b), qr_panel="pivoted", qr_prec="fp32")
     S.close()
+
+
+def test_full_size_rankdef_optimality(ski):
+    """The 50000 x 4000 rank-3500 workload in the launch configuration the benchmark times
+    (m = 6800, s = 3): the rank, x exactly zero outside J, the optimality certificate of the
+    least-squares problem ||A^T r|| / (||A||_F ||r||) (it vanishes only at a minimiser; J
+    spans range(A) when p = rank(A)), and R_11's diagonal ratio as a check that J is a set of
+    independent columns."""
+    c = workloads.CASES["rankdef"]
+    _say(f"full-size rank-deficient {c['n']}x{c['d']} rank {c['rank']}")
+    A, b, _ = workloads.rank_deficient(n=c["n"], d=c["d"], rank=c["rank"], case=c["case"])
+    At, bt = dev(A), dev(b)
+    del A
+    S = ski.Solver()
+    S.sketch(At, bt, gamma=c["gamma"], m=c["m"], s=c["s"], seed=2006, hadamard=True,
+             qr_panel="pivoted", tau_r=1e-14, it_max=400)
+    S.factor()
+    X, infos, rc = S.solve()
+    perm, p = S.get_pivots()
+    S.close()
+    assert p == c["rank"]
+    assert sorted(perm.tolist()) == list(range(c["d"]))
+    x = X[:, 0]
+    out = torch.as_tensor(perm[p:], device="cuda")
+    assert bool((x[out] == 0).all().item())
+    r = bt - At @ x
+    cert = float((At.T @ r).norm() / (At.norm() * r.norm()))
+    _say(f"  iters {infos[0]['iters']} certificate {cert:.2e} cond_est {infos[0]['cond_est']:.2e}")
+    assert cert <= 1e-12
+    assert infos[0]["cond_est"] < 1e6
+    del At, bt
+    torch.cuda.empty_cache()
