@@ -7,7 +7,7 @@ transform, gamma = 1.7 so m = 6800; Householder QR of the sketch; LSQR on A R^-1
 HBM.  Prints one JSON line on stdout (everything else goes to stderr).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-mixed]
-                       [--no-sparse] [--no-rankdef]
+                       [--no-sparse] [--no-rankdef] [--rankdef-only]
 """
 
 import argparse
@@ -255,6 +255,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-sparse", action="store_true")
     ap.add_argument("--no-rankdef", action="store_true")
+    ap.add_argument("--rankdef-only", action="store_true",
+                    help="only the rank-deficient workload (for profiling); prints its record")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the solver has no multi-GPU path, so --gpus "
@@ -263,6 +265,10 @@ def main():
 
     import torch
     import paper_2105_11815_amd as P
+
+    if args.rankdef_only:
+        print(json.dumps({"rankdef_50000x4000": rankdef_run(P, torch)}), flush=True)
+        return
 
     log("generating the dense 50000x4000 workload ...")
     A, b, cfg = workload_dense()

@@ -56,7 +56,12 @@ enum ski_status {
 enum ski_kind { SKI_DENSE = 0, SKI_CSR = 2 };
 enum ski_prec { SKI_FP64 = 0, SKI_FP32 = 1, SKI_BF16 = 2 };
 enum ski_op { SKI_OP_LLS = 0, SKI_OP_NORMAL = 1 };
-enum ski_qr_panel { SKI_QR_AUTO = 0, SKI_QR_HOUSEHOLDER = 1, SKI_QR_PIVOTED = 2 };
+enum ski_qr_panel {
+    SKI_QR_AUTO = 0,
+    SKI_QR_HOUSEHOLDER = 1,
+    SKI_QR_PIVOTED = 2,
+    SKI_QR_PIVOTED_HOUSEHOLDER = 3
+};
 
 /* The data matrix.  Dense: `a` (n x d, row-major, leading dimension lda >= d).
  * CSR: row_ptr[n+1] (int64, row_ptr[0] = 0), col[nnz] (int32 in [0, d), distinct
@@ -99,7 +104,11 @@ typedef struct {
  *                parameter rcond).  Each panel's 64 pivots are chosen by greedy column
  *                pivoting on a 72-row random sketch of the trailing columns (a
  *                tournament over groups of 512 columns), the panel is factored by
- *                Householder columns in FP64, and the sketch is updated from R_12.
+ *                CholeskyQR2 in FP64 (its columns saved first; a panel whose CholeskyQR2
+ *                checks fail, such as the one holding the rank boundary, is restored and
+ *                factored by Householder columns; one host synchronisation per panel),
+ *                and the sketch is updated from R_12.  SKI_QR_PIVOTED_HOUSEHOLDER: the
+ *                same with Householder-column panels only (no per-panel synchronisation).
  *                The rank p is the number of leading diagonal entries with
  *                |r_qq| >= rcond |r_11| (with rcond = 0: the leading non-zero ones);
  *                R_11 is the leading p x p block, V_1 the first p pivots J, and Steps
@@ -216,6 +225,10 @@ int ski_get_R(ski_handle h, double* R, double* c, double* Rinv);
  * the identity without pivoting) and the rank p (d without pivoting).  Either pointer
  * may be NULL.  SKI_ESTATE before a successful ski_factor. */
 int ski_get_pivots(ski_handle h, int32_t* perm, int64_t* rank);
+/* After ski_factor: stats[0] = rank p, stats[1] = number of 64-column panels,
+ * stats[2] = panels that CholeskyQR2 factored in a pivoted factorisation (-1 without
+ * pivoting), stats[3] = 1 if the factorisation pivoted.  SKI_ESTATE before ski_factor. */
+int ski_get_factor_stats(ski_handle h, int64_t stats[4]);
 
 #ifdef __cplusplus
 }

@@ -15,7 +15,7 @@ SKI_EINVAL, SKI_ENOMEM, SKI_EDEVICE, SKI_ERANK, SKI_ESTATE = -1, -2, -3, -4, -5
 SKI_DENSE, SKI_CSR = 0, 2
 SKI_FP64, SKI_FP32, SKI_BF16 = 0, 1, 2
 SKI_OP_LLS, SKI_OP_NORMAL = 0, 1
-SKI_QR_AUTO, SKI_QR_HOUSEHOLDER, SKI_QR_PIVOTED = 0, 1, 2
+SKI_QR_AUTO, SKI_QR_HOUSEHOLDER, SKI_QR_PIVOTED, SKI_QR_PIVOTED_HOUSEHOLDER = 0, 1, 2, 3
 
 STATUS_NAMES = {0: "OK", 1: "WNOCONV", 2: "WEARLY", -1: "EINVAL", -2: "ENOMEM",
                 -3: "EDEVICE", -4: "ERANK", -5: "ESTATE"}
@@ -23,7 +23,8 @@ STATUS_NAMES = {0: "OK", 1: "WNOCONV", 2: "WEARLY", -1: "EINVAL", -2: "ENOMEM",
 EXPORTED = ["ski_create", "ski_destroy", "ski_params_default", "ski_sketch", "ski_factor",
             "ski_solve", "ski_gradients", "ski_last_error", "ski_get_dims", "ski_get_hash",
             "ski_get_dsign", "ski_get_SA", "ski_get_R", "ski_set_profiling",
-            "ski_set_profiling_mask", "ski_get_profile", "ski_get_pivots"]
+            "ski_set_profiling_mask", "ski_get_profile", "ski_get_pivots",
+            "ski_get_factor_stats"]
 PROF_CLASSES = 16
 PROF_NAMES = ["lsqr_pass", "pass_reduce", "tri_gemv", "spmv_csr", "spmv_csrT", "lsqr_step",
               "hash", "wht_gather", "gather", "qr", "trtri", "qr_householder", "qr_pivoted"]
@@ -88,6 +89,7 @@ def load():
     lib.ski_set_profiling_mask.argtypes = [H, C.c_uint32]
     lib.ski_get_profile.argtypes = [H, P, P]
     lib.ski_get_pivots.argtypes = [H, P, P]
+    lib.ski_get_factor_stats.argtypes = [H, P]
     for name in EXPORTED:
         if name not in ("ski_params_default", "ski_last_error"):
             getattr(lib, name).restype = C.c_int

@@ -15,7 +15,7 @@ from . import _lib as L
 
 _PREC = {"fp64": L.SKI_FP64, "fp32": L.SKI_FP32, "bf16": L.SKI_BF16}
 _PANEL = {"auto": L.SKI_QR_AUTO, "householder": L.SKI_QR_HOUSEHOLDER,
-          "pivoted": L.SKI_QR_PIVOTED}
+          "pivoted": L.SKI_QR_PIVOTED, "pivoted_householder": L.SKI_QR_PIVOTED_HOUSEHOLDER}
 
 
 class SkiError(RuntimeError):
@@ -245,6 +245,14 @@ class Solver:
         except SkiError:
             p = dm["d"]
         return R, c, Ri[: p * p].reshape(p, p)
+
+    def factor_stats(self):
+        """{rank, panels, panels_cqr (-1 without pivoting), pivoted} of the last factor."""
+        a = np.zeros(4, dtype=np.int64)
+        rc = self._lib.ski_get_factor_stats(self._h, a.ctypes.data)
+        if rc != L.SKI_OK:
+            self._raise(rc, "ski_get_factor_stats")
+        return dict(rank=int(a[0]), panels=int(a[1]), panels_cqr=int(a[2]), pivoted=bool(a[3]))
 
     def get_pivots(self):
         """(perm: position j holds column perm[j] of A, rank p) of the last factor."""

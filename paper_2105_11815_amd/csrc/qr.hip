@@ -518,46 +518,99 @@ hipError_t qr_impl_cqr(T* Ac, int64_t m, int64_t ncols, int64_t d, QrWs& ws, boo
 }
 
 // Column-pivoted panels (FP64): before each panel its pivots are chosen on the sketch of
-// the trailing columns and moved to the front; the panel is factored column by column;
-// the whole trailing matrix (with the ride-along columns) gets Q^T at once, because the
-// next panel's pivots depend on the updated R_12 through the sketch update.
+// the trailing columns and moved to the front.  The panel is factored by CholeskyQR2 with
+// Householder reconstruction when `cqr` is set: its columns are saved first, the host reads
+// the panel's failure flag (one synchronisation per panel), and a failed panel (the one
+// that holds the rank boundary, typically) is restored and factored column by column.
+// The trailing matrix (with the ride-along columns) then gets Q^T: W = C^T V and W2 = W T
+// on the caller's stream, then the panel's rows of C (R_12, which the sketch update needs)
+// there too, while the rows below go to the second stream; the sketch update and the next
+// selection overlap that bulk update, and the next column moves wait for it.
 hipError_t qr_impl_pivoted(double* Ac, int64_t m, int64_t ncols, int64_t d, QrWs& ws, PivWs& pw,
-                           uint64_t seed, hipStream_t st) {
+                           uint64_t seed, bool cqr, int* hflag, int* panels_cqr,
+                           hipStream_t st) {
     using T = double;
     T* tau = (T*)ws.tau;
     T* Tl = (T*)ws.Tl;
     T* VC = (T*)ws.Vt;
     T* GW = (T*)ws.Tp;
+    T* Tq = (T*)ws.cqr.Tx;
+    hipStream_t s2 = ws.st2;
+    if (panels_cqr) *panels_cqr = 0;
     SKI_HIP(piv_init(Ac, m, d, seed, pw, ws.g, st));
-    for (int64_t j0 = 0; j0 < d; j0 += NBP) {
+    int64_t p = 0;
+    bool pending = false;  // a bulk update is queued on s2
+    for (int64_t j0 = 0; j0 < d; j0 += NBP, ++p) {
         const int nb = (int)std::min<int64_t>(NBP, d - j0);
+        const int64_t mr = m - j0;
         SKI_HIP(piv_select(j0, d, nb, pw, st));
+        // the moved columns, and the panel, need the previous panel's bulk update
+        if (pending) SKI_HIP(hipStreamWaitEvent(st, ws.evE[(p - 1) & 1], 0));
+        pending = false;
         SKI_HIP(piv_apply(Ac, m, j0, nb, pw, st));
-        for (int jl = 0; jl < nb; jl += NBL) {
-            const int64_t jc = j0 + jl;
-            const int w = std::min(NBL, nb - jl);
-            SKI_HIP(launch_leaf<T>(Ac, m, jc, w, tau, Tl, st));
-            const int nc = nb - jl - w;
-            if (nc > 0) SKI_HIP(launch_narrow<T>(Ac, m, jc, w, Tl, nc, st));
+        bool done = false;
+        if (cqr) {
+            // the staging buffer of the moves is free again: keep the panel's columns there
+            SKI_HIP(hipMemcpyAsync(pw.tA, Ac + j0 * m, (size_t)nb * m * sizeof(T),
+                                   hipMemcpyDeviceToDevice, st));
+            SKI_HIP(cqr_clear_flag(ws.cqr.flag, st));
+            SKI_HIP(cqr_gram_update<T>(Ac, m, -1, j0, nb, nullptr, nullptr, ws.cqr, st));
+            SKI_HIP(cqr_factor_panel<T>(Ac, m, j0, nb, ws.cqr, Tq, st));
+            SKI_HIP(cqr_finish_panel<T>(Ac, m, j0, nb, 0, ws.cqr, VC, st));
+            SKI_HIP(hipMemcpyAsync(hflag, ws.cqr.flag, sizeof(int), hipMemcpyDeviceToHost, st));
+            SKI_HIP(hipStreamSynchronize(st));
+            if (*hflag == 0) {
+                done = true;
+                if (panels_cqr) ++*panels_cqr;
+            } else {
+                SKI_HIP(hipMemcpyAsync(Ac + j0 * m, pw.tA, (size_t)nb * m * sizeof(T),
+                                       hipMemcpyDeviceToDevice, st));
+            }
         }
         const int64_t nrest = ncols - j0 - nb;
-        if (nrest <= 0) break;
-        const int64_t mr = m - j0;
-        hipLaunchKernelGGL((k_make_VC<T>),
-                           dim3((unsigned)std::min<int64_t>((mr + 255) / 256, 64), (unsigned)nb),
-                           dim3(256), 0, st, Ac, m, j0, nb, j0 + nb, VC);
-        SKI_HIP(hipGetLastError());
-        // V^T V for T, then W = C^T V, W2 = W T, C -= V W2^T over every remaining column
-        SKI_HIP(gemm_t<T>(false, true, nb, nb, mr, (T)1, VC, mr, VC, mr, (T)0, GW, nb, false,
-                          ws.g, st));
         T* Ct = Ac + (j0 + nb) * m + j0;
+        if (!done) {
+            for (int jl = 0; jl < nb; jl += NBL) {
+                const int64_t jc = j0 + jl;
+                const int w = std::min(NBL, nb - jl);
+                SKI_HIP(launch_leaf<T>(Ac, m, jc, w, tau, Tl, st));
+                const int nc = nb - jl - w;
+                if (nc > 0) SKI_HIP(launch_narrow<T>(Ac, m, jc, w, Tl, nc, st));
+            }
+        }
+        if (nrest <= 0) break;
+        // W = C^T V and W2 = W T (explicit V, ld mr, and T from CholeskyQR2; or the explicit
+        // reflectors and T^-1 = diag(1/tau) + striu(V^T V) of the column-by-column panel)
+        if (!done) {
+            hipLaunchKernelGGL((k_make_VC<T>),
+                               dim3((unsigned)std::min<int64_t>((mr + 255) / 256, 64),
+                                    (unsigned)nb),
+                               dim3(256), 0, st, Ac, m, j0, nb, j0 + nb, VC);
+            SKI_HIP(hipGetLastError());
+            SKI_HIP(gemm_t<T>(false, true, nb, nb, mr, (T)1, VC, mr, VC, mr, (T)0, GW, nb, false,
+                              ws.g, st));
+        }
         SKI_HIP(gemm_t<T>(false, true, nrest, nb, mr, (T)1, Ct, m, VC, mr, (T)0, (T*)ws.Wt2, nb,
                           false, ws.g, st));
-        SKI_HIP(launch_Tinv<T>((T*)ws.Wt2, nrest, nb, GW, nb, tau + j0, (T*)ws.W2t2, st));
-        SKI_HIP(gemm_t<T>(false, false, nrest, mr, nb, (T)-1, (T*)ws.W2t2, nb, VC, mr, (T)1, Ct,
+        if (done)
+            SKI_HIP(gemm_t<T>(false, false, nrest, nb, nb, (T)1, (T*)ws.Wt2, nb, Tq, NBP, (T)0,
+                              (T*)ws.W2t2, nb, false, ws.g, st));
+        else
+            SKI_HIP(launch_Tinv<T>((T*)ws.Wt2, nrest, nb, GW, nb, tau + j0, (T*)ws.W2t2, st));
+        // C -= V W2^T: the panel's rows here, the rows below on the second stream
+        SKI_HIP(gemm_t<T>(false, false, nrest, nb, nb, (T)-1, (T*)ws.W2t2, nb, VC, mr, (T)1, Ct,
                           m, false, ws.g, st));
+        if (mr > nb) {
+            SKI_HIP(hipEventRecord(ws.evF[p & 1], st));
+            SKI_HIP(hipStreamWaitEvent(s2, ws.evF[p & 1], 0));
+            SKI_HIP(gemm_t<T>(false, false, nrest, mr - nb, nb, (T)-1, (T*)ws.W2t2, nb, VC + nb,
+                              mr, (T)1, Ct + nb, m, false, ws.g2, s2));
+            SKI_HIP(hipEventRecord(ws.evE[p & 1], s2));
+            pending = true;
+        }
         SKI_HIP(piv_update_sketch(Ac, m, j0, nb, d, pw, ws.g, st));
     }
+    if (pending) SKI_HIP(hipStreamWaitEvent(st, ws.evE[(p - 1) & 1], 0));
     return hipSuccess;
 }
 
@@ -633,13 +686,14 @@ hipError_t qr_factor(Prec prec, const void* SA, int64_t m, int64_t ncols, int64_
 }
 
 hipError_t qr_factor_pivoted(const double* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws,
-                             PivWs& pw, uint64_t seed, hipStream_t st) {
+                             PivWs& pw, uint64_t seed, bool cqr, int* hflag, int* panels_cqr,
+                             hipStream_t st) {
     double* Ac = (double*)ws.Ac;
     hipLaunchKernelGGL((k_to_colmajor<double>),
                        dim3((unsigned)((ncols + 63) / 64), (unsigned)((m + 63) / 64)), dim3(256), 0,
                        st, SA, m, ncols, Ac);
     SKI_HIP(hipGetLastError());
-    return qr_impl_pivoted(Ac, m, ncols, d, ws, pw, seed, st);
+    return qr_impl_pivoted(Ac, m, ncols, d, ws, pw, seed, cqr, hflag, panels_cqr, st);
 }
 
 hipError_t launch_extract_Rc(Prec prec, const QrWs& ws, int64_t m, int64_t d, int64_t k, double* R,

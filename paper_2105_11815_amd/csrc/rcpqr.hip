@@ -21,13 +21,14 @@
 // random signs come from Philox4x64-10 keyed by the caller's seed: the pivots are
 // deterministic.  Ties in the selection go to the lower candidate slot.
 #include "ski_internal.h"
+#include "tile64.h"
 
 namespace ski {
 
 namespace {
 
-constexpr int TN = 1024;       // threads of a tournament workgroup
-constexpr int TC = TN / 2;     // candidate columns per workgroup (two lanes per column)
+constexpr int TN = 512;        // threads of a tournament workgroup
+constexpr int TC = 512;        // candidate columns per workgroup (two per lane pair)
 constexpr int YH = PIV_YL / 2; // sketch rows per lane
 constexpr int NBP = 64;
 
@@ -47,76 +48,140 @@ __global__ __launch_bounds__(256) void k_iota(int32_t* __restrict__ p, int64_t n
     if (o < n) p[o] = (int32_t)o;
 }
 
+// the better of (key, idx) and its value in the lane that the DPP control selects: larger
+// key, then lower index (lanes without a source keep their own value)
+template <int CTRL>
+__device__ __forceinline__ void dpp_best(double& key, int& idx) {
+    const int lo = __double2loint(key), hi = __double2hiint(key);
+    const int olo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
+    const int ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
+    const int oi = __builtin_amdgcn_update_dpp(idx, idx, CTRL, 0xf, 0xf, false);
+    const double ok = __hiloint2double(ohi, olo);
+    if (ok > key || (ok == key && oi < idx)) {
+        key = ok;
+        idx = oi;
+    }
+}
+// argmax over the wave with the lane moves of wave_sum; lane 63 ends with the best, which
+// is broadcast
+__device__ __forceinline__ void wave_best(double& key, int& idx) {
+    dpp_best<0xb1>(key, idx);   // quad_perm [1,0,3,2]
+    dpp_best<0x4e>(key, idx);   // quad_perm [2,3,0,1]
+    dpp_best<0x124>(key, idx);  // row_ror 4
+    dpp_best<0x128>(key, idx);  // row_ror 8
+    dpp_best<0x142>(key, idx);  // row_bcast 15
+    dpp_best<0x143>(key, idx);  // row_bcast 31
+    key = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(key), 63),
+                           __builtin_amdgcn_readlane(__double2loint(key), 63));
+    idx = __builtin_amdgcn_readlane(idx, 63);
+}
+
 // One round of the tournament.  Group g owns up to TC candidate slots: on the first round
 // the positions first + g*TC + c (c < TC, within the nrem trailing columns); later, slot
 // c = 64 q' + i holds the i-th winner of input group q = 8 g + q' (i < nin[q]).  The group
 // picks min(nsel, #candidates) of them by greedy pivoting on their sketch columns and
 // writes the chosen positions in order to cout[g*64 ..], their number to nout[g], and,
 // when nu is given, the remaining sketch norm at each choice to nu.
+//
+// Layout: 8 waves; wave w holds rows 36 h .. 36 h + 35 (h = w / 4) of the two columns
+// 128 (w % 4) + lane and 128 (w % 4) + 64 + lane in registers.  Every lane of a wave needs
+// the same 36 entries of the chosen column: one LDS read per lane, then scalar registers.
+// The two halves of a column exchange partial sums through LDS (two buffers, alternating
+// by step); every sum has four accumulators added in a fixed order.  The squared norms are
+// recomputed after every projection (no downdating: the norms of a 72-row sketch collapse
+// by design as the selection proceeds).  The choices stay in LDS until the end (a global
+// store inside the loop would make every later barrier wait for it).
 __global__ __launch_bounds__(TN) void k_tourney(const double* __restrict__ Yt, int64_t first,
                                                 int64_t nrem, const int32_t* __restrict__ cin,
                                                 const int32_t* __restrict__ nin, int nin_groups,
                                                 int nsel, int32_t* __restrict__ cout,
                                                 int32_t* __restrict__ nout,
                                                 double* __restrict__ nu) {
-    __shared__ double skey[TN / 64];
-    __shared__ int sidx[TN / 64];
-    __shared__ double qv[PIV_YL];
+    constexpr int NW = TN / 64;
+    constexpr int NWH = NW / 2;
+    __shared__ double pn[2][2][TC];   // [parity][half][slot]
+    __shared__ double skey[NWH];
+    __shared__ int sidx[NWH];
+    __shared__ __align__(16) double qv[PIV_YL];
     __shared__ int spos[TC];
+    __shared__ int ssel[NBP];
+    __shared__ double snu[NBP];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int c = tid >> 1, h = tid & 1;
+    const int h = wv / NWH;
+    const int c0 = ((wv % NWH) << 7) | lane, c1 = c0 + 64;
     const int g = blockIdx.x;
-    int pos = -1;
-    if (cin == nullptr) {
-        const int64_t off = (int64_t)g * TC + c;
-        if (off < nrem) pos = (int)(first + off);
-    } else {
+    auto slot_pos = [&](int c) -> int {
+        if (cin == nullptr) {
+            const int64_t off = (int64_t)g * TC + c;
+            return off < nrem ? (int)(first + off) : -1;
+        }
         const int q = 8 * g + (c >> 6), i = c & 63;
-        if (q < nin_groups && i < nin[q]) pos = cin[q * 64 + i];
+        return (q < nin_groups && i < nin[q]) ? cin[q * 64 + i] : -1;
+    };
+    const int pos0 = slot_pos(c0), pos1 = slot_pos(c1);
+    if (h == 0) {
+        spos[c0] = pos0;
+        spos[c1] = pos1;
     }
-    if (h == 0) spos[c] = pos;
-    double y[YH];
-    if (pos >= 0) {
-        const double2* src = reinterpret_cast<const double2*>(Yt + (int64_t)pos * PIV_YL + h * YH);
+    double y0[YH], y1[YH];
+    auto load = [&](int pos, double (&y)[YH]) {
+        if (pos >= 0) {
+            const double2* src =
+                reinterpret_cast<const double2*>(Yt + (int64_t)pos * PIV_YL + h * YH);
 #pragma unroll
-        for (int r = 0; r < YH / 2; ++r) {
-            const double2 v = src[r];
-            y[2 * r] = v.x;
-            y[2 * r + 1] = v.y;
-        }
-    } else {
-#pragma unroll
-        for (int r = 0; r < YH; ++r) y[r] = 0.0;
-    }
-    const int ncand = __syncthreads_count(pos >= 0 && h == 0);
-    const int steps = min(nsel, ncand);
-    bool taken = pos < 0;
-    for (int s = 0; s < steps; ++s) {
-        double n2 = 0.0;
-#pragma unroll
-        for (int r = 0; r < YH; ++r) n2 += y[r] * y[r];
-        n2 += __shfl_xor(n2, 1);
-        // candidates still free rank by norm (a non-finite norm ranks as zero)
-        double key = taken ? -1.0 : (n2 >= 0.0 && n2 <= 1.7e308 ? n2 : 0.0);
-        int idx = c;
-#pragma unroll
-        for (int off = 2; off < 64; off <<= 1) {
-            const double ok = __shfl_xor(key, off);
-            const int oi = __shfl_xor(idx, off);
-            if (ok > key || (ok == key && oi < idx)) {
-                key = ok;
-                idx = oi;
+            for (int r = 0; r < YH / 2; ++r) {
+                const double2 v = src[r];
+                y[2 * r] = v.x;
+                y[2 * r + 1] = v.y;
             }
+        } else {
+#pragma unroll
+            for (int r = 0; r < YH; ++r) y[r] = 0.0;
         }
-        if (lane == 0) {
-            skey[wv] = key;
-            sidx[wv] = idx;
+    };
+    load(pos0, y0);
+    load(pos1, y1);
+    bool taken0 = pos0 < 0, taken1 = pos1 < 0;
+    // partial squared norms, four accumulators each, summed in a fixed order
+    auto partial_norms = [&](int par) {
+        double a[4] = {0, 0, 0, 0}, b[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int r = 0; r < YH; ++r) {
+            a[r & 3] += y0[r] * y0[r];
+            b[r & 3] += y1[r] * y1[r];
+        }
+        pn[par][h][c0] = (a[0] + a[1]) + (a[2] + a[3]);
+        pn[par][h][c1] = (b[0] + b[1]) + (b[2] + b[3]);
+    };
+    const int ncand = __syncthreads_count(h == 0 && pos0 >= 0) +
+                      __syncthreads_count(h == 0 && pos1 >= 0);
+    const int steps = min(nsel, ncand);
+    partial_norms(0);
+    __syncthreads();
+    for (int s = 0; s < steps; ++s) {
+        const int par = s & 1;
+        if (h == 0) {
+            const double n20 = pn[par][0][c0] + pn[par][1][c0];
+            const double n21 = pn[par][0][c1] + pn[par][1][c1];
+            const double k0 = taken0 ? -1.0 : (n20 >= 0.0 && n20 <= 1.7e308 ? n20 : 0.0);
+            const double k1 = taken1 ? -1.0 : (n21 >= 0.0 && n21 <= 1.7e308 ? n21 : 0.0);
+            double key = k0;
+            int idx = c0;
+            if (k1 > k0) {
+                key = k1;
+                idx = c1;
+            }
+            wave_best(key, idx);
+            if (lane == 0) {
+                skey[wv] = key;
+                sidx[wv] = idx;
+            }
         }
         __syncthreads();
         double bkey = skey[0];
         int bidx = sidx[0];
 #pragma unroll
-        for (int w = 1; w < TN / 64; ++w) {
+        for (int w = 1; w < NWH; ++w) {
             const double k2 = skey[w];
             const int i2 = sidx[w];
             if (k2 > bkey || (k2 == bkey && i2 < bidx)) {
@@ -124,29 +189,59 @@ __global__ __launch_bounds__(TN) void k_tourney(const double* __restrict__ Yt, i
                 bidx = i2;
             }
         }
-        if (c == bidx) {
-            taken = true;
+        if (c0 == bidx) {
+            taken0 = true;
 #pragma unroll
-            for (int r = 0; r < YH; ++r) qv[h * YH + r] = y[r];
+            for (int r = 0; r < YH; ++r) qv[h * YH + r] = y0[r];
+        } else if (c1 == bidx) {
+            taken1 = true;
+#pragma unroll
+            for (int r = 0; r < YH; ++r) qv[h * YH + r] = y1[r];
         }
         if (tid == 0) {
-            cout[g * 64 + s] = spos[bidx];
-            if (nu) nu[s] = sqrt(bkey);
+            ssel[s] = spos[bidx];
+            snu[s] = sqrt(bkey);
         }
         __syncthreads();
         if (bkey > 0.0) {
-            // project the chosen direction out of every column (modified Gram-Schmidt):
-            // y -= (y . c) c / ||c||^2 for the chosen column c, read from LDS
-            double dt = 0.0;
+            // this half's 36 entries of the chosen column: one LDS read per lane, then
+            // broadcast into scalar registers
+            const double qsrc = lane < YH ? qv[h * YH + lane] : 0.0;
+            double q[YH];
 #pragma unroll
-            for (int r = 0; r < YH; ++r) dt += qv[h * YH + r] * y[r];
-            dt += __shfl_xor(dt, 1);
-            const double f = dt / bkey;
-            // read the chosen column from LDS again rather than hold 36 more registers
-            __asm__ volatile("" ::: "memory");
+            for (int r = 0; r < YH; ++r)
+                q[r] = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(qsrc), r),
+                                        __builtin_amdgcn_readlane(__double2loint(qsrc), r));
+            double a[4] = {0, 0, 0, 0}, b[4] = {0, 0, 0, 0};
 #pragma unroll
-            for (int r = 0; r < YH; ++r) y[r] -= f * qv[h * YH + r];
+            for (int r = 0; r < YH; ++r) {
+                a[r & 3] += q[r] * y0[r];
+                b[r & 3] += q[r] * y1[r];
+            }
+            pn[par ^ 1][h][c0] = (a[0] + a[1]) + (a[2] + a[3]);
+            pn[par ^ 1][h][c1] = (b[0] + b[1]) + (b[2] + b[3]);
+            __syncthreads();
+            const double inv = 1.0 / bkey;
+            const double f0 = (pn[par ^ 1][0][c0] + pn[par ^ 1][1][c0]) * inv;
+            const double f1 = (pn[par ^ 1][0][c1] + pn[par ^ 1][1][c1]) * inv;
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < YH; ++r) {
+                y0[r] -= f0 * q[r];
+                y1[r] -= f1 * q[r];
+            }
+            partial_norms(par ^ 1);
+        } else {
+            // nothing left to project: carry the norms to the next parity
+            pn[par ^ 1][h][c0] = pn[par][h][c0];
+            pn[par ^ 1][h][c1] = pn[par][h][c1];
         }
+        __syncthreads();
+    }
+    __syncthreads();
+    if (tid < steps) {
+        cout[g * 64 + tid] = ssel[tid];
+        if (nu) nu[tid] = snu[tid];
     }
     if (tid == 0) nout[g] = steps;
 }
@@ -231,41 +326,66 @@ __global__ __launch_bounds__(256) void k_pivot_move(double* __restrict__ Ac, int
     }
 }
 
-// Bt = R_11^-T Y_1^T (nb x yl) for the sketch update: forward substitution with the panel's
-// R_11 (upper, rows and columns j0 .. j0+nb-1 of Ac); a diagonal entry below 1e-13 of the
-// panel's largest one gives a zero row (that direction is left in the sketch)
+// Bt = R_11^-T Y_1^T (nb x yl) for the sketch update, with the panel's R_11 (upper, rows and
+// columns j0 .. j0+nb-1 of Ac).  A diagonal entry at or below 1e-13 of the panel's largest
+// one leaves its direction in the sketch: its column of R_11 is replaced by the unit vector
+// and its row of Y_1^T by zeros, which gives a zero row of Bt (what forward substitution
+// that skips the entry gives).  R_11 is inverted in LDS (padded to 64 with the identity),
+// then multiplied.
 __global__ __launch_bounds__(256) void k_sketch_bt(const double* __restrict__ Ac, int64_t m,
                                                    int64_t j0, int nb,
                                                    const double* __restrict__ Yt,
                                                    double* __restrict__ Bt) {
-    __shared__ double R[NBP][NBP + 1];
-    __shared__ double Bs[NBP][PIV_YL];
-    const int tid = threadIdx.x;
-    for (int o = tid; o < nb * nb; o += 256) {
-        const int i = o / nb, k = o - i * nb;  // column i, row k
-        R[k][i] = k <= i ? Ac[(j0 + i) * m + j0 + k] : 0.0;
+    __shared__ double R[NBP][tile::PP];
+    __shared__ double Ys[NBP][PIV_YL];
+    __shared__ int skip[NBP];
+    const int t = threadIdx.x;
+    // every load is issued before the first one is used
+    constexpr int NR = NBP * NBP / 256, NY = NBP * PIV_YL / 256;
+    double ra[NR], ya[NY];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        const int o = t + 256 * q, i = o / NBP, k = o - i * NBP;  // column i, row k
+        ra[q] = (i < nb && k <= i) ? Ac[(j0 + i) * m + j0 + k] : (k == i ? 1.0 : 0.0);
     }
-    for (int o = tid; o < nb * PIV_YL; o += 256) {
-        const int i = o / PIV_YL, t = o - i * PIV_YL;
-        Bs[i][t] = Yt[(j0 + i) * PIV_YL + t];
+#pragma unroll
+    for (int q = 0; q < NY; ++q) {
+        const int o = t + 256 * q, i = o / PIV_YL, u = o - i * PIV_YL;
+        ya[q] = i < nb ? Yt[(j0 + i) * PIV_YL + u] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        const int o = t + 256 * q;
+        R[o % NBP][o / NBP] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NY; ++q) {
+        const int o = t + 256 * q;
+        Ys[o / PIV_YL][o % PIV_YL] = ya[q];
     }
     __syncthreads();
-    double dmax = 0.0;
-    for (int i = 0; i < nb; ++i) dmax = fmax(dmax, fabs(R[i][i]));
-    const double thr = 1e-13 * dmax;
-    if (tid < PIV_YL) {
-        const int t = tid;
-        for (int i = 0; i < nb; ++i) {
-            double a = Bs[i][t];
-            for (int k = 0; k < i; ++k) a -= R[k][i] * Bs[k][t];
-            const double di = R[i][i];
-            Bs[i][t] = fabs(di) > thr ? a / di : 0.0;
-        }
+    if (t < NBP) {
+        double dmax = 0.0;
+        for (int i = 0; i < nb; ++i) dmax = fmax(dmax, fabs(R[i][i]));
+        skip[t] = !(fabs(R[t][t]) > 1e-13 * dmax);
     }
     __syncthreads();
-    for (int o = tid; o < nb * PIV_YL; o += 256) {
-        const int i = o / PIV_YL, t = o - i * PIV_YL;
-        Bt[i * PIV_YL + t] = Bs[i][t];
+    for (int o = t; o < NBP * NBP; o += 256) {
+        const int i = o / NBP, k = o - i * NBP;
+        if (skip[i]) R[k][i] = k == i ? 1.0 : 0.0;
+    }
+    for (int o = t; o < NBP * PIV_YL; o += 256) {
+        const int i = o / PIV_YL, u = o - i * PIV_YL;
+        if (skip[i]) Ys[i][u] = 0.0;
+    }
+    __syncthreads();
+    tile::tile_trinv(R, t, false);
+    // Bt(i, u) = sum_{k <= i} R^-1(k, i) Y(k, u)
+    for (int o = t; o < nb * PIV_YL; o += 256) {
+        const int i = o / PIV_YL, u = o - i * PIV_YL;
+        double a = 0.0;
+        for (int k = 0; k <= i; ++k) a += R[k][i] * Ys[k][u];
+        Bt[i * PIV_YL + u] = a;
     }
 }
 

@@ -52,6 +52,7 @@ struct ski_handle_s {
     // column-pivoted factor: workspace, the permutation, compact R_11, p x k staging
     DevBuf piv_part, pivd, Rc, ptmp;
     int64_t rank = 0;      // p: columns kept (d without pivoting)
+    int panels_cqr = 0;    // pivoted factor: panels factored by CholeskyQR2
     bool pivoted = false;  // the last ski_factor pivoted
     hipStream_t st2 = nullptr;           // second stream of the QR's look-ahead
     hipEvent_t qev[4] = {};
@@ -263,12 +264,10 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
     if (A->kind == SKI_CSR && p->hadamard)
         return fail(h, SKI_EINVAL, "ski_sketch: the Hadamard transform is for dense A only");
     if (p->s < 1 || p->s > 32) return fail(h, SKI_EINVAL, "ski_sketch: need 1 <= s <= 32");
-    if (p->qr_panel != SKI_QR_AUTO && p->qr_panel != SKI_QR_HOUSEHOLDER &&
-        p->qr_panel != SKI_QR_PIVOTED)
-        return fail(h, SKI_EINVAL,
-                    "ski_sketch: qr_panel must be SKI_QR_AUTO, SKI_QR_HOUSEHOLDER or SKI_QR_PIVOTED");
-    if (p->qr_panel == SKI_QR_PIVOTED && p->qr_prec != SKI_FP64)
-        return fail(h, SKI_EINVAL, "ski_sketch: SKI_QR_PIVOTED needs qr_prec = SKI_FP64");
+    if (p->qr_panel < SKI_QR_AUTO || p->qr_panel > SKI_QR_PIVOTED_HOUSEHOLDER)
+        return fail(h, SKI_EINVAL, "ski_sketch: unknown qr_panel");
+    if (p->qr_panel >= SKI_QR_PIVOTED && p->qr_prec != SKI_FP64)
+        return fail(h, SKI_EINVAL, "ski_sketch: the pivoted factorisation needs qr_prec = SKI_FP64");
     if (p->sketch_prec < 0 || p->sketch_prec > 2 || p->qr_prec < 0 || p->qr_prec > 2)
         return fail(h, SKI_EINVAL, "ski_sketch: unknown precision");
     if (!(p->tau_r >= 0) || !(p->tau_a >= 0) || p->it_max < 1)
@@ -425,7 +424,7 @@ int ski_factor(ski_handle h, void* stream) {
         h->hdiag_n = d;
     }
     int* hflag = (int*)(h->hdiag + 2 * d);
-    const bool piv = h->p.qr_panel == SKI_QR_PIVOTED;
+    const bool piv = h->p.qr_panel == SKI_QR_PIVOTED || h->p.qr_panel == SKI_QR_PIVOTED_HOUSEHOLDER;
     h->pivoted = false;
     h->rank = d;
     if (piv) {
@@ -435,7 +434,8 @@ int ski_factor(ski_handle h, void* stream) {
         PivWs pw;
         piv_ws_carve(h->piv_part.p, m, d, pw);
         prof_begin(h, PC_QR_PIV, st);
-        SKI_TRY(h, qr_factor_pivoted((const double*)h->SA.p, m, ncols, d, ws, pw, h->p.seed, st),
+        SKI_TRY(h, qr_factor_pivoted((const double*)h->SA.p, m, ncols, d, ws, pw, h->p.seed,
+                                     h->p.qr_panel == SKI_QR_PIVOTED, hflag, &h->panels_cqr, st),
                 "pivoted qr");
         prof_end(h, st);
         SKI_TRY(h, launch_extract_Rc(h->qprec, ws, m, d, k, P<double>(h->R), P<double>(h->c), st),
@@ -1056,6 +1056,16 @@ int ski_get_R(ski_handle h, double* R, double* c, double* Rinv) {
     if (Rinv && h->factored && h->rank > 0 &&
         hipMemcpy(Rinv, h->Rinv.p, h->rank * h->rank * 8, hipMemcpyDeviceToHost) != hipSuccess)
         return fail(h, SKI_EDEVICE, "copy");
+    return SKI_OK;
+}
+
+int ski_get_factor_stats(ski_handle h, int64_t stats[4]) {
+    if (!h || !stats) return SKI_EINVAL;
+    if (!h->factored) return fail(h, SKI_ESTATE, "ski_get_factor_stats: not factored");
+    stats[0] = h->rank;
+    stats[1] = (h->d + 63) / 64;
+    stats[2] = h->pivoted ? h->panels_cqr : -1;
+    stats[3] = h->pivoted ? 1 : 0;
     return SKI_OK;
 }
 

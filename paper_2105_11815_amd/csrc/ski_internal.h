@@ -251,10 +251,15 @@ size_t qr_ws_bytes(Prec prec, int64_t m, int64_t ncols, size_t* gemm_bytes);
 void qr_ws_carve(Prec prec, void* base, int64_t m, int64_t ncols, QrWs& ws);
 hipError_t qr_factor(Prec prec, const void* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws,
                      hipStream_t st);
-// FP64 QR with column pivoting of the first d columns (the last ncols - d ride along):
-// Householder panels, pivots chosen on the sketch of rcpqr.hip; the permutation in pw.perm
+// FP64 QR with column pivoting of the first d columns (the last ncols - d ride along),
+// pivots chosen on the sketch of rcpqr.hip, the permutation in pw.perm.  Panels by
+// CholeskyQR2 (cqr) with a per-panel fallback to Householder columns, or Householder
+// columns only; hflag: pinned host int used to read each panel's flag; panels_cqr (may be
+// null) receives the number of panels that CholeskyQR2 factored.  Synchronises st once per
+// panel when cqr is set.
 hipError_t qr_factor_pivoted(const double* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws,
-                             PivWs& pw, uint64_t seed, hipStream_t st);
+                             PivWs& pw, uint64_t seed, bool cqr, int* hflag, int* panels_cqr,
+                             hipStream_t st);
 // copy R (d x d) and c (d x k) out of the factored copy into FP64 row-major, flipping
 // rows so that diag(R) >= 0
 hipError_t launch_extract_Rc(Prec prec, const QrWs& ws, int64_t m, int64_t d, int64_t k, double* R,

@@ -61,19 +61,30 @@ RANKDEF_CASES = [
 ]
 
 
+@pytest.mark.parametrize("panel", ["pivoted", "pivoted_householder"])
 @pytest.mark.parametrize("n,d,r,case", RANKDEF_CASES)
-def test_pivoted_solve_parity(ski, n, d, r, case):
-    _say(f"pivoted solve n={n} d={d} rank={r} case={case}")
+def test_pivoted_solve_parity(ski, n, d, r, case, panel):
+    _say(f"pivoted solve n={n} d={d} rank={r} case={case} panel={panel}")
     A, b, _ = workloads.rank_deficient(n, d, r, case=case)
     m = lls.sketch_size(1.7, d)
     seed = 500 + case
     S = ski.Solver()
-    S.sketch(dev(A), dev(b), m=m, s=3, seed=seed, hadamard=True, qr_panel="pivoted",
+    S.sketch(dev(A), dev(b), m=m, s=3, seed=seed, hadamard=True, qr_panel=panel,
              tau_r=1e-14, it_max=500)
     S.factor()
     X, infos, rc = S.solve()
     x = X[:, 0].cpu().numpy()
     perm, p = S.get_pivots()
+    st = S.factor_stats()
+    # CholeskyQR2 factors every panel of a full-rank input; the panel holding the rank
+    # boundary fails its checks and is factored by Householder columns
+    assert st["pivoted"] and st["panels"] == (d + 63) // 64
+    if panel == "pivoted_householder":
+        assert st["panels_cqr"] == 0
+    elif r == d:
+        assert st["panels_cqr"] == st["panels"]
+    else:
+        assert 0 < st["panels_cqr"] < st["panels"]
     R, c, Rinv = S.get_R()
     SA = S.get_SA()
     S.close()
