@@ -7,7 +7,7 @@ transform, gamma = 1.7 so m = 6800; Householder QR of the sketch; LSQR on A R^-1
 HBM.  Prints one JSON line on stdout (everything else goes to stderr).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-mixed]
-                       [--no-sparse] [--no-rankdef] [--rankdef-only]
+                       [--no-sparse] [--no-rankdef] [--rankdef-only] [--sweep]
 """
 
 import argparse
@@ -213,6 +213,75 @@ def rankdef_run(P, torch):
                           for k, v in prof.items() if v[1]}}
 
 
+def sweep_run(P, torch):
+    """Sketch size and hashing density on the GPU (gamma = m/d and s): for the dense
+    50000 x 4000 and the sparse 200000 x 5000 workloads, one warm-up and one timed solve per
+    (gamma, s), with the time of each step, the LSQR iterations and the optimality
+    certificate recomputed in FP64.  m stays within the 12288 rows the library supports."""
+    import scipy.sparse as sp
+    import workloads
+    out = {}
+
+    def run(label, A_arg, bt, certf, d, gammas, ss, base):
+        rows = []
+        for s in ss:
+            for g in gammas:
+                m = int(math.ceil(g * d - 1e-9))
+                if m > 12288:
+                    continue
+                kw = dict(base, m=m, s=s)
+                S = P.Solver()
+                try:
+                    one_solve(P, S, A_arg, bt, **kw)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    X, info, rc = one_solve(P, S, A_arg, bt, **kw)
+                    torch.cuda.synchronize()
+                    ms = (time.perf_counter() - t0) * 1e3
+                finally:
+                    S.close()
+                rows.append(dict(gamma=g, s=s, m=m, ms=round(ms, 3), iters=int(info["iters"]),
+                                 status=int(rc), ms_sketch=round(info["ms_sketch"], 3),
+                                 ms_factor=round(info["ms_factor"], 3),
+                                 ms_solve=round(info["ms_solve"], 3),
+                                 optimality=certf(X[:, 0])))
+                log(f"{label} " + json.dumps(rows[-1]))
+        return rows
+
+    A, b, cfg = workload_dense()
+    At = torch.as_tensor(A).to("cuda")
+    bt = torch.as_tensor(b).to("cuda")
+    del A
+
+    def cert_dense(x):
+        r = bt - At @ x
+        return float((At.T @ r).norm() / (At.norm() * r.norm()))
+
+    out["dense_50000x4000"] = run("dense", At, bt, cert_dense, cfg["d"],
+                                  [1.3, 1.5, 1.7, 2.0, 2.5, 3.0], [1, 2, 3],
+                                  dict(seed=2002, tau_r=1e-10, hadamard=True))
+    del At, bt
+    torch.cuda.empty_cache()
+    c = workloads.CASES["sparse"]
+    n, d = c["n"], c["d"]
+    rp, ci, va, b = workloads.sparse_power_law(n=n, d=d, case=c["case"])
+    dev = lambda a, t: torch.as_tensor(a).to(device="cuda", dtype=t)
+    Acsr = ("csr", dev(rp, torch.int64), dev(ci, torch.int32), dev(va, torch.float64), (n, d))
+    bt = dev(b, torch.float64)
+    Ah = sp.csr_matrix((va, ci, rp), shape=(n, d))
+    anorm = sp.linalg.norm(Ah)
+
+    def cert_sparse(x):
+        xh = x.cpu().numpy()
+        r = b - Ah @ xh
+        return float(np.linalg.norm(Ah.T @ r) / (anorm * np.linalg.norm(r)))
+
+    out["sparse_200000x5000"] = run("sparse", Acsr, bt, cert_sparse, d,
+                                    [1.2, 1.4, 1.5, 1.7, 2.0, 2.4], [1, 2, 3],
+                                    dict(seed=2003, tau_r=1e-10, hadamard=False))
+    return out
+
+
 def mixed_runs(P, torch, At, bt, base_kw, forms, label):
     """Time one solve per precision form (after a warm-up solve) and recompute the
     residual and the optimality certificate ||A^T r|| / (||A||_F ||r||) in FP64."""
@@ -257,6 +326,8 @@ def main():
     ap.add_argument("--no-rankdef", action="store_true")
     ap.add_argument("--rankdef-only", action="store_true",
                     help="only the rank-deficient workload (for profiling); prints its record")
+    ap.add_argument("--sweep", action="store_true",
+                    help="only the gamma/s sweep of the dense and sparse workloads; prints it")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the solver has no multi-GPU path, so --gpus "
@@ -268,6 +339,9 @@ def main():
 
     if args.rankdef_only:
         print(json.dumps({"rankdef_50000x4000": rankdef_run(P, torch)}), flush=True)
+        return
+    if args.sweep:
+        print(json.dumps({"gamma_s_sweep": sweep_run(P, torch)}), flush=True)
         return
 
     log("generating the dense 50000x4000 workload ...")
