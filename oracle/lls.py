@@ -226,9 +226,11 @@ def solve(A, B, seed, sparse=None, **kw):
         return None, dict(status=EINVAL)
     if sparse:
         Ac = A.tocsr()
-        out = sk.sketch_csr(Ac.indptr, Ac.indices, Ac.data, n, d, B2, m, p["s"], seed)
+        out = sk.sketch_csr(Ac.indptr, Ac.indices, Ac.data, n, d, B2, m, p["s"], seed,
+                            kind=p.get("hash_kind", "hash"))
     else:
-        out = sk.sketch_dense(A, B2, m, p["s"], seed, hadamard=p["hadamard"])
+        out = sk.sketch_dense(A, B2, m, p["s"], seed, hadamard=p["hadamard"],
+                              kind=p.get("hash_kind", "hash"))
     X = np.zeros((d, B2.shape[1]))
     recs = []
     extra = {}

@@ -12,6 +12,12 @@ Definitions followed
   matrix H_ij = n^-1/2 (-1)^<(i-1)_2, (j-1)_2>, and S_h independent of D.
 * Sparse input (Section 6, sparse variant): S is an s-hashing matrix alone.
 * Step 1 of Algorithm 1 sketches b with the same S (the augmented column).
+* s-hashing variant (Section 4, Definition of the s-hashing variant): the s
+  rows of a column are drawn WITH replacement; a row drawn twice receives both
+  +-1/sqrt(s) contributions.
+* Row sampling (Section 7, the sampled transform of Blendenpik that the paper
+  compares against): every sketch row is one row of H D [A b] (or of [A b]
+  without H), drawn uniformly with replacement, with value 1.
 
 Readings of the paper taken here (each also listed in the design notes):
 * H needs a power-of-two order, so the rows are zero-padded to
@@ -25,12 +31,18 @@ Readings of the paper taken here (each also listed in the design notes):
     column stops at s accepted rows.
   - sign d_i of D: bit (i mod 64) of word ((i >> 6) mod 4) of the block at
     counter (i >> 8, 0, 1, 0); d_i = -1 iff that bit is set.
+  - hash of column j in the variant: the same words, none rejected: the column
+    takes the rows of its first s words.
+  - sampled row of sketch row i: word 0 of the block at counter (i, 0, 2, 0),
+    row floor((w >> 32) * n / 2^32) over the n rows sampled from (n' with H).
 * The scalars of H and S_h are applied once, at the end, as the single FP64
-  factor 1 / sqrt(n' * s) (dense) or 1 / sqrt(s) (sparse).
+  factor 1 / sqrt(n' * s) (dense) or 1 / sqrt(s) (sparse); for row sampling
+  1 / sqrt(n') (H's normalisation) or 1.
 * The Walsh-Hadamard transform is applied by butterflies (x, y) -> (x+y, x-y)
   over row-index bit 0, then bit 1, and so on; the bucket sums run over the
   bucket's columns in ascending order, starting from +0.0.  Fixing both orders
-  makes the sketch reproducible to the last bit.
+  makes the sketch reproducible to the last bit.  A row that a column of the
+  variant drew twice is added twice, the positive entry before the negative.
 """
 
 import math
@@ -50,13 +62,24 @@ def next_pow2(n):
     return p
 
 
-def hash_columns(ncols, m, s, seed):
-    """Rows and sign bits of an s-hashing matrix with m rows and ncols columns.
+def hash_columns(ncols, m, s, seed, replace=False):
+    """Rows and sign bits of an s-hashing matrix with m rows and ncols columns
+    (with replace=True, of the s-hashing variant).
 
     Returns (rows, neg): int64 [ncols, s] rows in the order they were accepted
     and bool [ncols, s], True where the entry is negative."""
     if not (1 <= s <= m):
         raise ValueError("need 1 <= s <= m")
+    if replace:
+        rows = np.empty((ncols, s), dtype=np.int64)
+        neg = np.empty((ncols, s), dtype=bool)
+        j = np.arange(ncols, dtype=np.uint64)
+        mm = np.uint64(m)
+        for t in range(s):
+            w = philox4x64_10(j, np.uint64(t // 4), 0, 0, np.uint64(seed), 0)[t % 4]
+            rows[:, t] = (((w >> np.uint64(32)) * mm) >> np.uint64(32)).astype(np.int64)
+            neg[:, t] = (w & np.uint64(1)) == 1
+        return rows, neg
     rows = np.full((ncols, s), -1, dtype=np.int64)
     neg = np.zeros((ncols, s), dtype=bool)
     count = np.zeros(ncols, dtype=np.int64)
@@ -81,6 +104,13 @@ def hash_columns(ncols, m, s, seed):
     return rows, neg
 
 
+def sample_rows(m, nrows, seed):
+    """The row of [A b] (or of H D [A b]) that each of the m sketch rows samples."""
+    i = np.arange(m, dtype=np.uint64)
+    w = philox4x64_10(i, 0, np.uint64(2), 0, np.uint64(seed), 0)[0]
+    return (((w >> np.uint64(32)) * np.uint64(nrows)) >> np.uint64(32)).astype(np.int64)
+
+
 def d_signs(nrows, seed):
     """The +-1 diagonal of D, as float64 of length nrows."""
     i = np.arange(nrows, dtype=np.int64)
@@ -95,12 +125,14 @@ def hash_csr(rows, neg, m):
     """Bucket-sorted form of the hashing matrix: for each sketch row (bucket) b,
     the columns j with S_h[b, j] != 0, ascending, and their sign bits.
 
-    Returns (bucket_ptr int64[m+1], src int64[ncols*s], neg bool[ncols*s])."""
+    Returns (bucket_ptr int64[m+1], src int64[ncols*s], neg bool[ncols*s]).
+    Inside a bucket the entries ascend by column, then sign bit (a row that a
+    column of the variant drew twice)."""
     ncols, s = rows.shape
     b = rows.reshape(-1)
     j = np.repeat(np.arange(ncols, dtype=np.int64), s)
     sg = neg.reshape(-1)
-    order = np.lexsort((j, b))
+    order = np.lexsort((sg, j, b))
     counts = np.bincount(b, minlength=m)
     ptr = np.zeros(m + 1, dtype=np.int64)
     np.cumsum(counts, out=ptr[1:])
@@ -139,10 +171,24 @@ def bucket_sum(ptr, src, neg, rows_of):
     return acc
 
 
-def sketch_dense(A, B, m, s, seed, hadamard=True):
+def _sketch_structure(nrows, m, s, seed, kind):
+    """(rows, neg, bucket_ptr, src, src_neg) of S_h for kind "hash", "variant" or
+    "sample" (rows/neg are per column of S_h; for sampling, the sampled rows)."""
+    if kind == "sample":
+        r = sample_rows(m, nrows, seed)
+        ptr = np.arange(m + 1, dtype=np.int64)
+        return r, np.zeros(m, dtype=bool), ptr, r.copy(), np.zeros(m, dtype=bool)
+    rows, neg = hash_columns(nrows, m, s, seed, replace=(kind == "variant"))
+    ptr, src, sg = hash_csr(rows, neg, m)
+    return rows, neg, ptr, src, sg
+
+
+def sketch_dense(A, B, m, s, seed, hadamard=True, kind="hash"):
     """S [A B] for dense A (n x d) and B (n x k), S = S_h H D (or S_h alone).
 
-    Returns dict with SA_aug (m x (d+k)), and the hashing/sign arrays."""
+    kind: "hash" (s-hashing), "variant" (the s-hashing variant) or "sample"
+    (row sampling, s ignored).  Returns dict with SA_aug (m x (d+k)), and the
+    hashing/sign arrays."""
     A = np.asarray(A, dtype=np.float64)
     B = np.asarray(B, dtype=np.float64).reshape(A.shape[0], -1)
     n, d = A.shape
@@ -154,20 +200,19 @@ def sketch_dense(A, B, m, s, seed, hadamard=True):
         D = d_signs(npad, seed)
         X *= D[:, None]
         fwht_inplace(X)
-        scale = 1.0 / math.sqrt(float(npad * s))
+        scale = 1.0 / math.sqrt(float(npad * (1 if kind == "sample" else s)))
     else:
         npad = n
         X = np.concatenate([A, B], axis=1)
         D = None
-        scale = 1.0 / math.sqrt(float(s))
-    rows, neg = hash_columns(npad, m, s, seed)
-    ptr, src, sg = hash_csr(rows, neg, m)
+        scale = 1.0 if kind == "sample" else 1.0 / math.sqrt(float(s))
+    rows, neg, ptr, src, sg = _sketch_structure(npad, m, s, seed, kind)
     SA = bucket_sum(ptr, src, sg, lambda idx: X[idx]) * scale
     return dict(SA_aug=SA, rows=rows, neg=neg, bucket_ptr=ptr, src=src,
                 src_neg=sg, dsign=D, npad=npad, scale=scale)
 
 
-def sketch_csr(row_ptr, col, val, n, d, B, m, s, seed):
+def sketch_csr(row_ptr, col, val, n, d, B, m, s, seed, kind="hash"):
     """S [A B] for sparse A in CSR form (no Hadamard; Section 6, sparse input).
 
     Only the stored entries are added, in bucket order; adding an absent
@@ -177,8 +222,7 @@ def sketch_csr(row_ptr, col, val, n, d, B, m, s, seed):
     val = np.asarray(val, dtype=np.float64)
     B = np.asarray(B, dtype=np.float64).reshape(n, -1)
     k = B.shape[1]
-    rows, neg = hash_columns(n, m, s, seed)
-    ptr, src, sg = hash_csr(rows, neg, m)
+    rows, neg, ptr, src, sg = _sketch_structure(n, m, s, seed, kind)
     lens = np.diff(ptr)
     acc = np.zeros((m, d + k))
     for t in range(int(lens.max()) if m else 0):
@@ -198,7 +242,7 @@ def sketch_csr(row_ptr, col, val, n, d, B, m, s, seed):
         acc[bb, cc] = np.where(ss < 0, cur - vv, cur + vv)
         cur = acc[b, d:]
         acc[b, d:] = np.where(sg[p][:, None], cur - B[i], cur + B[i])
-    scale = 1.0 / math.sqrt(float(s))
+    scale = 1.0 if kind == "sample" else 1.0 / math.sqrt(float(s))
     return dict(SA_aug=acc * scale, rows=rows, neg=neg, bucket_ptr=ptr,
                 src=src, src_neg=sg, dsign=None, npad=n, scale=scale)
 

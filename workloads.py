@@ -29,6 +29,16 @@ Recipes (host numpy Generator(PCG64(1000 + case)) unless stated):
             Stands in for the paper's rank-deficient test matrices (Table 2),
             which come from the Florida collection.
 
+* coherent  the paper's coherent dense type [I_d; 0] + 1e-8 J (J all ones),
+            4000 x 400 in its sketch comparisons; b = 1.
+* inco_sparse  a stand-in for MATLAB's sprandn(n, d, 0.01, 1e-6) (which is not
+            available): 1% of the entries N(0,1) at uniform positions, plus one
+            entry per column so that no column is empty, then columns scaled by
+            10^(-6 j/(d-1)) for a condition number near 1e6.
+* semico_sparse  the paper's semi-coherent type [B 0; 0 I_{d/2}] + 1e-8 J with B
+            an inco_sparse matrix of (n - d/2) x d/2 (the matrix of the paper's
+            s = 1, 2, 3 comparison), as dense float64.
+
 Every generator takes (n, d) so that the same recipe runs at test sizes.
 """
 
@@ -166,3 +176,32 @@ def rank_deficient(n=50000, d=4000, rank=3500, case=6, frac=0.2, scale=1e3):
     A = np.ascontiguousarray(A[:, order])  # column j of A is column order[j] above
     b = rng.standard_normal(n)
     return A, b, np.flatnonzero(order < rank)
+
+
+def coherent_dense(n=4000, d=400):
+    """[I_d; 0] + 1e-8 J and b = 1."""
+    A = np.full((n, d), 1e-8)
+    A[np.arange(d), np.arange(d)] += 1.0
+    return A, np.ones(n)
+
+
+def inco_sparse(n=4000, d=400, case=7, density=0.01, decades=6.0):
+    """Dense float64 form of the incoherent sparse stand-in (see the recipe)."""
+    rng = rng_for(case)
+    A = np.zeros((n, d))
+    nnz = int(round(density * n * d))
+    r = rng.integers(0, n, nnz)
+    c = rng.integers(0, d, nnz)
+    A[r, c] = rng.standard_normal(nnz)
+    A[rng.integers(0, n, d), np.arange(d)] = rng.standard_normal(d)
+    A *= 10.0 ** (-decades * np.arange(d) / max(d - 1, 1))
+    return A
+
+
+def semico_sparse(n=4000, d=400, case=8):
+    """[B 0; 0 I_{d/2}] + 1e-8 J with B = inco_sparse((n - d/2), d/2); b = 1."""
+    h = d // 2
+    A = np.full((n, d), 1e-8)
+    A[: n - h, :h] += inco_sparse(n - h, h, case=case)
+    A[n - h + np.arange(h), h + np.arange(h)] += 1.0
+    return A, np.ones(n)
