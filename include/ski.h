@@ -56,6 +56,7 @@ enum ski_status {
 enum ski_kind { SKI_DENSE = 0, SKI_CSR = 2 };
 enum ski_prec { SKI_FP64 = 0, SKI_FP32 = 1, SKI_BF16 = 2 };
 enum ski_op { SKI_OP_LLS = 0, SKI_OP_NORMAL = 1 };
+enum ski_hash_kind { SKI_HASH = 0, SKI_HASH_VARIANT = 1, SKI_SAMPLE_ROWS = 2 };
 enum ski_qr_panel {
     SKI_QR_AUTO = 0,
     SKI_QR_HOUSEHOLDER = 1,
@@ -114,7 +115,14 @@ typedef struct {
  *                R_11 is the leading p x p block, V_1 the first p pivots J, and Steps
  *                3-5 use W = A V_1 R_11^-1, so x is zero outside J.  Needs qr_prec =
  *                SKI_FP64; the rank guard (SKI_ERANK) does not apply.
- *   reserved     must be 0. */
+ *   hash_kind    the sparse factor of S: SKI_HASH (default), the s-hashing matrix of
+ *                Section 2.2 (s distinct rows per column); SKI_HASH_VARIANT, the s-hashing
+ *                variant of Section 4 (s rows drawn with replacement, a repeated row gets
+ *                both +-1/sqrt(s) entries); SKI_SAMPLE_ROWS, row sampling (each sketch row
+ *                is one row of H D [A b], or of [A b] without H, drawn uniformly with
+ *                replacement, value 1: the sampled transform that Section 7 compares
+ *                hashing against; needs s = 1).  The sketch is scaled by 1/sqrt(n') with
+ *                H and left unscaled without it. */
 typedef struct {
     double gamma;
     int64_t m;
@@ -130,7 +138,7 @@ typedef struct {
     double rcond_thres;
     double perturb;
     int32_t qr_panel;
-    int32_t reserved;
+    int32_t hash_kind;
 } ski_params;
 
 /* Per right-hand side result of ski_solve. */
@@ -191,7 +199,8 @@ const char* ski_last_error(ski_handle h);
  *   dims: n, d, k, m, n' (padded rows, = n without Hadamard), s.
  *   hash: rows[n'*s] and neg[n'*s] per column in acceptance order; the bucket-sorted
  *         form bucket_ptr[m+1], src[n'*s] (column index), src_neg[n'*s].  Any pointer
- *         may be NULL.
+ *         may be NULL.  With SKI_SAMPLE_ROWS: rows[m] = the row each sketch row samples,
+ *         neg[m] = 0, src[m] = rows, src_neg[m] = 0.
  *   dsign: the diagonal of D as int8 (+1 / -1), n' entries (dense with Hadamard only).
  *   SA: the sketch m x (d+k) row-major, converted to double.
  *   R: d x d row-major (upper triangle, zeros below); c: d x k; Rinv: d x d (after a

@@ -16,6 +16,7 @@ SKI_DENSE, SKI_CSR = 0, 2
 SKI_FP64, SKI_FP32, SKI_BF16 = 0, 1, 2
 SKI_OP_LLS, SKI_OP_NORMAL = 0, 1
 SKI_QR_AUTO, SKI_QR_HOUSEHOLDER, SKI_QR_PIVOTED, SKI_QR_PIVOTED_HOUSEHOLDER = 0, 1, 2, 3
+SKI_HASH, SKI_HASH_VARIANT, SKI_SAMPLE_ROWS = 0, 1, 2
 
 STATUS_NAMES = {0: "OK", 1: "WNOCONV", 2: "WEARLY", -1: "EINVAL", -2: "ENOMEM",
                 -3: "EDEVICE", -4: "ERANK", -5: "ESTATE"}
@@ -42,7 +43,7 @@ class SkiParams(C.Structure):
                 ("hadamard", C.c_int32), ("seed", C.c_uint64), ("sketch_prec", C.c_int32),
                 ("qr_prec", C.c_int32), ("tau_a", C.c_double), ("tau_r", C.c_double),
                 ("it_max", C.c_int64), ("rcond", C.c_double), ("rcond_thres", C.c_double),
-                ("perturb", C.c_double), ("qr_panel", C.c_int32), ("reserved", C.c_int32)]
+                ("perturb", C.c_double), ("qr_panel", C.c_int32), ("hash_kind", C.c_int32)]
 
 
 class SkiInfo(C.Structure):

@@ -14,6 +14,7 @@ import torch
 from . import _lib as L
 
 _PREC = {"fp64": L.SKI_FP64, "fp32": L.SKI_FP32, "bf16": L.SKI_BF16}
+_HASH = {"hash": L.SKI_HASH, "variant": L.SKI_HASH_VARIANT, "sample": L.SKI_SAMPLE_ROWS}
 _PANEL = {"auto": L.SKI_QR_AUTO, "householder": L.SKI_QR_HOUSEHOLDER,
           "pivoted": L.SKI_QR_PIVOTED, "pivoted_householder": L.SKI_QR_PIVOTED_HOUSEHOLDER}
 
@@ -49,6 +50,8 @@ def params(kind="dense", **kw):
             val = _PREC[val]
         if key == "qr_panel" and isinstance(val, str):
             val = _PANEL[val]
+        if key == "hash_kind" and isinstance(val, str):
+            val = _HASH[val]
         if key == "hadamard":
             val = int(bool(val))
         if not hasattr(p, key):
@@ -199,9 +202,10 @@ class Solver:
         return dict(n=int(a[0]), d=int(a[1]), k=int(a[2]), m=int(a[3]), npad=int(a[4]),
                     s=int(a[5]))
 
-    def get_hash(self):
+    def get_hash(self, sampled=False):
+        """The sketch's sparse factor; sampled=True after row sampling (rows has m entries)."""
         dm = self.dims()
-        nk = dm["npad"] * dm["s"]
+        nk = dm["m"] if sampled else dm["npad"] * dm["s"]
         rows = np.zeros(nk, dtype=np.int32)
         neg = np.zeros(nk, dtype=np.int8)
         ptr = np.zeros(dm["m"] + 1, dtype=np.int64)
@@ -211,7 +215,7 @@ class Solver:
                                     src.ctypes.data, sneg.ctypes.data)
         if rc != L.SKI_OK:
             self._raise(rc, "ski_get_hash")
-        s = dm["s"]
+        s = 1 if sampled else dm["s"]
         return dict(rows=rows.reshape(-1, s), neg=neg.reshape(-1, s).astype(bool),
                     bucket_ptr=ptr, src=src, src_neg=sneg.astype(bool))
 

@@ -5,12 +5,17 @@
 //     row already taken by this column is rejected; the column stops at s rows.
 //   d_i: bit (i mod 64) of word ((i >> 6) mod 4) of the block at counter
 //     (i >> 8, 0, 1, 0); d_i = -1 iff the bit is set.
+// The s-hashing variant (Section 4) takes the rows of the first s words without rejection
+// (a row drawn twice gets both entries).  Row sampling (the sampled transform that
+// Section 7 compares hashing against) gives sketch row i the row floor((w >> 32) n / 2^32)
+// of the block at counter (i, 0, 2, 0), word 0, with sign +.
 // The bucket-sorted form (CSR of S_h by sketch row) is built by a deterministic,
 // atomic-free sort of the unique keys (row << 32 | (j << 1 | neg)): every workgroup
 // sorts a chunk of keys in LDS and counts its runs per bucket; a column-wise scan
 // over chunks gives each chunk's offset inside every bucket; a scatter places each
-// key at bucket start + chunk offset + rank within the chunk's run.  Because the
-// keys are unique, the result is the unique sorted order: columns ascend inside a
+// key at bucket start + chunk offset + rank within the chunk's run.  The result is the
+// sorted order of the keys (equal keys, from a row that a column of the variant drew
+// twice with the same sign, are interchangeable): columns, then signs, ascend inside a
 // bucket, which fixes the floating-point order of the hashing sums.
 #include "ski_internal.h"
 
@@ -21,7 +26,7 @@ namespace {
 constexpr int HT = 256;  // threads per workgroup
 
 __global__ __launch_bounds__(HT) void k_hash_keys(int64_t ncols, uint32_t m, int s, uint64_t seed,
-                                                  int32_t* colrows, int8_t* colneg,
+                                                  int replace, int32_t* colrows, int8_t* colneg,
                                                   uint64_t* keys) {
     int64_t j = (int64_t)blockIdx.x * HT + threadIdx.x;
     if (j >= ncols) return;
@@ -35,7 +40,8 @@ __global__ __launch_bounds__(HT) void k_hash_keys(int64_t ncols, uint32_t m, int
                 uint64_t word = w.x[t];
                 uint32_t row = (uint32_t)(((word >> 32) * (uint64_t)m) >> 32);
                 bool dup = false;
-                for (int q = 0; q < got; ++q) dup |= (taken[q] == (int32_t)row);
+                if (!replace)
+                    for (int q = 0; q < got; ++q) dup |= (taken[q] == (int32_t)row);
                 if (!dup) {
                     int neg = (int)(word & 1ull);
                     taken[got] = (int32_t)row;
@@ -47,6 +53,19 @@ __global__ __launch_bounds__(HT) void k_hash_keys(int64_t ncols, uint32_t m, int
             }
         }
     }
+}
+
+// row sampling: key (i << 32 | row << 1) for sketch row i
+__global__ __launch_bounds__(HT) void k_sample_keys(int64_t m, uint64_t nrows, uint64_t seed,
+                                                    int32_t* colrows, int8_t* colneg,
+                                                    uint64_t* keys) {
+    const int64_t i = (int64_t)blockIdx.x * HT + threadIdx.x;
+    if (i >= m) return;
+    const P4 w = philox4x64_10((uint64_t)i, 0, 2, 0, seed, 0);
+    const uint64_t row = ((w.x[0] >> 32) * nrows) >> 32;
+    colrows[i] = (int32_t)row;
+    colneg[i] = 0;
+    keys[i] = ((uint64_t)i << 32) | (row << 1);
 }
 
 __global__ __launch_bounds__(HT) void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
@@ -198,13 +217,22 @@ hipError_t launch_bucket_sort(const uint64_t* keys_unsorted, int64_t nkeys, int6
     return hipGetLastError();
 }
 
-hipError_t launch_hash_build(int64_t ncols, int64_t m, int s, uint64_t seed, HashBuffers& hb,
-                             hipStream_t st) {
-    const int64_t nkeys = ncols * s;
+int64_t hash_num_keys(int64_t ncols, int64_t m, int s, int kind) {
+    return kind == SKI_SAMPLE_ROWS ? m : ncols * s;
+}
+
+hipError_t launch_hash_build(int64_t ncols, int64_t m, int s, uint64_t seed, int kind,
+                             HashBuffers& hb, hipStream_t st) {
+    const int64_t nkeys = hash_num_keys(ncols, m, s, kind);
     // the unsorted keys go to the tail half of hb.keys (sized 2 * nchunks * CHUNK)
     uint64_t* unsorted = hb.keys + hash_num_chunks(nkeys) * SORT_CHUNK;
-    hipLaunchKernelGGL(k_hash_keys, dim3(grid_for(ncols, HT)), dim3(HT), 0, st, ncols,
-                       (uint32_t)m, s, seed, hb.colrows, hb.colneg, unsorted);
+    if (kind == SKI_SAMPLE_ROWS)
+        hipLaunchKernelGGL(k_sample_keys, dim3(grid_for(m, HT)), dim3(HT), 0, st, m,
+                           (uint64_t)ncols, seed, hb.colrows, hb.colneg, unsorted);
+    else
+        hipLaunchKernelGGL(k_hash_keys, dim3(grid_for(ncols, HT)), dim3(HT), 0, st, ncols,
+                           (uint32_t)m, s, seed, kind == SKI_HASH_VARIANT ? 1 : 0, hb.colrows,
+                           hb.colneg, unsorted);
     SKI_HIP(hipGetLastError());
     return launch_bucket_sort(unsorted, nkeys, m, hb.keys, hb.table, hb.bucket_ptr, hb.src, st);
 }

@@ -27,7 +27,7 @@ struct ski_handle_s {
     std::string err;
     // problem description from ski_sketch
     int32_t kind = SKI_DENSE;
-    int64_t n = 0, d = 0, k = 0, m = 0, npad = 0, ncols_hash = 0;
+    int64_t n = 0, d = 0, k = 0, m = 0, npad = 0, ncols_hash = 0, nkeys = 0;
     int s = 1;
     bool had = false;
     ski_params p{};
@@ -266,6 +266,10 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
     if (p->s < 1 || p->s > 32) return fail(h, SKI_EINVAL, "ski_sketch: need 1 <= s <= 32");
     if (p->qr_panel < SKI_QR_AUTO || p->qr_panel > SKI_QR_PIVOTED_HOUSEHOLDER)
         return fail(h, SKI_EINVAL, "ski_sketch: unknown qr_panel");
+    if (p->hash_kind < SKI_HASH || p->hash_kind > SKI_SAMPLE_ROWS)
+        return fail(h, SKI_EINVAL, "ski_sketch: unknown hash_kind");
+    if (p->hash_kind == SKI_SAMPLE_ROWS && p->s != 1)
+        return fail(h, SKI_EINVAL, "ski_sketch: row sampling needs s = 1");
     if (p->qr_panel >= SKI_QR_PIVOTED && p->qr_prec != SKI_FP64)
         return fail(h, SKI_EINVAL, "ski_sketch: the pivoted factorisation needs qr_prec = SKI_FP64");
     if (p->sketch_prec < 0 || p->sketch_prec > 2 || p->qr_prec < 0 || p->qr_prec > 2)
@@ -308,7 +312,8 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
 
     const int64_t nhc = npad;  // hashed columns of S_h
     h->ncols_hash = nhc;
-    const int64_t nkeys = nhc * p->s;
+    const int64_t nkeys = hash_num_keys(nhc, m, p->s, p->hash_kind);
+    h->nkeys = nkeys;
     const int64_t nch = hash_num_chunks(nkeys);
     SKI_TRY(h, ensure(h->colrows, nkeys * 4), "alloc");
     SKI_TRY(h, ensure(h->colneg, nkeys), "alloc");
@@ -329,7 +334,9 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
     hb.keys = P<uint64_t>(h->keys);
     hb.table = P<int32_t>(h->table);
     prof_begin(h, PC_HASH, st);
-    SKI_TRY(h, launch_hash_build(nhc, m, p->s, p->seed, hb, st), "hash build");
+    SKI_TRY(h, launch_hash_build(nhc, m, p->s, p->seed, p->hash_kind, hb, st), "hash build");
+    // the scalars of S: H's 1/sqrt(n') and the hashing's 1/sqrt(s) (sampling: value 1)
+    const double hscale = p->hash_kind == SKI_SAMPLE_ROWS ? 1.0 : 1.0 / sqrt((double)p->s);
     prof_end(h, st);
 
     // the SA storage type for the gathers: FP64, or FP32 for the mixed forms
@@ -341,20 +348,20 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
         SKI_TRY(h, ensure(h->T0, (size_t)npad * sc * te), "alloc");
         prof_begin(h, PC_WHT, st);
         SKI_TRY(h, launch_dsign(npad, p->seed, P<uint32_t>(h->dbits), st), "dsign");
-        const double scale = 1.0 / sqrt((double)npad * (double)p->s);
+        const double scale = hscale / sqrt((double)npad);
         SKI_TRY(h, launch_sketch_dense(A->a, A->lda, B, ldb, n, d, k, npad, P<uint32_t>(h->dbits),
                                        h->T0.p, sc, P<int32_t>(h->bucket_ptr), P<int32_t>(h->src),
                                        m, scale, gprec, h->SA.p, st),
                 "sketch");
         prof_end(h, st);
     } else if (A->kind == SKI_DENSE) {
-        const double scale = 1.0 / sqrt((double)p->s);
+        const double scale = hscale;
         SKI_TRY(h, launch_gather_plain(A->a, A->lda, B, ldb, d, k, P<int32_t>(h->bucket_ptr),
                                        P<int32_t>(h->src), m, scale,
                                        qprec == Prec::F64 ? Prec::F64 : Prec::F32, h->SA.p, st),
                 "gather");
     } else {
-        const double scale = 1.0 / sqrt((double)p->s);
+        const double scale = hscale;
         SKI_TRY(h, launch_gather_csr(A->row_ptr, A->col, A->val, B, ldb, d, k,
                                      P<int32_t>(h->bucket_ptr), P<int32_t>(h->src), m, scale,
                                      qprec == Prec::F64 ? Prec::F64 : Prec::F32, h->SA.p, st),
@@ -991,7 +998,7 @@ int ski_get_hash(ski_handle h, int32_t* rows, int8_t* neg, int64_t* bucket_ptr, 
                  int8_t* src_neg) {
     if (!h) return SKI_EINVAL;
     if (!h->sketched) return fail(h, SKI_ESTATE, "ski_get_hash: nothing sketched");
-    const int64_t nk = h->ncols_hash * h->s;
+    const int64_t nk = h->nkeys;
     if (hipDeviceSynchronize() != hipSuccess) return fail(h, SKI_EDEVICE, "sync");
     if (rows && hipMemcpy(rows, h->colrows.p, nk * 4, hipMemcpyDeviceToHost) != hipSuccess)
         return fail(h, SKI_EDEVICE, "copy");

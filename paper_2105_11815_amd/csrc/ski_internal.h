@@ -118,8 +118,12 @@ struct HashBuffers {
 };
 constexpr int SORT_CHUNK = 4096;  // keys sorted per workgroup in LDS
 int64_t hash_num_chunks(int64_t nkeys);
-hipError_t launch_hash_build(int64_t ncols, int64_t m, int s, uint64_t seed, HashBuffers& hb,
-                             hipStream_t st);
+// keys of the sketch's sparse factor: ncols * s for the two hashings, m for row sampling
+int64_t hash_num_keys(int64_t ncols, int64_t m, int s, int kind);
+// kind: SKI_HASH (s-hashing), SKI_HASH_VARIANT (rows with replacement), SKI_SAMPLE_ROWS
+// (one of the ncols rows per sketch row; colrows[i] = that row)
+hipError_t launch_hash_build(int64_t ncols, int64_t m, int s, uint64_t seed, int kind,
+                             HashBuffers& hb, hipStream_t st);
 // generic deterministic bucket sort of nkeys (bucket << 32 | payload) keys already in
 // `keys_unsorted` (payloads unique): writes bucket_ptr[nb+1] and out_payload[nkeys]
 hipError_t launch_bucket_sort(const uint64_t* keys_unsorted, int64_t nkeys, int64_t nbuckets,

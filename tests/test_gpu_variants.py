@@ -1,0 +1,106 @@
+"""GPU parity of the sketch variants through the C interface: the s-hashing variant (rows
+drawn with replacement) and row sampling after the transform.  The sparse factor is
+integer data (bit-exact); the sketch keeps the oracle's summation order (bit-exact);
+the solution is compared within 1e-10."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import lls, sketch as sk
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ski():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2105_11815_amd as P
+    return P
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+@pytest.mark.parametrize("n,d,m,s,had", [(3000, 70, 150, 3, True), (600, 12, 20, 4, True),
+                                         (5000, 40, 60, 2, False)])
+def test_variant_sketch_bitexact(ski, n, d, m, s, had):
+    _say(f"variant sketch n={n} d={d} m={m} s={s} H={had}")
+    rng = np.random.default_rng(n + m)
+    A = rng.standard_normal((n, d))
+    A[: n // 5] *= 1e3
+    b = rng.standard_normal(n)
+    ref = sk.sketch_dense(A, b, m, s, 77, hadamard=had, kind="variant")
+    S = ski.Solver()
+    S.sketch(dev(A), dev(b), m=m, s=s, seed=77, hadamard=had, hash_kind="variant")
+    hsh = S.get_hash()
+    np.testing.assert_array_equal(hsh["rows"], ref["rows"])
+    np.testing.assert_array_equal(hsh["neg"], ref["neg"])
+    np.testing.assert_array_equal(hsh["bucket_ptr"], ref["bucket_ptr"])
+    np.testing.assert_array_equal(hsh["src"], ref["src"])
+    np.testing.assert_array_equal(hsh["src_neg"], ref["src_neg"])
+    np.testing.assert_array_equal(S.get_SA(), ref["SA_aug"])
+    S.close()
+
+
+@pytest.mark.parametrize("n,d,m,had", [(3000, 70, 280, True), (5000, 40, 160, False)])
+def test_sampling_sketch_bitexact(ski, n, d, m, had):
+    _say(f"row sampling n={n} d={d} m={m} H={had}")
+    rng = np.random.default_rng(n)
+    A = rng.standard_normal((n, d))
+    b = rng.standard_normal(n)
+    ref = sk.sketch_dense(A, b, m, 1, 91, hadamard=had, kind="sample")
+    S = ski.Solver()
+    S.sketch(dev(A), dev(b), m=m, s=1, seed=91, hadamard=had, hash_kind="sample")
+    hsh = S.get_hash(sampled=True)
+    np.testing.assert_array_equal(hsh["rows"][:, 0], ref["rows"])
+    np.testing.assert_array_equal(hsh["bucket_ptr"], ref["bucket_ptr"])
+    np.testing.assert_array_equal(hsh["src"], ref["src"])
+    np.testing.assert_array_equal(S.get_SA(), ref["SA_aug"])
+    S.close()
+
+
+def test_variant_csr_sketch_bitexact(ski):
+    _say("variant sketch, CSR 20000 x 300")
+    rp, ci, va, b = workloads.sparse_power_law(n=20000, d=300, case=3)
+    ref = sk.sketch_csr(rp, ci, va, 20000, 300, b, 450, 3, 55, kind="variant")
+    S = ski.Solver()
+    S.sketch(("csr", dev(rp, torch.int64), dev(ci, torch.int32), dev(va), (20000, 300)),
+             dev(b), m=450, s=3, seed=55, hadamard=False, hash_kind="variant")
+    np.testing.assert_array_equal(S.get_SA(), ref["SA_aug"])
+    S.close()
+
+
+@pytest.mark.parametrize("kind,m", [("variant", 256), ("sample", 512)])
+def test_variant_solves_match_the_oracle(ski, kind, m):
+    _say(f"solve with {kind}, tiny workload, m={m}")
+    A, b, _ = workloads.tiny()
+    s = 1 if kind == "sample" else 3
+    X, info = lls.solve(A, b, 19, m=m, s=s, hash_kind=kind, tau_r=1e-14, it_max=300)
+    S = ski.Solver()
+    S.sketch(dev(A), dev(b), m=m, s=s, seed=19, hash_kind=kind, tau_r=1e-14, it_max=300)
+    S.factor()
+    Xg, infos, rc = S.solve()
+    S.close()
+    assert rc == 0
+    x, xr = Xg[:, 0].cpu().numpy(), X[:, 0]
+    assert np.abs(x - xr).max() / np.abs(xr).max() <= 1e-10
+    assert abs(infos[0]["iters"] - info["records"][0]["iters"]) <= 1
+
+
+def test_sampling_rejects_s_above_one(ski):
+    A = np.random.default_rng(1).standard_normal((500, 20))
+    S = ski.Solver()
+    with pytest.raises(ski.SkiError):
+        S.sketch(dev(A), dev(np.ones(500)), m=60, s=2, hash_kind="sample")
+    S.close()
