@@ -8,6 +8,7 @@ HBM.  Prints one JSON line on stdout (everything else goes to stderr).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-mixed]
                        [--no-sparse] [--no-rankdef] [--rankdef-only] [--sweep]
+                       [--sketch-study]
 """
 
 import argparse
@@ -282,6 +283,68 @@ def sweep_run(P, torch):
     return out
 
 
+def sketch_study(P, torch):
+    """Preconditioner quality kappa(A R^-1) from the GPU's sketch and QR (R copied back;
+    kappa by a host SVD of A R^-1) on the paper's 4000 x 400 test types: hashing against
+    row sampling after the transform on the coherent dense type, and s = 1, 2, 3 (s-hashing
+    and its variant) on the incoherent and semi-coherent sparse types (CSR input, no
+    transform)."""
+    import scipy.linalg as sla
+    import scipy.sparse as sp
+    import workloads
+
+    def kappa(A, R):
+        sv = np.linalg.svd(sla.solve_triangular(R, A.T, trans="T").T, compute_uv=False)
+        return float(sv[0] / sv[-1])
+
+    def run(A, b, m, s, kind, dense):
+        n, d = A.shape
+        S = P.Solver()
+        try:
+            if dense:
+                S.sketch(torch.as_tensor(A).to("cuda"), torch.as_tensor(b).to("cuda"), m=m, s=s,
+                         seed=31, hadamard=True, hash_kind=kind)
+            else:
+                C = sp.csr_matrix(A)
+                dv = lambda a, t: torch.as_tensor(a).to(device="cuda", dtype=t)
+                S.sketch(("csr", dv(C.indptr.astype(np.int64), torch.int64),
+                          dv(C.indices.astype(np.int32), torch.int32), dv(C.data, torch.float64),
+                          (n, d)), dv(b, torch.float64), m=m, s=s, seed=31, hadamard=False,
+                         hash_kind=kind)
+            S.factor()
+            R = S.get_R()[0]
+        except P.SkiError as e:
+            return None if "rank" in str(e).lower() or "ERANK" in str(e) else str(e)
+        finally:
+            S.close()
+        return kappa(A, R)
+
+    out = {}
+    A, b = workloads.coherent_dense(4000, 400)
+    rows = []
+    for ratio in (1.25, 1.5, 2, 3, 4, 6, 8):
+        m = int(ratio * 400)
+        rows.append(dict(m_over_d=ratio, hashing_s1=run(A, b, m, 1, "hash", True),
+                         sampling=run(A, b, m, 1, "sample", True)))
+        log("coherent dense " + json.dumps(rows[-1]))
+    out["coherent_dense_4000x400"] = rows
+    for name, A in (("inco_sparse_4000x400", workloads.inco_sparse(4000, 400)),
+                    ("semico_sparse_4000x400", workloads.semico_sparse(4000, 400)[0])):
+        b = np.ones(4000)
+        rows = []
+        for ratio in (1.25, 1.5, 2, 3, 4):
+            m = int(ratio * 400)
+            r = dict(m_over_d=ratio)
+            for s in (1, 2, 3):
+                r[f"hash_s{s}"] = run(A, b, m, s, "hash", False)
+                if s > 1:
+                    r[f"variant_s{s}"] = run(A, b, m, s, "variant", False)
+            rows.append(r)
+            log(f"{name} " + json.dumps(r))
+        out[name] = rows
+    return out
+
+
 def mixed_runs(P, torch, At, bt, base_kw, forms, label):
     """Time one solve per precision form (after a warm-up solve) and recompute the
     residual and the optimality certificate ||A^T r|| / (||A||_F ||r||) in FP64."""
@@ -328,6 +391,8 @@ def main():
                     help="only the rank-deficient workload (for profiling); prints its record")
     ap.add_argument("--sweep", action="store_true",
                     help="only the gamma/s sweep of the dense and sparse workloads; prints it")
+    ap.add_argument("--sketch-study", action="store_true",
+                    help="only the preconditioner-quality study of the sketch variants")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the solver has no multi-GPU path, so --gpus "
@@ -342,6 +407,9 @@ def main():
         return
     if args.sweep:
         print(json.dumps({"gamma_s_sweep": sweep_run(P, torch)}), flush=True)
+        return
+    if args.sketch_study:
+        print(json.dumps({"sketch_study": sketch_study(P, torch)}), flush=True)
         return
 
     log("generating the dense 50000x4000 workload ...")
