@@ -263,48 +263,49 @@ __global__ __launch_bounds__(256) void k_lsqr_pass(const double* __restrict__ A,
 }
 
 // g[c] = sum_g gpart[g][c] and beta2 = sum_g upart[g], each in a fixed order: a
-// workgroup takes 64 columns; its sixteen waves sum a sixteenth of the partials each
-// (the 64 lanes read 64 consecutive columns), then the sixteen sums are added in order.
-// Workgroup 0 also sums the squared-norm partials the same way.
-constexpr int RSL = 16;  // slices of the partials
-__global__ __launch_bounds__(64 * RSL) void k_reduce_pass(const double* __restrict__ gpart,
-                                                          const double* __restrict__ upart,
-                                                          int64_t G, int64_t d,
-                                                          double* __restrict__ g,
-                                                          LsqrState* __restrict__ stt) {
+// workgroup sums RC columns; lane t takes column t % RC and the partial rows
+// g = t / RC, t / RC + RR, ... (RR = 256 / RC row slots, 128-byte segments per row), then
+// the RR slot sums of a column are added in slot order.  Workgroup 0 also sums the
+// norm partials.
+constexpr int RC = 16;
+constexpr int RR = 256 / RC;
+__global__ __launch_bounds__(256) void k_reduce_pass(const double* __restrict__ gpart,
+                                                     const double* __restrict__ upart,
+                                                     int64_t G, int64_t d,
+                                                     double* __restrict__ g,
+                                                     LsqrState* __restrict__ stt) {
     if (stt->done) return;
-    __shared__ double part[RSL][64];
-    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int64_t c = (int64_t)blockIdx.x * 64 + lane;
-    const int64_t g0 = q * G / RSL, g1 = (q + 1) * G / RSL;
+    __shared__ double part[RR][RC];
+    const int t = threadIdx.x;
+    const int cl = t % RC, slot = t / RC;
+    const int64_t c = (int64_t)blockIdx.x * RC + cl;
     double s = 0;
     if (c < d) {
-        int64_t gq = g0;
-        for (; gq + 8 <= g1; gq += 8) {
+        int64_t gq = slot;
+        for (; gq + 7 * RR < G; gq += 8 * RR) {
             double a[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) a[u] = gpart[(gq + u) * d + c];
+            for (int u = 0; u < 8; ++u) a[u] = gpart[(gq + u * RR) * d + c];
 #pragma unroll
             for (int u = 0; u < 8; ++u) s += a[u];
         }
-        for (; gq < g1; ++gq) s += gpart[gq * d + c];
+        for (; gq < G; gq += RR) s += gpart[gq * d + c];
     }
-    part[q][lane] = s;
+    part[slot][cl] = s;
     __syncthreads();
-    if (q == 0 && c < d) {
-        double t = 0;
-        for (int j = 0; j < RSL; ++j) t += part[j][lane];
-        g[c] = t;
+    if (t < RC && c < d) {
+        double tot = 0;
+        for (int j = 0; j < RR; ++j) tot += part[j][t];
+        g[c] = tot;
     }
     if (blockIdx.x == 0) {
-        __shared__ double us[64 * RSL];
-        const int t = threadIdx.x;
-        const int64_t u0 = t * G / (64 * RSL), u1 = (t + 1) * G / (64 * RSL);
+        __shared__ double us[256];
+        const int64_t u0 = t * G / 256, u1 = (t + 1) * G / 256;
         double su = 0;
         for (int64_t i = u0; i < u1; ++i) su += upart[i];
         us[t] = su;
         __syncthreads();
-        for (int off = 32 * RSL; off > 0; off >>= 1) {
+        for (int off = 128; off > 0; off >>= 1) {
             if (t < off) us[t] = us[t] + us[t + off];
             __syncthreads();
         }
@@ -807,7 +808,7 @@ hipError_t launch_pass_kernel(const double* A, int64_t lda, int64_t n, int64_t d
 
 hipError_t launch_pass_reduce(const double* gpart, const double* upart, int64_t G, int64_t d,
                               double* g, LsqrState* stt_w, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce_pass, dim3((unsigned)((d + 63) / 64)), dim3(64 * RSL), 0, st,
+    hipLaunchKernelGGL(k_reduce_pass, dim3((unsigned)((d + RC - 1) / RC)), dim3(256), 0, st,
                        gpart, upart, G, d, g, stt_w);
     return hipGetLastError();
 }
