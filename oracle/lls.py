@@ -230,7 +230,8 @@ def solve(A, B, seed, sparse=None, **kw):
                             kind=p.get("hash_kind", "hash"))
     else:
         out = sk.sketch_dense(A, B2, m, p["s"], seed, hadamard=p["hadamard"],
-                              kind=p.get("hash_kind", "hash"))
+                              kind=p.get("hash_kind", "hash"),
+                              transform=p.get("transform", "wht"))
     X = np.zeros((d, B2.shape[1]))
     recs = []
     extra = {}

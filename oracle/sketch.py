@@ -10,6 +10,10 @@ Definitions followed
 * HRHT (Section 4.3, Definition of the Hashed-Randomised-Hadamard-Transform):
   S = S_h H D with D a random +-1 diagonal, H the normalised Walsh-Hadamard
   matrix H_ij = n^-1/2 (-1)^<(i-1)_2, (j-1)_2>, and S_h independent of D.
+* HR-DHT (Section 6, the paper's dense software): S = S_h F D with F the
+  normalised discrete Hartley transform, F_kj = n^-1/2 cas(2 pi k j / n),
+  cas = cos + sin, applied here to the zero-padded n' rows like H; it is
+  computed through the discrete Fourier transform (DHT = Re - Im of the DFT).
 * Sparse input (Section 6, sparse variant): S is an s-hashing matrix alone.
 * Step 1 of Algorithm 1 sketches b with the same S (the augmented column).
 * s-hashing variant (Section 4, Definition of the s-hashing variant): the s
@@ -154,6 +158,14 @@ def fwht_inplace(X):
     return X
 
 
+def dht_inplace(X):
+    """Unnormalised discrete Hartley transform along axis 0: X_k = sum_j x_j cas(2 pi k j / n),
+    computed as Re - Im of the discrete Fourier transform (numpy's FFT)."""
+    F = np.fft.fft(X, axis=0)
+    X[...] = F.real - F.imag
+    return X
+
+
 def bucket_sum(ptr, src, neg, rows_of):
     """out[b] = sum over the bucket's entries, ascending, of +-rows_of(src).
 
@@ -183,12 +195,13 @@ def _sketch_structure(nrows, m, s, seed, kind):
     return rows, neg, ptr, src, sg
 
 
-def sketch_dense(A, B, m, s, seed, hadamard=True, kind="hash"):
+def sketch_dense(A, B, m, s, seed, hadamard=True, kind="hash", transform="wht"):
     """S [A B] for dense A (n x d) and B (n x k), S = S_h H D (or S_h alone).
 
     kind: "hash" (s-hashing), "variant" (the s-hashing variant) or "sample"
-    (row sampling, s ignored).  Returns dict with SA_aug (m x (d+k)), and the
-    hashing/sign arrays."""
+    (row sampling, s ignored).  transform (with hadamard=True): "wht" (the
+    Walsh-Hadamard H) or "dht" (the Hartley F).  Returns dict with SA_aug
+    (m x (d+k)), and the hashing/sign arrays."""
     A = np.asarray(A, dtype=np.float64)
     B = np.asarray(B, dtype=np.float64).reshape(A.shape[0], -1)
     n, d = A.shape
@@ -199,7 +212,10 @@ def sketch_dense(A, B, m, s, seed, hadamard=True, kind="hash"):
         X[:n, d:] = B
         D = d_signs(npad, seed)
         X *= D[:, None]
-        fwht_inplace(X)
+        if transform == "dht":
+            dht_inplace(X)
+        else:
+            fwht_inplace(X)
         scale = 1.0 / math.sqrt(float(npad * (1 if kind == "sample" else s)))
     else:
         npad = n

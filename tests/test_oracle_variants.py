@@ -120,3 +120,43 @@ def test_s_above_one_is_needed_on_semicoherent_sparse_input():
     k = {s: _kappa_AR(A, sk.sketch_dense(A, b, m, s, seed=13, hadamard=False)["SA_aug"][:, :400])
          for s in (1, 2, 3)}
     assert k[2] < 10 and k[3] < 10 and k[1] > 100 * k[2], k
+
+
+def test_dht_is_the_hartley_transform():
+    # the definition, entry by entry, on small orders; and F F = I for the normalised F
+    rng = np.random.default_rng(21)
+    for n in (1, 2, 8, 32):
+        x = rng.standard_normal((n, 3))
+        k = np.arange(n)
+        C = np.cos(2 * np.pi * np.outer(k, k) / n) + np.sin(2 * np.pi * np.outer(k, k) / n)
+        ref = C @ x
+        got = sk.dht_inplace(x.copy())
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * max(1.0, np.abs(ref).max()))
+    x = rng.standard_normal((1024, 2))
+    np.testing.assert_allclose(sk.dht_inplace(sk.dht_inplace(x.copy())) / 1024, x, atol=1e-13)
+
+
+def test_dht_sketch_equals_the_explicit_product():
+    rng = np.random.default_rng(23)
+    A = rng.standard_normal((200, 5))
+    b = rng.standard_normal(200)
+    out = sk.sketch_dense(A, b, 17, 2, seed=2, transform="dht")
+    n2 = out["npad"]
+    k = np.arange(n2)
+    F = (np.cos(2 * np.pi * np.outer(k, k) / n2) + np.sin(2 * np.pi * np.outer(k, k) / n2)) / math.sqrt(n2)
+    X = np.zeros((n2, 6))
+    X[:200, :5] = A
+    X[:200, 5] = b
+    T = _dense_S(out["rows"], out["neg"], 17)
+    ref = T @ (F @ (out["dsign"][:, None] * X))
+    np.testing.assert_allclose(out["SA_aug"], ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def test_hashing_beats_sampling_with_the_hartley_transform():
+    # the paper's own setting of the comparison (HR-DHT against SR-DHT)
+    A, b = workloads.coherent_dense(4000, 400)
+    m = 2 * 400
+    kh = _kappa_AR(A, sk.sketch_dense(A, b, m, 1, seed=11, transform="dht")["SA_aug"][:, :400])
+    ks = _kappa_AR(A, sk.sketch_dense(A, b, m, 1, seed=11, kind="sample",
+                                      transform="dht")["SA_aug"][:, :400])
+    assert kh < 10.0 and ks > 5 * kh, (kh, ks)
