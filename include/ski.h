@@ -83,7 +83,10 @@ typedef struct {
 /* Parameters (defaults of Section 6 from ski_params_default).
  *   gamma, m     sketch rows m = ceil(gamma d) unless m > 0 is given; d <= m.
  *   s            nonzeros per column of S_h, 1 <= s <= min(m, 32).
- *   hadamard     1: S = S_h H D (dense only); 0: S = S_h.
+ *   hadamard     1: S = S_h H D (dense only); 0: S = S_h; 2: S = S_h F D with F the
+ *                discrete Hartley transform of the paper's dense software (Section 6,
+ *                HR-DHT), on the zero-padded n' rows; needs n' <= 65536 and FP64 sketch
+ *                and QR; computed through the DFT, so it matches a reference to rounding.
  *   seed         Philox4x64-10 key (seed, 0) for S_h and D.
  *   sketch_prec  arithmetic/storage of H D A and of the sketch (FP64/FP32/BF16).
  *   qr_prec      arithmetic of the QR of the sketch (FP64/FP32/BF16 MFMA inputs,

@@ -53,7 +53,7 @@ def params(kind="dense", **kw):
         if key == "hash_kind" and isinstance(val, str):
             val = _HASH[val]
         if key == "hadamard":
-            val = int(bool(val))
+            val = 2 if val == "dht" else (val if isinstance(val, int) and val == 2 else int(bool(val)))
         if not hasattr(p, key):
             raise KeyError(f"unknown parameter {key}")
         setattr(p, key, val)

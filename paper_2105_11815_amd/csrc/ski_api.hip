@@ -261,6 +261,8 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
     if (A->kind == SKI_CSR && (!A->row_ptr || !A->col || !A->val || A->nnz < 0 ||
                                A->nnz >= ((int64_t)1 << 31)))
         return fail(h, SKI_EINVAL, "ski_sketch: CSR A needs row_ptr, col, val, nnz < 2^31");
+    if (p->hadamard < 0 || p->hadamard > 2)
+        return fail(h, SKI_EINVAL, "ski_sketch: hadamard must be 0, 1 or 2");
     if (A->kind == SKI_CSR && p->hadamard)
         return fail(h, SKI_EINVAL, "ski_sketch: the Hadamard transform is for dense A only");
     if (p->s < 1 || p->s > 32) return fail(h, SKI_EINVAL, "ski_sketch: need 1 <= s <= 32");
@@ -281,6 +283,10 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
     const int64_t npad = had ? next_pow2(n) : n;
     if (m < d) return fail(h, SKI_EINVAL, "ski_sketch: need m >= d");
     if (m > npad) return fail(h, SKI_EINVAL, "ski_sketch: need m <= n (n' with Hadamard)");
+    if (had && p->hadamard == 2 &&
+        (!dht_supported(npad) || p->sketch_prec != SKI_FP64 || p->qr_prec != SKI_FP64))
+        return fail(h, SKI_EINVAL,
+                    "ski_sketch: the Hartley transform needs n' <= 65536 and FP64 sketch and QR");
     if (p->s > m) return fail(h, SKI_EINVAL, "ski_sketch: need s <= m");
     if (m > 12288) return fail(h, SKI_EINVAL, "ski_sketch: m above 12288 is not supported");
     const int64_t ncols = d + k;
@@ -349,10 +355,18 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
         prof_begin(h, PC_WHT, st);
         SKI_TRY(h, launch_dsign(npad, p->seed, P<uint32_t>(h->dbits), st), "dsign");
         const double scale = hscale / sqrt((double)npad);
-        SKI_TRY(h, launch_sketch_dense(A->a, A->lda, B, ldb, n, d, k, npad, P<uint32_t>(h->dbits),
-                                       h->T0.p, sc, P<int32_t>(h->bucket_ptr), P<int32_t>(h->src),
-                                       m, scale, gprec, h->SA.p, st),
-                "sketch");
+        if (p->hadamard == 2)
+            SKI_TRY(h, launch_sketch_dht(A->a, A->lda, B, ldb, n, d, k, npad,
+                                         P<uint32_t>(h->dbits), P<double>(h->T0), sc,
+                                         P<int32_t>(h->bucket_ptr), P<int32_t>(h->src), m, scale,
+                                         P<double>(h->SA), st),
+                    "sketch (Hartley)");
+        else
+            SKI_TRY(h, launch_sketch_dense(A->a, A->lda, B, ldb, n, d, k, npad,
+                                           P<uint32_t>(h->dbits), h->T0.p, sc,
+                                           P<int32_t>(h->bucket_ptr), P<int32_t>(h->src), m, scale,
+                                           gprec, h->SA.p, st),
+                    "sketch");
         prof_end(h, st);
     } else if (A->kind == SKI_DENSE) {
         const double scale = hscale;

@@ -104,3 +104,51 @@ def test_sampling_rejects_s_above_one(ski):
     with pytest.raises(ski.SkiError):
         S.sketch(dev(A), dev(np.ones(500)), m=60, s=2, hash_kind="sample")
     S.close()
+
+
+TOL_DHT = 1e-12  # max |SA - SA_ref| / max |SA_ref|: two FFT orders, n' <= 65536
+
+
+@pytest.mark.parametrize("n,d,m,s", [(3000, 70, 150, 3), (200, 10, 17, 1), (40000, 13, 40, 2),
+                                     (100, 4, 9, 2)])
+def test_dht_sketch_matches_the_oracle(ski, n, d, m, s):
+    _say(f"Hartley sketch n={n} d={d} m={m} s={s}")
+    rng = np.random.default_rng(n + d)
+    A = rng.standard_normal((n, d))
+    A[: n // 5] *= 1e3
+    b = rng.standard_normal(n)
+    ref = sk.sketch_dense(A, b, m, s, 77, transform="dht")
+    S = ski.Solver()
+    S.sketch(dev(A), dev(b), m=m, s=s, seed=77, hadamard="dht")
+    np.testing.assert_array_equal(S.get_dsign(), ref["dsign"])
+    SA = S.get_SA()
+    S.close()
+    err = np.abs(SA - ref["SA_aug"]).max() / np.abs(ref["SA_aug"]).max()
+    _say(f"  max rel err {err:.2e}")
+    assert err <= TOL_DHT
+
+
+def test_dht_solve_matches_the_oracle(ski):
+    _say("solve with the Hartley transform, coherent 20000 x 200")
+    rng = np.random.default_rng(44)
+    A = rng.standard_normal((20000, 200))
+    A[:4000] *= 1e3
+    b = rng.standard_normal(20000)
+    X, info = lls.solve(A, b, 23, s=2, transform="dht", tau_r=1e-14, it_max=300)
+    S = ski.Solver()
+    S.sketch(dev(A), dev(b), s=2, seed=23, hadamard="dht", tau_r=1e-14, it_max=300)
+    S.factor()
+    Xg, infos, rc = S.solve()
+    S.close()
+    assert rc == 0
+    x, xr = Xg[:, 0].cpu().numpy(), X[:, 0]
+    assert np.abs(x - xr).max() / np.abs(xr).max() <= 1e-10
+
+
+def test_dht_rejects_unsupported_forms(ski):
+    A = np.random.default_rng(2).standard_normal((500, 20))
+    b = np.ones(500)
+    S = ski.Solver()
+    with pytest.raises(ski.SkiError):
+        S.sketch(dev(A), dev(b), hadamard="dht", sketch_prec="fp32", qr_prec="fp32")
+    S.close()
