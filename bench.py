@@ -297,13 +297,13 @@ def sketch_study(P, torch):
         sv = np.linalg.svd(sla.solve_triangular(R, A.T, trans="T").T, compute_uv=False)
         return float(sv[0] / sv[-1])
 
-    def run(A, b, m, s, kind, dense):
+    def run(A, b, m, s, kind, dense, transform=True):
         n, d = A.shape
         S = P.Solver()
         try:
             if dense:
                 S.sketch(torch.as_tensor(A).to("cuda"), torch.as_tensor(b).to("cuda"), m=m, s=s,
-                         seed=31, hadamard=True, hash_kind=kind)
+                         seed=31, hadamard=transform, hash_kind=kind)
             else:
                 C = sp.csr_matrix(A)
                 dv = lambda a, t: torch.as_tensor(a).to(device="cuda", dtype=t)
@@ -325,7 +325,9 @@ def sketch_study(P, torch):
     for ratio in (1.25, 1.5, 2, 3, 4, 6, 8):
         m = int(ratio * 400)
         rows.append(dict(m_over_d=ratio, hashing_s1=run(A, b, m, 1, "hash", True),
-                         sampling=run(A, b, m, 1, "sample", True)))
+                         sampling=run(A, b, m, 1, "sample", True),
+                         hashing_s1_dht=run(A, b, m, 1, "hash", True, "dht"),
+                         sampling_dht=run(A, b, m, 1, "sample", True, "dht")))
         log("coherent dense " + json.dumps(rows[-1]))
     out["coherent_dense_4000x400"] = rows
     for name, A in (("inco_sparse_4000x400", workloads.inco_sparse(4000, 400)),
@@ -342,6 +344,33 @@ def sketch_study(P, torch):
             rows.append(r)
             log(f"{name} " + json.dumps(r))
         out[name] = rows
+    # the two transforms on the dense 50000 x 4000 workload: sketch and whole solve
+    Ad, bd, cfg = workload_dense()
+    At = torch.as_tensor(Ad).to("cuda")
+    bt = torch.as_tensor(bd).to("cuda")
+    del Ad
+    tr = {}
+    for name, hv in (("walsh_hadamard", True), ("hartley", "dht")):
+        kw = dict(m=cfg["m"], s=cfg["s"], seed=2002, tau_r=1e-10, hadamard=hv)
+        S = P.Solver()
+        one_solve(P, S, At, bt, **kw)
+        torch.cuda.synchronize()
+        ts, infos = [], []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            X, info, rc = one_solve(P, S, At, bt, **kw)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+            infos.append(info)
+        S.close()
+        x = X[:, 0]
+        r = bt - At @ x
+        tr[name] = dict(ms=round(float(np.median(ts)), 3),
+                        ms_sketch=round(float(np.median([i["ms_sketch"] for i in infos])), 3),
+                        iters=int(infos[-1]["iters"]),
+                        optimality=float((At.T @ r).norm() / (At.norm() * r.norm())))
+        log(f"dense 50000x4000 {name} " + json.dumps(tr[name]))
+    out["transforms_dense_50000x4000"] = tr
     return out
 
 
