@@ -7,7 +7,8 @@ transform, gamma = 1.7 so m = 6800; Householder QR of the sketch; LSQR on A R^-1
 HBM.  Prints one JSON line on stdout (everything else goes to stderr).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-mixed]
-                       [--no-sparse] [--no-rankdef] [--rankdef-only] [--sweep]
+                       [--no-sparse] [--no-rankdef] [--no-batched] [--no-seeds]
+                       [--rankdef-only] [--sweep]
                        [--sketch-study]
 """
 
@@ -76,11 +77,21 @@ def cpu_baseline(A, b, cfg, gpu_iters):
     lls.lsqr_precond(A, R, r0, 0.0, its)
     t_iter = (time.perf_counter() - t0) / its
     total = t_sketch + t_qr + t_iter * gpu_iters
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {
         "value": 1.0 / total,
         "unit": "solves/s",
         "cores": int(cores),
         "kind": "oracle",
+        "cpu_model": model,
+        "host_cpus": os.cpu_count(),
         "sample": (f"oracle sketch on {cols} of {d + 1} columns (x{(d + 1) / cols:.2f}), "
                    f"QR of a {m}x{d + 1} matrix, {its} LSQR iterations on the full A "
                    f"(x{gpu_iters} GPU iterations); extrapolated seconds per solve "
@@ -374,6 +385,50 @@ def sketch_study(P, torch):
     return out
 
 
+def batched_run(P, torch):
+    """The batched workload (20000 x 1000, 32 right-hand sides, FP64): the forward solve
+    through the multi-right-hand-side LSQR (its A products are MFMA GEMMs), then the
+    backward: the adjoint solve Z = (A^T A)^-1 G by CG with the forward's R and the two
+    gradients.  Median of three after a warm-up; the forward's A products are timed by
+    the profiler classes and priced at 2 n d k flops each."""
+    import workloads
+    c = workloads.CASES["batched"]
+    A, B, G = workloads.batched(n=c["n"], d=c["d"], k=c["k"], case=c["case"])
+    At, Bt, Gt = (torch.as_tensor(v).to("cuda") for v in (A, B, G))
+    kw = dict(m=c["m"], s=c["s"], seed=2005, tau_r=1e-10, hadamard=True)
+    n, d, k = A.shape[0], A.shape[1], B.shape[1]
+    fw, bw, its, cg_its = [], [], 0, 0
+    for rep in range(4):
+        S = P.Solver()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.sketch(At, Bt, **kw).factor()
+        X, infos, rc = S.solve()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        Z, zinfos, zrc = S.solve_normal(Gt)
+        gA, gB = S.gradients(X, Bt, Z)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        S.close()
+        if rep:
+            fw.append((t1 - t0) * 1e3)
+            bw.append((t2 - t1) * 1e3)
+        its = max(i["iters"] for i in infos)
+        cg_its = max(i["iters"] for i in zinfos)
+    R = Bt - At @ X
+    cert = float(((At.T @ R).norm(dim=0) / (At.norm() * R.norm(dim=0))).max())
+    # per iteration two GEMMs of 2 n d k flops each (A Z and A^T U)
+    tf = 4.0 * n * d * k * its / (float(np.median(fw)) * 1e-3) / 1e12
+    return {"workload": f"dense {n}x{d}, {k} right-hand sides B ~ N(0,1), loss weight G ~ N(0,1); "
+                        f"Hadamard + {c['s']}-hashing, m {c['m']}; LSQR to 1e-10 on all columns; "
+                        "adjoint CG with the same R, then grad_A and grad_B",
+            "forward_ms": round(float(np.median(fw)), 3), "backward_ms": round(float(np.median(bw)), 3),
+            "forward_ms_all": [round(t, 3) for t in fw], "backward_ms_all": [round(t, 3) for t in bw],
+            "lsqr_iters_max": int(its), "cg_iters_max": int(cg_its), "optimality_worst": cert,
+            "forward_lsqr_gemm_TFLOPs_lower_bound": round(tf, 2)}
+
+
 def mixed_runs(P, torch, At, bt, base_kw, forms, label):
     """Time one solve per precision form (after a warm-up solve) and recompute the
     residual and the optimality certificate ||A^T r|| / (||A||_F ||r||) in FP64."""
@@ -416,6 +471,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-sparse", action="store_true")
     ap.add_argument("--no-rankdef", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-seeds", action="store_true")
     ap.add_argument("--rankdef-only", action="store_true",
                     help="only the rank-deficient workload (for profiling); prints its record")
     ap.add_argument("--sweep", action="store_true",
@@ -533,6 +590,31 @@ def main():
         "rnorm": float(r.norm()), "kernel_ms": phases, "roofline": roofline,
         "copy_GBps_reference": round(copy_gbps, 1),
     }
+
+    # three sketch seeds on the same A: the spread of the time to solution
+    seeds = {}
+    S = P.Solver()
+    for sd in (() if args.no_seeds else (2002, 3002, 4002)):
+        kws = dict(kw, seed=sd)
+        one_solve(P, S, At, bt, **kws)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            Xs, infs, _ = one_solve(P, S, At, bt, **kws)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        seeds[str(sd)] = dict(ms_median=round(float(np.median(ts)), 3),
+                              ms_min=round(min(ts), 3), ms_max=round(max(ts), 3),
+                              iters=int(infs["iters"]))
+    S.close()
+    if seeds:
+        out["seeds"] = seeds
+
+    if not args.no_batched:
+        log("batched 20000x1000 workload ...")
+        out["batched_20000x1000_k32"] = batched_run(P, torch)
+        torch.cuda.empty_cache()
 
     if not args.no_sparse:
         log("sparse 200000x5000 workload ...")
