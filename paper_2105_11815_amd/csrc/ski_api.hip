@@ -566,11 +566,24 @@ namespace {
 // W v products for the multi-RHS dense path through the GEMM
 hipError_t dense_AZ(ski_handle h, const double* Zm, int k, double* out, GemmWs& gw,
                     hipStream_t st) {
+    if (gemm_ts_eligible(k))
+        return gemm_ts_f64(false, h->n, k, h->d, 1.0, h->A, h->lda, Zm, k, 0.0, out, k, gw, st);
     return gemm_f64(false, false, h->n, k, h->d, 1.0, h->A, h->lda, Zm, k, 0.0, out, k, gw, st);
 }
 hipError_t dense_ATU(ski_handle h, const double* U, int k, double* out, GemmWs& gw,
                      hipStream_t st) {
+    if (gemm_ts_eligible(k))
+        return gemm_ts_f64(true, h->d, k, h->n, 1.0, h->A, h->lda, U, k, 0.0, out, k, gw, st);
     return gemm_f64(true, false, h->d, k, h->n, 1.0, h->A, h->lda, U, k, 0.0, out, k, gw, st);
+}
+
+// y = s M x for the p x p triangle M (R_11^-1 upper, R_11^-T lower) and k > 1 columns
+hipError_t tri_products(const double* Mtx, int64_t dp, bool upper, const double* x, double* y,
+                        int64_t ldy, int k, double s, GemmWs& gw, hipStream_t st) {
+    if (gemm_ts_eligible(k))
+        return gemm_ts_f64(false, dp, k, dp, s, Mtx, dp, x, k, 0.0, y, ldy, gw, st,
+                           upper ? GEMM_A_UPPER : GEMM_A_LOWER);
+    return gemm_f64(false, false, dp, k, dp, s, Mtx, dp, x, k, 0.0, y, ldy, gw, st);
 }
 
 int alloc_solve_ws(ski_handle h, int k) {
@@ -603,14 +616,14 @@ hipError_t apply_Rinv(ski_handle h, const double* Mtx, bool upper, const double*
     if (dp <= 0) return hipSuccess;
     const int32_t* perm = h->pivoted ? (const int32_t*)h->pivd.p : nullptr;
     if (k == 1) return launch_tri_gemv(Mtx, dp, upper, x, 1, y, 1, s, done, st, perm);
-    if (!perm) return gemm_f64(false, false, dp, k, dp, s, Mtx, dp, x, k, 0.0, y, k, gw, st);
+    if (!perm) return tri_products(Mtx, dp, upper, x, y, k, k, s, gw, st);
     double* t = (double*)h->ptmp.p;
     if (upper) {
-        SKI_HIP(gemm_f64(false, false, dp, k, dp, s, Mtx, dp, x, k, 0.0, t, k, gw, st));
+        SKI_HIP(tri_products(Mtx, dp, upper, x, t, k, k, s, gw, st));
         return launch_permute_rows(t, k, y, k, perm, dp, k, true, st);
     }
     SKI_HIP(launch_permute_rows(x, k, t, k, perm, dp, k, false, st));
-    return gemm_f64(false, false, dp, k, dp, s, Mtx, dp, t, k, 0.0, y, k, gw, st);
+    return tri_products(Mtx, dp, upper, t, y, k, k, s, gw, st);
 }
 
 // Convergence status read back with a one-iteration lag: after iteration i the all-done
@@ -816,8 +829,7 @@ int solve_lls(ski_handle h, const double* B, int k, int64_t ldb, double* X, int6
                                        P<int32_t>(h->pivd)),
                     "x");
         } else if (dp > 0) {
-            SKI_TRY(h, gemm_f64(false, false, dp, k, dp, 1.0, Rinv, dp, y, k, 0.0,
-                                P<double>(h->ptmp), k, gw, st),
+            SKI_TRY(h, tri_products(Rinv, dp, true, y, P<double>(h->ptmp), k, k, 1.0, gw, st),
                     "x");
             SKI_TRY(h, launch_permute_rows(P<double>(h->ptmp), k, X, ldx, P<int32_t>(h->pivd), dp,
                                            k, true, st),
@@ -826,7 +838,7 @@ int solve_lls(ski_handle h, const double* B, int k, int64_t ldb, double* X, int6
     } else if (k == 1) {
         SKI_TRY(h, launch_tri_gemv(Rinv, d, true, y, 1, X, ldx, 1.0, nullptr, st), "x");
     } else {
-        SKI_TRY(h, gemm_f64(false, false, d, k, d, 1.0, Rinv, d, y, k, 0.0, X, ldx, gw, st), "x");
+        SKI_TRY(h, tri_products(Rinv, d, true, y, X, ldx, k, 1.0, gw, st), "x");
     }
     float ms = 0;
     if (h->ev_ok) {
@@ -890,15 +902,14 @@ int solve_normal(ski_handle h, const double* G, int k, int64_t ldg, double* Z, i
     if (h->pivoted) {
         SKI_TRY(h, launch_fill_rows(Z, d, k, ldz, 0.0, st), "zero Z");
         if (dp > 0) {
-            SKI_TRY(h, gemm_f64(false, false, dp, k, dp, 1.0, Rinv, dp, y, k, 0.0,
-                                P<double>(h->ptmp), k, gw, st),
+            SKI_TRY(h, tri_products(Rinv, dp, true, y, P<double>(h->ptmp), k, k, 1.0, gw, st),
                     "z");
             SKI_TRY(h, launch_permute_rows(P<double>(h->ptmp), k, Z, ldz, P<int32_t>(h->pivd), dp,
                                            k, true, st),
                     "z scatter");
         }
     } else {
-        SKI_TRY(h, gemm_f64(false, false, d, k, d, 1.0, Rinv, d, y, k, 0.0, Z, ldz, gw, st), "z");
+        SKI_TRY(h, tri_products(Rinv, d, true, y, Z, ldz, k, 1.0, gw, st), "z");
     }
     float ms = 0;
     if (h->ev_ok) {

@@ -165,8 +165,9 @@ struct GemmWs {
     size_t bytes = 0;
 };
 // tri: GEMM_A_UPPER when op(A) is upper triangular (A(i, k) = 0 for k < i), GEMM_B_UPPER
-// when op(B) is (B(k, j) = 0 for k > j); each output tile then skips the zero part of K
-enum { GEMM_A_UPPER = 1, GEMM_B_UPPER = 2 };
+// when op(B) is (B(k, j) = 0 for k > j), GEMM_A_LOWER (narrow products only) when
+// A(i, k) = 0 for k > i; each output tile then skips the zero part of K
+enum { GEMM_A_UPPER = 1, GEMM_B_UPPER = 2, GEMM_A_LOWER = 4 };
 hipError_t gemm_f64(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
                     const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
                     double* C, int64_t ldc, GemmWs& ws, hipStream_t st, int unitA = 0,
@@ -175,6 +176,14 @@ hipError_t gemm_f32(bool ta, bool tb, int64_t M, int64_t N, int64_t K, float alp
                     const float* A, int64_t lda, const float* B, int64_t ldb, float beta, float* C,
                     int64_t ldc, bool bf16_inputs, GemmWs& ws, hipStream_t st, int unitA = 0);
 size_t gemm_ws_bytes(int64_t M, int64_t N, int64_t K, size_t elem);
+// FP64 products with a narrow right operand (tsgemm.hip): C = alpha op(A) B + beta C with
+// op(A) = A (M x K) or, with ta, A^T (A stored K x M); B K x N; N <= TS_MAX_N is where they
+// beat the general GEMM.  Split-K partials go to ws (fewer splits when it is small).
+constexpr int64_t TS_MAX_N = 64;
+bool gemm_ts_eligible(int64_t N);
+hipError_t gemm_ts_f64(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+                       int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                       int64_t ldc, GemmWs& ws, hipStream_t st, int tri = 0);
 
 // panel factorisation by CholeskyQR2 and Householder reconstruction (qr_panel.hip)
 struct CqrWs {

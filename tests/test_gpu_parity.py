@@ -381,6 +381,35 @@ def test_adjoint_and_gradients(ski):
     S.close()
 
 
+@pytest.mark.parametrize("n,d,k", [
+    # ragged rows, columns and right-hand sides: two 32-column output tiles, a partial
+    # last tile in every dimension, split K in the triangular and transposed products
+    (7001, 333, 40),
+    # the batched workload's shape (20000 x 1000, 32 right-hand sides)
+    (20000, 1000, 32),
+])
+def test_many_rhs_forward_and_adjoint(ski, n, d, k):
+    _say(f"many right-hand sides n={n} d={d} k={k}")
+    A, B, G = workloads.batched(n=n, d=d, k=k, case=5)
+    S = ski.Solver()
+    S.sketch(dev(A), dev(B), gamma=1.7, s=3, seed=2005, tau_r=1e-14, it_max=400).factor()
+    X, infos, rc = S.solve()
+    Z, zinfo, zrc = S.solve_normal(dev(G))
+    gA, gB = S.gradients(X, dev(B), Z)
+    S.close()
+    assert rc == 0 and zrc == 0
+    Xn = X.cpu().numpy()
+    Xd = lls.lstsq_direct(A, B)
+    err = np.abs(Xn - Xd).max(axis=0) / np.abs(Xd).max(axis=0)
+    _say(f"  iters {max(i['iters'] for i in infos)} cg {max(i['iters'] for i in zinfo)} "
+         f"max rel err {err.max():.2e}")
+    assert err.max() <= 1e-10
+    gA_ref, gB_ref, Z_ref = lls.grads_closed_form(A, Xn, B, G)
+    np.testing.assert_allclose(Z.cpu().numpy(), Z_ref, rtol=0, atol=1e-10 * np.abs(Z_ref).max())
+    np.testing.assert_allclose(gB.cpu().numpy(), gB_ref, rtol=0, atol=1e-10 * np.abs(gB_ref).max())
+    np.testing.assert_allclose(gA.cpu().numpy(), gA_ref, rtol=0, atol=1e-10 * np.abs(gA_ref).max())
+
+
 def test_autograd_function(ski):
     n, d, k = 2000, 60, 3
     A, B, G = workloads.batched(n=n, d=d, k=k, case=5)
