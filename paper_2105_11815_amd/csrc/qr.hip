@@ -23,6 +23,8 @@
 // Every sum has a fixed order: the factorisation is deterministic.
 #include "ski_internal.h"
 
+#include <type_traits>
+
 namespace ski {
 
 namespace {
@@ -400,6 +402,26 @@ hipError_t launch_Tinv(const T* Wt, int64_t n, int nb, const T* G, int ldg, cons
     return hipGetLastError();
 }
 
+// queue block column [j0, j0 + nb) of R_h^-1 on the third stream once the panel's
+// columns of R_h are final (FP64 only)
+template <typename T>
+hipError_t queue_rinv(T* Ac, int64_t m, int64_t d, int64_t j0, int nb, QrWs& ws, hipStream_t st) {
+    if constexpr (std::is_same<T, double>::value) {
+        if (!ws.Xinv) return hipSuccess;
+        SKI_HIP(hipEventRecord(ws.evP, st));
+        SKI_HIP(hipStreamWaitEvent(ws.st3, ws.evP, 0));
+        return rinv_block(Ac, m, j0, nb, ws.Xinv, d, ws.Zinv, ws.g3, ws.st3);
+    }
+    return hipSuccess;
+}
+
+// the caller's stream waits for every block of R_h^-1
+inline hipError_t join_rinv(const QrWs& ws, hipStream_t st) {
+    if (!ws.Xinv) return hipSuccess;
+    SKI_HIP(hipEventRecord(ws.evI, ws.st3));
+    return hipStreamWaitEvent(st, ws.evI, 0);
+}
+
 // Column-by-column panels with a look-ahead of one panel.  After panel p is factored, one
 // GEMM gives both V^T V (for T) and V^T C of the next panel's columns; those columns are
 // updated on the caller's stream, so panel p+1 can be factored at once, while the
@@ -427,6 +449,7 @@ hipError_t qr_impl_hh(T* Ac, int64_t m, int64_t ncols, int64_t d, QrWs& ws, bool
             const int nc = nb - jl - w;
             if (nc > 0) SKI_HIP(launch_narrow<T>(Ac, m, jc, w, Tl, nc, st));
         }
+        SKI_HIP(queue_rinv<T>(Ac, m, d, j0, nb, ws, st));
         if (ncols - j0 - nb <= 0) break;
         const int64_t mr = m - j0;
         const int64_t nx0 = j0 + nb;
@@ -464,7 +487,7 @@ hipError_t qr_impl_hh(T* Ac, int64_t m, int64_t ncols, int64_t d, QrWs& ws, bool
         }
     }
     if (pending_rest) SKI_HIP(hipStreamWaitEvent(st, ws.evE[(p - 1) & 1], 0));
-    return hipSuccess;
+    return join_rinv(ws, st);
 }
 
 // CholeskyQR2 panels.  The look-ahead is fused into the panel kernels: the finished panel
@@ -490,6 +513,7 @@ hipError_t qr_impl_cqr(T* Ac, int64_t m, int64_t ncols, int64_t d, QrWs& ws, boo
             SKI_HIP(cqr_gram_update<T>(Ac, m, j0 - NBP, j0, nb, Vb[(p - 1) & 1], Tb[(p - 1) & 1],
                                        ws.cqr, st));
         SKI_HIP(cqr_factor_panel<T>(Ac, m, j0, nb, ws.cqr, Tb[p & 1], st));
+        SKI_HIP(queue_rinv<T>(Ac, m, d, j0, nb, ws, st));
         const int64_t nx0 = j0 + nb;
         const int64_t nx1 = std::min<int64_t>(nx0 + NBP, d);  // next panel's columns
         const int nbn = (int)std::max<int64_t>(0, nx1 - nx0);
@@ -514,7 +538,7 @@ hipError_t qr_impl_cqr(T* Ac, int64_t m, int64_t ncols, int64_t d, QrWs& ws, boo
         }
     }
     if (pending_rest) SKI_HIP(hipStreamWaitEvent(st, ws.evE[(p - 1) & 1], 0));
-    return hipSuccess;
+    return join_rinv(ws, st);
 }
 
 // Column-pivoted panels (FP64): before each panel its pivots are chosen on the sketch of

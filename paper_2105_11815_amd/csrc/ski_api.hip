@@ -48,7 +48,7 @@ struct ski_handle_s {
     DevBuf qr_part, qr_W, qr_T, qr_Y, qr_tau;
     DevBuf tkeys, tkeys_tmp, ttable, tp, tpay, ti, tv;
     DevBuf u, t, v, h, delta, z, wp, g, gpart, upart, y, st;
-    DevBuf cg_r, cg_p, cg_q, t2, dtmp, gemm_ws2;
+    DevBuf cg_r, cg_p, cg_q, t2, dtmp, gemm_ws2, gemm_ws3;
     // column-pivoted factor: workspace, the permutation, compact R_11, p x k staging
     DevBuf piv_part, pivd, Rc, ptmp;
     int64_t rank = 0;      // p: columns kept (d without pivoting)
@@ -56,6 +56,8 @@ struct ski_handle_s {
     bool pivoted = false;  // the last ski_factor pivoted
     hipStream_t st2 = nullptr;           // second stream of the QR's look-ahead
     hipEvent_t qev[4] = {};
+    hipStream_t st3 = nullptr;           // third stream: R^-1 formed during the QR
+    hipEvent_t rev[2] = {};
     double* hdiag = nullptr;  // pinned host copy of diag(R)
     int64_t hdiag_n = 0;
     hipEvent_t ev[6] = {};
@@ -203,7 +205,7 @@ int ski_destroy(ski_handle h) {
                      &h->qr_Y, &h->qr_tau, &h->tkeys, &h->tkeys_tmp, &h->ttable, &h->tp,
                      &h->tpay, &h->ti, &h->tv, &h->u, &h->t, &h->v, &h->h, &h->delta, &h->z,
                      &h->wp, &h->g, &h->gpart, &h->upart, &h->y, &h->st, &h->cg_r,
-                     &h->cg_p, &h->cg_q, &h->t2, &h->dtmp, &h->gemm_ws2,
+                     &h->cg_p, &h->cg_q, &h->t2, &h->dtmp, &h->gemm_ws2, &h->gemm_ws3,
                      &h->piv_part, &h->pivd, &h->Rc, &h->ptmp};
     for (DevBuf* b : all) release(*b);
     if (h->ev_ok)
@@ -211,7 +213,10 @@ int ski_destroy(ski_handle h) {
     for (auto& e : h->pool) (void)hipEventDestroy(e);
     for (auto& e : h->qev)
         if (e) (void)hipEventDestroy(e);
+    for (auto& e : h->rev)
+        if (e) (void)hipEventDestroy(e);
     if (h->st2) (void)hipStreamDestroy(h->st2);
+    if (h->st3) (void)hipStreamDestroy(h->st3);
     if (h->hdiag) (void)hipHostFree(h->hdiag);
     delete h;
     return SKI_OK;
@@ -422,6 +427,8 @@ int ski_factor(ski_handle h, void* stream) {
         // default priority (no priority argument), non-blocking with respect to stream 0
         SKI_TRY(h, hipStreamCreateWithFlags(&h->st2, hipStreamNonBlocking), "stream");
         for (auto& e : h->qev) SKI_TRY(h, hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+        SKI_TRY(h, hipStreamCreateWithFlags(&h->st3, hipStreamNonBlocking), "stream");
+        for (auto& e : h->rev) SKI_TRY(h, hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
     }
     QrWs ws;
     qr_ws_carve(h->qprec, h->qr_part.p, m, ncols, ws);
@@ -470,6 +477,18 @@ int ski_factor(ski_handle h, void* stream) {
         SKI_TRY(h, hipStreamSynchronize(st), "sync");
     }
     bool cqr = h->p.qr_panel == SKI_QR_AUTO;
+    // without pivoting, in FP64, R_h^-1 is formed block by block on a third stream while the
+    // panels are factored (the Rinv buffer holds it until the signs are applied)
+    if (!piv && h->qprec == Prec::F64 && d > 0) {
+        SKI_TRY(h, ensure(h->gemm_ws3, rinv_ws_bytes(d)), "alloc");
+        ws.Xinv = P<double>(h->Rinv);
+        ws.Zinv = P<double>(h->tri_tmp);
+        ws.g3.part = h->gemm_ws3.p;
+        ws.g3.bytes = h->gemm_ws3.bytes;
+        ws.st3 = h->st3;
+        ws.evP = h->rev[0];
+        ws.evI = h->rev[1];
+    }
     for (; !piv;) {
         ws.cqr_panels = cqr;
         prof_begin(h, cqr ? PC_QR : PC_QR_HH, st);
@@ -546,10 +565,16 @@ int ski_factor(ski_handle h, void* stream) {
         R11 = P<double>(h->Rc);
     }
     prof_begin(h, PC_TRTRI, st);
-    if (dp > 0)
+    if (ws.Xinv && !pert) {
+        // the blocks of R_h^-1 are done (the QR's stream waited for them): R^-1 = R_h^-1 D
+        SKI_TRY(h, rinv_finish((const double*)ws.Ac, m, d, P<double>(h->Rinv), P<double>(h->RinvT),
+                               st),
+                "R inverse");
+    } else if (dp > 0) {
         SKI_TRY(h, trtri_upper(R11, dp, P<double>(h->Rinv), P<double>(h->RinvT),
                                P<double>(h->diag_add), P<double>(h->tri_tmp), gw, st),
                 "R inverse");
+    }
     prof_end(h, st);
     h->pivoted = piv;
     if (h->ev_ok) (void)hipEventRecord(h->ev[3], st);

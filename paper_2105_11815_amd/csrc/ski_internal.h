@@ -267,7 +267,23 @@ struct QrWs {
     hipStream_t st2 = nullptr;
     hipEvent_t evF[2] = {nullptr, nullptr};  // panel's V^T V and reflectors ready
     hipEvent_t evE[2] = {nullptr, nullptr};  // remaining-columns update done
+    // R_h^-1 formed alongside (FP64 without pivoting; rinv.hip): when Xinv is set, block
+    // column j of X = R_h^-1 (row-major d x d) is formed on st3 once panel j is factored
+    double* Xinv = nullptr;
+    double* Zinv = nullptr;  // d x 64 scratch
+    GemmWs g3;               // split-K partials, third stream
+    hipStream_t st3 = nullptr;
+    hipEvent_t evP = nullptr;  // panel factored
+    hipEvent_t evI = nullptr;  // inverse blocks done
 };
+// R_h^-1 block by block (rinv.hip): block column [j0, j0 + nb) of X from the factored
+// working copy Ac (column-major, ld m) and the blocks of X left of it; then R^-1 = X D with
+// D the signs of R_h's diagonal, the lower triangle cleared, and XT = (R^-1)^T
+size_t rinv_ws_bytes(int64_t d);
+hipError_t rinv_block(const double* Ac, int64_t m, int64_t j0, int nb, double* X, int64_t d,
+                      double* Z, GemmWs& g, hipStream_t s);
+hipError_t rinv_finish(const double* Ac, int64_t m, int64_t d, double* X, double* XT,
+                       hipStream_t st);
 size_t qr_ws_bytes(Prec prec, int64_t m, int64_t ncols, size_t* gemm_bytes);
 void qr_ws_carve(Prec prec, void* base, int64_t m, int64_t ncols, QrWs& ws);
 hipError_t qr_factor(Prec prec, const void* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws,
