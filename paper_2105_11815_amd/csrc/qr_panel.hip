@@ -42,13 +42,49 @@ constexpr int RSL = 16;      // slices of the partial-sum reduction
 constexpr double EPS_SERIES = 1e-8;  // |G2 - I| below which R2 comes from the series
 constexpr double EPS_FIRST = 1e-11;  // ... from its first-order term alone
 
-// rows [r0, r1) of an nb-column column-major block -> sh[GR][PP], zero padded
+// x if keep, else +0.0, without a branch (a select can be turned into a branch around the
+// load, which then waits at once; integer masking keeps the loads together)
+template <typename T>
+__device__ __forceinline__ T keep_or_zero(T x, bool keep) {
+    if constexpr (sizeof(T) == 8) {
+        const uint64_t b = __builtin_bit_cast(uint64_t, x) & (keep ? ~0ull : 0ull);
+        return __builtin_bit_cast(T, b);
+    } else {
+        const uint32_t b = __builtin_bit_cast(uint32_t, x) & (keep ? ~0u : 0u);
+        return __builtin_bit_cast(T, b);
+    }
+}
+
+// rows [r0, r1) of an nb-column column-major block -> sh[GR][PP], zero padded (r1 > r0).
+// Thread t takes row r0 + t%64 of the columns t/64 + 4q: all 16 loads are issued before the
+// first is used (addresses clamped into the block, masked values zeroed).
 template <typename T>
 __device__ __forceinline__ void stage_chunk(const T* __restrict__ P, int64_t ldp, int64_t r0,
                                             int64_t r1, int nb, T (*sh)[PP], int t) {
-    for (int o = t; o < GR * PB; o += 256) {
-        const int rr = o % GR, c = o / GR;
-        sh[rr][c] = (r0 + rr < r1 && c < nb) ? P[c * ldp + r0 + rr] : (T)0;
+    const int rr = t & (GR - 1), c0 = t / GR;
+    const int64_t r = r0 + rr;
+    const bool rok = r < r1;
+    const int64_t rc = rok ? r : r1 - 1;
+    T v[PB / 4];
+#pragma unroll
+    for (int q = 0; q < PB / 4; ++q) {
+        const int c = c0 + 4 * q;
+        v[q] = P[(int64_t)(c < nb ? c : nb - 1) * ldp + rc];
+    }
+#pragma unroll
+    for (int q = 0; q < PB / 4; ++q) sh[rr][c0 + 4 * q] = keep_or_zero(v[q], rok && c0 + 4 * q < nb);
+}
+
+// a full row-major PB x PB tile -> LDS, the loads issued together
+template <typename T>
+__device__ __forceinline__ void load_tile(const T* __restrict__ src, T (*dst)[PP], int t) {
+    T v[PB * PB / 256];
+#pragma unroll
+    for (int q = 0; q < PB * PB / 256; ++q) v[q] = src[t + 256 * q];
+#pragma unroll
+    for (int q = 0; q < PB * PB / 256; ++q) {
+        const int o = t + 256 * q;
+        dst[o / PB][o % PB] = v[q];
     }
 }
 
@@ -153,9 +189,15 @@ __global__ __launch_bounds__(256) void k_cqr_chol1(const T* __restrict__ G, int 
     __shared__ int bad;
     const int t = threadIdx.x;
     if (t == 0) bad = 0;
-    for (int o = t; o < PB * PB; o += 256) {
-        const int i = o / PB, j = o % PB;
-        A[i][j] = (i < nb && j < nb) ? G[o] : (i == j ? (T)1 : (T)0);
+    {
+        T v[PB * PB / 256];
+#pragma unroll
+        for (int q = 0; q < PB * PB / 256; ++q) v[q] = G[t + 256 * q];
+#pragma unroll
+        for (int q = 0; q < PB * PB / 256; ++q) {
+            const int o = t + 256 * q, i = o / PB, j = o % PB;
+            A[i][j] = (i < nb && j < nb) ? v[q] : (i == j ? (T)1 : (T)0);
+        }
     }
     __syncthreads();
     tile_chol(A, t, &bad);
@@ -177,7 +219,7 @@ __global__ __launch_bounds__(256) void k_cqr_apply_gram(const T* __restrict__ P,
     __shared__ T sh[GR][PP];
     const int t = threadIdx.x;
     const int64_t r0 = (int64_t)blockIdx.x * GR, r1 = std::min<int64_t>(mr, r0 + GR);
-    for (int o = t; o < PB * PB; o += 256) Xs[o / PB][o % PB] = Ri[o];
+    load_tile(Ri, Xs, t);
     stage_chunk(P, ldp, r0, r1, nb, sh, t);
     __syncthreads();
     chunk_times_upper(sh, Xs, t);
@@ -206,18 +248,31 @@ __global__ __launch_bounds__(256) void k_cqr_chol2(const T* __restrict__ G, int 
     __shared__ int bad;
     const int t = threadIdx.x;
     int off = 0, big = 0, second = 0;
-    for (int o = t; o < PB * PB; o += 256) {
-        const int i = o / PB, j = o % PB;
-        const T g = (i < nb && j < nb) ? G[o] : (i == j ? (T)1 : (T)0);
-        A[i][j] = g;
-        // G2 must be close to the identity for the second step to be accurate
-        const T e = fabs(g - (i == j ? (T)1 : (T)0));
-        off |= !(e <= (T)0.01);
-        big |= !(e <= (T)EPS_SERIES);
-        second |= !(e <= (T)EPS_FIRST);
-        B[i][j] = R1[o];
-        const int r = o % PB, c = o / PB;  // column-major walk of Q1 for coalescing
-        C[r][c] = (r < nb && c < nb) ? Q[c * ldq + r] : (T)0;
+    {
+        // all loads first (Q1's top block walked column-major for coalescing; rows and
+        // columns beyond nb are clamped and zeroed)
+        T gv[PB * PB / 256], rv[PB * PB / 256], qv[PB * PB / 256];
+#pragma unroll
+        for (int q = 0; q < PB * PB / 256; ++q) {
+            const int o = t + 256 * q, r = o % PB, c = o / PB;
+            gv[q] = G[o];
+            rv[q] = R1[o];
+            qv[q] = Q[(int64_t)(c < nb ? c : nb - 1) * ldq + (r < nb ? r : nb - 1)];
+        }
+#pragma unroll
+        for (int q = 0; q < PB * PB / 256; ++q) {
+            const int o = t + 256 * q, i = o / PB, j = o % PB;
+            const T g = (i < nb && j < nb) ? gv[q] : (i == j ? (T)1 : (T)0);
+            A[i][j] = g;
+            // G2 must be close to the identity for the second step to be accurate
+            const T e = fabs(g - (i == j ? (T)1 : (T)0));
+            off |= !(e <= (T)0.01);
+            big |= !(e <= (T)EPS_SERIES);
+            second |= !(e <= (T)EPS_FIRST);
+            B[i][j] = rv[q];
+            const int r = o % PB, c = o / PB;
+            C[r][c] = keep_or_zero(qv[q], r < nb && c < nb);
+        }
     }
     if (t == 0) bad = 0;
     off = __syncthreads_or(off);
@@ -312,10 +367,8 @@ __global__ __launch_bounds__(256) void k_cqr_update_gram(T* __restrict__ Ac, int
     const int t = threadIdx.x;
     const int64_t mq = m - jq;
     const int64_t r0 = (int64_t)blockIdx.x * GR, r1 = std::min<int64_t>(mq, r0 + GR);
-    for (int o = t; o < PB * PB; o += 256) {
-        Vs[o / PB][o % PB] = Tq[o];
-        Cs[o / PB][o % PB] = W[o];
-    }
+    load_tile(Tq, Vs, t);
+    load_tile(W, Cs, t);
     __syncthreads();
     // Y = T^T W (T upper)
     tile_mma(Ys, t, [&](int i, int k) { return Vs[k][i]; }, [&](int k, int j) { return Cs[k][j]; },
@@ -344,7 +397,7 @@ __global__ __launch_bounds__(256) void k_cqr_v2x(const T* __restrict__ Q, int64_
     __shared__ T Cs[PB][PP];
     const int t = threadIdx.x;
     const int64_t r0 = (int64_t)blockIdx.x * GR, r1 = std::min<int64_t>(mr, r0 + GR);
-    for (int o = t; o < PB * PB; o += 256) Ms[o / PB][o % PB] = Mx[o];
+    load_tile(Mx, Ms, t);
     stage_chunk(Q, ldq, r0, r1, nb, Qs, t);
     if (nbn > 0) stage_chunk(P + (int64_t)nb * ldp, ldp, r0, r1, nbn, Cs, t);
     __syncthreads();
