@@ -69,6 +69,17 @@ __device__ __forceinline__ TOut store_as(TAcc v) {
         return from_f<TOut>(v);
 }
 
+// x if keep, else +0.0, without a branch: a conditional load becomes a branch that waits
+// for its load at once; clamped addresses and integer masking keep the loads together
+template <typename TAcc>
+__device__ __forceinline__ TAcc keep_or_zero(TAcc x, bool keep) {
+    if constexpr (sizeof(TAcc) == 8) {
+        return __builtin_bit_cast(TAcc, __builtin_bit_cast(uint64_t, x) & (keep ? ~0ull : 0ull));
+    } else {
+        return __builtin_bit_cast(TAcc, __builtin_bit_cast(uint32_t, x) & (keep ? ~0u : 0u));
+    }
+}
+
 // One 256-point pass over row bits [p, p+8).
 template <typename TIn, typename TOut, typename TAcc>
 __global__ __launch_bounds__(WT) void k_wht256(const TIn* in, int64_t ld_in,
@@ -84,15 +95,22 @@ __global__ __launch_bounds__(WT) void k_wht256(const TIn* in, int64_t ld_in,
     const int c = threadIdx.x & (WC - 1);
     if (skip_zero_lines && line_row(line, p, 8, 0) >= rows_valid) return;  // p == 0 here
     const bool colok = col < ncols_src;
+    const int64_t colc = colok ? col : ncols_src - 1;
     TAcc v[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-        int64_t row = line_row(line, p, 8, 16 * q + i);
-        TAcc x = 0;
-        if (colok && row < rows_valid) {
-            x = load_in<TIn, TAcc>(in + row * ld_in + col);
-            if (dbits && dneg(dbits, row)) x = -x;
-        }
+        const int64_t row = line_row(line, p, 8, 16 * q + i);
+        const int64_t rc = row < rows_valid ? row : rows_valid - 1;
+        v[i] = load_in<TIn, TAcc>(in + rc * ld_in + colc);
+    }
+    // the signs D come with the first pass only (p == 0): rows 16q .. 16q+15 of the line
+    // share one 32-bit word
+    const uint32_t sw = dbits ? dbits[line_row(line, p, 8, 16 * q) >> 5] : 0u;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int64_t row = line_row(line, p, 8, 16 * q + i);
+        TAcc x = keep_or_zero(v[i], colok && row < rows_valid);
+        if ((sw >> (row & 31)) & 1u) x = -x;
         v[i] = x;
     }
 #pragma unroll
@@ -150,18 +168,26 @@ __global__ __launch_bounds__(WT) void k_wht_small(const TIn* in, int64_t ld_in,
     const bool colok = col < ncols_src;
     const int pmask = (1 << R) - 1;
     if (skip_zero_lines && line_row(line0, p, R, 0) >= rows_valid) return;  // p == 0 here
-    for (int i = 0; i < 16; ++i) {
-        int e = 16 * q + i;
-        int64_t line = line0 + (e >> R);
-        TAcc x = 0;
-        if (line < nlines) {
-            int64_t row = line_row(line, p, R, e & pmask);
-            if (colok && row < rows_valid) {
-                x = load_in<TIn, TAcc>(in + row * ld_in + col);
-                if (dbits && dneg(dbits, row)) x = -x;
-            }
+    {
+        const int64_t colc = colok ? col : ncols_src - 1;
+        TAcc v[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int e = 16 * q + i;
+            const int64_t line = std::min(line0 + (e >> R), nlines - 1);
+            const int64_t row = line_row(line, p, R, e & pmask);
+            const int64_t rc = row < rows_valid ? row : rows_valid - 1;
+            v[i] = load_in<TIn, TAcc>(in + rc * ld_in + colc);
         }
-        lds[e * (WC + 1) + c] = x;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int e = 16 * q + i;
+            const int64_t line = line0 + (e >> R);
+            const int64_t row = line_row(std::min(line, nlines - 1), p, R, e & pmask);
+            TAcc x = keep_or_zero(v[i], line < nlines && colok && row < rows_valid);
+            if (dbits && dneg(dbits, row)) x = -x;
+            lds[e * (WC + 1) + c] = x;
+        }
     }
     __syncthreads();
     for (int lh = 0; lh < R; ++lh) {
