@@ -303,11 +303,18 @@ __global__ __launch_bounds__(256) void k_pivot_move(double* __restrict__ Ac, int
     const int col = dir == 0 ? src : dst;
     double* a = Ac + (int64_t)col * m;
     double* t = tA + (int64_t)i * m;
-    for (int64_t r = (int64_t)blockIdx.y * 256 + threadIdx.x; r < m; r += (int64_t)gridDim.y * 256) {
-        if (dir == 0)
-            t[r] = a[r];
-        else
-            a[r] = t[r];
+    const double* from = dir == 0 ? a : t;
+    double* to = dir == 0 ? t : a;
+    // four rows per thread per step, their loads issued together (clamped into the column;
+    // only rows < m are stored)
+    const int64_t stride = (int64_t)gridDim.y * 256;
+    for (int64_t r0 = (int64_t)blockIdx.y * 256 + threadIdx.x; r0 < m; r0 += 4 * stride) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = from[std::min(r0 + u * stride, m - 1)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (r0 + u * stride < m) to[r0 + u * stride] = v[u];
     }
     if (blockIdx.y == 0) {
         double* yr = Yt + (int64_t)col * PIV_YL;
@@ -343,15 +350,32 @@ __global__ __launch_bounds__(256) void k_sketch_bt(const double* __restrict__ Ac
     // every load is issued before the first one is used
     constexpr int NR = NBP * NBP / 256, NY = NBP * PIV_YL / 256;
     double ra[NR], ya[NY];
+    // (addresses clamped into the panel and the unused values masked: a conditional load
+    // becomes a branch that waits for its own load)
+    auto keep = [](double x, bool k) {
+        return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, x) & (k ? ~0ull : 0ull));
+    };
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
         const int o = t + 256 * q, i = o / NBP, k = o - i * NBP;  // column i, row k
-        ra[q] = (i < nb && k <= i) ? Ac[(j0 + i) * m + j0 + k] : (k == i ? 1.0 : 0.0);
+        const int ic = i < nb ? i : nb - 1, kc = k < ic ? k : ic;
+        ra[q] = Ac[(j0 + ic) * m + j0 + kc];
     }
 #pragma unroll
     for (int q = 0; q < NY; ++q) {
         const int o = t + 256 * q, i = o / PIV_YL, u = o - i * PIV_YL;
-        ya[q] = i < nb ? Yt[(j0 + i) * PIV_YL + u] : 0.0;
+        ya[q] = Yt[(j0 + (i < nb ? i : nb - 1)) * PIV_YL + u];
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        const int o = t + 256 * q, i = o / NBP, k = o - i * NBP;
+        const bool in = i < nb && k <= i;
+        ra[q] = keep(ra[q], in) + (!in && k == i ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < NY; ++q) {
+        const int o = t + 256 * q, i = o / PIV_YL;
+        ya[q] = keep(ya[q], i < nb);
     }
 #pragma unroll
     for (int q = 0; q < NR; ++q) {

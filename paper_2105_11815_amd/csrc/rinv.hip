@@ -20,6 +20,12 @@ namespace {
 
 using namespace tile;
 
+// x if keep, else +0.0, by integer masking (a conditional load would become a branch that
+// waits for its own load; the loads below are clamped into the block and issued together)
+__device__ __forceinline__ double keep_or_zero(double x, bool keep) {
+    return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, x) & (keep ? ~0ull : 0ull));
+}
+
 // X_jj = inverse of the nb x nb diagonal block of R_h at (j0, j0), read from the column-major
 // working copy (ld m); identity padding beyond nb; zeros below the diagonal are written too
 __global__ __launch_bounds__(256) void k_rinv_diag(const double* __restrict__ Ac, int64_t m,
@@ -27,11 +33,20 @@ __global__ __launch_bounds__(256) void k_rinv_diag(const double* __restrict__ Ac
                                                    int64_t d) {
     __shared__ double Rs[PB][PP];
     const int t = threadIdx.x;
-    for (int o = t; o < PB * PB; o += 256) {
-        const int i = o % PB, j = o / PB;  // column-major walk: consecutive threads, one column
-        double v = i == j ? 1.0 : 0.0;
-        if (i < nb && j < nb && i <= j) v = Ac[(j0 + j) * m + j0 + i];
-        Rs[i][j] = v;
+    {
+        double v[PB * PB / 256];
+#pragma unroll
+        for (int q = 0; q < PB * PB / 256; ++q) {
+            const int o = t + 256 * q, i = o % PB, j = o / PB;  // column-major walk
+            const int jc = j < nb ? j : nb - 1, ic = i < jc ? i : jc;
+            v[q] = Ac[(j0 + jc) * m + j0 + ic];
+        }
+#pragma unroll
+        for (int q = 0; q < PB * PB / 256; ++q) {
+            const int o = t + 256 * q, i = o % PB, j = o / PB;
+            const bool in = i < nb && j < nb && i <= j;
+            Rs[i][j] = keep_or_zero(v[q], in) + (!in && i == j ? 1.0 : 0.0);
+        }
     }
     __syncthreads();
     tile_trinv(Rs, t, false);
@@ -51,11 +66,25 @@ __global__ __launch_bounds__(256) void k_rinv_panel(const double* __restrict__ A
     __shared__ double Xs[PB][PP];
     const int t = threadIdx.x;
     const int64_t r0 = (int64_t)blockIdx.x * PB;
-    for (int o = t; o < PB * PB; o += 256) {
-        const int rr = o % PB, c = o / PB;
-        Ts[rr][c] = (r0 + rr < j0 && c < nb) ? Ac[(j0 + c) * m + r0 + rr] : 0.0;
-        const int i = o / PB, j = o % PB;
-        Xs[i][j] = (i < nb && j < nb) ? X[(j0 + i) * d + j0 + j] : 0.0;
+    {
+        double tv[PB * PB / 256], xv[PB * PB / 256];
+#pragma unroll
+        for (int q = 0; q < PB * PB / 256; ++q) {
+            const int o = t + 256 * q;
+            const int rr = o % PB, c = o / PB;  // R_h column-major: rows r0 + rr, column c
+            const int64_t r = std::min<int64_t>(r0 + rr, j0 - 1);
+            tv[q] = Ac[(j0 + (c < nb ? c : nb - 1)) * m + r];
+            const int i = o / PB, j = o % PB;   // X_jj row-major
+            xv[q] = X[(j0 + (i < nb ? i : nb - 1)) * d + j0 + (j < nb ? j : nb - 1)];
+        }
+#pragma unroll
+        for (int q = 0; q < PB * PB / 256; ++q) {
+            const int o = t + 256 * q;
+            const int rr = o % PB, c = o / PB;
+            Ts[rr][c] = keep_or_zero(tv[q], r0 + rr < j0 && c < nb);
+            const int i = o / PB, j = o % PB;
+            Xs[i][j] = keep_or_zero(xv[q], i < nb && j < nb);
+        }
     }
     __syncthreads();
     tile_mma(Ts, t, [&](int i, int k) { return Ts[i][k]; }, [&](int k, int j) { return Xs[k][j]; },
