@@ -475,6 +475,8 @@ def main():
     ap.add_argument("--no-seeds", action="store_true")
     ap.add_argument("--rankdef-only", action="store_true",
                     help="only the rank-deficient workload (for profiling); prints its record")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the batched 32-right-hand-side workload (for profiling)")
     ap.add_argument("--sweep", action="store_true",
                     help="only the gamma/s sweep of the dense and sparse workloads; prints it")
     ap.add_argument("--sketch-study", action="store_true",
@@ -490,6 +492,9 @@ def main():
 
     if args.rankdef_only:
         print(json.dumps({"rankdef_50000x4000": rankdef_run(P, torch)}), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps({"batched_20000x1000_k32": batched_run(P, torch)}), flush=True)
         return
     if args.sweep:
         print(json.dumps({"gamma_s_sweep": sweep_run(P, torch)}), flush=True)
