@@ -475,6 +475,9 @@ __device__ double block_sum(double v, double* sh) {
     return s;
 }
 
+// entries per thread kept in registers by the step kernels (1024 threads: d <= 4096)
+constexpr int STEP_REG = 4;
+
 // init: beta_1 u_1 = r_0 (u holds r_0, beta2 = ||r_0||^2), wp = R^-T A^T r_0
 __global__ __launch_bounds__(1024) void k_lsqr_init(LsqrState* __restrict__ stt, int64_t d, int k,
                                                     const double* __restrict__ wp,
@@ -542,10 +545,32 @@ __global__ __launch_bounds__(1024) void k_lsqr_step(LsqrState* __restrict__ stt,
     const double rhobar = S.rhobar, phibar = S.phibar, anorm2_old = S.anorm2;
     const int64_t iters_old = S.iters;
     const double ib = beta > 0 ? 1.0 / beta : 0.0;
+    // d <= STEP_REG * blockDim: each thread's entries are loaded once, all loads issued
+    // together (indices clamped), and stay in registers between the norm and the update; the
+    // per-thread sums run over the same entries in the same order as the general loops
+    const bool reg = d <= (int64_t)STEP_REG * blockDim.x;
+    double wv[STEP_REG], vv[STEP_REG], hv[STEP_REG], dv[STEP_REG];
     double ss = 0;
-    for (int64_t i = threadIdx.x; i < d; i += blockDim.x) {
-        const double w = wp[i * k + j] * ib - beta * v[i * k + j];
-        ss += w * w;
+    if (reg) {
+#pragma unroll
+        for (int u = 0; u < STEP_REG; ++u) {
+            const int64_t i = threadIdx.x + (int64_t)u * blockDim.x;
+            const int64_t o = (i < d ? i : d - 1) * k + j;
+            wv[u] = wp[o];
+            vv[u] = v[o];
+            hv[u] = h[o];
+            dv[u] = delta[o];
+        }
+#pragma unroll
+        for (int u = 0; u < STEP_REG; ++u) {
+            const double w = wv[u] * ib - beta * vv[u];
+            if (threadIdx.x + (int64_t)u * blockDim.x < d) ss += w * w;
+        }
+    } else {
+        for (int64_t i = threadIdx.x; i < d; i += blockDim.x) {
+            const double w = wp[i * k + j] * ib - beta * v[i * k + j];
+            ss += w * w;
+        }
     }
     const double alpha = sqrt(block_sum(ss, sh));
     const double ia = alpha > 0 ? 1.0 / alpha : 0.0;
@@ -555,13 +580,26 @@ __global__ __launch_bounds__(1024) void k_lsqr_step(LsqrState* __restrict__ stt,
     const double theta = sn * alpha;
     const double phi = cs * phibar;
     const double t1 = phi / rho, t2 = theta / rho;
-    for (int64_t i = threadIdx.x; i < d; i += blockDim.x) {
-        const double w = wp[i * k + j] * ib - beta * v[i * k + j];
-        const double vn = w * ia;
-        const double hi = h[i * k + j];
-        delta[i * k + j] += t1 * hi;
-        h[i * k + j] = vn - t2 * hi;
-        v[i * k + j] = vn;
+    if (reg) {
+#pragma unroll
+        for (int u = 0; u < STEP_REG; ++u) {
+            const int64_t i = threadIdx.x + (int64_t)u * blockDim.x;
+            if (i < d) {
+                const double vn = (wv[u] * ib - beta * vv[u]) * ia;
+                delta[i * k + j] = dv[u] + t1 * hv[u];
+                h[i * k + j] = vn - t2 * hv[u];
+                v[i * k + j] = vn;
+            }
+        }
+    } else {
+        for (int64_t i = threadIdx.x; i < d; i += blockDim.x) {
+            const double w = wp[i * k + j] * ib - beta * v[i * k + j];
+            const double vn = w * ia;
+            const double hi = h[i * k + j];
+            delta[i * k + j] += t1 * hi;
+            h[i * k + j] = vn - t2 * hi;
+            v[i * k + j] = vn;
+        }
     }
     if (threadIdx.x == 0) {
         const double anorm2 = anorm2_old + alpha_old * alpha_old + beta * beta;
@@ -672,20 +710,61 @@ __global__ __launch_bounds__(1024) void k_cg_step(LsqrState* __restrict__ stt, i
     if (S.done) return;
     const double rr_old = S.rr, stop2 = S.stop2;
     const int64_t iters_old = S.iters;
+    // as in the LSQR step: registers for d <= STEP_REG * blockDim, the same sums otherwise
+    const bool reg = d <= (int64_t)STEP_REG * blockDim.x;
+    double pv[STEP_REG], qv[STEP_REG], rv[STEP_REG], yv[STEP_REG];
     double pq = 0;
-    for (int64_t i = threadIdx.x; i < d; i += blockDim.x) pq += p[i * k + j] * q[i * k + j];
+    if (reg) {
+#pragma unroll
+        for (int u = 0; u < STEP_REG; ++u) {
+            const int64_t i = threadIdx.x + (int64_t)u * blockDim.x;
+            const int64_t o = (i < d ? i : d - 1) * k + j;
+            pv[u] = p[o];
+            qv[u] = q[o];
+            rv[u] = r[o];
+            yv[u] = y[o];
+        }
+#pragma unroll
+        for (int u = 0; u < STEP_REG; ++u)
+            if (threadIdx.x + (int64_t)u * blockDim.x < d) pq += pv[u] * qv[u];
+    } else {
+        for (int64_t i = threadIdx.x; i < d; i += blockDim.x) pq += p[i * k + j] * q[i * k + j];
+    }
     pq = block_sum(pq, sh);
     const double a = rr_old / pq;
     double ss = 0;
-    for (int64_t i = threadIdx.x; i < d; i += blockDim.x) {
-        y[i * k + j] += a * p[i * k + j];
-        const double rn = r[i * k + j] - a * q[i * k + j];
-        r[i * k + j] = rn;
-        ss += rn * rn;
+    if (reg) {
+#pragma unroll
+        for (int u = 0; u < STEP_REG; ++u) {
+            const int64_t i = threadIdx.x + (int64_t)u * blockDim.x;
+            if (i < d) {
+                y[i * k + j] = yv[u] + a * pv[u];
+                const double rn = rv[u] - a * qv[u];
+                r[i * k + j] = rn;
+                rv[u] = rn;
+                ss += rn * rn;
+            }
+        }
+    } else {
+        for (int64_t i = threadIdx.x; i < d; i += blockDim.x) {
+            y[i * k + j] += a * p[i * k + j];
+            const double rn = r[i * k + j] - a * q[i * k + j];
+            r[i * k + j] = rn;
+            ss += rn * rn;
+        }
     }
     const double rr_new = block_sum(ss, sh);
     const double bb = rr_new / rr_old;
-    for (int64_t i = threadIdx.x; i < d; i += blockDim.x) p[i * k + j] = r[i * k + j] + bb * p[i * k + j];
+    if (reg) {
+#pragma unroll
+        for (int u = 0; u < STEP_REG; ++u) {
+            const int64_t i = threadIdx.x + (int64_t)u * blockDim.x;
+            if (i < d) p[i * k + j] = rv[u] + bb * pv[u];
+        }
+    } else {
+        for (int64_t i = threadIdx.x; i < d; i += blockDim.x)
+            p[i * k + j] = r[i * k + j] + bb * p[i * k + j];
+    }
     if (threadIdx.x == 0) {
         S.rr = rr_new;
         S.iters = iters_old + 1;
@@ -700,10 +779,16 @@ __global__ __launch_bounds__(1024) void k_cg_step(LsqrState* __restrict__ stt, i
     }
 }
 
-__global__ void k_all_done(const LsqrState* __restrict__ stt, int k, int32_t* __restrict__ flag) {
+// one wavefront: lane j reads column j's flag (64 columns per step), a vote ANDs them
+__global__ __launch_bounds__(64) void k_all_done(const LsqrState* __restrict__ stt, int k,
+                                                 int32_t* __restrict__ flag) {
     int all = 1;
-    for (int j = 0; j < k; ++j) all &= stt[j].done ? 1 : 0;
-    *flag = all;
+    for (int j0 = 0; j0 < k; j0 += 64) {
+        const int j = j0 + (int)threadIdx.x;
+        const int dn = j < k ? (stt[j].done ? 1 : 0) : 1;
+        all &= __all(dn) ? 1 : 0;
+    }
+    if (threadIdx.x == 0) *flag = all;
 }
 
 }  // namespace
@@ -912,7 +997,7 @@ hipError_t launch_cg_step(LsqrState* stt, int64_t d, int k, const double* q, dou
 }
 
 hipError_t launch_all_done(const LsqrState* stt, int k, int32_t* flag, hipStream_t st) {
-    hipLaunchKernelGGL(k_all_done, dim3(1), dim3(1), 0, st, stt, k, flag);
+    hipLaunchKernelGGL(k_all_done, dim3(1), dim3(64), 0, st, stt, k, flag);
     return hipGetLastError();
 }
 
