@@ -157,7 +157,38 @@ def test_qr_falls_back_on_an_ill_conditioned_panel(ski):
     tol = 1e-13 * math.sqrt(m) * np.outer(nrm, nrm)
     assert np.all(np.abs(R.T @ R - SA.T @ SA) <= tol[:d, :d])
     assert np.all(np.abs(R.T @ c - SA.T @ Sb) <= tol[:d, d:])
+    # R^-1 (formed again with the second factorisation): R R^-1 = I to the accuracy that
+    # cond(R) allows
+    Ri = S.get_R()[2]
+    assert np.all(np.isfinite(Ri))
+    assert np.abs(R @ Ri - np.eye(d)).max() <= 1e-14 * np.linalg.cond(R)
     S.close()
+
+
+def test_perturbed_diagonal_gives_the_inverse_of_the_perturbed_r(ski):
+    """With the perturbation switched on (rcond_thres = 1 makes every cond(R) qualify), R^-1
+    is the inverse of R + diag(copysign(perturb, r_ii)) (the recursive inversion after the
+    QR, not the blocks formed during it), and the solve still reaches the least-squares
+    solution: any nonsingular preconditioner applied as W = A P, x = P y does."""
+    n, d = 4000, 150
+    _say(f"perturbed diagonal n={n} d={d}")
+    rng = np.random.default_rng(8)
+    A = rng.standard_normal((n, d))
+    A[: n // 5] *= 1e3
+    b = rng.standard_normal(n)
+    S = ski.Solver()
+    S.sketch(dev(A), dev(b), s=3, seed=17, rcond_thres=1.0, perturb=1e-3, tau_r=1e-14,
+             it_max=500).factor()
+    R, c, Ri = S.get_R()
+    Rp = R + np.diag(np.copysign(1e-3, np.diag(R)))
+    np.testing.assert_allclose(Ri @ Rp, np.eye(d), rtol=0, atol=1e-12 * np.linalg.cond(Rp))
+    # not the unperturbed inverse
+    assert np.abs(Ri @ R - np.eye(d)).max() > 1e-9
+    X, infos, rc = S.solve()
+    S.close()
+    assert rc == 0
+    xd = lls.lstsq_direct(A, b)
+    assert np.abs(X[:, 0].cpu().numpy() - xd).max() <= 1e-10 * np.abs(xd).max()
 
 
 def test_illconditioned_solve_reaches_the_optimality_bound(ski):
