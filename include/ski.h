@@ -53,7 +53,7 @@ enum ski_status {
     SKI_ESTATE = -5    /* calls out of order (e.g. ski_factor before ski_sketch)           */
 };
 
-enum ski_kind { SKI_DENSE = 0, SKI_CSR = 2 };
+enum ski_kind { SKI_DENSE = 0, SKI_DENSE_COLMAJOR = 1, SKI_CSR = 2 };
 enum ski_prec { SKI_FP64 = 0, SKI_FP32 = 1, SKI_BF16 = 2 };
 enum ski_op { SKI_OP_LLS = 0, SKI_OP_NORMAL = 1 };
 enum ski_hash_kind { SKI_HASH = 0, SKI_HASH_VARIANT = 1, SKI_SAMPLE_ROWS = 2 };
@@ -65,10 +65,15 @@ enum ski_qr_panel {
 };
 
 /* The data matrix.  Dense: `a` (n x d, row-major, leading dimension lda >= d).
+ * Dense column-major (SKI_DENSE_COLMAJOR): entry (i, j) at a[j lda + i], lda >= n;
+ * ski_sketch transposes it once, in stream order, into a row-major copy that the handle
+ * owns (n d doubles, kept until the next ski_sketch or ski_destroy), and every later call
+ * reads the copy, so this A may change or be freed once ski_sketch's work on the stream is
+ * done; gradients with respect to A are returned row-major as for SKI_DENSE.
  * CSR: row_ptr[n+1] (int64, row_ptr[0] = 0), col[nnz] (int32 in [0, d), distinct
- * within a row), val[nnz].  The caller owns the arrays and must keep them alive
- * and unmodified from ski_sketch until the last ski_solve/ski_gradients call on
- * the handle: LSQR streams A directly, the handle keeps pointers, not copies. */
+ * within a row), val[nnz].  For SKI_DENSE and SKI_CSR the caller owns the arrays and must
+ * keep them alive and unmodified from ski_sketch until the last ski_solve/ski_gradients
+ * call on the handle: LSQR streams A directly, the handle keeps pointers, not copies. */
 typedef struct {
     int64_t n, d;
     int32_t kind;

@@ -102,11 +102,18 @@ class Solver:
             keep = (rp, ci, va)
         else:
             _check_dev(A, "A", torch.float64)
-            if A.dim() != 2 or A.stride(1) != 1:
-                raise ValueError("A must be 2-D with unit column stride (row-major)")
+            if A.dim() != 2:
+                raise ValueError("A must be 2-D")
             n, d = A.shape
-            M = L.SkiMatrix(n=n, d=d, kind=L.SKI_DENSE, a=A.data_ptr(), lda=A.stride(0),
-                            row_ptr=None, col=None, val=None, nnz=0)
+            if A.stride(1) == 1 and (d == 1 or A.stride(0) >= d):
+                M = L.SkiMatrix(n=n, d=d, kind=L.SKI_DENSE, a=A.data_ptr(), lda=A.stride(0),
+                                row_ptr=None, col=None, val=None, nnz=0)
+            elif A.stride(0) == 1 and A.stride(1) >= n:
+                # column-major (e.g. a transposed view): the library keeps a row-major copy
+                M = L.SkiMatrix(n=n, d=d, kind=L.SKI_DENSE_COLMAJOR, a=A.data_ptr(),
+                                lda=A.stride(1), row_ptr=None, col=None, val=None, nnz=0)
+            else:
+                raise ValueError("A must be row-major or column-major (one unit stride)")
             kind = "dense"
             keep = (A,)
         _check_dev(B, "B", torch.float64)

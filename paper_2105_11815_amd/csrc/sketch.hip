@@ -406,6 +406,38 @@ hipError_t sketch_slabs(const double* A, int64_t lda, const double* B, int64_t l
 
 }  // namespace
 
+namespace {
+
+// dst (n x d row-major, ld d) = src (n x d column-major, ld lds); 64 x 64 tiles through LDS so
+// that both the reads (down columns) and the writes (along rows) are contiguous
+__global__ __launch_bounds__(256) void k_colmajor_to_rowmajor(const double* __restrict__ src,
+                                                              int64_t lds, int64_t n, int64_t d,
+                                                              double* __restrict__ dst) {
+    __shared__ double tl[64][65];
+    const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int c = ty; c < 64; c += 4) {
+        const int64_t i = i0 + tx, j = j0 + c;
+        if (i < n && j < d) tl[c][tx] = src[j * lds + i];
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        const int64_t i = i0 + r, j = j0 + tx;
+        if (i < n && j < d) dst[i * d + j] = tl[tx][r];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_colmajor_to_rowmajor(const double* src, int64_t lds, int64_t n, int64_t d,
+                                       double* dst, hipStream_t st) {
+    if (n <= 0 || d <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((d + 63) / 64), (unsigned)((n + 63) / 64));
+    if (grid.y > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_colmajor_to_rowmajor, grid, dim3(256), 0, st, src, lds, n, d, dst);
+    return hipGetLastError();
+}
+
 int64_t sketch_slab_cols(int64_t npad, int64_t ncols, Prec prec) {
     const int64_t te = prec == Prec::F64 ? 8 : (prec == Prec::F32 ? 4 : 2);
     int64_t sc = ((int64_t)128 << 20) / (npad * te);  // ~128 MB of slab

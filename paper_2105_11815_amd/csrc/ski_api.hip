@@ -44,6 +44,7 @@ struct ski_handle_s {
     double cond_est = 0.0;
     // device buffers
     DevBuf colrows, colneg, bucket_ptr, src, keys, table, dbits, T0, SA;
+    DevBuf Arow;  // row-major copy of a column-major dense A
     DevBuf R, c, Rinv, RinvT, diag_add, tri_tmp, gemm_ws;
     DevBuf qr_part, qr_W, qr_T, qr_Y, qr_tau;
     DevBuf tkeys, tkeys_tmp, ttable, tp, tpay, ti, tv;
@@ -200,7 +201,7 @@ int ski_destroy(ski_handle h) {
     if (!h) return SKI_EINVAL;
     (void)hipDeviceSynchronize();
     DevBuf* all[] = {&h->colrows, &h->colneg, &h->bucket_ptr, &h->src, &h->keys, &h->table,
-                     &h->dbits, &h->T0, &h->SA, &h->R, &h->c, &h->Rinv, &h->RinvT,
+                     &h->dbits, &h->T0, &h->SA, &h->Arow, &h->R, &h->c, &h->Rinv, &h->RinvT,
                      &h->diag_add, &h->tri_tmp, &h->gemm_ws, &h->qr_part, &h->qr_W, &h->qr_T,
                      &h->qr_Y, &h->qr_tau, &h->tkeys, &h->tkeys_tmp, &h->ttable, &h->tp,
                      &h->tpay, &h->ti, &h->tv, &h->u, &h->t, &h->v, &h->h, &h->delta, &h->z,
@@ -259,16 +260,22 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
     if (d < 1 || n < d) return fail(h, SKI_EINVAL, "ski_sketch: need n >= d >= 1");
     if (n > ((int64_t)1 << 30)) return fail(h, SKI_EINVAL, "ski_sketch: n above 2^30 rows");
     if (k < 1 || ldb < k) return fail(h, SKI_EINVAL, "ski_sketch: need k >= 1 and ldb >= k");
-    if (A->kind != SKI_DENSE && A->kind != SKI_CSR)
+    if (A->kind != SKI_DENSE && A->kind != SKI_DENSE_COLMAJOR && A->kind != SKI_CSR)
         return fail(h, SKI_EINVAL, "ski_sketch: unknown matrix kind");
     if (A->kind == SKI_DENSE && (!A->a || A->lda < d))
         return fail(h, SKI_EINVAL, "ski_sketch: dense A needs a and lda >= d");
+    if (A->kind == SKI_DENSE_COLMAJOR && (!A->a || A->lda < n))
+        return fail(h, SKI_EINVAL, "ski_sketch: column-major A needs a and lda >= n");
+    if (A->kind == SKI_DENSE_COLMAJOR && n > (int64_t)64 * 65535)
+        return fail(h, SKI_EINVAL, "ski_sketch: column-major A above 4194240 rows");
+    // a column-major A is copied to row-major below; from here on it is dense
+    const int32_t akind = A->kind == SKI_DENSE_COLMAJOR ? (int32_t)SKI_DENSE : A->kind;
     if (A->kind == SKI_CSR && (!A->row_ptr || !A->col || !A->val || A->nnz < 0 ||
                                A->nnz >= ((int64_t)1 << 31)))
         return fail(h, SKI_EINVAL, "ski_sketch: CSR A needs row_ptr, col, val, nnz < 2^31");
     if (p->hadamard < 0 || p->hadamard > 2)
         return fail(h, SKI_EINVAL, "ski_sketch: hadamard must be 0, 1 or 2");
-    if (A->kind == SKI_CSR && p->hadamard)
+    if (akind == SKI_CSR && p->hadamard)
         return fail(h, SKI_EINVAL, "ski_sketch: the Hadamard transform is for dense A only");
     if (p->s < 1 || p->s > 32) return fail(h, SKI_EINVAL, "ski_sketch: need 1 <= s <= 32");
     if (p->qr_panel < SKI_QR_AUTO || p->qr_panel > SKI_QR_PIVOTED_HOUSEHOLDER)
@@ -284,7 +291,7 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
     if (!(p->tau_r >= 0) || !(p->tau_a >= 0) || p->it_max < 1)
         return fail(h, SKI_EINVAL, "ski_sketch: bad tolerances or it_max");
     int64_t m = p->m > 0 ? p->m : (int64_t)ceil(p->gamma * (double)d - 1e-9);
-    const bool had = (A->kind == SKI_DENSE) && p->hadamard;
+    const bool had = (akind == SKI_DENSE) && p->hadamard;
     const int64_t npad = had ? next_pow2(n) : n;
     if (m < d) return fail(h, SKI_EINVAL, "ski_sketch: need m >= d");
     if (m > npad) return fail(h, SKI_EINVAL, "ski_sketch: need m <= n (n' with Hadamard)");
@@ -299,7 +306,7 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
     // the sketch storage follows the QR precision: FP64 QR needs an FP64 sketch
     if (qprec == Prec::F64) sprec = Prec::F64;
 
-    h->kind = A->kind;
+    h->kind = akind;
     h->n = n;
     h->d = d;
     h->k = k;
@@ -313,6 +320,13 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
     h->qprec = qprec;
     h->A = A->a;
     h->lda = A->lda;
+    if (A->kind == SKI_DENSE_COLMAJOR) {
+        SKI_TRY(h, ensure(h->Arow, n * d * 8), "alloc");
+        SKI_TRY(h, launch_colmajor_to_rowmajor(A->a, A->lda, n, d, P<double>(h->Arow), st),
+                "transpose");
+        h->A = P<double>(h->Arow);
+        h->lda = d;
+    }
     h->rp = A->row_ptr;
     h->ci = A->col;
     h->va = A->val;
@@ -352,7 +366,7 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
 
     // the SA storage type for the gathers: FP64, or FP32 for the mixed forms
     const Prec gprec = qprec == Prec::F64 ? Prec::F64 : (sprec == Prec::F64 ? Prec::F32 : sprec);
-    if (A->kind == SKI_DENSE && had) {
+    if (akind == SKI_DENSE && had) {
         const size_t te = elem_bytes(gprec);
         SKI_TRY(h, ensure(h->dbits, ((npad + 255) / 256) * 32), "alloc");
         const int64_t sc = sketch_slab_cols(npad, ncols, gprec);
@@ -361,21 +375,21 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
         SKI_TRY(h, launch_dsign(npad, p->seed, P<uint32_t>(h->dbits), st), "dsign");
         const double scale = hscale / sqrt((double)npad);
         if (p->hadamard == 2)
-            SKI_TRY(h, launch_sketch_dht(A->a, A->lda, B, ldb, n, d, k, npad,
+            SKI_TRY(h, launch_sketch_dht(h->A, h->lda, B, ldb, n, d, k, npad,
                                          P<uint32_t>(h->dbits), P<double>(h->T0), sc,
                                          P<int32_t>(h->bucket_ptr), P<int32_t>(h->src), m, scale,
                                          P<double>(h->SA), st),
                     "sketch (Hartley)");
         else
-            SKI_TRY(h, launch_sketch_dense(A->a, A->lda, B, ldb, n, d, k, npad,
+            SKI_TRY(h, launch_sketch_dense(h->A, h->lda, B, ldb, n, d, k, npad,
                                            P<uint32_t>(h->dbits), h->T0.p, sc,
                                            P<int32_t>(h->bucket_ptr), P<int32_t>(h->src), m, scale,
                                            gprec, h->SA.p, st),
                     "sketch");
         prof_end(h, st);
-    } else if (A->kind == SKI_DENSE) {
+    } else if (akind == SKI_DENSE) {
         const double scale = hscale;
-        SKI_TRY(h, launch_gather_plain(A->a, A->lda, B, ldb, d, k, P<int32_t>(h->bucket_ptr),
+        SKI_TRY(h, launch_gather_plain(h->A, h->lda, B, ldb, d, k, P<int32_t>(h->bucket_ptr),
                                        P<int32_t>(h->src), m, scale,
                                        qprec == Prec::F64 ? Prec::F64 : Prec::F32, h->SA.p, st),
                 "gather");

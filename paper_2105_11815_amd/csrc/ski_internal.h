@@ -153,6 +153,9 @@ hipError_t launch_gather_plain(const double* A, int64_t lda, const double* B, in
                                int64_t d, int64_t k, const int32_t* bucket_ptr,
                                const int32_t* src, int64_t m, double scale, Prec prec, void* SA,
                                hipStream_t st);
+// dst (n x d row-major) = the column-major src (ld lds >= n); n <= 64 * 65535
+hipError_t launch_colmajor_to_rowmajor(const double* src, int64_t lds, int64_t n, int64_t d,
+                                       double* dst, hipStream_t st);
 hipError_t launch_gather_csr(const int64_t* row_ptr, const int32_t* col, const double* val,
                              const double* B, int64_t ldb, int64_t d, int64_t k,
                              const int32_t* bucket_ptr, const int32_t* src, int64_t m,

@@ -394,6 +394,45 @@ def test_repeat_runs_are_bitwise_identical(ski):
     assert outs[0][1] == outs[1][1]
 
 
+def test_column_major_input_matches_row_major(ski):
+    """A column-major A (SKI_DENSE_COLMAJOR: here a transposed view, n and d ragged against
+    the 64 x 64 transpose tiles) is copied to row-major once at ski_sketch; the sketch, the
+    iterations and x are then bit-identical to those of the row-major input."""
+    A, b = workloads.dense_coherent(n=5000, d=150, case=2)
+    outs = []
+    for layout in ("row", "col"):
+        At = dev(A)
+        if layout == "col":
+            At = At.t().contiguous().t()
+            assert At.stride() == (1, A.shape[0])
+        S = ski.Solver()
+        S.sketch(At, dev(b), gamma=1.7, s=3, seed=7, tau_r=1e-10).factor()
+        X, infos, rc = S.solve()
+        assert rc == 0
+        outs.append((X.cpu().numpy().copy(), infos[0]["iters"], S.get_SA().copy()))
+        S.close()
+    np.testing.assert_array_equal(outs[0][2], outs[1][2])
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    assert outs[0][1] == outs[1][1]
+
+
+def test_column_major_rejects_short_leading_dimension(ski):
+    import ctypes as C
+    from paper_2105_11815_amd import _lib as L
+    A = dev(np.ones((300, 20)))
+    b = dev(np.ones(300))
+    lib = L.load()
+    h = C.c_void_p()
+    assert lib.ski_create(C.byref(h)) == L.SKI_OK
+    M = L.SkiMatrix(n=300, d=20, kind=L.SKI_DENSE_COLMAJOR, a=A.data_ptr(), lda=299,
+                    row_ptr=None, col=None, val=None, nnz=0)
+    p = ski.params("dense")
+    rc = lib.ski_sketch(h, C.byref(M), C.c_void_p(b.data_ptr()), 1, 1, C.byref(p), None)
+    assert rc == L.SKI_EINVAL
+    assert b"lda >= n" in lib.ski_last_error(h)
+    lib.ski_destroy(h)
+
+
 # -------------------------------------------------------------------------- adjoint
 def test_adjoint_and_gradients(ski):
     n, d, k = 3000, 100, 4
