@@ -34,6 +34,13 @@ column set, and the quantities that parity compares (p, the residual, and the
 solution on a given column set) do not depend on which.  V_1 holds the first
 p pivots J, so x_s = V_1 R11^-1 Q_1^T S b, W = A V_1 R11^-1 = A_J R11^-1 and
 x = V_1 R11^-1 y vanishes outside J.
+
+Minimal-norm form (cod=True): the complete orthogonal decomposition with R_12 = 0
+that the factorisation remark lists and the minimal-norm guarantee (Section 3) needs.
+The truncated rows Rtop = [R11 R12] of the pivoted QR are factored as Rtop^T = Y L;
+then S A = Q_1 L^T V_1^T with V_1 = Pi Y orthonormal, and Algorithm 1 runs with
+P = V_1 L^-T.  range(P) = range((SA)^T) = range(A^T) under an embedding, so the LSQR
+solution is the minimal-norm least-squares solution.
 """
 
 import math
@@ -114,6 +121,52 @@ def solve_pivoted_with_factor(A, b, R11, c, J, tau_a=1e-8, tau_r=1e-6, it_max=10
     return x, rec
 
 
+def factor_cod(SA_aug, d, rcond):
+    """Step 2 as a complete orthogonal decomposition (the factorisation remark allows it;
+    R_12 = 0 is what the minimal-norm guarantee needs).
+
+    The column-pivoted QR S A Pi = Q R is truncated at p (as in factor_pivoted); its top
+    rows Rtop = [R11 R12] (p x d, full row rank) are factored as Rtop^T = Y L (a QR of the
+    d x p matrix, L upper triangular).  Then S A = Q_1 L^T (Pi Y)^T: V_1 = Pi Y has
+    orthonormal columns, the p x p factor is L^T and R_12 = 0.
+
+    Returns (L, V1 d x p, c = (Q_1^T S b) p x k, perm, p)."""
+    SA = np.asarray(SA_aug[:, :d], dtype=np.float64)
+    SB = np.asarray(SA_aug[:, d:], dtype=np.float64)
+    Q, R, perm = sla.qr(SA, mode="economic", pivoting=True)
+    p = rank_count(R, rcond)
+    c = Q[:, :p].T @ SB
+    if p == 0:
+        return np.zeros((0, 0)), np.zeros((d, 0)), c, np.asarray(perm, dtype=np.int64), 0
+    Y, L = np.linalg.qr(R[:p, :].T, mode="reduced")
+    V1 = np.zeros((d, p))
+    V1[np.asarray(perm)] = Y
+    return L, V1, c, np.asarray(perm, dtype=np.int64), p
+
+
+def solve_cod_with_factor(A, b, L, V1, c, tau_a=1e-8, tau_r=1e-6, it_max=10000):
+    """Steps 3-5 of Algorithm 1 with V_1 and R_11 = L^T from factor_cod:
+    P = V_1 L^-T, x_s = P c, LSQR on W = A P from y_0 = c, x = P (c + delta)."""
+    d = A.shape[1]
+    p = L.shape[0]
+    if p == 0:
+        r = np.asarray(b, dtype=np.float64)
+        return np.zeros(d), dict(iters=0, status=OK, rnorm=float(np.linalg.norm(r)),
+                                 arnorm=0.0, anorm=0.0, tc=0.0, xs=np.zeros(d))
+    Pm = lambda y: V1 @ sla.solve_triangular(L, y, lower=False, trans="T")   # V_1 L^-T y
+    PTm = lambda g: sla.solve_triangular(L, V1.T @ g, lower=False)          # L^-1 V_1^T g
+    xs = Pm(c)
+    r0 = b - A @ xs
+    if np.linalg.norm(r0) <= tau_a:
+        return xs, dict(iters=0, status=WEARLY, rnorm=float(np.linalg.norm(r0)), arnorm=0.0,
+                        anorm=0.0, tc=0.0, xs=xs)
+    delta, rec = lsqr_op(A, Pm, PTm, p, r0, tau_r, it_max)
+    x = Pm(c + delta)
+    rec["status"] = OK if rec["converged"] else WNOCONV
+    rec["xs"] = xs
+    return x, rec
+
+
 def perturbed(R, rcond_thres, perturb):
     """R with its diagonal moved away from zero when it looks singular."""
     dg = np.abs(np.diag(R))
@@ -134,10 +187,15 @@ def _matvecs(A):
 
 def lsqr_precond(A, R, r0, tau_r, it_max):
     """LSQR on min ||W delta - r0||, W = A R^-1.  Returns delta and a record."""
-    Amul, ATmul = _matvecs(A)
     Rs = lambda v: sla.solve_triangular(R, v, lower=False)           # R^-1 v
     RTs = lambda g: sla.solve_triangular(R, g, lower=False, trans="T")  # R^-T g
-    d = R.shape[0]
+    return lsqr_op(A, Rs, RTs, R.shape[0], r0, tau_r, it_max)
+
+
+def lsqr_op(A, Rs, RTs, d, r0, tau_r, it_max):
+    """LSQR (Paige and Saunders) on min ||W delta - r0|| with W = A P, P given by its
+    products Rs(v) = P v and RTs(g) = P^T g (P is d_A x d).  Returns delta (length d)."""
+    Amul, ATmul = _matvecs(A)
     delta = np.zeros(d)
     beta = float(np.linalg.norm(r0))
     rec = dict(iters=0, rnorm=beta, arnorm=0.0, anorm=0.0, tc=0.0, converged=True)
@@ -235,7 +293,15 @@ def solve(A, B, seed, sparse=None, **kw):
     X = np.zeros((d, B2.shape[1]))
     recs = []
     extra = {}
-    if p.get("pivoting"):
+    if p.get("cod"):
+        L, V1, c, perm, rank = factor_cod(out["SA_aug"], d, p["rcond"])
+        R = L
+        extra = dict(perm=perm, p=rank, V1=V1)
+        for j in range(B2.shape[1]):
+            X[:, j], rec = solve_cod_with_factor(A, B2[:, j], L, V1, c[:, j], p["tau_a"],
+                                                 p["tau_r"], p["it_max"])
+            recs.append(rec)
+    elif p.get("pivoting"):
         R, c, perm, rank, dg = factor_pivoted(out["SA_aug"], d, p["rcond"])
         R = perturbed(R, p["rcond_thres"], p["perturb"])
         J = perm[:rank]

@@ -25,6 +25,12 @@ def _sketch(A, b, seed, gamma=1.7, s=3):
     return sk.sketch_dense(A, b, m, s, seed)["SA_aug"]
 
 
+def _sketch_aug(A, b, seed, gamma=1.7, s=3):
+    d = A.shape[1]
+    m = lls.sketch_size(gamma, d)
+    return sk.sketch_dense(A, b, m, s, seed)["SA_aug"]
+
+
 def _svd_residual(A, b, rcond=1e-12):
     """Residual of the truncated-SVD solution (singular values below rcond sigma_1 cut,
     as in the paper's comparison of rank-deficient residuals)."""
@@ -124,3 +130,57 @@ def test_pivoted_path_equals_unpivoted_on_full_rank_input():
     np.testing.assert_allclose(X2, X1, rtol=1e-10, atol=1e-12 * np.abs(X1).max())
     xr = lls.lstsq_direct(A, b)
     np.testing.assert_allclose(X2[:, 0], xr, rtol=1e-10, atol=1e-12 * np.abs(xr).max())
+
+
+# ------------------------------------------------------------ minimal-norm form (COD)
+def test_cod_factor_structure():
+    """S A = Q_1 L^T V_1^T with V_1 orthonormal and spanning the row space of SA (R_12 = 0)."""
+    A, b, _ = workloads.rank_deficient(n=3000, d=120, rank=90, case=6)
+    SA_aug = _sketch_aug(A, b, seed=11)
+    L, V1, c, perm, p = lls.factor_cod(SA_aug, 120, 1e-12)
+    assert p == 90
+    np.testing.assert_allclose(V1.T @ V1, np.eye(p), rtol=0, atol=1e-13)
+    SA = SA_aug[:, :120]
+    # every row of SA lies in range(V_1): SA = (SA V_1) V_1^T
+    np.testing.assert_allclose(SA @ V1 @ V1.T, SA, rtol=0, atol=1e-12 * np.abs(SA).max())
+    # (SA V_1)^T (SA V_1) = L L^T (= R_11^T R_11 with R_11 = L^T)
+    G = (SA @ V1).T @ (SA @ V1)
+    np.testing.assert_allclose(L @ L.T, G, rtol=0, atol=1e-12 * np.abs(G).max())
+
+
+def test_cod_gives_the_minimal_norm_solution():
+    """The minimal-norm guarantee: with R_12 = 0 the solution is pinv(A) b, which LAPACK's
+    SVD-based solver returns (singular values below rcond sigma_1 cut)."""
+    A, b, _ = workloads.rank_deficient(n=3000, d=120, rank=90, case=7)
+    X, info = lls.solve(A, b, seed=12, cod=True, tau_r=1e-14, it_max=500)
+    assert info["status"] == lls.OK and info["p"] == 90
+    x = X[:, 0]
+    xmin = sla.lstsq(A, b, cond=1e-12, lapack_driver="gelsd")[0]
+    np.testing.assert_allclose(x, xmin, rtol=0, atol=1e-10 * np.abs(xmin).max())
+    # shorter than the basic solution of the pivoted form, with the same residual
+    Xb, ib = lls.solve(A, b, seed=12, pivoting=True, tau_r=1e-14, it_max=500)
+    assert np.linalg.norm(x) < np.linalg.norm(Xb[:, 0])
+    np.testing.assert_allclose(b - A @ x, b - A @ Xb[:, 0], rtol=0, atol=1e-10 * np.linalg.norm(b))
+
+
+def test_cod_closed_form_on_copied_columns():
+    """[a, a, 0]: the minimal-norm solution splits a^T b / a^T a equally between the copies."""
+    rng = np.random.default_rng(5)
+    a = rng.standard_normal(400)
+    b = rng.standard_normal(400)
+    A = np.stack([a, a, np.zeros(400)], axis=1)
+    X, info = lls.solve(A, b, seed=3, cod=True, m=40, tau_r=1e-14)
+    assert info["p"] == 1
+    t = a @ b / (a @ a)
+    np.testing.assert_allclose(X[:, 0], [t / 2, t / 2, 0.0], rtol=1e-12, atol=1e-15)
+
+
+def test_cod_equals_unpivoted_on_full_rank_input():
+    rng = np.random.default_rng(9)
+    A = rng.standard_normal((2000, 60))
+    A[:400] *= 1e3
+    b = rng.standard_normal(2000)
+    X1, _ = lls.solve(A, b, seed=4, tau_r=1e-14, it_max=300)
+    X2, i2 = lls.solve(A, b, seed=4, cod=True, tau_r=1e-14, it_max=300)
+    assert i2["p"] == 60
+    np.testing.assert_allclose(X2, X1, rtol=1e-10, atol=1e-12 * np.abs(X1).max())
