@@ -61,7 +61,8 @@ enum ski_qr_panel {
     SKI_QR_AUTO = 0,
     SKI_QR_HOUSEHOLDER = 1,
     SKI_QR_PIVOTED = 2,
-    SKI_QR_PIVOTED_HOUSEHOLDER = 3
+    SKI_QR_PIVOTED_HOUSEHOLDER = 3,
+    SKI_QR_PIVOTED_COD = 4
 };
 
 /* The data matrix.  Dense: `a` (n x d, row-major, leading dimension lda >= d).
@@ -118,6 +119,14 @@ typedef struct {
  *                factored by Householder columns; one host synchronisation per panel),
  *                and the sketch is updated from R_12.  SKI_QR_PIVOTED_HOUSEHOLDER: the
  *                same with Householder-column panels only (no per-panel synchronisation).
+ *                SKI_QR_PIVOTED_COD: the minimal-norm form (the complete orthogonal
+ *                decomposition that the factorisation remark allows, with R_12 = 0): the
+ *                SKI_QR_PIVOTED factorisation truncated at p, then a QR of the transposed
+ *                top rows Rtop^T = Y L (d x p, Rtop = [R_11 R_12]); S A = Q_1 L^T V_1^T
+ *                with V_1 = Pi Y, and Steps 3-5 use P = V_1 L^-T = Pi Rtop^T (L^T L)^-1,
+ *                held as an explicit d x p matrix.  range(P) = range(A^T) under an
+ *                embedding, so x is the minimal-norm least-squares solution (Section 3's
+ *                minimal-norm guarantee).  The diagonal perturbation does not apply.
  *                The rank p is the number of leading diagonal entries with
  *                |r_qq| >= rcond |r_11| (with rcond = 0: the leading non-zero ones);
  *                R_11 is the leading p x p block, V_1 the first p pivots J, and Steps
@@ -212,7 +221,8 @@ const char* ski_last_error(ski_handle h);
  *   dsign: the diagonal of D as int8 (+1 / -1), n' entries (dense with Hadamard only).
  *   SA: the sketch m x (d+k) row-major, converted to double.
  *   R: d x d row-major (upper triangle, zeros below); c: d x k; Rinv: d x d (after a
- *      pivoted factor: R of the permuted sketch S A P, and Rinv = R_11^-1, p x p). */
+ *      pivoted factor: R of the permuted sketch S A P, and Rinv = R_11^-1, p x p; after
+ *      SKI_QR_PIVOTED_COD: Rinv = L^-1, p x p, for Rtop^T = Y L). */
 /* Kernel timing for measurement (not needed to solve).  ski_set_profiling(h, 1) makes the
  * library record a HIP event pair on the launch stream around every launch of the kernel
  * classes below (clearing earlier totals); ski_get_profile returns, per class, the summed

@@ -15,7 +15,7 @@ SKI_EINVAL, SKI_ENOMEM, SKI_EDEVICE, SKI_ERANK, SKI_ESTATE = -1, -2, -3, -4, -5
 SKI_DENSE, SKI_DENSE_COLMAJOR, SKI_CSR = 0, 1, 2
 SKI_FP64, SKI_FP32, SKI_BF16 = 0, 1, 2
 SKI_OP_LLS, SKI_OP_NORMAL = 0, 1
-SKI_QR_AUTO, SKI_QR_HOUSEHOLDER, SKI_QR_PIVOTED, SKI_QR_PIVOTED_HOUSEHOLDER = 0, 1, 2, 3
+SKI_QR_AUTO, SKI_QR_HOUSEHOLDER, SKI_QR_PIVOTED, SKI_QR_PIVOTED_HOUSEHOLDER, SKI_QR_PIVOTED_COD = 0, 1, 2, 3, 4
 SKI_HASH, SKI_HASH_VARIANT, SKI_SAMPLE_ROWS = 0, 1, 2
 
 STATUS_NAMES = {0: "OK", 1: "WNOCONV", 2: "WEARLY", -1: "EINVAL", -2: "ENOMEM",

@@ -16,7 +16,8 @@ from . import _lib as L
 _PREC = {"fp64": L.SKI_FP64, "fp32": L.SKI_FP32, "bf16": L.SKI_BF16}
 _HASH = {"hash": L.SKI_HASH, "variant": L.SKI_HASH_VARIANT, "sample": L.SKI_SAMPLE_ROWS}
 _PANEL = {"auto": L.SKI_QR_AUTO, "householder": L.SKI_QR_HOUSEHOLDER,
-          "pivoted": L.SKI_QR_PIVOTED, "pivoted_householder": L.SKI_QR_PIVOTED_HOUSEHOLDER}
+          "pivoted": L.SKI_QR_PIVOTED, "pivoted_householder": L.SKI_QR_PIVOTED_HOUSEHOLDER,
+          "cod": L.SKI_QR_PIVOTED_COD}
 
 
 class SkiError(RuntimeError):

@@ -55,6 +55,8 @@ struct ski_handle_s {
     int64_t rank = 0;      // p: columns kept (d without pivoting)
     int panels_cqr = 0;    // pivoted factor: panels factored by CholeskyQR2
     bool pivoted = false;  // the last ski_factor pivoted
+    bool cod = false;      // ... and formed the minimal-norm P (d x p in cod_m)
+    DevBuf cod_a, cod_m;   // Rtop^T and work, then P = Pi Rtop^T (L^T L)^-1
     hipStream_t st2 = nullptr;           // second stream of the QR's look-ahead
     hipEvent_t qev[4] = {};
     hipStream_t st3 = nullptr;           // third stream: R^-1 formed during the QR
@@ -207,7 +209,7 @@ int ski_destroy(ski_handle h) {
                      &h->tpay, &h->ti, &h->tv, &h->u, &h->t, &h->v, &h->h, &h->delta, &h->z,
                      &h->wp, &h->g, &h->gpart, &h->upart, &h->y, &h->st, &h->cg_r,
                      &h->cg_p, &h->cg_q, &h->t2, &h->dtmp, &h->gemm_ws2, &h->gemm_ws3,
-                     &h->piv_part, &h->pivd, &h->Rc, &h->ptmp};
+                     &h->piv_part, &h->pivd, &h->Rc, &h->ptmp, &h->cod_a, &h->cod_m};
     for (DevBuf* b : all) release(*b);
     if (h->ev_ok)
         for (auto& e : h->ev) (void)hipEventDestroy(e);
@@ -278,7 +280,7 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
     if (akind == SKI_CSR && p->hadamard)
         return fail(h, SKI_EINVAL, "ski_sketch: the Hadamard transform is for dense A only");
     if (p->s < 1 || p->s > 32) return fail(h, SKI_EINVAL, "ski_sketch: need 1 <= s <= 32");
-    if (p->qr_panel < SKI_QR_AUTO || p->qr_panel > SKI_QR_PIVOTED_HOUSEHOLDER)
+    if (p->qr_panel < SKI_QR_AUTO || p->qr_panel > SKI_QR_PIVOTED_COD)
         return fail(h, SKI_EINVAL, "ski_sketch: unknown qr_panel");
     if (p->hash_kind < SKI_HASH || p->hash_kind > SKI_SAMPLE_ROWS)
         return fail(h, SKI_EINVAL, "ski_sketch: unknown hash_kind");
@@ -419,6 +421,68 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
     return SKI_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// The minimal-norm form of Step 2, after the pivoted factorisation truncated at p:
+//   Rtop^T (d x p) = the transpose of R's first p rows (pivoted column order);
+//   Rtop^T = Y L by the same QR (CholeskyQR2 panels, column-by-column if a panel fails),
+//   L^-1 formed during it on the third stream, L^-T alongside;
+//   P = Pi (Rtop^T L^-1) L^-T, rows scattered by the pivots, into cod_m (d x p).
+// Rinv / RinvT then hold L^-1 / L^-T (p x p).  Uses the QR workspace of the sketch (the
+// d x p factorisation needs less).
+int cod_factor(ski_handle h, QrWs& ws, int64_t p, int* hflag, GemmWs& gw, hipStream_t st) {
+    const int64_t d = h->d;
+    SKI_TRY(h, ensure(h->cod_a, d * p * 8), "alloc");
+    SKI_TRY(h, ensure(h->cod_m, d * p * 8), "alloc");
+    double* Rt = P<double>(h->cod_a);
+    double* Mw = P<double>(h->cod_m);
+    // R (d x d row-major): its first p rows, read as a d x p column-major matrix (ld d)
+    SKI_TRY(h, launch_colmajor_to_rowmajor(P<double>(h->R), d, d, p, Rt, st), "transpose");
+    QrWs w2;
+    qr_ws_carve(Prec::F64, h->qr_part.p, d, p, w2);
+    w2.g = ws.g;
+    w2.g2 = ws.g2;
+    w2.st2 = ws.st2;
+    w2.evF[0] = ws.evF[0];
+    w2.evF[1] = ws.evF[1];
+    w2.evE[0] = ws.evE[0];
+    w2.evE[1] = ws.evE[1];
+    SKI_TRY(h, ensure(h->gemm_ws3, rinv_ws_bytes(p)), "alloc");
+    w2.Xinv = P<double>(h->Rinv);
+    w2.Zinv = P<double>(h->tri_tmp);
+    w2.g3.part = h->gemm_ws3.p;
+    w2.g3.bytes = h->gemm_ws3.bytes;
+    w2.st3 = h->st3;
+    w2.evP = h->rev[0];
+    w2.evI = h->rev[1];
+    for (bool cqr = true;;) {
+        w2.cqr_panels = cqr;
+        SKI_TRY(h, qr_factor(Prec::F64, Rt, d, p, p, w2, st), "qr of Rtop^T");
+        if (!cqr) break;
+        SKI_TRY(h, hipMemcpyAsync(hflag, w2.cqr.flag, sizeof(int), hipMemcpyDeviceToHost, st),
+                "flag copy");
+        SKI_TRY(h, hipStreamSynchronize(st), "sync");
+        if (*hflag == 0) break;
+        cqr = false;  // a panel too ill-conditioned for CholeskyQR2: column by column
+    }
+    double* Li = P<double>(h->Rinv);
+    double* LiT = P<double>(h->RinvT);
+    SKI_TRY(h, rinv_finish((const double*)w2.Ac, d, p, Li, LiT, st), "L inverse");
+    // Rt still holds Rtop^T (the QR copied it into its working copy)
+    SKI_TRY(h, gemm_f64(false, false, d, p, p, 1.0, Rt, p, Li, p, 0.0, Mw, p, gw, st, 0,
+                        GEMM_B_UPPER),
+            "Rtop^T L^-1");
+    SKI_TRY(h, gemm_f64(false, false, d, p, p, 1.0, Mw, p, LiT, p, 0.0, Rt, p, gw, st), "(.) L^-T");
+    SKI_TRY(h, launch_permute_rows(Rt, p, Mw, p, P<int32_t>(h->pivd), d, p, true, st), "Pi");
+    return SKI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int ski_factor(ski_handle h, void* stream) {
     if (!h) return SKI_EINVAL;
     if (!h->sketched) return fail(h, SKI_ESTATE, "ski_factor: call ski_sketch first");
@@ -466,7 +530,10 @@ int ski_factor(ski_handle h, void* stream) {
         h->hdiag_n = d;
     }
     int* hflag = (int*)(h->hdiag + 2 * d);
-    const bool piv = h->p.qr_panel == SKI_QR_PIVOTED || h->p.qr_panel == SKI_QR_PIVOTED_HOUSEHOLDER;
+    const bool cod = h->p.qr_panel == SKI_QR_PIVOTED_COD;
+    const bool piv = h->p.qr_panel == SKI_QR_PIVOTED ||
+                     h->p.qr_panel == SKI_QR_PIVOTED_HOUSEHOLDER || cod;
+    h->cod = false;
     h->pivoted = false;
     h->rank = d;
     if (piv) {
@@ -477,7 +544,8 @@ int ski_factor(ski_handle h, void* stream) {
         piv_ws_carve(h->piv_part.p, m, d, pw);
         prof_begin(h, PC_QR_PIV, st);
         SKI_TRY(h, qr_factor_pivoted((const double*)h->SA.p, m, ncols, d, ws, pw, h->p.seed,
-                                     h->p.qr_panel == SKI_QR_PIVOTED, hflag, &h->panels_cqr, st),
+                                     h->p.qr_panel != SKI_QR_PIVOTED_HOUSEHOLDER, hflag,
+                                     &h->panels_cqr, st),
                 "pivoted qr");
         prof_end(h, st);
         SKI_TRY(h, launch_extract_Rc(h->qprec, ws, m, d, k, P<double>(h->R), P<double>(h->c), st),
@@ -578,6 +646,13 @@ int ski_factor(ski_handle h, void* stream) {
                 "R11 copy");
         R11 = P<double>(h->Rc);
     }
+    if (cod && dp > 0) {
+        // the minimal-norm P = Pi Rtop^T (L^T L)^-1 from the QR Rtop^T = Y L of the top p rows
+        // of R (Rtop = [R_11 R_12], pivoted column order); L^-1 is formed during that QR
+        const int rc = cod_factor(h, ws, dp, hflag, gw, st);
+        if (rc != SKI_OK) return rc;
+        h->cod = true;
+    } else {
     prof_begin(h, PC_TRTRI, st);
     if (ws.Xinv && !pert) {
         // the blocks of R_h^-1 are done (the QR's stream waited for them): R^-1 = R_h^-1 D
@@ -590,6 +665,7 @@ int ski_factor(ski_handle h, void* stream) {
                 "R inverse");
     }
     prof_end(h, st);
+    }
     h->pivoted = piv;
     if (h->ev_ok) (void)hipEventRecord(h->ev[3], st);
     SKI_TRY(h, hipStreamSynchronize(st), "sync");
@@ -653,6 +729,18 @@ hipError_t apply_Rinv(ski_handle h, const double* Mtx, bool upper, const double*
                       double s, const int32_t* done, GemmWs& gw, hipStream_t st) {
     const int64_t dp = h->rank;
     if (dp <= 0) return hipSuccess;
+    if (h->cod) {
+        // P = cod_m (d x p): upper: y (d x k) = s P x (p x k); lower: y (p x k) = s P^T x
+        const double* Pm = (const double*)h->cod_m.p;
+        const int64_t d = h->d;
+        if (upper)
+            return gemm_ts_eligible(k)
+                       ? gemm_ts_f64(false, d, k, dp, s, Pm, dp, x, k, 0.0, y, k, gw, st)
+                       : gemm_f64(false, false, d, k, dp, s, Pm, dp, x, k, 0.0, y, k, gw, st);
+        return gemm_ts_eligible(k)
+                   ? gemm_ts_f64(true, dp, k, d, s, Pm, dp, x, k, 0.0, y, k, gw, st)
+                   : gemm_f64(true, false, dp, k, d, s, Pm, dp, x, k, 0.0, y, k, gw, st);
+    }
     const int32_t* perm = h->pivoted ? (const int32_t*)h->pivd.p : nullptr;
     if (k == 1) return launch_tri_gemv(Mtx, dp, upper, x, 1, y, 1, s, done, st, perm);
     if (!perm) return tri_products(Mtx, dp, upper, x, y, k, k, s, gw, st);
@@ -663,6 +751,15 @@ hipError_t apply_Rinv(ski_handle h, const double* Mtx, bool upper, const double*
     }
     SKI_HIP(launch_permute_rows(x, k, t, k, perm, dp, k, false, st));
     return tri_products(Mtx, dp, upper, t, y, k, k, s, gw, st);
+}
+
+// out (d x k, ld ldo) = P y for the minimal-norm P = cod_m (d x p), y p x k (ld k)
+hipError_t apply_P_out(ski_handle h, const double* y, double* out, int64_t ldo, int k,
+                       GemmWs& gw, hipStream_t st) {
+    const double* Pm = (const double*)h->cod_m.p;
+    const int64_t d = h->d, p = h->rank;
+    if (gemm_ts_eligible(k)) return gemm_ts_f64(false, d, k, p, 1.0, Pm, p, y, k, 0.0, out, ldo, gw, st);
+    return gemm_f64(false, false, d, k, p, 1.0, Pm, p, y, k, 0.0, out, ldo, gw, st);
 }
 
 // Convergence status read back with a one-iteration lag: after iteration i the all-done
@@ -861,7 +958,10 @@ int solve_lls(ski_handle h, const double* B, int k, int64_t ldb, double* X, int6
     if (out != SKI_OK) return out;
     // x = R^-1 (c + delta); with pivoting x = V_1 R_11^-1 (c + delta), zero elsewhere
     SKI_TRY(h, launch_final_y(S, dp, k, c, dl, y, st), "final y");
-    if (h->pivoted) {
+    if (h->cod) {
+        // x = P (c + delta), P = cod_m (d x p)
+        if (dp > 0) SKI_TRY(h, apply_P_out(h, y, X, ldx, k, gw, st), "x");
+    } else if (h->pivoted) {
         SKI_TRY(h, launch_fill_rows(X, d, k, ldx, 0.0, st), "zero x");
         if (k == 1) {
             SKI_TRY(h, launch_tri_gemv(Rinv, dp, true, y, 1, X, ldx, 1.0, nullptr, st,
@@ -938,7 +1038,9 @@ int solve_normal(ski_handle h, const double* G, int k, int64_t ldg, double* Z, i
     }
     lf.release();
     if (out != SKI_OK) return out;
-    if (h->pivoted) {
+    if (h->cod) {
+        if (dp > 0) SKI_TRY(h, apply_P_out(h, y, Z, ldz, k, gw, st), "z");
+    } else if (h->pivoted) {
         SKI_TRY(h, launch_fill_rows(Z, d, k, ldz, 0.0, st), "zero Z");
         if (dp > 0) {
             SKI_TRY(h, tri_products(Rinv, dp, true, y, P<double>(h->ptmp), k, k, 1.0, gw, st),

@@ -13,6 +13,7 @@ import sys
 
 import numpy as np
 import pytest
+import scipy.linalg as sla
 import scipy.sparse as sp
 
 import workloads
@@ -245,5 +246,97 @@ def test_full_size_rankdef_optimality(ski):
     _say(f"  iters {infos[0]['iters']} certificate {cert:.2e} cond_est {infos[0]['cond_est']:.2e}")
     assert cert <= 1e-12
     assert infos[0]["cond_est"] < 1e6
+    del At, bt
+    torch.cuda.empty_cache()
+
+
+# ------------------------------------------------------------ minimal-norm form (COD)
+COD_CASES = [(3000, 120, 90, 6), (6000, 700, 600, 7), (4000, 333, 333, 9)]
+
+
+@pytest.mark.parametrize("n,d,r,case", COD_CASES)
+def test_cod_gives_the_minimal_norm_solution(ski, n, d, r, case):
+    """qr_panel = cod: x is the minimal-norm least-squares solution (Section 3's guarantee
+    with R_12 = 0), against LAPACK's SVD-based solver (a plain definition, independent of
+    the factorisation) and against the oracle's COD form on the same inputs."""
+    _say(f"cod n={n} d={d} rank={r} case={case}")
+    A, b, _ = workloads.rank_deficient(n, d, r, case=case)
+    m = lls.sketch_size(1.7, d)
+    seed = 700 + case
+    S = ski.Solver()
+    S.sketch(dev(A), dev(b), m=m, s=3, seed=seed, hadamard=True, qr_panel="cod",
+             tau_r=1e-14, it_max=500)
+    S.factor()
+    X, infos, rc = S.solve()
+    perm, p = S.get_pivots()
+    S.close()
+    assert rc == 0 and p == r
+    x = X[:, 0].cpu().numpy()
+    xmin = sla.lstsq(A, b, cond=1e-12, lapack_driver="gelsd")[0]
+    err = np.abs(x - xmin).max() / np.abs(xmin).max()
+    _say(f"  iters {infos[0]['iters']} max rel err vs minimal-norm {err:.2e}")
+    assert err <= TOL_X
+    Xo, io = lls.solve(A, b, seed, cod=True, m=m, s=3, tau_r=1e-14, it_max=500)
+    assert io["p"] == r
+    assert np.abs(x - Xo[:, 0]).max() <= TOL_X * np.abs(xmin).max()
+
+
+def test_cod_multiple_rhs(ski):
+    _say("cod, 3 right-hand sides, 4000 x 300 rank 250")
+    A, _, _ = workloads.rank_deficient(4000, 300, 250, case=10)
+    rng = np.random.default_rng(12)
+    B = rng.standard_normal((4000, 3))
+    S = ski.Solver()
+    S.sketch(dev(A), dev(B), s=3, seed=21, qr_panel="cod", tau_r=1e-14, it_max=400)
+    S.factor()
+    X, infos, rc = S.solve()
+    S.close()
+    assert rc == 0
+    X = X.cpu().numpy()
+    Xmin = sla.lstsq(A, B, cond=1e-12, lapack_driver="gelsd")[0]
+    for j in range(3):
+        assert np.abs(X[:, j] - Xmin[:, j]).max() <= TOL_X * np.abs(Xmin[:, j]).max()
+
+
+def test_full_size_cod_minimal_norm_properties(ski):
+    """The 50000 x 4000 rank-3500 workload with qr_panel = cod: the optimality certificate,
+    and the conditions that single out the minimal-norm solution among all least-squares
+    solutions on this input's structure: x_j = 0 on every zero column (e_j spans a null
+    direction) and x_i = x_j for every exact copy a_j = a_i (e_i - e_j is a null direction),
+    which the basic solution of the pivoted form violates."""
+    c = workloads.CASES["rankdef"]
+    _say(f"full-size cod {c['n']}x{c['d']} rank {c['rank']}")
+    A, b, ind = workloads.rank_deficient(n=c["n"], d=c["d"], rank=c["rank"], case=c["case"])
+    d = c["d"]
+    zero = np.flatnonzero(~A.any(axis=0))
+    # exact copies of an independent column, matched on their first rows
+    key = {tuple(A[:4, i]): i for i in ind}
+    dep = np.setdiff1d(np.arange(d), ind)
+    copies = [(key[tuple(A[:4, j])], j) for j in dep
+              if j not in set(zero) and tuple(A[:4, j]) in key
+              and np.array_equal(A[:, key[tuple(A[:4, j])]], A[:, j])]
+    assert len(zero) > 0 and len(copies) > 0
+    At, bt = dev(A), dev(b)
+    del A
+    S = ski.Solver()
+    S.sketch(At, bt, gamma=c["gamma"], m=c["m"], s=c["s"], seed=2006, hadamard=True,
+             qr_panel="cod", tau_r=1e-14, it_max=400)
+    S.factor()
+    X, infos, rc = S.solve()
+    perm, p = S.get_pivots()
+    S.close()
+    assert rc == 0 and p == c["rank"]
+    x = X[:, 0]
+    r = bt - At @ x
+    cert = float((At.T @ r).norm() / (At.norm() * r.norm()))
+    xh = x.cpu().numpy()
+    scale = np.abs(xh).max()
+    zmax = np.abs(xh[zero]).max() / scale
+    cmax = max(abs(xh[i] - xh[j]) for i, j in copies) / scale
+    _say(f"  iters {infos[0]['iters']} certificate {cert:.2e} zero cols {zmax:.1e} "
+         f"copies {cmax:.1e} ({len(copies)} pairs)")
+    assert cert <= 1e-12
+    assert zmax <= 1e-12
+    assert cmax <= 1e-10
     del At, bt
     torch.cuda.empty_cache()
