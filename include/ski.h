@@ -125,7 +125,7 @@ typedef struct {
  *                top rows Rtop^T = Y L (d x p, Rtop = [R_11 R_12]); S A = Q_1 L^T V_1^T
  *                with V_1 = Pi Y, and Steps 3-5 use P = V_1 L^-T = Pi Rtop^T (L^T L)^-1,
  *                held as an explicit d x p matrix.  range(P) = range(A^T) under an
- *                embedding, so x is the minimal-norm least-squares solution (Section 3's
+ *                embedding, so x is the minimal-norm least-squares solution (Section 5's
  *                minimal-norm guarantee).  The diagonal perturbation does not apply.
  *                The rank p is the number of leading diagonal entries with
  *                |r_qq| >= rcond |r_11| (with rcond = 0: the leading non-zero ones);

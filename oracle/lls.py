@@ -36,7 +36,8 @@ p pivots J, so x_s = V_1 R11^-1 Q_1^T S b, W = A V_1 R11^-1 = A_J R11^-1 and
 x = V_1 R11^-1 y vanishes outside J.
 
 Minimal-norm form (cod=True): the complete orthogonal decomposition with R_12 = 0
-that the factorisation remark lists and the minimal-norm guarantee (Section 3) needs.
+that the factorisation remark lists and the minimal-norm guarantee of Section 5 (the
+theorem on the minimal Euclidean norm solution) needs.
 The truncated rows Rtop = [R11 R12] of the pivoted QR are factored as Rtop^T = Y L;
 then S A = Q_1 L^T V_1^T with V_1 = Pi Y orthonormal, and Algorithm 1 runs with
 P = V_1 L^-T.  range(P) = range((SA)^T) = range(A^T) under an embedding, so the LSQR

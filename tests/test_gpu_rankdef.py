@@ -256,7 +256,7 @@ COD_CASES = [(3000, 120, 90, 6), (6000, 700, 600, 7), (4000, 333, 333, 9)]
 
 @pytest.mark.parametrize("n,d,r,case", COD_CASES)
 def test_cod_gives_the_minimal_norm_solution(ski, n, d, r, case):
-    """qr_panel = cod: x is the minimal-norm least-squares solution (Section 3's guarantee
+    """qr_panel = cod: x is the minimal-norm least-squares solution (Section 5's guarantee
     with R_12 = 0), against LAPACK's SVD-based solver (a plain definition, independent of
     the factorisation) and against the oracle's COD form on the same inputs."""
     _say(f"cod n={n} d={d} rank={r} case={case}")
