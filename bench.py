@@ -171,8 +171,7 @@ def sparse_run(P, torch):
             "ms_factor": round(float(info["ms_factor"]), 3),
             "ms_solve": round(float(info["ms_solve"]), 3),
             "kernel_ms": {k: {"ms_total": round(v[0], 3), "launches": v[1]}
-                          for k, v in prof.items() if v[1]},
-            "minimal_norm_cod": cod}
+                          for k, v in prof.items() if v[1]}}
 
 
 def rankdef_run(P, torch):

@@ -315,7 +315,13 @@ __global__ __launch_bounds__(256) void k_reduce_pass(const double* __restrict__ 
 
 // ---------------------------------------------------------------------------
 // CSR products (k right-hand sides, vectors row-major with leading dimension k)
-// u[i] = (A z)[i] - coef_j u[i]; eight lanes per row; squared-norm partial per workgroup
+// u[i] = (A z)[i] - coef_j u[i] for the 32 rows of a workgroup; squared-norm partial per
+// workgroup.  The rows' nonzeros are contiguous, so all 256 threads stream them in chunks of
+// SP_CH (eight loads per thread issued together, then the gathers of z) and leave the
+// products in LDS; then lane l of a row's eight adds the row's products l, l + 8, ... in
+// order.  A long row (the power-law workloads reach 500 entries) thus costs a few LDS reads
+// per lane instead of a chain of dependent global loads that holds up its workgroup.
+constexpr int SP_CH = 2048;
 __global__ __launch_bounds__(256) void k_spmv_csr(const int64_t* __restrict__ rp,
                                                   const int32_t* __restrict__ ci,
                                                   const double* __restrict__ va, int64_t n, int k,
@@ -323,16 +329,54 @@ __global__ __launch_bounds__(256) void k_spmv_csr(const int64_t* __restrict__ rp
                                                   double* __restrict__ u,
                                                   const LsqrState* __restrict__ stt,
                                                   int use_coef_m1, double* __restrict__ upart) {
+    __shared__ double prod[SP_CH];
     __shared__ double red[32];
-    const int grp = threadIdx.x >> 3, gl = threadIdx.x & 7;
-    const int64_t i = (int64_t)blockIdx.x * 32 + grp;
+    constexpr int PT = SP_CH / 256;
+    const int t = threadIdx.x, grp = t >> 3, gl = t & 7;
+    const int64_t r0 = (int64_t)blockIdx.x * 32;
+    const int64_t i = r0 + grp;
+    const int64_t rl = r0 + 32 < n ? r0 + 32 : n;
+    const int64_t e0 = rp[r0], e1 = rp[rl];                // the workgroup's nonzeros
+    const int64_t rb = i < n ? rp[i] : e1, re = i < n ? rp[i + 1] : e1;  // this row's
     for (int j = 0; j < k; ++j) {
         const bool act = !stt[j].done;
         double sq = 0.0;
         if (act) {
             double acc = 0.0;
-            if (i < n)
-                for (int64_t e = rp[i] + gl; e < rp[i + 1]; e += 8) acc += va[e] * z[(int64_t)ci[e] * k + j];
+            for (int64_t c0 = e0; c0 < e1; c0 += SP_CH) {
+                const int64_t c1 = c0 + SP_CH < e1 ? c0 + SP_CH : e1;
+                int cv[PT];
+                double vv[PT], zv[PT];
+#pragma unroll
+                for (int q = 0; q < PT; ++q) {
+                    const int64_t e = c0 + t + 256 * q;
+                    const int64_t ec = e < c1 ? e : c1 - 1;
+                    cv[q] = ci[ec];
+                    vv[q] = va[ec];
+                }
+                // keep the index arithmetic below from being interleaved with the loads
+                // (each use would wait for its own load)
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int q = 0; q < PT; ++q) zv[q] = z[(int64_t)cv[q] * k + j];
+#pragma unroll
+                for (int q = 0; q < PT; ++q) prod[t + 256 * q] = vv[q] * zv[q];
+                __syncthreads();
+                // this lane's entries rb + gl + 8s that lie in [c0, c1), in increasing order
+                const int64_t lo = rb > c0 ? rb : c0, hi = re < c1 ? re : c1;
+                int64_t e = rb + gl;
+                if (e < lo) e += (lo - e + 7) / 8 * 8;
+                for (; e + 24 < hi; e += 32) {
+                    const double a0 = prod[e - c0], a1 = prod[e + 8 - c0];
+                    const double a2 = prod[e + 16 - c0], a3 = prod[e + 24 - c0];
+                    acc += a0;
+                    acc += a1;
+                    acc += a2;
+                    acc += a3;
+                }
+                for (; e < hi; e += 8) acc += prod[e - c0];
+                __syncthreads();
+            }
             acc += __shfl_xor(acc, 1, 64);
             acc += __shfl_xor(acc, 2, 64);
             acc += __shfl_xor(acc, 4, 64);

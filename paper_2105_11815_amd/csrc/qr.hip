@@ -664,20 +664,14 @@ __global__ __launch_bounds__(256) void k_extract_Rc(const T* __restrict__ Ac, in
 
 }  // namespace
 
-size_t qr_ws_bytes(Prec prec, int64_t m, int64_t ncols, size_t* gemm_bytes) {
-    const size_t e = prec == Prec::F64 ? 8 : 4;
-    *gemm_bytes = gemm_ws_bytes(2 * NBP, NBP, m, e);
-    const size_t pad = 16 * 256;
-    const size_t cqr = (size_t)NBP * m + ((size_t)cqr_num_chunks(m) + 7) * NBP * NBP;
-    return ((size_t)m * ncols + 4 * (size_t)NBP * m + 3 * (size_t)ncols * NBP +
-            4 * NBP * NBP + NBL * NBL + (size_t)ncols + cqr) * e + 14 * 256 + pad;
-}
+namespace {
 
-void qr_ws_carve(Prec prec, void* base, int64_t m, int64_t ncols, QrWs& ws) {
+// the workspace's layout from a base address (each piece 256-byte aligned); returns the end
+uintptr_t qr_ws_layout(Prec prec, uintptr_t base, int64_t m, int64_t ncols, QrWs& ws) {
     const size_t e = prec == Prec::F64 ? 8 : 4;
-    char* p = (char*)base;
+    uintptr_t p = base;
     auto take = [&](size_t count) {
-        void* q = p;
+        void* q = (void*)p;
         p += ((count * e + 255) / 256) * 256;
         return q;
     };
@@ -701,6 +695,21 @@ void qr_ws_carve(Prec prec, void* base, int64_t m, int64_t ncols, QrWs& ws) {
     ws.cqr.W = take(NBP * NBP);
     ws.cqr.tau = ws.tau;
     ws.cqr.flag = (int*)take(1);
+    return p;
+}
+
+}  // namespace
+
+// the size is the layout's own end, so the two cannot disagree
+size_t qr_ws_bytes(Prec prec, int64_t m, int64_t ncols, size_t* gemm_bytes) {
+    const size_t e = prec == Prec::F64 ? 8 : 4;
+    *gemm_bytes = gemm_ws_bytes(2 * NBP, NBP, m, e);
+    QrWs w;
+    return (size_t)qr_ws_layout(prec, 0, m, ncols, w);
+}
+
+void qr_ws_carve(Prec prec, void* base, int64_t m, int64_t ncols, QrWs& ws) {
+    qr_ws_layout(prec, (uintptr_t)base, m, ncols, ws);
 }
 
 hipError_t qr_factor(Prec prec, const void* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws,

@@ -283,6 +283,44 @@ def test_sparse_x_parity(ski):
         S.close()
 
 
+def _csr_with_long_rows(seed=41):
+    """Rows 0-9 with 1800 entries each (the first 32-row block then holds ~18000 entries,
+    so its products run over nine chunks of 2048 and rows straddle chunk edges), 6000 rows
+    of 1-20 entries, then d identity rows for full rank; N(0,1) values."""
+    rng = np.random.default_rng(seed)
+    n0, d = 6000, 2000
+    lens = np.concatenate([np.full(10, 1800), rng.integers(1, 21, n0 - 10)])
+    cols = [np.sort(rng.choice(d, size=int(L), replace=False)) for L in lens]
+    cols += [np.array([j]) for j in range(d)]
+    rp = np.zeros(n0 + d + 1, dtype=np.int64)
+    rp[1:] = np.cumsum([len(c) for c in cols])
+    ci = np.concatenate(cols).astype(np.int32)
+    va = rng.standard_normal(len(ci))
+    va[rp[n0]:] = 1.0
+    return rp, ci, va, (n0 + d, d)
+
+
+def test_sparse_long_rows_multiple_rhs(ski):
+    """CSR products whose 32-row blocks span several chunks, with three right-hand sides:
+    every column within 1e-10 of the direct solution."""
+    rp, ci, va, (n, d) = _csr_with_long_rows()
+    _say(f"sparse long rows n={n} d={d} nnz={len(ci)}, 3 right-hand sides")
+    A = sp.csr_matrix((va, ci, rp), shape=(n, d))
+    B = np.random.default_rng(42).standard_normal((n, 3))
+    Xd = lls.lstsq_direct(A, B)
+    S = ski.Solver()
+    S.sketch(("csr", dev(rp, torch.int64), dev(ci, torch.int32), dev(va), (n, d)), dev(B),
+             gamma=1.5, s=2, seed=2004, tau_r=1e-14, it_max=500).factor()
+    X, infos, rc = S.solve()
+    S.close()
+    assert rc in (0, 1)
+    X = X.cpu().numpy()
+    for j in range(3):
+        err = np.linalg.norm(X[:, j] - Xd[:, j]) / np.linalg.norm(Xd[:, j])
+        _say(f"  column {j}: iters {infos[j]['iters']} rel err {err:.2e}")
+        assert err <= 1e-10
+
+
 # -------------------------------------------------------------------------- full sizes
 def test_full_size_dense_matches_the_direct_solution(ski):
     # the dense 50000 x 4000 workload with the benchmark's sketch (gamma 1.7, m 6800, s 3,
