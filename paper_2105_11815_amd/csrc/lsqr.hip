@@ -338,10 +338,13 @@ __global__ __launch_bounds__(256) void k_spmv_csr(const int64_t* __restrict__ rp
     const int64_t rl = r0 + 32 < n ? r0 + 32 : n;
     const int64_t e0 = rp[r0], e1 = rp[rl];                // the workgroup's nonzeros
     const int64_t rb = i < n ? rp[i] : e1, re = i < n ? rp[i + 1] : e1;  // this row's
+    const int64_t iu = i < n ? i : n - 1;
     for (int j = 0; j < k; ++j) {
         const bool act = !stt[j].done;
         double sq = 0.0;
         if (act) {
+            // the old u, loaded now (clamped row) so that it arrives with the nonzeros
+            const double uo = u[iu * k + j];
             double acc = 0.0;
             for (int64_t c0 = e0; c0 < e1; c0 += SP_CH) {
                 const int64_t c1 = c0 + SP_CH < e1 ? c0 + SP_CH : e1;
@@ -382,7 +385,7 @@ __global__ __launch_bounds__(256) void k_spmv_csr(const int64_t* __restrict__ rp
             acc += __shfl_xor(acc, 4, 64);
             if (i < n && gl == 0) {
                 const double coef = use_coef_m1 ? -1.0 : stt[j].coef;
-                const double v = acc - coef * u[i * k + j];
+                const double v = acc - coef * uo;
                 u[i * k + j] = v;
                 sq = v * v;
             }
