@@ -91,7 +91,7 @@ typedef struct {
  *   s            nonzeros per column of S_h, 1 <= s <= min(m, 32).
  *   hadamard     1: S = S_h H D (dense only); 0: S = S_h; 2: S = S_h F D with F the
  *                discrete Hartley transform of the paper's dense software (Section 6,
- *                HR-DHT), on the zero-padded n' rows; needs n' <= 65536 and FP64 sketch
+ *                HR-DHT), on the zero-padded n' rows; needs n' <= 2^24 and FP64 sketch
  *                and QR; computed through the DFT, so it matches a reference to rounding.
  *   seed         Philox4x64-10 key (seed, 0) for S_h and D.
  *   sketch_prec  arithmetic/storage of H D A and of the sketch (FP64/FP32/BF16).

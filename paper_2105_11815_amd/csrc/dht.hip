@@ -1,6 +1,6 @@
 // The randomised Hartley transform of the paper's dense software (Section 6, HR-DHT):
 // S = S_h F D with F the discrete Hartley transform, F_kj = n'^-1/2 cas(2 pi k j / n'),
-// applied to the zero-padded n' rows of [A b] (n' a power of two, at most 65536).
+// applied to the zero-padded n' rows of [A b] (n' a power of two, at most 2^24).
 //
 // F is computed through the discrete Fourier transform: for real x, DHT(x)_k = Re X_k -
 // Im X_k with X = DFT(x).  Two real columns a, b ride in one complex column z = a + i b;
@@ -13,6 +13,13 @@
 //           load), times the twiddle e^{-2 pi i j1 k2 / N}, stored at slab row k2 N1 + j1;
 //   pass B: for each k2 < N2, the N1-point DFT over j1 of those rows, in place: slab row
 //           k2 N1 + k1 then holds Z_{k2 + N2 k1}.
+// When N2 > 256 (n' > 65536), pass A is itself split the same way, N2 = Na Nb (Na = 256),
+// with j2 = ja + Na jb and k2 = kb + Nb ka:
+//   pass A1: for each (j1, ja), the Nb-point DFT over jb of z[j1 + N1 (ja + Na jb)] (D on
+//            load), times e^{-2 pi i ja kb / N2}, stored at slab row (kb + Nb ja) N1 + j1;
+//   pass A2: for each (j1, kb), the Na-point DFT over ja of those rows, times the twiddle
+//            e^{-2 pi i j1 k2 / N}, written back in place at row (kb + Nb ka) N1 + j1 =
+//            k2 N1 + j1, the layout pass A leaves; pass B and the gather are unchanged.
 // Each short DFT is radix-2 decimation in time in LDS, with its input in bit-reversed
 // order and twiddles from sincospi.  The hashing gather then forms H from the two rows
 // k and n' - k of every bucket entry and sums the bucket's entries in the same fixed
@@ -106,6 +113,69 @@ __global__ __launch_bounds__(FT) void k_dht_pass_a(const double* __restrict__ A,
     }
 }
 
+// pass A1 (N2 = Na Nb > 256): block x = j1 + N1 ja
+__global__ __launch_bounds__(FT) void k_dht_pass_a1(const double* __restrict__ A, int64_t lda,
+                                                    const double* __restrict__ B, int64_t ldb,
+                                                    int64_t n, int64_t d, int64_t w, int64_t c0,
+                                                    int64_t c1, const uint32_t* __restrict__ dbits,
+                                                    int N1, int Na, int Nb, int lgb, int64_t N2,
+                                                    double2* __restrict__ T, int64_t sq) {
+    __shared__ double2 X[LMAX][QW];
+    __shared__ double2 W[LMAX / 2];
+    const int tid = threadIdx.x;
+    const int j1 = (int)(blockIdx.x % (unsigned)N1), ja = (int)(blockIdx.x / (unsigned)N1);
+    const int64_t qb = (int64_t)blockIdx.y * QW;
+    twiddles(W, Nb, tid);
+    for (int o = tid; o < Nb * QW; o += FT) {
+        const int jb = o / QW, q = o - jb * QW;
+        const int64_t j = j1 + (int64_t)N1 * (ja + (int64_t)Na * jb);
+        const int64_t ca = c0 + 2 * (qb + q), cb = ca + 1;
+        const double sg = ((dbits[j >> 5] >> (j & 31)) & 1u) ? -1.0 : 1.0;
+        const bool qok = qb + q < sq;
+        const double va = (qok && ca < c1) ? aug(A, lda, B, ldb, n, d, w, j, ca) : 0.0;
+        const double vb = (qok && cb < c1) ? aug(A, lda, B, ldb, n, d, w, j, cb) : 0.0;
+        X[bitrev(jb, lgb)][q] = make_double2(sg * va, sg * vb);
+    }
+    __syncthreads();
+    dft_lds(X, Nb, W, tid);
+    for (int o = tid; o < Nb * QW; o += FT) {
+        const int kb = o / QW, q = o - kb * QW;
+        if (qb + q >= sq) continue;
+        const int64_t t = ((int64_t)ja * kb) % N2;
+        double s, c;
+        sincospi(-2.0 * (double)t / (double)N2, &s, &c);
+        T[((int64_t)(kb + (int64_t)Nb * ja) * N1 + j1) * sq + qb + q] =
+            cmul(X[kb][q], make_double2(c, s));
+    }
+}
+
+// pass A2 (N2 = Na Nb > 256), in place: block x = j1 + N1 kb
+__global__ __launch_bounds__(FT) void k_dht_pass_a2(double2* __restrict__ T, int64_t sq, int N1,
+                                                    int Na, int Nb, int lga, int64_t N) {
+    __shared__ double2 X[LMAX][QW];
+    __shared__ double2 W[LMAX / 2];
+    const int tid = threadIdx.x;
+    const int j1 = (int)(blockIdx.x % (unsigned)N1), kb = (int)(blockIdx.x / (unsigned)N1);
+    const int64_t qb = (int64_t)blockIdx.y * QW;
+    twiddles(W, Na, tid);
+    for (int o = tid; o < Na * QW; o += FT) {
+        const int ja = o / QW, q = o - ja * QW;
+        const int64_t row = (kb + (int64_t)Nb * ja) * N1 + j1;
+        X[bitrev(ja, lga)][q] = qb + q < sq ? T[row * sq + qb + q] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    dft_lds(X, Na, W, tid);
+    for (int o = tid; o < Na * QW; o += FT) {
+        const int ka = o / QW, q = o - ka * QW;
+        if (qb + q >= sq) continue;
+        const int64_t k2 = kb + (int64_t)Nb * ka;
+        const int64_t t = ((int64_t)j1 * k2) % N;
+        double s, c;
+        sincospi(-2.0 * (double)t / (double)N, &s, &c);
+        T[(k2 * N1 + j1) * sq + qb + q] = cmul(X[ka][q], make_double2(c, s));
+    }
+}
+
 __global__ __launch_bounds__(FT) void k_dht_pass_b(double2* __restrict__ T, int64_t sq, int N1,
                                                    int lg1) {
     __shared__ double2 X[LMAX][QW];
@@ -167,7 +237,7 @@ __global__ __launch_bounds__(FT) void k_dht_gather(const double2* __restrict__ T
 
 }  // namespace
 
-bool dht_supported(int64_t npad) { return npad >= 1 && npad <= (int64_t)LMAX * LMAX; }
+bool dht_supported(int64_t npad) { return npad >= 1 && npad <= (int64_t)LMAX * LMAX * LMAX; }
 
 hipError_t launch_sketch_dht(const double* A, int64_t lda, const double* B, int64_t ldb,
                              int64_t n, int64_t d, int64_t k, int64_t npad,
@@ -186,8 +256,19 @@ hipError_t launch_sketch_dht(const double* A, int64_t lda, const double* B, int6
     for (int64_t c0 = 0; c0 < w; c0 += 2 * sq) {
         const int64_t c1 = std::min(w, c0 + 2 * sq), cw = c1 - c0;
         const unsigned gq = (unsigned)(((cw + 1) / 2 + QW - 1) / QW);
-        hipLaunchKernelGGL(k_dht_pass_a, dim3((unsigned)N1, gq), dim3(FT), 0, st, A, lda, B, ldb,
-                           n, d, w, c0, c1, dbits, N1, N2, lg2, npad, Tc, sq);
+        if (lg2 <= 8) {
+            hipLaunchKernelGGL(k_dht_pass_a, dim3((unsigned)N1, gq), dim3(FT), 0, st, A, lda, B,
+                               ldb, n, d, w, c0, c1, dbits, N1, N2, lg2, npad, Tc, sq);
+        } else {
+            // N2 = Na Nb with Na = 256 and Nb = N2 / 256 <= 256
+            const int lga = 8, lgb = lg2 - 8, Na = 1 << lga, Nb = 1 << lgb;
+            hipLaunchKernelGGL(k_dht_pass_a1, dim3((unsigned)(N1 * Na), gq), dim3(FT), 0, st, A,
+                               lda, B, ldb, n, d, w, c0, c1, dbits, N1, Na, Nb, lgb, (int64_t)N2,
+                               Tc, sq);
+            SKI_HIP(hipGetLastError());
+            hipLaunchKernelGGL(k_dht_pass_a2, dim3((unsigned)(N1 * Nb), gq), dim3(FT), 0, st, Tc,
+                               sq, N1, Na, Nb, lga, npad);
+        }
         SKI_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_dht_pass_b, dim3((unsigned)N2, gq), dim3(FT), 0, st, Tc, sq, N1, lg1);
         SKI_HIP(hipGetLastError());

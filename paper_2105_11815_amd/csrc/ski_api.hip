@@ -300,7 +300,7 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
     if (had && p->hadamard == 2 &&
         (!dht_supported(npad) || p->sketch_prec != SKI_FP64 || p->qr_prec != SKI_FP64))
         return fail(h, SKI_EINVAL,
-                    "ski_sketch: the Hartley transform needs n' <= 65536 and FP64 sketch and QR");
+                    "ski_sketch: the Hartley transform needs n' <= 2^24 and FP64 sketch and QR");
     if (p->s > m) return fail(h, SKI_EINVAL, "ski_sketch: need s <= m");
     if (m > 12288) return fail(h, SKI_EINVAL, "ski_sketch: m above 12288 is not supported");
     const int64_t ncols = d + k;

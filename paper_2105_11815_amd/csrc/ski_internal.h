@@ -141,7 +141,7 @@ hipError_t launch_sketch_dense(const double* A, int64_t lda, const double* B, in
                                const uint32_t* dbits, void* T, int64_t sc,
                                const int32_t* bucket_ptr, const int32_t* src, int64_t m,
                                double scale, Prec prec, void* SA, hipStream_t st);
-// dense sketch with the randomised Hartley transform (FP64; n' <= 65536), through the
+// dense sketch with the randomised Hartley transform (FP64; n' <= 2^24), through the
 // same slab buffer T (npad x sc doubles, sc a multiple of 16) into SA (m x (d+k))
 bool dht_supported(int64_t npad);
 hipError_t launch_sketch_dht(const double* A, int64_t lda, const double* B, int64_t ldb,

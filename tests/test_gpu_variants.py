@@ -106,11 +106,12 @@ def test_sampling_rejects_s_above_one(ski):
     S.close()
 
 
-TOL_DHT = 1e-12  # max |SA - SA_ref| / max |SA_ref|: two FFT orders, n' <= 65536
+TOL_DHT = 1e-12  # max |SA - SA_ref| / max |SA_ref|: two FFT orders
 
 
+# the last two need the split outer pass: n' = 131072 (N2 = 256 x 2) and 524288 (256 x 8)
 @pytest.mark.parametrize("n,d,m,s", [(3000, 70, 150, 3), (200, 10, 17, 1), (40000, 13, 40, 2),
-                                     (100, 4, 9, 2)])
+                                     (100, 4, 9, 2), (70000, 6, 40, 2), (300000, 3, 40, 3)])
 def test_dht_sketch_matches_the_oracle(ski, n, d, m, s):
     _say(f"Hartley sketch n={n} d={d} m={m} s={s}")
     rng = np.random.default_rng(n + d)
@@ -137,6 +138,24 @@ def test_dht_solve_matches_the_oracle(ski):
     X, info = lls.solve(A, b, 23, s=2, transform="dht", tau_r=1e-14, it_max=300)
     S = ski.Solver()
     S.sketch(dev(A), dev(b), s=2, seed=23, hadamard="dht", tau_r=1e-14, it_max=300)
+    S.factor()
+    Xg, infos, rc = S.solve()
+    S.close()
+    assert rc == 0
+    x, xr = Xg[:, 0].cpu().numpy(), X[:, 0]
+    assert np.abs(x - xr).max() / np.abs(xr).max() <= 1e-10
+
+
+def test_dht_solve_beyond_65536_rows(ski):
+    """n = 70000 pads to n' = 131072, where the outer DFT takes two passes."""
+    _say("solve with the Hartley transform, coherent 70000 x 20")
+    rng = np.random.default_rng(45)
+    A = rng.standard_normal((70000, 20))
+    A[:14000] *= 1e3
+    b = rng.standard_normal(70000)
+    X, info = lls.solve(A, b, 29, s=2, transform="dht", tau_r=1e-14, it_max=300)
+    S = ski.Solver()
+    S.sketch(dev(A), dev(b), s=2, seed=29, hadamard="dht", tau_r=1e-14, it_max=300)
     S.factor()
     Xg, infos, rc = S.solve()
     S.close()
