@@ -51,17 +51,22 @@ hipError_t launch_combine_u(const double* t, double* u, int64_t n, int k, const 
                             hipStream_t st);
 hipError_t launch_lsqr_init(LsqrState* stt, int64_t d, int k, const double* wp, double* v,
                             double* h, double* delta, double tau_a, hipStream_t st);
+// hflag: the status word (1 once every column has stopped), written by the step itself:
+// directly when k == 1, through the counter cnt (one uint32, zero between launches) when
+// k > 1; with hflag null nothing is written
 hipError_t launch_lsqr_step(LsqrState* stt, int64_t d, int k, const double* wp, double* v,
                             double* h, double* delta, double tau_r, int64_t it_max,
-                            int32_t* hflag, hipStream_t st);  // hflag: status word when k == 1
+                            int32_t* hflag, uint32_t* cnt, hipStream_t st);
 hipError_t launch_final_y(const LsqrState* stt, int64_t d, int k, const double* c,
                           const double* delta, double* y, hipStream_t st);
 hipError_t launch_scale_copy(const double* x, int64_t rows, int64_t cols, int64_t ldx, double s,
                              double* y, int64_t ldy, hipStream_t st);
 hipError_t launch_cg_init(LsqrState* stt, int64_t d, int k, const double* rhs, double* r, double* p,
                           double* y, double tol, hipStream_t st);
+// word: the status word as for the LSQR step, through cnt (any k); null writes nothing
 hipError_t launch_cg_step(LsqrState* stt, int64_t d, int k, const double* q, double* r, double* p,
-                          double* y, int64_t it_max, hipStream_t st);
+                          double* y, int64_t it_max, int32_t* word, uint32_t* cnt,
+                          hipStream_t st);
 // flag <- 1 if every column has stopped (flag may be host memory mapped for the device)
 hipError_t launch_all_done(const LsqrState* stt, int k, int32_t* flag, hipStream_t st);
 

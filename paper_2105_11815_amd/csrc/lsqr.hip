@@ -574,17 +574,51 @@ __global__ __launch_bounds__(1024) void k_lsqr_init(LsqrState* __restrict__ stt,
     }
 }
 
+// Status word of a step over k > 1 columns (one workgroup each), without a kernel of its
+// own: every workgroup counts itself in once its column's state is written (release); in
+// the last one (acquire) the first wave reads the columns' done flags, one per lane, and
+// a vote ANDs them; it writes the word and re-arms the counter for the next step.  No
+// workgroup waits for another.
+__device__ __forceinline__ void post_all_done(LsqrState* stt, int k, int32_t* word,
+                                              uint32_t* cnt) {
+    __shared__ int last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(cnt, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last || threadIdx.x >= 64) return;
+    __threadfence();
+    int all = 1;
+    for (int j0 = 0; j0 < k; j0 += 64) {
+        const int j = j0 + (int)threadIdx.x;
+        const int jc = j < k ? j : k - 1;
+        const int dn =
+            __hip_atomic_load(&stt[jc].done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 1 : 0;
+        all &= __all(dn) ? 1 : 0;
+    }
+    if (threadIdx.x == 0) {
+        *word = all;
+        __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 // one step: u_hat holds W v - alpha u (beta2 = its squared norm), wp = R^-T A^T u_hat
 __global__ __launch_bounds__(1024) void k_lsqr_step(LsqrState* __restrict__ stt, int64_t d, int k,
                                                     const double* __restrict__ wp,
                                                     double* __restrict__ v, double* __restrict__ h,
                                                     double* __restrict__ delta, double tau_r,
-                                                    int64_t it_max, int32_t* hflag) {
+                                                    int64_t it_max, int32_t* hflag,
+                                                    uint32_t* cnt) {
     __shared__ double sh[16];
     const int j = blockIdx.x;
     LsqrState& S = stt[j];
     if (S.done) {
-        if (hflag && threadIdx.x == 0) *hflag = 1;
+        if (cnt)
+            post_all_done(stt, k, hflag, cnt);
+        else if (hflag && threadIdx.x == 0)
+            *hflag = 1;
         return;
     }
     const double beta = sqrt(S.beta2);
@@ -672,8 +706,9 @@ __global__ __launch_bounds__(1024) void k_lsqr_step(LsqrState* __restrict__ stt,
             S.status = SKI_WNOCONV;
         }
         // one right-hand side: this workgroup's state is the whole status word
-        if (hflag) *hflag = S.done;
+        if (hflag && !cnt) *hflag = S.done;
     }
+    if (cnt) post_all_done(stt, k, hflag, cnt);
 }
 
 // y = c + delta (per column) for the final x = R^-1 y, x_s when the early exit was taken
@@ -750,11 +785,15 @@ __global__ __launch_bounds__(1024) void k_cg_init(LsqrState* __restrict__ stt, i
 __global__ __launch_bounds__(1024) void k_cg_step(LsqrState* __restrict__ stt, int64_t d, int k,
                                                   const double* __restrict__ q,
                                                   double* __restrict__ r, double* __restrict__ p,
-                                                  double* __restrict__ y, int64_t it_max) {
+                                                  double* __restrict__ y, int64_t it_max,
+                                                  int32_t* word, uint32_t* cnt) {
     __shared__ double sh[16];
     const int j = blockIdx.x;
     LsqrState& S = stt[j];
-    if (S.done) return;
+    if (S.done) {
+        if (cnt) post_all_done(stt, k, word, cnt);
+        return;
+    }
     const double rr_old = S.rr, stop2 = S.stop2;
     const int64_t iters_old = S.iters;
     // as in the LSQR step: registers for d <= STEP_REG * blockDim, the same sums otherwise
@@ -824,6 +863,7 @@ __global__ __launch_bounds__(1024) void k_cg_step(LsqrState* __restrict__ stt, i
             S.status = SKI_WNOCONV;
         }
     }
+    if (cnt) post_all_done(stt, k, word, cnt);
 }
 
 // one wavefront: lane j reads column j's flag (64 columns per step), a vote ANDs them
@@ -1006,9 +1046,9 @@ hipError_t launch_lsqr_init(LsqrState* stt, int64_t d, int k, const double* wp, 
 
 hipError_t launch_lsqr_step(LsqrState* stt, int64_t d, int k, const double* wp, double* v,
                             double* h, double* delta, double tau_r, int64_t it_max,
-                            int32_t* hflag, hipStream_t st) {
+                            int32_t* hflag, uint32_t* cnt, hipStream_t st) {
     hipLaunchKernelGGL(k_lsqr_step, dim3((unsigned)k), dim3(1024), 0, st, stt, d, k, wp, v, h, delta,
-                       tau_r, it_max, k == 1 ? hflag : nullptr);
+                       tau_r, it_max, hflag, (k > 1 && hflag) ? cnt : nullptr);
     return hipGetLastError();
 }
 
@@ -1037,9 +1077,10 @@ hipError_t launch_cg_init(LsqrState* stt, int64_t d, int k, const double* rhs, d
 }
 
 hipError_t launch_cg_step(LsqrState* stt, int64_t d, int k, const double* q, double* r, double* p,
-                          double* y, int64_t it_max, hipStream_t st) {
+                          double* y, int64_t it_max, int32_t* word, uint32_t* cnt,
+                          hipStream_t st) {
     hipLaunchKernelGGL(k_cg_step, dim3((unsigned)k), dim3(1024), 0, st, stt, d, k, q, r, p, y,
-                       it_max);
+                       it_max, word, word ? cnt : nullptr);
     return hipGetLastError();
 }
 

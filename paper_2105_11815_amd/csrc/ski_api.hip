@@ -49,6 +49,7 @@ struct ski_handle_s {
     DevBuf qr_part, qr_W, qr_T, qr_Y, qr_tau;
     DevBuf tkeys, tkeys_tmp, ttable, tp, tpay, ti, tv;
     DevBuf u, t, v, h, delta, z, wp, g, gpart, upart, y, st;
+    DevBuf done_cnt;  // arrival counter of the step kernels' status word (zero between steps)
     DevBuf cg_r, cg_p, cg_q, t2, dtmp, gemm_ws2, gemm_ws3;
     // column-pivoted factor: workspace, the permutation, compact R_11, p x k staging
     DevBuf piv_part, pivd, Rc, ptmp;
@@ -209,7 +210,8 @@ int ski_destroy(ski_handle h) {
                      &h->tpay, &h->ti, &h->tv, &h->u, &h->t, &h->v, &h->h, &h->delta, &h->z,
                      &h->wp, &h->g, &h->gpart, &h->upart, &h->y, &h->st, &h->cg_r,
                      &h->cg_p, &h->cg_q, &h->t2, &h->dtmp, &h->gemm_ws2, &h->gemm_ws3,
-                     &h->piv_part, &h->pivd, &h->Rc, &h->ptmp, &h->cod_a, &h->cod_m};
+                     &h->piv_part, &h->pivd, &h->Rc, &h->ptmp, &h->cod_a, &h->cod_m,
+                     &h->done_cnt};
     for (DevBuf* b : all) release(*b);
     if (h->ev_ok)
         for (auto& e : h->ev) (void)hipEventDestroy(e);
@@ -716,6 +718,11 @@ int alloc_solve_ws(ski_handle h, int k) {
     const int64_t G = std::max<int64_t>({PASS_WG, spmv_csr_groups(n), 1});
     SKI_TRY(h, ensure(h->upart, G * k * 8), "alloc");
     SKI_TRY(h, ensure(h->st, k * sizeof(LsqrState)), "alloc");
+    if (!h->done_cnt.p) {
+        // zeroed once; every step that uses it leaves it at zero again
+        SKI_TRY(h, ensure(h->done_cnt, 256), "alloc");
+        SKI_TRY(h, hipMemset(h->done_cnt.p, 0, 256), "clear");
+    }
     if (h->pivoted) SKI_TRY(h, ensure(h->ptmp, d * k * 8), "alloc");
     return SKI_OK;
 }
@@ -766,10 +773,10 @@ hipError_t apply_P_out(ski_handle h, const double* y, double* out, int64_t ldo, 
 // word is copied to pinned host memory and an event recorded; the host waits on the event
 // of iteration i-1 only, so at most one idle iteration is ever launched.
 // The host learns that the iterations have stopped through a status word in pinned host
-// memory mapped for the device: the iteration's last kernel writes it (the scalar step
-// itself for one right-hand side, else a one-thread kernel), an event marks the
-// iteration, and the host reads the word one iteration later, so the device always has
-// the next iteration queued.
+// memory mapped for the device: the iteration's scalar step writes it (for several
+// right-hand sides, the last of its workgroups to finish; before the first iteration a
+// one-wave kernel), an event marks the iteration, and the host reads the word one
+// iteration later, so the device always has the next iteration queued.
 struct LagFlag {
     volatile int32_t* host = nullptr;  // [2], one slot per iteration parity
     int32_t* dev = nullptr;            // the same words, device address
@@ -941,7 +948,7 @@ int solve_lls(ski_handle h, const double* B, int k, int64_t ldb, double* X, int6
             prof_begin(h, PC_STEP, st);
             if (e == hipSuccess)
                 e = launch_lsqr_step(S, dp, k, wp, v, hh, dl, h->p.tau_r, h->p.it_max,
-                                     lf.slot_dev(it + 1), st);
+                                     lf.slot_dev(it + 1), P<uint32_t>(h->done_cnt), st);
             prof_end(h, st);
             if (e != hipSuccess) {
                 out = hip_fail(h, e, "lsqr iteration");
@@ -951,7 +958,7 @@ int solve_lls(ski_handle h, const double* B, int k, int64_t ldb, double* X, int6
         ++it;
         // status of this iteration is posted now and read one iteration later, so the
         // device always has the next iteration queued while the host checks
-        out = lf.post(h, k, st, it, k == 1);
+        out = lf.post(h, k, st, it, true);
         if (out == SKI_OK && it >= 2 && lf.wait(h, it - 1) == 1) break;
     }
     lf.release();
@@ -1027,13 +1034,15 @@ int solve_normal(ski_handle h, const double* G, int k, int64_t ldg, double* Z, i
         if (e == hipSuccess) e = dense_AZ(h, z, k, t, gw, st);
         if (e == hipSuccess) e = dense_ATU(h, t, k, g, gw, st);
         if (e == hipSuccess) e = apply_Rinv(h, RinvT, false, g, q, k, 1.0, nullptr, gw, st);
-        if (e == hipSuccess) e = launch_cg_step(S, dp, k, q, r, pp, y, h->p.it_max, st);
+        if (e == hipSuccess)
+            e = launch_cg_step(S, dp, k, q, r, pp, y, h->p.it_max, lf.slot_dev(it + 1),
+                               P<uint32_t>(h->done_cnt), st);
         if (e != hipSuccess) {
             out = hip_fail(h, e, "cg iteration");
             break;
         }
         ++it;
-        out = lf.post(h, k, st, it, false);
+        out = lf.post(h, k, st, it, true);
         if (out == SKI_OK && it >= 2 && lf.wait(h, it - 1) == 1) break;
     }
     lf.release();
