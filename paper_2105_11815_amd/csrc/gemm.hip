@@ -251,7 +251,9 @@ hipError_t gemm_impl(bool ta, bool tb, int64_t M, int64_t N, int64_t K, typename
     using T = typename MT<MD>::T;
     if (M <= 0 || N <= 0) return hipSuccess;
     int splits = choose_splits(M, N, K);
-    if (splits > 1 && (size_t)splits * M * N * sizeof(T) > ws.bytes) splits = 1;
+    // as many splits as the workspace holds (none if it cannot hold two)
+    if (splits > 1 && (size_t)splits * M * N * sizeof(T) > ws.bytes)
+        splits = (int)std::max<size_t>(1, ws.bytes / ((size_t)M * N * sizeof(T)));
     int64_t kchunk = K;
     if (splits > 1) {
         kchunk = ((K + splits - 1) / splits + BK - 1) / BK * BK;
