@@ -544,14 +544,15 @@ hipError_t qr_impl_cqr(T* Ac, int64_t m, int64_t ncols, int64_t d, QrWs& ws, boo
 // Column-pivoted panels (FP64): before each panel its pivots are chosen on the sketch of
 // the trailing columns and moved to the front.  The panel is factored by CholeskyQR2 with
 // Householder reconstruction when `cqr` is set: its columns are saved first, the host reads
-// the panel's failure flag (one synchronisation per panel), and a failed panel (the one
-// that holds the rank boundary, typically) is restored and factored column by column.
+// the panel's failure flag (published into a polled host word, once per panel), and a
+// failed panel (the one that holds the rank boundary, typically) is restored and factored
+// column by column.
 // The trailing matrix (with the ride-along columns) then gets Q^T: W = C^T V and W2 = W T
 // on the caller's stream, then the panel's rows of C (R_12, which the sketch update needs)
 // there too, while the rows below go to the second stream; the sketch update and the next
 // selection overlap that bulk update, and the next column moves wait for it.
 hipError_t qr_impl_pivoted(double* Ac, int64_t m, int64_t ncols, int64_t d, QrWs& ws, PivWs& pw,
-                           uint64_t seed, bool cqr, int* hflag, int* panels_cqr,
+                           uint64_t seed, bool cqr, HostFlag& pf, int* panels_cqr,
                            hipStream_t st) {
     using T = double;
     T* tau = (T*)ws.tau;
@@ -581,9 +582,10 @@ hipError_t qr_impl_pivoted(double* Ac, int64_t m, int64_t ncols, int64_t d, QrWs
             SKI_HIP(cqr_gram_update<T>(Ac, m, -1, j0, nb, nullptr, nullptr, ws.cqr, st));
             SKI_HIP(cqr_factor_panel<T>(Ac, m, j0, nb, ws.cqr, Tq, st));
             SKI_HIP(cqr_finish_panel<T>(Ac, m, j0, nb, 0, ws.cqr, VC, st));
-            SKI_HIP(hipMemcpyAsync(hflag, ws.cqr.flag, sizeof(int), hipMemcpyDeviceToHost, st));
-            SKI_HIP(hipStreamSynchronize(st));
-            if (*hflag == 0) {
+            int failed = 0;
+            SKI_HIP(launch_publish_flag(ws.cqr.flag, pf, st));
+            SKI_HIP(wait_flag(pf, st, &failed));
+            if (failed == 0) {
                 done = true;
                 if (panels_cqr) ++*panels_cqr;
             } else {
@@ -719,14 +721,49 @@ hipError_t qr_factor(Prec prec, const void* SA, int64_t m, int64_t ncols, int64_
 }
 
 hipError_t qr_factor_pivoted(const double* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws,
-                             PivWs& pw, uint64_t seed, bool cqr, int* hflag, int* panels_cqr,
+                             PivWs& pw, uint64_t seed, bool cqr, HostFlag& pf, int* panels_cqr,
                              hipStream_t st) {
     double* Ac = (double*)ws.Ac;
     hipLaunchKernelGGL((k_to_colmajor<double>),
                        dim3((unsigned)((ncols + 63) / 64), (unsigned)((m + 63) / 64)), dim3(256), 0,
                        st, SA, m, ncols, Ac);
     SKI_HIP(hipGetLastError());
-    return qr_impl_pivoted(Ac, m, ncols, d, ws, pw, seed, cqr, hflag, panels_cqr, st);
+    return qr_impl_pivoted(Ac, m, ncols, d, ws, pw, seed, cqr, pf, panels_cqr, st);
+}
+
+namespace {
+
+__global__ void k_publish_flag(const int* __restrict__ src, int32_t* dst, int32_t seq) {
+    if (threadIdx.x == 0) *(volatile int32_t*)dst = (int32_t)(seq << 1) | (*src != 0 ? 1 : 0);
+}
+
+}  // namespace
+
+hipError_t launch_publish_flag(const int* src, HostFlag& f, hipStream_t st) {
+    if (!f.dev) return hipErrorInvalidValue;
+    f.seq = (f.seq + 1) & 0x3fffffff;
+    hipLaunchKernelGGL(k_publish_flag, dim3(1), dim3(64), 0, st, src, f.dev, f.seq);
+    return hipGetLastError();
+}
+
+hipError_t wait_flag(HostFlag& f, hipStream_t st, int* flag) {
+    auto fresh = [&](int* out) {
+        const int32_t w = *f.host;
+        if ((w >> 1) != f.seq) return false;
+        *out = w & 1;
+        return true;
+    };
+    for (uint32_t spin = 1;; ++spin) {
+        if (fresh(flag)) return hipSuccess;
+        if ((spin & 255) == 0) {
+            const hipError_t q = hipStreamQuery(st);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) return q;
+            // the stream has drained: the word must be there once its writes are visible
+            SKI_HIP(hipStreamSynchronize(st));
+            return fresh(flag) ? hipSuccess : hipErrorUnknown;
+        }
+    }
 }
 
 hipError_t launch_extract_Rc(Prec prec, const QrWs& ws, int64_t m, int64_t d, int64_t k, double* R,

@@ -63,6 +63,7 @@ struct ski_handle_s {
     hipStream_t st3 = nullptr;           // third stream: R^-1 formed during the QR
     hipEvent_t rev[2] = {};
     double* hdiag = nullptr;  // pinned host copy of diag(R)
+    HostFlag pflag;           // the pivoted QR's per-panel flag, written by the device
     int64_t hdiag_n = 0;
     hipEvent_t ev[6] = {};
     bool ev_ok = false;
@@ -223,6 +224,7 @@ int ski_destroy(ski_handle h) {
     if (h->st2) (void)hipStreamDestroy(h->st2);
     if (h->st3) (void)hipStreamDestroy(h->st3);
     if (h->hdiag) (void)hipHostFree(h->hdiag);
+    if (h->pflag.host) (void)hipHostFree((void*)h->pflag.host);
     delete h;
     return SKI_OK;
 }
@@ -539,6 +541,15 @@ int ski_factor(ski_handle h, void* stream) {
     h->pivoted = false;
     h->rank = d;
     if (piv) {
+        if (!h->pflag.host) {
+            int32_t* w = nullptr;
+            SKI_TRY(h, hipHostMalloc((void**)&w, 256, hipHostMallocMapped | hipHostMallocCoherent),
+                    "pinned");
+            w[0] = 0;
+            h->pflag.host = w;
+            h->pflag.seq = 0;
+            SKI_TRY(h, hipHostGetDevicePointer((void**)&h->pflag.dev, w, 0), "device pointer");
+        }
         SKI_TRY(h, ensure(h->piv_part, piv_ws_bytes(m, d)), "alloc");
         SKI_TRY(h, ensure(h->pivd, d * 4), "alloc");
         SKI_TRY(h, ensure(h->Rc, d * d * 8), "alloc");
@@ -546,7 +557,7 @@ int ski_factor(ski_handle h, void* stream) {
         piv_ws_carve(h->piv_part.p, m, d, pw);
         prof_begin(h, PC_QR_PIV, st);
         SKI_TRY(h, qr_factor_pivoted((const double*)h->SA.p, m, ncols, d, ws, pw, h->p.seed,
-                                     h->p.qr_panel != SKI_QR_PIVOTED_HOUSEHOLDER, hflag,
+                                     h->p.qr_panel != SKI_QR_PIVOTED_HOUSEHOLDER, h->pflag,
                                      &h->panels_cqr, st),
                 "pivoted qr");
         prof_end(h, st);

@@ -293,12 +293,26 @@ hipError_t qr_factor(Prec prec, const void* SA, int64_t m, int64_t ncols, int64_
                      hipStream_t st);
 // FP64 QR with column pivoting of the first d columns (the last ncols - d ride along),
 // pivots chosen on the sketch of rcpqr.hip, the permutation in pw.perm.  Panels by
+// A word of mapped, coherent pinned host memory that a kernel writes and the host polls:
+// the host learns a device flag without a copy and a stream synchronisation.  host and dev
+// are the two addresses of the same word (zero when allocated); seq counts publications.
+struct HostFlag {
+    volatile int32_t* host = nullptr;
+    int32_t* dev = nullptr;
+    int32_t seq = 0;
+};
+// after the work queued on st so far: word <- (seq << 1) | (*src != 0), with seq advanced
+hipError_t launch_publish_flag(const int* src, HostFlag& f, hipStream_t st);
+// polls the word until it carries the last published seq and returns its flag bit in *flag.
+// The stream is queried while waiting, so an error on st (or st running dry without the
+// word appearing) ends the wait with an error instead of a hang.
+hipError_t wait_flag(HostFlag& f, hipStream_t st, int* flag);
 // CholeskyQR2 (cqr) with a per-panel fallback to Householder columns, or Householder
-// columns only; hflag: pinned host int used to read each panel's flag; panels_cqr (may be
-// null) receives the number of panels that CholeskyQR2 factored.  Synchronises st once per
-// panel when cqr is set.
+// columns only; pf: the host word through which each panel's flag is read (the host waits
+// for it once per panel when cqr is set); panels_cqr (may be null) receives the number of
+// panels that CholeskyQR2 factored.
 hipError_t qr_factor_pivoted(const double* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws,
-                             PivWs& pw, uint64_t seed, bool cqr, int* hflag, int* panels_cqr,
+                             PivWs& pw, uint64_t seed, bool cqr, HostFlag& pf, int* panels_cqr,
                              hipStream_t st);
 // copy R (d x d) and c (d x k) out of the factored copy into FP64 row-major, flipping
 // rows so that diag(R) >= 0
