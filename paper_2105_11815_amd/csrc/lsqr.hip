@@ -315,13 +315,15 @@ __global__ __launch_bounds__(256) void k_reduce_pass(const double* __restrict__ 
 
 // ---------------------------------------------------------------------------
 // CSR products (k right-hand sides, vectors row-major with leading dimension k)
-// u[i] = (A z)[i] - coef_j u[i] for the 32 rows of a workgroup; squared-norm partial per
+// u[i] = (A z)[i] - coef_j u[i] for the SP_R rows of a workgroup; squared-norm partial per
 // workgroup.  The rows' nonzeros are contiguous, so all 256 threads stream them in chunks of
 // SP_CH (eight loads per thread issued together, then the gathers of z) and leave the
-// products in LDS; then lane l of a row's eight adds the row's products l, l + 8, ... in
+// products in LDS; then lane l of a row's SP_L adds the row's products l, l + SP_L, ... in
 // order.  A long row (the power-law workloads reach 500 entries) thus costs a few LDS reads
 // per lane instead of a chain of dependent global loads that holds up its workgroup.
 constexpr int SP_CH = 2048;
+constexpr int SP_R = 64;           // rows per workgroup
+constexpr int SP_L = 256 / SP_R;   // lanes per row
 __global__ __launch_bounds__(256) void k_spmv_csr(const int64_t* __restrict__ rp,
                                                   const int32_t* __restrict__ ci,
                                                   const double* __restrict__ va, int64_t n, int k,
@@ -330,12 +332,12 @@ __global__ __launch_bounds__(256) void k_spmv_csr(const int64_t* __restrict__ rp
                                                   const LsqrState* __restrict__ stt,
                                                   int use_coef_m1, double* __restrict__ upart) {
     __shared__ double prod[SP_CH];
-    __shared__ double red[32];
+    __shared__ double red[SP_R];
     constexpr int PT = SP_CH / 256;
-    const int t = threadIdx.x, grp = t >> 3, gl = t & 7;
-    const int64_t r0 = (int64_t)blockIdx.x * 32;
+    const int t = threadIdx.x, grp = t / SP_L, gl = t % SP_L;
+    const int64_t r0 = (int64_t)blockIdx.x * SP_R;
     const int64_t i = r0 + grp;
-    const int64_t rl = r0 + 32 < n ? r0 + 32 : n;
+    const int64_t rl = r0 + SP_R < n ? r0 + SP_R : n;
     const int64_t e0 = rp[r0], e1 = rp[rl];                // the workgroup's nonzeros
     const int64_t rb = i < n ? rp[i] : e1, re = i < n ? rp[i + 1] : e1;  // this row's
     const int64_t iu = i < n ? i : n - 1;
@@ -365,24 +367,23 @@ __global__ __launch_bounds__(256) void k_spmv_csr(const int64_t* __restrict__ rp
 #pragma unroll
                 for (int q = 0; q < PT; ++q) prod[t + 256 * q] = vv[q] * zv[q];
                 __syncthreads();
-                // this lane's entries rb + gl + 8s that lie in [c0, c1), in increasing order
+                // this lane's entries rb + gl + SP_L s that lie in [c0, c1), in increasing order
                 const int64_t lo = rb > c0 ? rb : c0, hi = re < c1 ? re : c1;
                 int64_t e = rb + gl;
-                if (e < lo) e += (lo - e + 7) / 8 * 8;
-                for (; e + 24 < hi; e += 32) {
-                    const double a0 = prod[e - c0], a1 = prod[e + 8 - c0];
-                    const double a2 = prod[e + 16 - c0], a3 = prod[e + 24 - c0];
+                if (e < lo) e += (lo - e + SP_L - 1) / SP_L * SP_L;
+                for (; e + 3 * SP_L < hi; e += 4 * SP_L) {
+                    const double a0 = prod[e - c0], a1 = prod[e + SP_L - c0];
+                    const double a2 = prod[e + 2 * SP_L - c0], a3 = prod[e + 3 * SP_L - c0];
                     acc += a0;
                     acc += a1;
                     acc += a2;
                     acc += a3;
                 }
-                for (; e < hi; e += 8) acc += prod[e - c0];
+                for (; e < hi; e += SP_L) acc += prod[e - c0];
                 __syncthreads();
             }
-            acc += __shfl_xor(acc, 1, 64);
-            acc += __shfl_xor(acc, 2, 64);
-            acc += __shfl_xor(acc, 4, 64);
+#pragma unroll
+            for (int o = 1; o < SP_L; o <<= 1) acc += __shfl_xor(acc, o, 64);
             if (i < n && gl == 0) {
                 const double coef = use_coef_m1 ? -1.0 : stt[j].coef;
                 const double v = acc - coef * uo;
@@ -394,7 +395,7 @@ __global__ __launch_bounds__(256) void k_spmv_csr(const int64_t* __restrict__ rp
         __syncthreads();
         if (threadIdx.x == 0) {
             double s = 0;
-            for (int q = 0; q < 32; ++q) s += red[q];
+            for (int q = 0; q < SP_R; ++q) s += red[q];
             upart[(int64_t)blockIdx.x * k + j] = s;
         }
         __syncthreads();
@@ -996,7 +997,7 @@ hipError_t launch_lsqr_pass(const double* A, int64_t lda, int64_t n, int64_t d, 
 hipError_t launch_spmv_csr(const int64_t* rp, const int32_t* ci, const double* va, int64_t n, int k,
                            const double* z, double* u, LsqrState* stt, bool coef_m1,
                            double* upart, hipStream_t st) {
-    const int64_t G = (n + 31) / 32;
+    const int64_t G = (n + SP_R - 1) / SP_R;
     hipLaunchKernelGGL(k_spmv_csr, dim3((unsigned)G), dim3(256), 0, st, rp, ci, va, n, k, z, u, stt,
                        coef_m1 ? 1 : 0, upart);
     SKI_HIP(hipGetLastError());
@@ -1004,7 +1005,7 @@ hipError_t launch_spmv_csr(const int64_t* rp, const int32_t* ci, const double* v
     return hipGetLastError();
 }
 
-int64_t spmv_csr_groups(int64_t n) { return (n + 31) / 32; }
+int64_t spmv_csr_groups(int64_t n) { return (n + SP_R - 1) / SP_R; }
 
 hipError_t launch_spmv_csrT(const int32_t* tp, const int32_t* ti, const double* tv, int64_t d, int k,
                             const double* u, double* g, const LsqrState* stt, hipStream_t st) {
