@@ -24,8 +24,12 @@
  *     pointers; dense matrices are row-major with an explicit leading dimension
  *     (element (i, j) of an n x d matrix at p[i * ld + j]).
  *   - `stream` is a hipStream_t (passed as void*); every call is ordered on it.
- *     ski_sketch and ski_factor are asynchronous; ski_solve returns after LSQR has
- *     stopped (it reads a small on-device status word every few iterations).
+ *     ski_sketch is asynchronous.  ski_factor synchronises the stream before it returns
+ *     (it reads diag(R) for the rank guard and the perturbation, and the device's checks
+ *     of the sketch; with qr_panel = SKI_QR_PIVOTED it also waits once per 64-column panel
+ *     for that panel's CholeskyQR2 check).  ski_solve returns after LSQR (or CG) has
+ *     stopped: it polls a status word in mapped host memory once per iteration, one
+ *     iteration behind the device.  The getters synchronise the device.
  *   - Return value: 0 (SKI_OK) on success, > 0 a warning, < 0 an error; the
  *     message of the last error is available from ski_last_error.  No C++
  *     exception crosses this interface.
@@ -46,7 +50,8 @@ enum ski_status {
     SKI_OK = 0,
     SKI_WNOCONV = 1,   /* it_max reached before (TC-lsqr) held; X holds the last iterate */
     SKI_WEARLY = 2,    /* Step 3 terminated early: ||A x_s - b|| <= tau_a, X = x_s       */
-    SKI_EINVAL = -1,   /* invalid argument (sizes, leading dimensions, NULL pointers)     */
+    SKI_EINVAL = -1,   /* invalid argument (sizes, leading dimensions, NULL pointers), or
+                          a non-finite entry in A, B or G (see ski_factor, ski_solve)       */
     SKI_ENOMEM = -2,   /* device allocation failed                                         */
     SKI_EDEVICE = -3,  /* a HIP call failed                                                */
     SKI_ERANK = -4,    /* rank guard: some |r_qq| < rcond |r_11| (A looks rank deficient)  */
@@ -87,7 +92,10 @@ typedef struct {
 } ski_matrix;
 
 /* Parameters (defaults of Section 6 from ski_params_default).
- *   gamma, m     sketch rows m = ceil(gamma d) unless m > 0 is given; d <= m.
+ *   gamma, m     sketch rows m = ceil(gamma d) unless m > 0 is given; d <= m <= 12288
+ *                (the column-by-column Householder panel, which every QR falls back to,
+ *                keeps a column's m entries in the registers of one 512-thread workgroup,
+ *                24 per thread).
  *   s            nonzeros per column of S_h, 1 <= s <= min(m, 32).
  *   hadamard     1: S = S_h H D (dense only); 0: S = S_h; 2: S = S_h F D with F the
  *                discrete Hartley transform of the paper's dense software (Section 6,
@@ -180,25 +188,36 @@ int ski_destroy(ski_handle h);
 void ski_params_default(int32_t kind, ski_params* p);
 
 /* Step 1.  Draws S from (m, s, seed), forms S [A B] (B: n x k, device, leading
- * dimension ldb >= k; k >= 1) and keeps it in the handle.  Errors: SKI_EINVAL for
- * n < d, d < 1, m < d, m > n' (dense with Hadamard) or m > n, s out of range, k < 1,
- * bad leading dimensions, Hadamard requested for CSR; SKI_ENOMEM. */
+ * dimension ldb >= k; k >= 1) and keeps it in the handle.  Errors (all found on the host,
+ * before any device work): SKI_EINVAL for n < d, d < 1, m < d, m > n' (dense with
+ * Hadamard) or m > n, m > 12288, s out of range, k < 1, bad leading dimensions, Hadamard
+ * requested for CSR; SKI_ENOMEM.  Non-finite entries of A and B are not looked for here
+ * (that would cost a pass over A); they are reported by ski_factor. */
 int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, int64_t ldb,
                const ski_params* p, void* stream);
 
 /* Step 2.  Householder QR of the sketch; forms R (FP64, diag(R) >= 0), c, and the
  * explicit inverse of R used by every later product with R^-1 (any nonsingular P
  * applied consistently keeps the implicit sketching guarantee).  SKI_ERANK if the
- * rank guard fails (the handle then holds R but cannot solve).  With qr_panel =
+ * rank guard fails (the handle then holds R but cannot solve).  SKI_EINVAL if the sketch
+ * holds a NaN or an infinity: with a transform, or with hashing, every row of [A B]
+ * enters S [A B] with a +-1 weight, so a non-finite entry anywhere in A or B shows up
+ * there (the check rides on the QR's first pass over the sketch); under row sampling
+ * without a transform only the sampled rows are seen, and ski_solve reports the rest.
+ * The handle cannot solve after an error.  With qr_panel =
  * SKI_QR_PIVOTED: the column-pivoted factorisation and its truncation to R_11
- * (p x p, p from rcond); p = 0 (a numerically zero A) gives x = 0. */
+ * (p x p, p from rcond); p = 0 (a numerically zero A) gives x = 0.  Synchronises the
+ * stream. */
 int ski_factor(ski_handle h, void* stream);
 
 /* Steps 3-5 (op = SKI_OP_LLS): B is n x k (ldb), X is d x k (ldx).  The k columns are
  * solved together but stop independently.  info: host array of k entries, or NULL.
  * Returns the worst status over the columns (SKI_WNOCONV > SKI_WEARLY > SKI_OK).
  * op = SKI_OP_NORMAL: B is G (d x k, ldb) and X receives Z = (A^T A)^-1 G; the CG
- * stops when ||rhs - M y|| <= tau_r ||rhs|| for M = R^-T A^T A R^-1. */
+ * stops when ||rhs - M y|| <= tau_r ||rhs|| for M = R^-T A^T A R^-1.
+ * SKI_EINVAL (the column's info status too) when a column's iteration meets a non-finite
+ * value: a NaN or infinity in B (LLS) or G (NORMAL), found at the first norm, so that no
+ * iterations run on it. */
 int ski_solve(ski_handle h, int32_t op, const double* B, int32_t k, int64_t ldb,
               double* X, int64_t ldx, ski_info* info, void* stream);
 

@@ -7,6 +7,7 @@ device memory and the stream; every step of the method runs in libski.so.
 """
 
 import ctypes as C
+import warnings
 
 import numpy as np
 import torch
@@ -287,11 +288,27 @@ def lstsq(A, B, **kw):
         s.close()
 
 
+def _warn_unconverged(rc, infos, where):
+    """A solve that stopped at it_max (SKI_WNOCONV) still returns its last iterate: say so."""
+    if rc == L.SKI_WNOCONV:
+        cols = [(j, i["iters"], i["tc"]) for j, i in enumerate(infos)
+                if i["status"] == L.SKI_WNOCONV]
+        warnings.warn(f"{where}: {len(cols)} column(s) reached it_max before the stopping "
+                      f"test held (column, iterations, test value): {cols[:8]}",
+                      RuntimeWarning, stacklevel=3)
+
+
 class SkiLstsq(torch.autograd.Function):
     """X = argmin ||A X - B||_F (columnwise) with a hand-written adjoint backward.
 
     Backward: Z = (A^T A)^-1 G by CG preconditioned with the forward's R, then
-    grad_B = A Z and grad_A = (B - A X) Z^T - (A Z) X^T, all in the HIP library."""
+    grad_B = A Z and grad_A = (B - A X) Z^T - (A Z) X^T, all in the HIP library.
+
+    float32 (or other floating) inputs are converted to float64 for the library, which
+    computes in FP64, and the results are converted back.  A solve (forward or adjoint)
+    that stops at it_max raises a RuntimeWarning naming the columns.  The library handle
+    (which holds the sketch, R and R^-1) lives as long as the autograd node, so backward
+    may run more than once (retain_graph=True); it is released with the graph."""
 
     @staticmethod
     def forward(ctx, A, B, opts=None):
@@ -302,6 +319,7 @@ class SkiLstsq(torch.autograd.Function):
         s = Solver()
         s.sketch(A64, B64, **opts).factor()
         X, infos, rc = s.solve()
+        _warn_unconverged(rc, infos, "SkiLstsq forward")
         ctx.solver = s
         ctx.save_for_backward(A64, B64, X)
         ctx.b_shape = B.shape
@@ -315,11 +333,10 @@ class SkiLstsq(torch.autograd.Function):
         A64, B64, X = ctx.saved_tensors
         s = ctx.solver
         G = gX.detach().to(torch.float64).reshape(X.shape).contiguous()
-        Z, _, _ = s.solve_normal(G)
+        Z, zinfos, zrc = s.solve_normal(G)
+        _warn_unconverged(zrc, zinfos, "SkiLstsq backward (adjoint solve)")
         gA, gB = s.gradients(X, B64, Z, want_A=ctx.needs_input_grad[0],
                              want_B=ctx.needs_input_grad[1])
-        s.close()
-        ctx.solver = None
         if gA is not None:
             gA = gA.to(ctx.in_dtype)
         if gB is not None:

@@ -536,6 +536,14 @@ __global__ __launch_bounds__(1024) void k_lsqr_init(LsqrState* __restrict__ stt,
     LsqrState& S = stt[j];
     if (S.done) return;
     const double beta = sqrt(S.beta2);
+    if (!isfinite(beta)) {  // r_0 is not finite: the right-hand side holds a NaN or infinity
+        if (threadIdx.x == 0) {
+            S.rnorm = beta;
+            S.done = 1;
+            S.status = SKI_EINVAL;
+        }
+        return;
+    }
     if (beta <= tau_a) {  // Step 3: early exit with x_s
         if (threadIdx.x == 0) {
             S.rnorm = beta;
@@ -571,6 +579,9 @@ __global__ __launch_bounds__(1024) void k_lsqr_init(LsqrState* __restrict__ stt,
         if (alpha == 0.0) {  // A^T r_0 = 0: x_s is optimal
             S.done = 1;
             S.status = SKI_OK;
+        } else if (!isfinite(alpha)) {
+            S.done = 1;
+            S.status = SKI_EINVAL;
         }
     }
 }
@@ -699,7 +710,11 @@ __global__ __launch_bounds__(1024) void k_lsqr_step(LsqrState* __restrict__ stt,
         S.arnorm = arnorm;
         S.tc = tc;
         S.iters = iters_old + 1;
-        if (phibar_n == 0.0 || arnorm == 0.0 || tc <= tau_r) {
+        if (!isfinite(alpha) || !isfinite(beta) || !isfinite(tc)) {
+            // a non-finite iterate never meets (TC-lsqr): stop at once
+            S.done = 1;
+            S.status = SKI_EINVAL;
+        } else if (phibar_n == 0.0 || arnorm == 0.0 || tc <= tau_r) {
             S.done = 1;
             S.status = SKI_OK;
         } else if (iters_old + 1 >= it_max) {
@@ -777,8 +792,8 @@ __global__ __launch_bounds__(1024) void k_cg_init(LsqrState* __restrict__ stt, i
         S.stop2 = tol * tol * rr;
         S.iters = 0;
         S.rnorm = sqrt(rr);
-        S.done = (rr <= S.stop2 || rr == 0.0) ? 1 : 0;
-        S.status = SKI_OK;
+        S.done = (rr <= S.stop2 || rr == 0.0 || !isfinite(rr)) ? 1 : 0;
+        S.status = isfinite(rr) ? SKI_OK : SKI_EINVAL;
         S.early = 0;
     }
 }
@@ -856,7 +871,10 @@ __global__ __launch_bounds__(1024) void k_cg_step(LsqrState* __restrict__ stt, i
         S.rr = rr_new;
         S.iters = iters_old + 1;
         S.rnorm = sqrt(rr_new);
-        if (rr_new <= stop2) {
+        if (!isfinite(rr_new) || !isfinite(a)) {
+            S.done = 1;
+            S.status = SKI_EINVAL;
+        } else if (rr_new <= stop2) {
             S.done = 1;
             S.status = SKI_OK;
         } else if (iters_old + 1 >= it_max) {

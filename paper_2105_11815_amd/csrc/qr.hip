@@ -309,18 +309,27 @@ __global__ __launch_bounds__(256) void k_apply_Tinv(const T* __restrict__ Wt, in
     }
 }
 
-// row-major m x n -> column-major (ld m), 64 x 64 tiles through LDS
+// row-major m x n -> column-major (ld m), 64 x 64 tiles through LDS.  *nonfinite is set
+// to 1 when an entry is not finite (a NaN or an infinity anywhere in [A B] reaches the
+// sketch: each row of the transformed matrix enters s sketch rows with a +-1 weight, so
+// this check costs no pass of its own)
 template <typename T>
 __global__ __launch_bounds__(256) void k_to_colmajor(const T* __restrict__ A, int64_t m,
-                                                     int64_t n, T* __restrict__ Ac) {
+                                                     int64_t n, T* __restrict__ Ac,
+                                                     int* __restrict__ nonfinite) {
     __shared__ T tile[64][65];
     const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    int bad = 0;
     for (int i = ty; i < 64; i += 4) {
         const int64_t r = r0 + i, c = c0 + tx;
-        if (r < m && c < n) tile[i][tx] = A[r * n + c];
+        if (r < m && c < n) {
+            const T v = A[r * n + c];
+            bad |= !isfinite(v);
+            tile[i][tx] = v;
+        }
     }
-    __syncthreads();
+    if (__syncthreads_or(bad) && threadIdx.x == 0) *nonfinite = 1;
     for (int i = ty; i < 64; i += 4) {
         const int64_t c = c0 + i, r = r0 + tx;
         if (r < m && c < n) Ac[c * m + r] = tile[tx][i];
@@ -644,9 +653,10 @@ template <typename T>
 hipError_t qr_impl(const T* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws, bool bf16,
                    hipStream_t st) {
     T* Ac = (T*)ws.Ac;  // column-major working copy, ld = m
+    SKI_HIP(cqr_clear_flag(ws.nonfinite, st));
     hipLaunchKernelGGL((k_to_colmajor<T>),
                        dim3((unsigned)((ncols + 63) / 64), (unsigned)((m + 63) / 64)), dim3(256), 0,
-                       st, SA, m, ncols, Ac);
+                       st, SA, m, ncols, Ac, ws.nonfinite);
     SKI_HIP(hipGetLastError());
     if (ws.cqr_panels) return qr_impl_cqr<T>(Ac, m, ncols, d, ws, bf16, st);
     return qr_impl_hh<T>(Ac, m, ncols, d, ws, bf16, st);
@@ -697,6 +707,7 @@ uintptr_t qr_ws_layout(Prec prec, uintptr_t base, int64_t m, int64_t ncols, QrWs
     ws.cqr.W = take(NBP * NBP);
     ws.cqr.tau = ws.tau;
     ws.cqr.flag = (int*)take(1);
+    ws.nonfinite = (int*)take(1);
     return p;
 }
 
@@ -724,9 +735,10 @@ hipError_t qr_factor_pivoted(const double* SA, int64_t m, int64_t ncols, int64_t
                              PivWs& pw, uint64_t seed, bool cqr, HostFlag& pf, int* panels_cqr,
                              hipStream_t st) {
     double* Ac = (double*)ws.Ac;
+    SKI_HIP(cqr_clear_flag(ws.nonfinite, st));
     hipLaunchKernelGGL((k_to_colmajor<double>),
                        dim3((unsigned)((ncols + 63) / 64), (unsigned)((m + 63) / 64)), dim3(256), 0,
-                       st, SA, m, ncols, Ac);
+                       st, SA, m, ncols, Ac, ws.nonfinite);
     SKI_HIP(hipGetLastError());
     return qr_impl_pivoted(Ac, m, ncols, d, ws, pw, seed, cqr, pf, panels_cqr, st);
 }

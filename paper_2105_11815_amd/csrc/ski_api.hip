@@ -528,12 +528,16 @@ int ski_factor(ski_handle h, void* stream) {
         if (h->hdiag) (void)hipHostFree(h->hdiag);
         h->hdiag = nullptr;
         h->hdiag_n = 0;
-        // 2d doubles: diag(R), then the perturbation; one more slot for the panel flag
-        SKI_TRY(h, hipHostMalloc((void**)&h->hdiag, (2 * d + 1) * 8, hipHostMallocDefault),
+        // 2d doubles: diag(R), then the perturbation; then the panel flag and the
+        // non-finite flag (one slot each)
+        SKI_TRY(h, hipHostMalloc((void**)&h->hdiag, (2 * d + 2) * 8, hipHostMallocDefault),
                 "pinned");
         h->hdiag_n = d;
     }
     int* hflag = (int*)(h->hdiag + 2 * d);
+    int* hnonfinite = (int*)(h->hdiag + 2 * d + 1);
+    const char* nonfinite_msg =
+        "ski_factor: the sketch holds a non-finite entry (A or B is not finite)";
     const bool cod = h->p.qr_panel == SKI_QR_PIVOTED_COD;
     const bool piv = h->p.qr_panel == SKI_QR_PIVOTED ||
                      h->p.qr_panel == SKI_QR_PIVOTED_HOUSEHOLDER || cod;
@@ -569,7 +573,10 @@ int ski_factor(ski_handle h, void* stream) {
                 "diag copy");
         SKI_TRY(h, hipMemcpyAsync(h->pivd.p, pw.perm, d * 4, hipMemcpyDeviceToDevice, st),
                 "perm copy");
+        SKI_TRY(h, hipMemcpyAsync(hnonfinite, ws.nonfinite, sizeof(int), hipMemcpyDeviceToHost, st),
+                "flag copy");
         SKI_TRY(h, hipStreamSynchronize(st), "sync");
+        if (*hnonfinite) return fail(h, SKI_EINVAL, nonfinite_msg);
     }
     bool cqr = h->p.qr_panel == SKI_QR_AUTO;
     // without pivoting, in FP64, R_h^-1 is formed block by block on a third stream while the
@@ -599,7 +606,10 @@ int ski_factor(ski_handle h, void* stream) {
         if (cqr)
             SKI_TRY(h, hipMemcpyAsync(hflag, ws.cqr.flag, sizeof(int), hipMemcpyDeviceToHost, st),
                     "flag copy");
+        SKI_TRY(h, hipMemcpyAsync(hnonfinite, ws.nonfinite, sizeof(int), hipMemcpyDeviceToHost, st),
+                "flag copy");
         SKI_TRY(h, hipStreamSynchronize(st), "sync");
+        if (*hnonfinite) return fail(h, SKI_EINVAL, nonfinite_msg);
         if (cqr && *hflag != 0) {
             // a panel was too ill-conditioned for CholeskyQR2: factor again column by column
             cqr = false;
@@ -610,7 +620,7 @@ int ski_factor(ski_handle h, void* stream) {
     const double* Rd = h->hdiag;
     bool finite = true;
     for (int64_t i = 0; i < d; ++i) finite = finite && std::isfinite(Rd[i]);
-    if (!finite) return fail(h, SKI_EINVAL, "ski_factor: non-finite R (non-finite input?)");
+    if (!finite) return fail(h, SKI_EINVAL, "ski_factor: non-finite R (overflow in the QR)");
     if (piv) {
         // p = the leading diagonal entries with |r_qq| >= rcond |r_11| (all non-zero ones
         // when rcond = 0): R_11 ends at the first entry below the threshold
@@ -729,11 +739,10 @@ int alloc_solve_ws(ski_handle h, int k) {
     const int64_t G = std::max<int64_t>({PASS_WG, spmv_csr_groups(n), 1});
     SKI_TRY(h, ensure(h->upart, G * k * 8), "alloc");
     SKI_TRY(h, ensure(h->st, k * sizeof(LsqrState)), "alloc");
-    if (!h->done_cnt.p) {
-        // zeroed once; every step that uses it leaves it at zero again
-        SKI_TRY(h, ensure(h->done_cnt, 256), "alloc");
-        SKI_TRY(h, hipMemset(h->done_cnt.p, 0, 256), "clear");
-    }
+    // the arrival counter of the step kernels' status word: every step that uses it leaves
+    // it at zero; it is cleared again here (on the solve's stream) so that a solve never
+    // depends on how an earlier one ended
+    SKI_TRY(h, ensure(h->done_cnt, 256), "alloc");
     if (h->pivoted) SKI_TRY(h, ensure(h->ptmp, d * k * 8), "alloc");
     return SKI_OK;
 }
@@ -839,9 +848,12 @@ int finish_info(ski_handle h, int k, ski_info* info, float ms_solve, bool cg, hi
         (void)hipEventElapsedTime(&ms_f, h->ev[2], h->ev[3]);
     }
     int worst = SKI_OK;
+    bool nonfinite = false;
     for (int j = 0; j < k; ++j) {
         const int stj = S[j].done ? S[j].status : SKI_WNOCONV;
-        if (stj == SKI_WNOCONV)
+        if (stj == SKI_EINVAL)
+            nonfinite = true;
+        else if (stj == SKI_WNOCONV)
             worst = SKI_WNOCONV;
         else if (stj == SKI_WEARLY && worst == SKI_OK)
             worst = SKI_WEARLY;
@@ -865,6 +877,10 @@ int finish_info(ski_handle h, int k, ski_info* info, float ms_solve, bool cg, hi
         for (int j = 0; j < k; ++j) all_early = all_early && S[j].early;
         if (!all_early) worst = SKI_OK;
     }
+    if (nonfinite)
+        return fail(h, SKI_EINVAL,
+                    cg ? "ski_solve: a non-finite value in the iteration (G is not finite)"
+                       : "ski_solve: a non-finite value in the iteration (B is not finite)");
     return worst;
 }
 
@@ -889,6 +905,7 @@ int solve_lls(ski_handle h, const double* B, int k, int64_t ldb, double* X, int6
     if (h->ev_ok) (void)hipEventRecord(e0, st);
     const int64_t dp = h->rank;  // the LSQR vectors v, h, delta, y live in R^p
     SKI_TRY(h, hipMemsetAsync(S, 0, k * sizeof(LsqrState), st), "state init");
+    SKI_TRY(h, hipMemsetAsync(h->done_cnt.p, 0, 256, st), "counter init");
     // with pivoting z = V_1 (...) is zero outside the kept columns
     if (h->pivoted) SKI_TRY(h, launch_fill_rows(z, d, k, k, 0.0, st), "zero z");
     // u = B (the residual is formed in place), z = -x_s
@@ -1030,6 +1047,7 @@ int solve_normal(ski_handle h, const double* G, int k, int64_t ldg, double* Z, i
     if (h->ev_ok) (void)hipEventRecord(e0, st);
     const int64_t dp = h->rank;  // CG runs in R^p (p = d without pivoting)
     SKI_TRY(h, hipMemsetAsync(S, 0, k * sizeof(LsqrState), st), "state init");
+    SKI_TRY(h, hipMemsetAsync(h->done_cnt.p, 0, 256, st), "counter init");
     if (h->pivoted) SKI_TRY(h, launch_fill_rows(z, d, k, k, 0.0, st), "zero z");
     // rhs = R^-T G (into wp, compact leading dimension k)
     SKI_TRY(h, launch_scale_copy(G, d, k, ldg, 1.0, g, k, st), "copy g");

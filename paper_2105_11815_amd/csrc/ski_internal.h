@@ -263,6 +263,7 @@ struct QrWs {
     void* Tp2 = nullptr;
     void* Tl = nullptr;   // the current leaf's T
     void* tau = nullptr;
+    int* nonfinite = nullptr;  // set to 1 when the sketch holds a non-finite entry
     CqrWs cqr;            // panel factorisation by CholeskyQR2 (when cqr_panels)
     bool cqr_panels = true;
     GemmWs g;             // split-K partials, caller's stream
@@ -291,8 +292,6 @@ size_t qr_ws_bytes(Prec prec, int64_t m, int64_t ncols, size_t* gemm_bytes);
 void qr_ws_carve(Prec prec, void* base, int64_t m, int64_t ncols, QrWs& ws);
 hipError_t qr_factor(Prec prec, const void* SA, int64_t m, int64_t ncols, int64_t d, QrWs& ws,
                      hipStream_t st);
-// FP64 QR with column pivoting of the first d columns (the last ncols - d ride along),
-// pivots chosen on the sketch of rcpqr.hip, the permutation in pw.perm.  Panels by
 // A word of mapped, coherent pinned host memory that a kernel writes and the host polls:
 // the host learns a device flag without a copy and a stream synchronisation.  host and dev
 // are the two addresses of the same word (zero when allocated); seq counts publications.
@@ -307,6 +306,8 @@ hipError_t launch_publish_flag(const int* src, HostFlag& f, hipStream_t st);
 // The stream is queried while waiting, so an error on st (or st running dry without the
 // word appearing) ends the wait with an error instead of a hang.
 hipError_t wait_flag(HostFlag& f, hipStream_t st, int* flag);
+// FP64 QR with column pivoting of the first d columns (the last ncols - d ride along),
+// pivots chosen on the sketch of rcpqr.hip, the permutation in pw.perm.  Panels by
 // CholeskyQR2 (cqr) with a per-panel fallback to Householder columns, or Householder
 // columns only; pf: the host word through which each panel's flag is read (the host waits
 // for it once per panel when cqr is set); panels_cqr (may be null) receives the number of

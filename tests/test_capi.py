@@ -82,6 +82,14 @@ def test_invalid_arguments_are_rejected_on_the_host():
         setattr(q, field, val)
         assert lib.ski_sketch(h, C.byref(M), fake, 1, 1, C.byref(q), None) == L.SKI_EINVAL, field
     assert lib.ski_sketch(h, C.byref(M), fake, 0, 1, C.byref(p), None) == L.SKI_EINVAL  # k < 1
+    # the declared limit m <= 12288 (n' = 32768 would allow more)
+    Mbig = L.SkiMatrix(n=20000, d=10, kind=L.SKI_DENSE, a=fake.value, lda=10, row_ptr=None,
+                       col=None, val=None, nnz=0)
+    q = L.SkiParams()
+    lib.ski_params_default(L.SKI_DENSE, C.byref(q))
+    q.m = 12289
+    assert lib.ski_sketch(h, C.byref(Mbig), fake, 1, 1, C.byref(q), None) == L.SKI_EINVAL
+    assert b"12288" in lib.ski_last_error(h)
     Mc = L.SkiMatrix(n=100, d=10, kind=L.SKI_CSR, a=None, lda=0, row_ptr=fake.value,
                      col=fake.value, val=fake.value, nnz=10)
     assert lib.ski_sketch(h, C.byref(Mc), fake, 1, 1, C.byref(p), None) == L.SKI_EINVAL  # H+CSR

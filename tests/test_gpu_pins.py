@@ -1,0 +1,305 @@
+"""Parity pins for what an end-to-end solution cannot show.
+
+By the implicit sketching guarantee (Section 5) any nonsingular preconditioner R still
+leads LSQR to x*, so a wrong sketch or a wrong R would only cost iterations.  These tests
+therefore compare the intermediate results themselves with the oracle, on the code paths
+that the benchmark runs: the sketch over several column slabs, the QR over twenty panels
+with R^-1 formed on its own stream, the FP32 and BF16 sketches and factors, the iteration
+count at full size, the ill-conditioned 50000 x 7000 workload, and FP32 input to the
+autograd function."""
+
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import lls, sketch as sk
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+U32 = 2.0 ** -24    # unit roundoff of FP32
+UBF = 2.0 ** -8     # unit roundoff of BF16
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ski():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2105_11815_amd as P
+    return P
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def _coherent(n, d, k, seed):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, d))
+    A[: n // 5] *= 1e3
+    return A, rng.standard_normal((n, k))
+
+
+# ------------------------------------------------------------------ sketch, several slabs
+def test_dense_sketch_bitexact_over_several_slabs(ski):
+    """n' = 65536 and d + k = 702 columns: the FP64 transform runs over three column slabs
+    of at most 256 columns (128 MB each), and the last slab holds B; the sketch, the
+    hashing and D must still be the oracle's, bit for bit."""
+    n, d, k, m, s = 33000, 700, 2, 1190, 3
+    _say(f"multi-slab sketch n={n} d={d} k={k} m={m} s={s}")
+    A, B = _coherent(n, d, k, 21)
+    seed = 2021
+    ref = sk.sketch_dense(A, B, m, s, seed)
+    S = ski.Solver()
+    S.sketch(dev(A), dev(B), m=m, s=s, seed=seed, hadamard=True)
+    hsh = S.get_hash()
+    np.testing.assert_array_equal(hsh["bucket_ptr"], ref["bucket_ptr"])
+    np.testing.assert_array_equal(hsh["src"], ref["src"])
+    np.testing.assert_array_equal(hsh["src_neg"], ref["src_neg"])
+    np.testing.assert_array_equal(S.get_dsign(), ref["dsign"])
+    np.testing.assert_array_equal(S.get_SA(), ref["SA_aug"])
+    S.close()
+
+
+# ------------------------------------------------------------------ QR over many panels
+@pytest.mark.parametrize("panel", ["auto", "householder"])
+def test_qr_over_twenty_one_panels_matches_oracle(ski, panel):
+    """m = 2300, d = 1300: 21 panels, so the look-ahead, the second stream's trailing
+    updates and the third stream's blocks of R^-1 all run many times; R, c and R^-1 against
+    the oracle's QR of the same (bit-identical) sketch."""
+    n, d, m, s = 4000, 1300, 2300, 2
+    _say(f"qr 21 panels n={n} d={d} m={m} panel={panel}")
+    A, B = _coherent(n, d, 1, 1300)
+    b = B[:, 0]
+    ref = sk.sketch_dense(A, b, m, s, 77)
+    Rref, cref, _ = lls.factor(ref["SA_aug"], d)
+    S = ski.Solver()
+    S.set_profiling(True)
+    S.sketch(dev(A), dev(b), m=m, s=s, seed=77, qr_panel=0 if panel == "auto" else 1)
+    np.testing.assert_array_equal(S.get_SA(), ref["SA_aug"])  # the QR starts from the same bits
+    S.factor()
+    prof = S.profile()
+    assert (prof["qr"][1], prof["qr_householder"][1]) == ((1, 0) if panel == "auto" else (0, 1))
+    R, c, Ri = S.get_R()
+    scale = np.abs(Rref).max()
+    err_R = np.abs(R - Rref).max() / scale
+    err_c = np.abs(c - cref).max() / np.abs(cref).max()
+    # the inverse against its definition, R R^-1 = I, and against the oracle's inverse
+    Ri_ref = np.linalg.inv(Rref)
+    err_I = np.abs(R @ Ri - np.eye(d)).max()
+    err_Ri = np.abs(Ri - Ri_ref).max() / np.abs(Ri_ref).max()
+    condR = np.linalg.cond(Rref)
+    _say(f"  R {err_R:.2e}  c {err_c:.2e}  R Rinv - I {err_I:.2e}  Rinv {err_Ri:.2e} "
+         f"(cond R {condR:.1f})")
+    # backward-stable Householder QRs of one matrix agree to O(u cond) row by row; the
+    # bound 1e-12 sqrt(d) holds with a wide margin for cond(R) ~ 5
+    assert err_R <= 1e-12 * math.sqrt(d)
+    assert err_c <= 1e-12 * math.sqrt(d)
+    assert err_I <= 1e-13 * condR * math.sqrt(d)
+    assert err_Ri <= 1e-12 * condR * math.sqrt(d)
+    S.close()
+
+
+# ------------------------------------------------------------------ FP32 and BF16 forms
+def _mixed_bounds(prec, npad, tmax, m):
+    """Normwise bounds (first order, see the design notes) for the low-precision sketch:
+    one rounding of A to the storage type, sqrt(2) u per butterfly stage over log2(n')
+    stages, and the bucket sums of at most tmax entries, each rounding at most u times the
+    sum of magnitudes (a bound of tmax u on the normwise error; random signs make it
+    ~sqrt(tmax) u in practice).  BF16 stores the transform twice (after each of its two
+    passes) and FP32 carries the arithmetic."""
+    L = int(round(math.log2(npad)))
+    arith = (1 + math.sqrt(2) * L + tmax) * U32
+    if prec == "fp32":
+        return arith
+    return arith + 2 * UBF
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_low_precision_sketch_and_factor_against_fp64_oracle(ski, prec):
+    """The FP32 and BF16 sketch (n' = 65536, two slabs in FP32 storage) and R from the
+    low-precision QR, against the oracle's FP64 sketch of the same S:
+    ||SA_low - SA|| / ||SA|| within the rounding bound of the transform and the sums, and
+    ||R^T R - (SA)^T SA|| / ||SA||^2 within 2 (that bound + the QR's backward error);
+    then the iteration count of the solve against the FP64 form's."""
+    n, d, k, m, s = 33000, 600, 1, 1020, 3
+    _say(f"{prec} sketch and factor n={n} d={d} m={m}")
+    A, B = _coherent(n, d, k, 600)
+    seed = 2600
+    ref = sk.sketch_dense(A, B, m, s, seed)
+    SA = ref["SA_aug"]
+    tmax = int(np.diff(ref["bucket_ptr"]).max())
+    S = ski.Solver()
+    S.sketch(dev(A), dev(B), m=m, s=s, seed=seed, hadamard=True, sketch_prec=prec,
+             qr_prec=prec, tau_r=1e-10)
+    SAl = S.get_SA()
+    e_sk = np.linalg.norm(SAl - SA) / np.linalg.norm(SA)
+    bound_sk = _mixed_bounds(prec, ref["npad"], tmax, m)
+    S.factor()
+    R, c, _ = S.get_R()
+    SAd = SA[:, :d]
+    G = SAd.T @ SAd
+    e_R = np.linalg.norm(R.T @ R - G) / np.linalg.norm(SAd) ** 2
+    # the QR's backward error ||dA||_F <= c sqrt(m) u ||A||_F in the probabilistic model of
+    # rounding errors (Higham and Mary, 2019), c = 8, in FP32 (the panels; all of the FP32
+    # QR); the BF16 form also rounds both operands of each panel's two trailing products to
+    # BF16, about 2 u_bf16 per panel, adding up like a random walk over the panels
+    panels = -(-d // 64)
+    delta = bound_sk + 8 * math.sqrt(m) * U32
+    if prec == "bf16":
+        delta += 2 * math.sqrt(panels) * UBF
+    bound_R = 2 * delta + delta ** 2
+    _say(f"  sketch error {e_sk:.2e} (bound {bound_sk:.2e}); factor {e_R:.2e} "
+         f"(bound {bound_R:.2e})")
+    assert e_sk <= bound_sk
+    assert e_R <= bound_R
+    X, infos, rc = S.solve()
+    S.close()
+    S64 = ski.Solver()
+    S64.sketch(dev(A), dev(B), m=m, s=s, seed=seed, hadamard=True, tau_r=1e-10).factor()
+    X64, infos64, rc64 = S64.solve()
+    R64 = S64.get_R()[0]
+    S64.close()
+    assert rc == 0 and rc64 == 0
+    # the preconditioned matrix: kappa(A R^-1) for both factors (host SVDs); LSQR's
+    # convergence factor per step is (kappa - 1) / (kappa + 1), so the step count scales by
+    # log rho(kappa_64) / log rho(kappa_low)
+    def kappa(Rm):
+        sv = np.linalg.svd(np.linalg.solve(Rm.T, A.T).T, compute_uv=False)
+        return sv[0] / sv[-1]
+    k64, klow = kappa(R64), kappa(R)
+    rho = lambda kk: (kk - 1) / (kk + 1)
+    ratio = math.log(rho(k64)) / math.log(rho(klow))
+    it, it64 = infos[0]["iters"], infos64[0]["iters"]
+    _say(f"  kappa(A R^-1) {klow:.4f} against {k64:.4f} in FP64; iterations {it} against "
+         f"{it64} (predicted ratio {ratio:.3f})")
+    assert it <= math.ceil(it64 * ratio * 1.1) + 2
+
+
+# ------------------------------------------------------------------ full-size iterations
+def test_full_size_dense_iterations_match_the_oracle(ski):
+    """The dense 50000 x 4000 workload with the benchmark's sketch (m 6800, s 3, seed 2002)
+    at tau_r = 1e-10: the GPU's LSQR stops within one step of the oracle's own run of
+    Algorithm 1 (tests/golden/make_dense_iters.py)."""
+    rec = {}
+    for line in open(os.path.join(GOLDEN, "dense_50000x4000_oracle_run.txt")):
+        if ":" in line and not line.startswith("#"):
+            key, val = line.split(":", 1)
+            rec[key.strip()] = float(val)
+    c = workloads.CASES["dense"]
+    _say(f"full-size dense iterations against the oracle's {int(rec['iters'])}")
+    A, b = workloads.dense_coherent(n=c["n"], d=c["d"], case=c["case"])
+    S = ski.Solver()
+    S.sketch(dev(A), dev(b), m=c["m"], s=c["s"], seed=2002, tau_r=1e-10).factor()
+    X, infos, rc = S.solve()
+    S.close()
+    it = infos[0]["iters"]
+    _say(f"  GPU {it} iterations, rnorm {infos[0]['rnorm']:.12e} "
+         f"(oracle {rec['rnorm']:.12e})")
+    assert rc == 0
+    assert abs(it - int(rec["iters"])) <= 1
+    assert abs(infos[0]["rnorm"] - rec["rnorm"]) <= 1e-10 * rec["rnorm"]
+
+
+# ------------------------------------------------------------------ ill-conditioned
+@pytest.fixture(scope="module")
+def illcond_problem():
+    """The ill-conditioned 50000 x 7000 workload generated on the host (so that the oracle
+    and the GPU see the same bits), with the oracle's direct solution."""
+    c = workloads.CASES["illcond"]
+    _say("generating the 50000 x 7000 ill-conditioned workload on the host ...")
+    At, bt = workloads.illcond(n=c["n"], d=c["d"], case=c["case"], device="cpu")
+    A, b = At.numpy(), bt.numpy()
+    _say("oracle: direct Householder solve ...")
+    xs = lls.lstsq_direct(A, b)
+    rs = b - A @ xs
+    return A, b, xs, float(np.linalg.norm(rs)), float(np.linalg.norm(A))
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_illcond_full_size_against_the_oracle(ski, illcond_problem, prec):
+    """cond(A) = 1e8, ||r*|| ~ 207: x itself is determined only to ~u cond^2 ||r|| / ||A x||
+    (about 2e-7 relative) by any FP64 solver, so the pins are the residual norm against the
+    oracle's direct solution (1e-10 relative), the optimality certificate within the bound
+    that (TC-lsqr) implies, and the x error reported beside that floor.  d = 7000 runs the
+    widest fused pass (32 column blocks of 4 per thread)."""
+    A, b, xs, rnorm_ref, anorm = illcond_problem
+    c = workloads.CASES["illcond"]
+    At, bt = dev(A), dev(b)
+    kw = dict(m=c["m"], s=c["s"], seed=2004, tau_r=1e-10, hadamard=True)
+    if prec != "fp64":
+        kw.update(sketch_prec=prec, qr_prec=prec, it_max=3000)
+    S = ski.Solver()
+    S.sketch(At, bt, **kw).factor()
+    X, infos, rc = S.solve()
+    R = S.get_R()[0]
+    S.close()
+    x = X[:, 0]
+    r = bt - At @ x
+    rn = float(r.norm())
+    cert = float((At.T @ r).norm()) / (anorm * rn)
+    bound = 1e-10 * np.linalg.norm(R, 2) * infos[0]["wnorm_est"] / anorm + 1e-11
+    xerr = float((x.cpu() - torch.as_tensor(xs)).norm() / np.linalg.norm(xs))
+    _say(f"  {prec}: status {rc}, {infos[0]['iters']} iterations, |r| {rn:.12e} "
+         f"(oracle {rnorm_ref:.12e}), certificate {cert:.2e} (bound {bound:.2e}), "
+         f"x error {xerr:.2e}")
+    del At, bt
+    torch.cuda.empty_cache()
+    assert rc == 0
+    assert abs(rn - rnorm_ref) <= 1e-10 * rnorm_ref
+    assert cert <= bound
+    assert xerr <= 1e-5
+
+
+# ------------------------------------------------------------------ FP32 autograd input
+def test_autograd_function_with_fp32_input(ski):
+    """float32 A and B: the library computes in FP64 on the converted values and the
+    results come back as float32; against the oracle's closed form on the same (converted)
+    values, to the FP32 rounding of the outputs."""
+    n, d, k = 3000, 80, 3
+    A, B, G = workloads.batched(n=n, d=d, k=k, case=5)
+    A32, B32 = A.astype(np.float32), B.astype(np.float32)
+    At = dev(A32, torch.float32).requires_grad_(True)
+    Bt = dev(B32, torch.float32).requires_grad_(True)
+    X = ski.SkiLstsq.apply(At, Bt, dict(gamma=1.7, s=3, seed=3, tau_r=1e-14))
+    assert X.dtype == torch.float32
+    (X * dev(G, torch.float32)).sum().backward()
+    assert At.grad.dtype == torch.float32 and Bt.grad.dtype == torch.float32
+    A64, B64 = A32.astype(np.float64), B32.astype(np.float64)
+    G64 = G.astype(np.float32).astype(np.float64)
+    Xd = lls.lstsq_direct(A64, B64)
+    gA_ref, gB_ref, _ = lls.grads_closed_form(A64, Xd, B64, G64)
+    tol = 4 * U32
+    np.testing.assert_allclose(X.detach().cpu().numpy(), Xd, rtol=0, atol=tol * np.abs(Xd).max())
+    np.testing.assert_allclose(At.grad.cpu().numpy(), gA_ref, rtol=0,
+                               atol=tol * np.abs(gA_ref).max())
+    np.testing.assert_allclose(Bt.grad.cpu().numpy(), gB_ref, rtol=0,
+                               atol=tol * np.abs(gB_ref).max())
+
+
+def test_autograd_backward_twice_with_retained_graph(ski):
+    """retain_graph=True: the handle stays with the graph, so a second backward gives the
+    same gradients; a solve that stops at it_max warns."""
+    n, d, k = 2000, 60, 2
+    A, B, G = workloads.batched(n=n, d=d, k=k, case=5)
+    At = dev(A).requires_grad_(True)
+    X = ski.SkiLstsq.apply(At, dev(B), dict(gamma=1.7, s=3, seed=3, tau_r=1e-14))
+    loss = (X * dev(G)).sum()
+    loss.backward(retain_graph=True)
+    g1 = At.grad.clone()
+    At.grad = None
+    loss.backward()
+    assert torch.equal(g1, At.grad)
+    with pytest.warns(RuntimeWarning, match="it_max"):
+        ski.SkiLstsq.apply(dev(A), dev(B), dict(gamma=1.7, s=3, seed=3, tau_r=1e-14, it_max=2))
