@@ -229,7 +229,30 @@ int ski_gradients(ski_handle h, const double* X, int64_t ldx, const double* B, i
                   const double* Z, int64_t ldz, int32_t k, double* grad_A, int64_t ldga,
                   double* grad_B, int64_t ldgb, void* stream);
 
+/* Message of the handle's last error.  With h = NULL: the message of the last failed
+ * ski_sketch_noalloc call on this host thread ("null handle" if there is none). */
 const char* ski_last_error(ski_handle h);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): Step 1 as ski_sketch computes it, with
+ * no handle and no allocation.  Writes SA = S [A B] (m x (d+k), FP64, row-major,
+ * leading dimension d+k; caller-owned device buffer) for the S that (m, s, seed,
+ * hadamard, hash_kind) define; the result equals the sketch ski_sketch forms from the
+ * same arguments, bit for bit.  A: SKI_DENSE (row-major) or SKI_CSR; B: n x k device
+ * (ldb >= k).  hadamard must be 0 or 1; sketch_prec and qr_prec must be SKI_FP64.
+ * Scratch: the hash keys, their bucket sort, the D sign bits and the transform's column
+ * slab live in one static device array of 64 MiB that the library holds on every GPU it
+ * runs on until the process ends (its address is looked up on the first call on each
+ * device, which must be the current device).  Limit: the hash buffers (10 bytes per key,
+ * n' s keys, plus 4 m bytes per 4096 keys and 4 (m + 1) bytes) and, with the Hadamard
+ * transform, a slab of 16 columns of n' doubles (n' <= 2^19) must fit in it; larger
+ * problems are refused with SKI_EINVAL before any device work.  Every call on one GPU
+ * shares that array: calls that overlap on one GPU (two streams, two threads) race and
+ * must be serialised by the caller.  Asynchronous on `stream`; nothing is synchronised.
+ * Returns SKI_OK, SKI_EINVAL (arguments, sizes; message from ski_last_error(NULL)) or
+ * SKI_EDEVICE (a launch failed). */
+int ski_sketch_noalloc(const ski_matrix* A, const double* B, int32_t k, int64_t ldb,
+                       const ski_params* p, double* SA, void* stream);
 
 /* Test and inspection getters: HOST copies, synchronous.
  *   dims: n, d, k, m, n' (padded rows, = n without Hadamard), s.

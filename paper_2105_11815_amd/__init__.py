@@ -5,4 +5,4 @@ The computation lives in the HIP library libski.so (C interface in include/ski.h
 this package is its Python binding.
 """
 
-from .api import Solver, SkiError, SkiLstsq, lstsq, params  # noqa: F401
+from .api import Solver, SkiError, SkiLstsq, lstsq, params, sketch_noalloc  # noqa: F401

@@ -25,7 +25,7 @@ EXPORTED = ["ski_create", "ski_destroy", "ski_params_default", "ski_sketch", "sk
             "ski_solve", "ski_gradients", "ski_last_error", "ski_get_dims", "ski_get_hash",
             "ski_get_dsign", "ski_get_SA", "ski_get_R", "ski_set_profiling",
             "ski_set_profiling_mask", "ski_get_profile", "ski_get_pivots",
-            "ski_get_factor_stats"]
+            "ski_get_factor_stats", "ski_sketch_noalloc"]
 PROF_CLASSES = 16
 PROF_NAMES = ["lsqr_pass", "pass_reduce", "tri_gemv", "spmv_csr", "spmv_csrT", "lsqr_step",
               "hash", "wht_gather", "gather", "qr", "trtri", "qr_householder", "qr_pivoted"]
@@ -91,6 +91,8 @@ def load():
     lib.ski_get_profile.argtypes = [H, P, P]
     lib.ski_get_pivots.argtypes = [H, P, P]
     lib.ski_get_factor_stats.argtypes = [H, P]
+    lib.ski_sketch_noalloc.argtypes = [C.POINTER(SkiMatrix), P, i32, i64, C.POINTER(SkiParams),
+                                       P, P]
     for name in EXPORTED:
         if name not in ("ski_params_default", "ski_last_error"):
             getattr(lib, name).restype = C.c_int

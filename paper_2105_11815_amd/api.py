@@ -62,6 +62,61 @@ def params(kind="dense", **kw):
     return p
 
 
+def _matrix(A):
+    """ski_matrix for a dense float64 CUDA tensor (row- or column-major) or for
+    ('csr', row_ptr, col, val, (n, d)); returns (matrix, kind, tensors to keep alive)."""
+    if isinstance(A, tuple) and A[0] == "csr":
+        _, rp, ci, va, (n, d) = A
+        _check_dev(rp, "row_ptr", torch.int64)
+        _check_dev(ci, "col", torch.int32)
+        _check_dev(va, "val", torch.float64)
+        M = L.SkiMatrix(n=n, d=d, kind=L.SKI_CSR, a=None, lda=0, row_ptr=rp.data_ptr(),
+                        col=ci.data_ptr(), val=va.data_ptr(), nnz=va.numel())
+        return M, "csr", (rp, ci, va)
+    _check_dev(A, "A", torch.float64)
+    if A.dim() != 2:
+        raise ValueError("A must be 2-D")
+    n, d = A.shape
+    if A.stride(1) == 1 and (d == 1 or A.stride(0) >= d):
+        M = L.SkiMatrix(n=n, d=d, kind=L.SKI_DENSE, a=A.data_ptr(), lda=A.stride(0),
+                        row_ptr=None, col=None, val=None, nnz=0)
+    elif A.stride(0) == 1 and A.stride(1) >= n:
+        # column-major (e.g. a transposed view): the library keeps a row-major copy
+        M = L.SkiMatrix(n=n, d=d, kind=L.SKI_DENSE_COLMAJOR, a=A.data_ptr(),
+                        lda=A.stride(1), row_ptr=None, col=None, val=None, nnz=0)
+    else:
+        raise ValueError("A must be row-major or column-major (one unit stride)")
+    return M, "dense", (A,)
+
+
+def sketch_noalloc(A, B, out=None, **kw):
+    """S [A B] through ski_sketch_noalloc (no device allocation in the library): A a
+    row-major float64 CUDA tensor or ('csr', row_ptr, col, val, (n, d)); B (n,) or (n x k).
+    out: an optional contiguous float64 CUDA tensor of m x (d + k).  Returns out."""
+    lib = L.load()
+    M, kind, keep = _matrix(A)
+    _check_dev(B, "B", torch.float64)
+    B2 = B.reshape(B.shape[0], -1)
+    if B2.stride(1) != 1:
+        B2 = B2.contiguous()
+    k = B2.shape[1]
+    p = params(kind, **kw)
+    d = M.d
+    m = p.m if p.m > 0 else int(np.ceil(p.gamma * d - 1e-9))
+    if out is None:
+        out = torch.empty((m, d + k), dtype=torch.float64, device=B2.device)
+    _check_dev(out, "out", torch.float64)
+    if tuple(out.shape) != (m, d + k) or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous {m} x {d + k} tensor")
+    rc = lib.ski_sketch_noalloc(C.byref(M), _ptr(B2), k, B2.stride(0), C.byref(p), _ptr(out),
+                                _stream())
+    if rc != L.SKI_OK:
+        msg = lib.ski_last_error(None)
+        raise SkiError(rc, f"ski_sketch_noalloc: {msg.decode() if msg else ''}")
+    del keep
+    return out
+
+
 class Solver:
     """One handle of the C library (one problem at a time, one stream at a time)."""
 
@@ -93,31 +148,7 @@ class Solver:
     def sketch(self, A, B, **kw):
         """A: dense (n x d) float64 CUDA tensor, or ('csr', row_ptr, col, val, (n, d)).
         B: (n,) or (n x k) float64 CUDA tensor.  Parameters as in ski_params."""
-        if isinstance(A, tuple) and A[0] == "csr":
-            _, rp, ci, va, (n, d) = A
-            _check_dev(rp, "row_ptr", torch.int64)
-            _check_dev(ci, "col", torch.int32)
-            _check_dev(va, "val", torch.float64)
-            M = L.SkiMatrix(n=n, d=d, kind=L.SKI_CSR, a=None, lda=0, row_ptr=rp.data_ptr(),
-                            col=ci.data_ptr(), val=va.data_ptr(), nnz=va.numel())
-            kind = "csr"
-            keep = (rp, ci, va)
-        else:
-            _check_dev(A, "A", torch.float64)
-            if A.dim() != 2:
-                raise ValueError("A must be 2-D")
-            n, d = A.shape
-            if A.stride(1) == 1 and (d == 1 or A.stride(0) >= d):
-                M = L.SkiMatrix(n=n, d=d, kind=L.SKI_DENSE, a=A.data_ptr(), lda=A.stride(0),
-                                row_ptr=None, col=None, val=None, nnz=0)
-            elif A.stride(0) == 1 and A.stride(1) >= n:
-                # column-major (e.g. a transposed view): the library keeps a row-major copy
-                M = L.SkiMatrix(n=n, d=d, kind=L.SKI_DENSE_COLMAJOR, a=A.data_ptr(),
-                                lda=A.stride(1), row_ptr=None, col=None, val=None, nnz=0)
-            else:
-                raise ValueError("A must be row-major or column-major (one unit stride)")
-            kind = "dense"
-            keep = (A,)
+        M, kind, keep = _matrix(A)
         _check_dev(B, "B", torch.float64)
         B2 = B.reshape(B.shape[0], -1)
         if B2.stride(1) != 1:

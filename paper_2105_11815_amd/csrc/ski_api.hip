@@ -255,7 +255,11 @@ void ski_params_default(int32_t kind, ski_params* p) {
     }
 }
 
-const char* ski_last_error(ski_handle h) { return h ? h->err.c_str() : "null handle"; }
+const char* ski_last_error(ski_handle h) {
+    if (h) return h->err.c_str();
+    const char* e = noalloc_last_error();  // the handle-free entry point reports here
+    return e[0] ? e : "null handle";
+}
 
 int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, int64_t ldb,
                const ski_params* p, void* stream) {

@@ -156,6 +156,8 @@ hipError_t launch_gather_plain(const double* A, int64_t lda, const double* B, in
 // dst (n x d row-major) = the column-major src (ld lds >= n); n <= 64 * 65535
 hipError_t launch_colmajor_to_rowmajor(const double* src, int64_t lds, int64_t n, int64_t d,
                                        double* dst, hipStream_t st);
+// message of the last failed ski_sketch_noalloc call on this host thread ("" if none)
+const char* noalloc_last_error();
 hipError_t launch_gather_csr(const int64_t* row_ptr, const int32_t* col, const double* val,
                              const double* B, int64_t ldb, int64_t d, int64_t k,
                              const int32_t* bucket_ptr, const int32_t* src, int64_t m,

@@ -97,3 +97,32 @@ def test_invalid_arguments_are_rejected_on_the_host():
     assert lib.ski_factor(h, None) == L.SKI_ESTATE
     assert lib.ski_solve(h, 0, fake, 1, 1, fake, 1, None, None) == L.SKI_ESTATE
     lib.ski_destroy(h)
+
+
+def test_noalloc_sketch_rejects_on_the_host():
+    """ski_sketch_noalloc validates sizes against its static scratch before any device
+    work, and reports through ski_last_error(NULL)."""
+    L, lib = _lib()
+    p = L.SkiParams()
+    lib.ski_params_default(L.SKI_DENSE, C.byref(p))
+    fake = C.c_void_p(0x1000)  # never dereferenced: every case fails validation first
+    M = L.SkiMatrix(n=600000, d=4, kind=L.SKI_DENSE, a=fake.value, lda=4, row_ptr=None,
+                    col=None, val=None, nnz=0)
+    p.m = 64
+    # n' = 2^20: a 16-column slab of n' doubles is 128 MiB, above the 64 MiB scratch
+    assert lib.ski_sketch_noalloc(C.byref(M), fake, 1, 1, C.byref(p), fake, None) == L.SKI_EINVAL
+    assert b"too large" in lib.ski_last_error(None)
+    assert lib.ski_sketch_noalloc(None, fake, 1, 1, C.byref(p), fake, None) == L.SKI_EINVAL
+    assert b"NULL" in lib.ski_last_error(None)
+    Mc = L.SkiMatrix(n=100, d=10, kind=L.SKI_DENSE_COLMAJOR, a=fake.value, lda=100,
+                     row_ptr=None, col=None, val=None, nnz=0)
+    assert lib.ski_sketch_noalloc(C.byref(Mc), fake, 1, 1, C.byref(p), fake, None) == L.SKI_EINVAL
+    q = L.SkiParams()
+    lib.ski_params_default(L.SKI_DENSE, C.byref(q))
+    q.sketch_prec = L.SKI_FP32
+    M2 = L.SkiMatrix(n=100, d=10, kind=L.SKI_DENSE, a=fake.value, lda=10, row_ptr=None,
+                     col=None, val=None, nnz=0)
+    assert lib.ski_sketch_noalloc(C.byref(M2), fake, 1, 1, C.byref(q), fake, None) == L.SKI_EINVAL
+    q.sketch_prec = L.SKI_FP64
+    q.hadamard = 2
+    assert lib.ski_sketch_noalloc(C.byref(M2), fake, 1, 1, C.byref(q), fake, None) == L.SKI_EINVAL
