@@ -48,55 +48,91 @@ def one_solve(P, S, At, bt, **kw):
     return X, infos[0], rc
 
 
-def cpu_baseline(A, b, cfg, gpu_iters):
-    """The oracle as it stands, on a bounded sample of the same workload, extrapolated to
-    one full solve: the sketch on 400 of the 4001 columns (the transform and the hashing
-    act column by column, so time scales with the column count), the QR of an m x (d+1)
-    matrix of the workload's shape, and 5 LSQR iterations on the full A, scaled by the
-    GPU's iteration count."""
-    from oracle import lls, sketch as sk
+def cpu_model():
+    """The host CPU's model name as lscpu reports it (else /proc/cpuinfo)."""
+    import subprocess
     try:
-        from threadpoolctl import threadpool_info
-        cores = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name"):
+                return line.split(":", 1)[1].strip()
     except Exception:
-        cores = os.cpu_count() or 1
-    n, d, m, s = A.shape[0], A.shape[1], cfg["m"], cfg["s"]
-    cols = 400
-    t0 = time.perf_counter()
-    sk.sketch_dense(A[:, : cols - 1], b, m, s, seed=2002)
-    t_sketch = (time.perf_counter() - t0) * (d + 1) / cols
-    rng = np.random.default_rng(0)
-    SA = rng.standard_normal((m, d + 1))
-    t0 = time.perf_counter()
-    R, c, _ = lls.factor(SA, d)
-    t_qr = time.perf_counter() - t0
-    xs = np.zeros(d)
-    r0 = b - A @ xs
-    its = 5
-    t0 = time.perf_counter()
-    lls.lsqr_precond(A, R, r0, 0.0, its)
-    t_iter = (time.perf_counter() - t0) / its
-    total = t_sketch + t_qr + t_iter * gpu_iters
-    model = "unknown"
+        pass
     try:
         for line in open("/proc/cpuinfo"):
             if line.startswith("model name"):
-                model = line.split(":", 1)[1].strip()
-                break
+                return line.split(":", 1)[1].strip()
     except OSError:
         pass
+    return "unknown"
+
+
+def cpu_phases(A, b, cfg, iters, threads, cols=(60, 180), reps=3, its=4):
+    """Per-phase seconds of one oracle solve on the dense workload, with the BLAS pool
+    limited to `threads` (None: all of them).  Measured on the real A and b:
+      sketch -- the oracle's Walsh-Hadamard + hashing of the first c columns of [A b]
+                for the two column counts in `cols` (median of `reps` runs each); the
+                transform and the hashing act column by column, so the time is a fixed
+                part (drawing S_h and D) plus a per-column part, and the line through
+                the two points gives the full d+1 columns;
+      qr     -- the oracle's Householder QR (LAPACK) of an m x (d+1) matrix, once (its
+                cost does not depend on the values: no pivoting);
+      lsqr   -- `its` iterations of the oracle's preconditioned LSQR on the full A, median
+                seconds per iteration over `reps` runs, times `iters` iterations."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+    from oracle import lls, sketch as sk
+    n, d, m, s = A.shape[0], A.shape[1], cfg["m"], cfg["s"]
+    with threadpool_limits(limits=threads):
+        used = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+        tc = []
+        for c in cols:
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                sk.sketch_dense(A[:, : c - 1], b, m, s, seed=2002)
+                ts.append(time.perf_counter() - t0)
+            tc.append(float(np.median(ts)))
+        # fixed part (S_h and D: the same for any column count) plus a per-column part
+        per_col = (tc[1] - tc[0]) / (cols[1] - cols[0])
+        t_sketch = tc[0] + per_col * (d + 1 - cols[0])
+        SA = np.random.default_rng(0).standard_normal((m, d + 1))
+        t0 = time.perf_counter()
+        R, _, _ = lls.factor(SA, d)
+        t_qr = time.perf_counter() - t0
+        tl = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            lls.lsqr_precond(A, R, b.copy(), 0.0, its)
+            tl.append((time.perf_counter() - t0) / its)
+        t_iter = float(np.median(tl))
+    total = t_sketch + t_qr + t_iter * iters
+    return {"threads": int(used), "s_per_solve": round(total, 3),
+            "sketch_s": round(t_sketch, 3), "sketch_sample_s": [round(t, 3) for t in tc],
+            "qr_s": round(t_qr, 3),
+            "lsqr_s": round(t_iter * iters, 3), "lsqr_s_per_iter": round(t_iter, 4)}
+
+
+def cpu_baseline(A, b, cfg, iters):
+    """The oracle as it stands, timed phase by phase on the host (cpu_phases), once with
+    one BLAS thread (the sequential mode of the paper's experiments) and once with all of
+    the host's threads; `value` is the all-threads rate."""
+    seq = cpu_phases(A, b, cfg, iters, threads=1)
+    par = cpu_phases(A, b, cfg, iters, threads=None)
     return {
-        "value": 1.0 / total,
+        "value": 1.0 / par["s_per_solve"],
         "unit": "solves/s",
-        "cores": int(cores),
+        "cores": par["threads"],
         "kind": "oracle",
-        "cpu_model": model,
+        "cpu_model": cpu_model(),
         "host_cpus": os.cpu_count(),
-        "sample": (f"oracle sketch on {cols} of {d + 1} columns (x{(d + 1) / cols:.2f}), "
-                   f"QR of a {m}x{d + 1} matrix, {its} LSQR iterations on the full A "
-                   f"(x{gpu_iters} GPU iterations); extrapolated seconds per solve "
-                   f"{total:.2f} (sketch {t_sketch:.2f}, qr {t_qr:.2f}, "
-                   f"lsqr {t_iter * gpu_iters:.2f})"),
+        "all_threads": par,
+        "sequential": dict(seq, value=1.0 / seq["s_per_solve"]),
+        "sample": (f"measured per phase on the real A and b: oracle sketch of 60 and of 180 "
+                   f"of the {A.shape[1] + 1} columns (median of 3 each; fixed + per-column "
+                   f"line to all columns), "
+                   f"one QR of a {cfg['m']}x{A.shape[1] + 1} matrix, 4 LSQR iterations on "
+                   f"the full A (median of 3, x{iters} iterations, the oracle's and the "
+                   f"GPU's count on this workload)"),
     }
 
 
