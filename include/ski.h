@@ -102,7 +102,11 @@ typedef struct {
  *                HR-DHT), on the zero-padded n' rows; needs n' <= 2^24 and FP64 sketch
  *                and QR; computed through the DFT, so it matches a reference to rounding.
  *   seed         Philox4x64-10 key (seed, 0) for S_h and D.
- *   sketch_prec  arithmetic/storage of H D A and of the sketch (FP64/FP32/BF16).
+ *   sketch_prec  arithmetic of H D A and of the hashing sums, and the type of the
+ *                transform's intermediate (FP64; FP32; BF16 storage with FP32 arithmetic).
+ *                The sketch is stored in the type the QR reads: FP64 when qr_prec = FP64
+ *                (which makes the sketch FP64 whatever sketch_prec says), FP32 otherwise
+ *                (an FP64 sketch is then rounded once, when it is written).
  *   qr_prec      arithmetic of the QR of the sketch (FP64/FP32/BF16 MFMA inputs,
  *                FP32 accumulation for BF16); R is always used in FP64.
  *   tau_a        early exit when ||A x_s - b|| <= tau_a (absolute).

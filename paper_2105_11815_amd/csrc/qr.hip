@@ -402,6 +402,26 @@ hipError_t gemm_t(bool ta, bool tb, int64_t M, int64_t N, int64_t K, T alpha, co
         return gemm_f32(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bf16, ws, st, 0);
 }
 
+// C -= A B for one panel's K <= 64 reflectors: the tile kernel that reads C once
+// (rank_update.hip); the BF16 form keeps the general GEMM, which rounds its operands
+template <typename T>
+hipError_t rank_update_t(int64_t M, int64_t N, int K, const T* A, int64_t lda, const T* B,
+                         int64_t ldb, T* C, int64_t ldc, bool bf16, GemmWs& ws, hipStream_t st) {
+    if (!bf16 && K <= 64) return launch_rank_update<T>(M, N, K, A, lda, B, ldb, C, ldc, st);
+    return gemm_t<T>(false, false, M, N, K, (T)-1, A, lda, B, ldb, (T)1, C, ldc, bf16, ws, st);
+}
+
+// W = C V^T for one panel's K <= 64 reflectors (C: M x N, V: K x N, row-major views):
+// the tile kernel with fixed-order partial sums over ranges of N (rank_update.hip); the
+// BF16 form keeps the general GEMM
+template <typename T>
+hipError_t rank_project_t(int64_t M, int64_t N, int K, const T* C, int64_t ldc, const T* V,
+                          int64_t ldv, T* W, int64_t ldw, bool bf16, GemmWs& ws, hipStream_t st) {
+    if (!bf16 && K <= 64 && rank_project_ws_bytes(M, N, sizeof(T)) <= ws.bytes)
+        return launch_rank_project<T>(M, N, K, C, ldc, V, ldv, W, ldw, ws.part, ws.bytes, st);
+    return gemm_t<T>(false, true, M, K, N, (T)1, C, ldc, V, ldv, (T)0, W, ldw, bf16, ws, st);
+}
+
 template <typename T>
 hipError_t launch_Tinv(const T* Wt, int64_t n, int nb, const T* G, int ldg, const T* tau, T* W2t,
                        hipStream_t s) {
@@ -479,18 +499,18 @@ hipError_t qr_impl_hh(T* Ac, int64_t m, int64_t ncols, int64_t d, QrWs& ws, bool
         if (ncn > 0) {
             T* W2n = (T*)ws.W2t;
             SKI_HIP(launch_Tinv<T>(GW + (int64_t)nb * nb, ncn, nb, GW, nb, tau + j0, W2n, st));
-            SKI_HIP(gemm_t<T>(false, false, ncn, mr, nb, (T)-1, W2n, nb, VC, mr, (T)1,
-                              Ac + nx0 * m + j0, m, bf16, ws.g, st));
+            SKI_HIP(rank_update_t<T>(ncn, mr, nb, W2n, nb, VC, mr, Ac + nx0 * m + j0, m, bf16,
+                                     ws.g, st));
         }
         if (nx1 < ncols) {
             const int64_t nrest = ncols - nx1;
             T* Ct = Ac + nx1 * m + j0;
             SKI_HIP(hipStreamWaitEvent(s2, ws.evF[p & 1], 0));
-            SKI_HIP(gemm_t<T>(false, true, nrest, nb, mr, (T)1, Ct, m, VC, mr, (T)0, (T*)ws.Wt2,
-                              nb, bf16, ws.g2, s2));
+            SKI_HIP(rank_project_t<T>(nrest, mr, nb, Ct, m, VC, mr, (T*)ws.Wt2, nb, bf16, ws.g2,
+                                      s2));
             SKI_HIP(launch_Tinv<T>((T*)ws.Wt2, nrest, nb, GW, nb, tau + j0, (T*)ws.W2t2, s2));
-            SKI_HIP(gemm_t<T>(false, false, nrest, mr, nb, (T)-1, (T*)ws.W2t2, nb, VC, mr, (T)1,
-                              Ct, m, bf16, ws.g2, s2));
+            SKI_HIP(rank_update_t<T>(nrest, mr, nb, (T*)ws.W2t2, nb, VC, mr, Ct, m, bf16, ws.g2,
+                                     s2));
             SKI_HIP(hipEventRecord(ws.evE[p & 1], s2));
             pending_rest = true;
         }
@@ -536,12 +556,12 @@ hipError_t qr_impl_cqr(T* Ac, int64_t m, int64_t ncols, int64_t d, QrWs& ws, boo
             T* V = Vb[p & 1];
             SKI_HIP(hipEventRecord(ws.evF[p & 1], st));
             SKI_HIP(hipStreamWaitEvent(s2, ws.evF[p & 1], 0));
-            SKI_HIP(gemm_t<T>(false, true, nrest, nb, mr, (T)1, Ct, m, V, mr, (T)0, (T*)ws.Wt2, nb,
-                              bf16, ws.g2, s2));
+            SKI_HIP(rank_project_t<T>(nrest, mr, nb, Ct, m, V, mr, (T*)ws.Wt2, nb, bf16, ws.g2,
+                                      s2));
             SKI_HIP(gemm_t<T>(false, false, nrest, nb, nb, (T)1, (T*)ws.Wt2, nb, Tb[p & 1], NBP,
                               (T)0, (T*)ws.W2t2, nb, false, ws.g2, s2));
-            SKI_HIP(gemm_t<T>(false, false, nrest, mr, nb, (T)-1, (T*)ws.W2t2, nb, V, mr, (T)1,
-                              Ct, m, bf16, ws.g2, s2));
+            SKI_HIP(rank_update_t<T>(nrest, mr, nb, (T*)ws.W2t2, nb, V, mr, Ct, m, bf16, ws.g2,
+                                     s2));
             SKI_HIP(hipEventRecord(ws.evE[p & 1], s2));
             pending_rest = true;
         }
@@ -625,8 +645,7 @@ hipError_t qr_impl_pivoted(double* Ac, int64_t m, int64_t ncols, int64_t d, QrWs
             SKI_HIP(gemm_t<T>(false, true, nb, nb, mr, (T)1, VC, mr, VC, mr, (T)0, GW, nb, false,
                               ws.g, st));
         }
-        SKI_HIP(gemm_t<T>(false, true, nrest, nb, mr, (T)1, Ct, m, VC, mr, (T)0, (T*)ws.Wt2, nb,
-                          false, ws.g, st));
+        SKI_HIP(rank_project_t<T>(nrest, mr, nb, Ct, m, VC, mr, (T*)ws.Wt2, nb, false, ws.g, st));
         if (done)
             SKI_HIP(gemm_t<T>(false, false, nrest, nb, nb, (T)1, (T*)ws.Wt2, nb, Tq, NBP, (T)0,
                               (T*)ws.W2t2, nb, false, ws.g, st));
@@ -638,8 +657,8 @@ hipError_t qr_impl_pivoted(double* Ac, int64_t m, int64_t ncols, int64_t d, QrWs
         if (mr > nb) {
             SKI_HIP(hipEventRecord(ws.evF[p & 1], st));
             SKI_HIP(hipStreamWaitEvent(s2, ws.evF[p & 1], 0));
-            SKI_HIP(gemm_t<T>(false, false, nrest, mr - nb, nb, (T)-1, (T*)ws.W2t2, nb, VC + nb,
-                              mr, (T)1, Ct + nb, m, false, ws.g2, s2));
+            SKI_HIP(rank_update_t<T>(nrest, mr - nb, nb, (T*)ws.W2t2, nb, VC + nb, mr, Ct + nb, m,
+                                     false, ws.g2, s2));
             SKI_HIP(hipEventRecord(ws.evE[p & 1], s2));
             pending = true;
         }

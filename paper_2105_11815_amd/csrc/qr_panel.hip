@@ -144,10 +144,15 @@ __device__ __forceinline__ void chunk_times_upper(T (*sh)[PP], T (*Xs)[PP], int 
     __syncthreads();
 }
 
+// The panel chain is the QR's critical path, and its kernels share CUs with the trailing
+// products of the second stream: their waves ask for the highest issue priority.
+__device__ __forceinline__ void chain_priority() { __builtin_amdgcn_s_setprio(3); }
+
 // Gram partials: workgroup b sums P^T P over the rows [b GR, (b+1) GR) -> Gp[b] (PB x PB)
 template <typename T>
 __global__ __launch_bounds__(256) void k_cqr_gram(const T* __restrict__ P, int64_t ldp, int64_t mr,
                                                   int nb, T* __restrict__ Gp) {
+    chain_priority();
     __shared__ T sh[GR][PP];
     const int t = threadIdx.x;
     const int64_t r0 = (int64_t)blockIdx.x * GR, r1 = std::min<int64_t>(mr, r0 + GR);
@@ -161,6 +166,7 @@ __global__ __launch_bounds__(256) void k_cqr_gram(const T* __restrict__ P, int64
 template <typename T>
 __global__ __launch_bounds__(256) void k_cqr_reduce(const T* __restrict__ Gp, int nch,
                                                     T* __restrict__ G) {
+    chain_priority();
     __shared__ T part[RSL][256 / RSL];
     constexpr int EPB = 256 / RSL;  // entries per workgroup
     const int t = threadIdx.x, el = t % EPB, sl = t / EPB;
@@ -185,6 +191,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_cqr_chol1(const T* __restrict__ G, int nb,
                                                    T* __restrict__ R1, T* __restrict__ R1i,
                                                    int* __restrict__ flag) {
+    chain_priority();
     __shared__ T A[PB][PP];
     __shared__ int bad;
     const int t = threadIdx.x;
@@ -215,6 +222,7 @@ __global__ __launch_bounds__(256) void k_cqr_apply_gram(const T* __restrict__ P,
                                                         const T* __restrict__ Ri,
                                                         T* __restrict__ Q, int64_t ldq,
                                                         T* __restrict__ Gp) {
+    chain_priority();
     __shared__ T Xs[PB][PP];
     __shared__ T sh[GR][PP];
     const int t = threadIdx.x;
@@ -240,6 +248,7 @@ __global__ __launch_bounds__(256) void k_cqr_chol2(const T* __restrict__ G, int 
                                                    T* __restrict__ Pt, int64_t ldp,
                                                    T* __restrict__ tau, T* __restrict__ Mx,
                                                    T* __restrict__ Tx, int* __restrict__ flag) {
+    chain_priority();
     __shared__ T A[PB][PP];  // G2 -> R2 -> R2^-1 -> M
     __shared__ T B[PB][PP];  // R1 -> R = R2 R1
     __shared__ T C[PB][PP];  // Q1 top -> Qt -> L1 and the eliminated Qt
@@ -361,6 +370,7 @@ __global__ __launch_bounds__(256) void k_cqr_update_gram(T* __restrict__ Ac, int
                                                          const T* __restrict__ Tq,
                                                          const T* __restrict__ W,
                                                          T* __restrict__ Gp) {
+    chain_priority();
     __shared__ T Ys[PB][PP];
     __shared__ T Vs[PB][PP];
     __shared__ T Cs[PB][PP];
@@ -392,6 +402,7 @@ __global__ __launch_bounds__(256) void k_cqr_v2x(const T* __restrict__ Q, int64_
                                                  T* __restrict__ P, int64_t ldp,
                                                  T* __restrict__ Vout, int nbn,
                                                  T* __restrict__ Gp) {
+    chain_priority();
     __shared__ T Ms[PB][PP];
     __shared__ T Qs[PB][PP];
     __shared__ T Cs[PB][PP];

@@ -449,12 +449,17 @@ hipError_t launch_sketch_dense(const double* A, int64_t lda, const double* B, in
                                int64_t n, int64_t d, int64_t k, int64_t npad,
                                const uint32_t* dbits, void* T, int64_t sc,
                                const int32_t* bucket_ptr, const int32_t* src, int64_t m,
-                               double scale, Prec prec, void* SA, hipStream_t st) {
+                               double scale, Prec prec, Prec out, void* SA, hipStream_t st) {
     switch (prec) {
         case Prec::F64:
-            return sketch_slabs<double, double, double>(A, lda, B, ldb, n, d, k, npad, dbits,
-                                                        (double*)T, sc, bucket_ptr, src, m, scale,
-                                                        (double*)SA, st);
+            if (out == Prec::F64)
+                return sketch_slabs<double, double, double>(A, lda, B, ldb, n, d, k, npad, dbits,
+                                                            (double*)T, sc, bucket_ptr, src, m,
+                                                            scale, (double*)SA, st);
+            // FP64 transform and sums, the sketch rounded once to FP32 for an FP32/BF16 QR
+            return sketch_slabs<double, double, float>(A, lda, B, ldb, n, d, k, npad, dbits,
+                                                       (double*)T, sc, bucket_ptr, src, m, scale,
+                                                       (float*)SA, st);
         case Prec::F32:
             return sketch_slabs<float, float, float>(A, lda, B, ldb, n, d, k, npad, dbits,
                                                      (float*)T, sc, bucket_ptr, src, m, scale,
@@ -470,13 +475,16 @@ hipError_t launch_sketch_dense(const double* A, int64_t lda, const double* B, in
 
 hipError_t launch_gather_plain(const double* A, int64_t lda, const double* B, int64_t ldb,
                                int64_t d, int64_t k, const int32_t* bucket_ptr,
-                               const int32_t* src, int64_t m, double scale, Prec prec, void* SA,
-                               hipStream_t st) {
+                               const int32_t* src, int64_t m, double scale, Prec prec, Prec out,
+                               void* SA, hipStream_t st) {
     const int64_t ncols = d + k;
     dim3 grid((unsigned)m, (unsigned)((ncols + GT * GU - 1) / (GT * GU)));
-    if (prec == Prec::F64)
+    if (prec == Prec::F64 && out == Prec::F64)
         hipLaunchKernelGGL((k_gather_dense<double, double, double>), grid, dim3(GT), 0, st, A, lda,
                            d, B, ldb, k, bucket_ptr, src, scale, (double*)SA, ncols);
+    else if (prec == Prec::F64)
+        hipLaunchKernelGGL((k_gather_dense<double, double, float>), grid, dim3(GT), 0, st, A, lda,
+                           d, B, ldb, k, bucket_ptr, src, scale, (float*)SA, ncols);
     else
         hipLaunchKernelGGL((k_gather_dense<double, float, float>), grid, dim3(GT), 0, st, A, lda, d,
                            B, ldb, k, bucket_ptr, src, scale, (float*)SA, ncols);
@@ -486,12 +494,15 @@ hipError_t launch_gather_plain(const double* A, int64_t lda, const double* B, in
 hipError_t launch_gather_csr(const int64_t* row_ptr, const int32_t* col, const double* val,
                              const double* B, int64_t ldb, int64_t d, int64_t k,
                              const int32_t* bucket_ptr, const int32_t* src, int64_t m,
-                             double scale, Prec prec, void* SA, hipStream_t st) {
+                             double scale, Prec prec, Prec out, void* SA, hipStream_t st) {
     const int64_t ncols = d + k;
     dim3 grid((unsigned)m, (unsigned)((ncols + CSR_RANGE - 1) / CSR_RANGE));
-    if (prec == Prec::F64)
+    if (prec == Prec::F64 && out == Prec::F64)
         hipLaunchKernelGGL((k_gather_csr<double, double>), grid, dim3(64), 0, st, row_ptr, col, val,
                            B, ldb, d, k, bucket_ptr, src, scale, (double*)SA);
+    else if (prec == Prec::F64)
+        hipLaunchKernelGGL((k_gather_csr<double, float>), grid, dim3(64), 0, st, row_ptr, col, val,
+                           B, ldb, d, k, bucket_ptr, src, scale, (float*)SA);
     else
         hipLaunchKernelGGL((k_gather_csr<float, float>), grid, dim3(64), 0, st, row_ptr, col, val,
                            B, ldb, d, k, bucket_ptr, src, scale, (float*)SA);

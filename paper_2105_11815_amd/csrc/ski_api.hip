@@ -374,8 +374,13 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
     const double hscale = p->hash_kind == SKI_SAMPLE_ROWS ? 1.0 : 1.0 / sqrt((double)p->s);
     prof_end(h, st);
 
-    // the SA storage type for the gathers: FP64, or FP32 for the mixed forms
-    const Prec gprec = qprec == Prec::F64 ? Prec::F64 : (sprec == Prec::F64 ? Prec::F32 : sprec);
+    // gprec: the transform's arithmetic and slab type (sketch_prec); oprec: SA's storage,
+    // FP64 for the FP64 QR, FP32 for the FP32 and BF16 QR forms (an FP64 sketch is then
+    // rounded once, when it is written)
+    const Prec gprec = sprec;
+    const Prec oprec = qprec == Prec::F64 ? Prec::F64 : Prec::F32;
+    // the hashing sums without a transform: FP64 for an FP64 sketch, else FP32
+    const Prec hprec = sprec == Prec::F64 ? Prec::F64 : Prec::F32;
     if (akind == SKI_DENSE && had) {
         const size_t te = elem_bytes(gprec);
         SKI_TRY(h, ensure(h->dbits, ((npad + 255) / 256) * 32), "alloc");
@@ -394,20 +399,19 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
             SKI_TRY(h, launch_sketch_dense(h->A, h->lda, B, ldb, n, d, k, npad,
                                            P<uint32_t>(h->dbits), h->T0.p, sc,
                                            P<int32_t>(h->bucket_ptr), P<int32_t>(h->src), m, scale,
-                                           gprec, h->SA.p, st),
+                                           gprec, oprec, h->SA.p, st),
                     "sketch");
         prof_end(h, st);
     } else if (akind == SKI_DENSE) {
         const double scale = hscale;
         SKI_TRY(h, launch_gather_plain(h->A, h->lda, B, ldb, d, k, P<int32_t>(h->bucket_ptr),
-                                       P<int32_t>(h->src), m, scale,
-                                       qprec == Prec::F64 ? Prec::F64 : Prec::F32, h->SA.p, st),
+                                       P<int32_t>(h->src), m, scale, hprec, oprec, h->SA.p, st),
                 "gather");
     } else {
         const double scale = hscale;
         SKI_TRY(h, launch_gather_csr(A->row_ptr, A->col, A->val, B, ldb, d, k,
                                      P<int32_t>(h->bucket_ptr), P<int32_t>(h->src), m, scale,
-                                     qprec == Prec::F64 ? Prec::F64 : Prec::F32, h->SA.p, st),
+                                     hprec, oprec, h->SA.p, st),
                 "gather csr");
         // CSR of A^T for the transposed products of LSQR
         const int64_t nnz = A->nnz;

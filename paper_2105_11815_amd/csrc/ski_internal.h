@@ -134,13 +134,15 @@ hipError_t launch_dsign(int64_t npad, uint64_t seed, uint32_t* bits, hipStream_t
 // Walsh-Hadamard passes and the hashing gathers
 enum class Prec { F64 = 0, F32 = 1, BF16 = 2 };
 // dense sketch with the Hadamard row mix, by column slabs of sc columns through the slab
-// buffer T (npad x sc elements of the storage type), into SA (m x (d+k))
+// buffer T (npad x sc elements of the storage type), into SA (m x (d+k)).  prec: the
+// transform's arithmetic and slab type (F64, F32, or BF16 storage with F32 arithmetic);
+// out: SA's type (F64 only with prec F64; otherwise F32)
 int64_t sketch_slab_cols(int64_t npad, int64_t ncols, Prec prec);
 hipError_t launch_sketch_dense(const double* A, int64_t lda, const double* B, int64_t ldb,
                                int64_t n, int64_t d, int64_t k, int64_t npad,
                                const uint32_t* dbits, void* T, int64_t sc,
                                const int32_t* bucket_ptr, const int32_t* src, int64_t m,
-                               double scale, Prec prec, void* SA, hipStream_t st);
+                               double scale, Prec prec, Prec out, void* SA, hipStream_t st);
 // dense sketch with the randomised Hartley transform (FP64; n' <= 2^24), through the
 // same slab buffer T (npad x sc doubles, sc a multiple of 16) into SA (m x (d+k))
 bool dht_supported(int64_t npad);
@@ -151,8 +153,8 @@ hipError_t launch_sketch_dht(const double* A, int64_t lda, const double* B, int6
                              double scale, double* SA, hipStream_t st);
 hipError_t launch_gather_plain(const double* A, int64_t lda, const double* B, int64_t ldb,
                                int64_t d, int64_t k, const int32_t* bucket_ptr,
-                               const int32_t* src, int64_t m, double scale, Prec prec, void* SA,
-                               hipStream_t st);
+                               const int32_t* src, int64_t m, double scale, Prec prec, Prec out,
+                               void* SA, hipStream_t st);
 // dst (n x d row-major) = the column-major src (ld lds >= n); n <= 64 * 65535
 hipError_t launch_colmajor_to_rowmajor(const double* src, int64_t lds, int64_t n, int64_t d,
                                        double* dst, hipStream_t st);
@@ -161,7 +163,7 @@ const char* noalloc_last_error();
 hipError_t launch_gather_csr(const int64_t* row_ptr, const int32_t* col, const double* val,
                              const double* B, int64_t ldb, int64_t d, int64_t k,
                              const int32_t* bucket_ptr, const int32_t* src, int64_t m,
-                             double scale, Prec prec, void* SA, hipStream_t st);
+                             double scale, Prec prec, Prec out, void* SA, hipStream_t st);
 
 // GEMM: C[MxN] = alpha op(A) op(B) + beta C, row-major, on MFMA.
 //   T = double (FP64 MFMA), float (FP32 MFMA), or float with bf16 MFMA inputs.
@@ -189,6 +191,20 @@ bool gemm_ts_eligible(int64_t N);
 hipError_t gemm_ts_f64(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                        int64_t lda, const double* B, int64_t ldb, double beta, double* C,
                        int64_t ldc, GemmWs& ws, hipStream_t st, int tri = 0);
+
+// C -= A B (row-major, leading dimensions) for K <= 64: the QR's trailing update
+// (rank_update.hip); FP64 or FP32
+template <typename T>
+hipError_t launch_rank_update(int64_t M, int64_t N, int K, const T* A, int64_t lda, const T* B,
+                              int64_t ldb, T* C, int64_t ldc, hipStream_t st);
+
+// W = C V^T (W: M x K, ldw) for K <= 64, C: M x N (ldc), V: K x N (ldv), with partial sums
+// over ranges of N in ws (rank_project_ws_bytes(M, N, elem) bytes); FP64 or FP32
+size_t rank_project_ws_bytes(int64_t M, int64_t N, size_t elem);
+template <typename T>
+hipError_t launch_rank_project(int64_t M, int64_t N, int K, const T* C, int64_t ldc, const T* V,
+                               int64_t ldv, T* W, int64_t ldw, void* ws, size_t ws_bytes,
+                               hipStream_t st);
 
 // panel factorisation by CholeskyQR2 and Householder reconstruction (qr_panel.hip)
 struct CqrWs {

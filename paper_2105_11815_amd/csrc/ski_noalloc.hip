@@ -171,13 +171,13 @@ extern "C" int ski_sketch_noalloc(const ski_matrix* A, const double* B, int32_t 
         if (e == hipSuccess)
             e = launch_sketch_dense(A->a, A->lda, B, ldb, n, d, k, npad, dbits, base + Lo.slab,
                                     Lo.sc, hb.bucket_ptr, hb.src, m, hscale / sqrt((double)npad),
-                                    Prec::F64, SA, st);
+                                    Prec::F64, Prec::F64, SA, st);
     } else if (A->kind == SKI_DENSE) {
         e = launch_gather_plain(A->a, A->lda, B, ldb, d, k, hb.bucket_ptr, hb.src, m, hscale,
-                                Prec::F64, SA, st);
+                                Prec::F64, Prec::F64, SA, st);
     } else {
         e = launch_gather_csr(A->row_ptr, A->col, A->val, B, ldb, d, k, hb.bucket_ptr, hb.src, m,
-                              hscale, Prec::F64, SA, st);
+                              hscale, Prec::F64, Prec::F64, SA, st);
     }
     if (e != hipSuccess) return fail(SKI_EDEVICE, std::string("sketch: ") + hipGetErrorString(e));
     return SKI_OK;

@@ -14,6 +14,7 @@ import sys
 
 import numpy as np
 import pytest
+import scipy.sparse as sp
 
 import workloads
 from oracle import lls, sketch as sk
@@ -186,6 +187,83 @@ def test_low_precision_sketch_and_factor_against_fp64_oracle(ski, prec):
     assert it <= math.ceil(it64 * ratio * 1.1) + 2
 
 
+def test_fp64_sketch_rounded_once_for_the_low_precision_qr(ski):
+    """sketch_prec = FP64 with qr_prec = FP32: the transform and the hashing sums run in
+    FP64 (bit-exact with the oracle) and the sketch is rounded once to FP32 when written,
+    so the stored sketch equals the oracle's FP64 sketch rounded to FP32, bit for bit: with
+    the transform (n' = 65536, three 256-column FP64 slabs), without it, and for CSR A."""
+    n, d, k, m, s = 33000, 600, 1, 1020, 3
+    _say(f"FP64 sketch for an FP32 QR: dense + H n={n} d={d} m={m}")
+    A, B = _coherent(n, d, k, 601)
+    ref = sk.sketch_dense(A, B, m, s, 2601)["SA_aug"]
+    S = ski.Solver()
+    S.sketch(dev(A), dev(B), m=m, s=s, seed=2601, hadamard=True, sketch_prec="fp64",
+             qr_prec="fp32")
+    np.testing.assert_array_equal(S.get_SA(), ref.astype(np.float32).astype(np.float64))
+    _say("  dense without the transform")
+    ref = sk.sketch_dense(A, B, m, s, 2602, hadamard=False)["SA_aug"]
+    S.sketch(dev(A), dev(B), m=m, s=s, seed=2602, hadamard=False, sketch_prec="fp64",
+             qr_prec="bf16")
+    np.testing.assert_array_equal(S.get_SA(), ref.astype(np.float32).astype(np.float64))
+    _say("  CSR")
+    M = sp.random(20000, 300, density=0.01, format="csr", random_state=5,
+                  data_rvs=np.random.default_rng(5).standard_normal)
+    M.sort_indices()
+    Bc = np.random.default_rng(6).standard_normal((20000, 1))
+    ref = sk.sketch_csr(M.indptr, M.indices, M.data, 20000, 300, Bc, 450, 2, 2603)["SA_aug"]
+    Ac = ("csr", dev(M.indptr.astype(np.int64), torch.int64),
+          dev(M.indices.astype(np.int32), torch.int32), dev(M.data), (20000, 300))
+    S.sketch(Ac, dev(Bc), m=450, s=2, seed=2603, hadamard=False, sketch_prec="fp64",
+             qr_prec="fp32")
+    np.testing.assert_array_equal(S.get_SA(), ref.astype(np.float32).astype(np.float64))
+    S.close()
+
+
+def test_fp32_qr_preconditions_like_lapack_sgeqrf_at_cond_1e8(ski):
+    """On a 6000 x 300 matrix with singular values from 1 to 1e-8 (the ill-conditioned
+    workload's spectrum) the FP64 sketch, rounded once to FP32, is factored by the GPU's
+    FP32 QR (CholeskyQR2 panels and column-by-column Householder panels) and, on the host,
+    by LAPACK's single-precision Householder QR (scipy sgeqrf) of the same FP32 sketch.
+    A QR in FP32 arithmetic leaves kappa(A R^-1) several times the FP64 factor's (about
+    26 for sgeqrf against 7.2): the rounding of every Householder update is of the order
+    u32 |SA|, against a smallest singular value of 1e-8 |SA|.  The GPU's two forms land
+    within a factor of 2 of sgeqrf's, and LSQR's iteration count grows with kappa (rate
+    ((kappa - 1) / (kappa + 1)) per step)."""
+    import scipy.linalg as sla
+    At, bt = workloads.illcond(n=6000, d=300, case=4, device="cpu")
+    A, b = At.numpy(), bt.numpy()
+    d = A.shape[1]
+    m = int(math.ceil(1.7 * d))
+    SA32 = sk.sketch_dense(A, b, m, 3, 2004)["SA_aug"][:, :d].astype(np.float32)
+    Rl = sla.qr(SA32, mode="r")[0][:d, :d].astype(np.float64)
+
+    def kappa(Rm):
+        sv = np.linalg.svd(sla.solve_triangular(Rm, A.T, trans="T").T, compute_uv=False)
+        return sv[0] / sv[-1]
+
+    k_lapack = kappa(Rl)
+    _say(f"cond 1e8, 6000 x 300: LAPACK sgeqrf kappa(A R^-1) {k_lapack:.3f}")
+    res = {}
+    for name, kw in [("fp64", {}),
+                     ("fp32_cqr", dict(sketch_prec="fp64", qr_prec="fp32")),
+                     ("fp32_hh", dict(sketch_prec="fp64", qr_prec="fp32",
+                                      qr_panel="householder"))]:
+        S = ski.Solver()
+        S.sketch(dev(A), dev(b), m=m, s=3, seed=2004, tau_r=1e-10, it_max=3000, **kw).factor()
+        X, infos, rc = S.solve()
+        R = S.get_R()[0]
+        S.close()
+        res[name] = (infos[0]["iters"], kappa(R), rc)
+        _say(f"  {name}: {infos[0]['iters']} iterations, kappa(A R^-1) {res[name][1]:.3f}, "
+             f"status {rc}")
+    assert all(v[2] == 0 for v in res.values())
+    assert res["fp64"][1] < 8.0
+    assert 2.0 * res["fp64"][1] < k_lapack
+    for name in ("fp32_cqr", "fp32_hh"):
+        assert 0.5 * k_lapack <= res[name][1] <= 2.0 * k_lapack
+        assert res[name][0] > res["fp64"][0]
+
+
 # ------------------------------------------------------------------ full-size iterations
 def test_full_size_dense_iterations_match_the_oracle(ski):
     """The dense 50000 x 4000 workload with the benchmark's sketch (m 6800, s 3, seed 2002)
@@ -227,7 +305,7 @@ def illcond_problem():
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp64sketch_fp32qr"])
 def test_illcond_full_size_against_the_oracle(ski, illcond_problem, prec):
     """cond(A) = 1e8, ||r*|| ~ 207: x itself is determined only to ~u cond^2 ||r|| / ||A x||
     (about 2e-7 relative) by any FP64 solver, so the pins are the residual norm against the
@@ -238,7 +316,9 @@ def test_illcond_full_size_against_the_oracle(ski, illcond_problem, prec):
     c = workloads.CASES["illcond"]
     At, bt = dev(A), dev(b)
     kw = dict(m=c["m"], s=c["s"], seed=2004, tau_r=1e-10, hadamard=True)
-    if prec != "fp64":
+    if prec == "fp64sketch_fp32qr":
+        kw.update(sketch_prec="fp64", qr_prec="fp32", it_max=3000)
+    elif prec != "fp64":
         kw.update(sketch_prec=prec, qr_prec=prec, it_max=3000)
     S = ski.Solver()
     S.sketch(At, bt, **kw).factor()
