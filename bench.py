@@ -8,8 +8,8 @@ HBM.  Prints one JSON line on stdout (everything else goes to stderr).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-mixed]
                        [--no-sparse] [--no-rankdef] [--no-batched] [--no-seeds]
-                       [--rankdef-only] [--sweep]
-                       [--sketch-study]
+                       [--rankdef-only] [--batched-only] [--sweep]
+                       [--sketch-study] [--cache-ceiling]
 """
 
 import argparse
@@ -488,6 +488,33 @@ def batched_run(P, torch):
             "forward_lsqr_gemm_TFLOPs_lower_bound": round(tf, 2)}
 
 
+def cache_ceiling(torch):
+    """Read+write rate of a device-to-device copy whose source and destination together
+    take `mb` MB, for footprints from well inside the 256 MB last-level cache to well
+    beyond it (median of 20 timed copies after 5 untimed): the rate the sketch's slab
+    passes can reach while their slab stays cache-resident, against the HBM rate."""
+    out = {}
+    for mb in (16, 32, 64, 128, 192, 256, 512, 2048):
+        nel = mb * (1 << 20) // 16  # two buffers of mb/2 MB each
+        a = torch.empty(nel, dtype=torch.float64, device="cuda").normal_()
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        ts = []
+        for _ in range(20):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            b.copy_(a)
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = float(np.median(ts))
+        out[f"{mb}MB"] = {"ms": round(ms, 5), "GBps_read_plus_write": round(2 * nel * 8 / (ms * 1e-3) / 1e9, 1)}
+        del a, b
+        torch.cuda.empty_cache()
+    return out
+
+
 def mixed_runs(P, torch, At, bt, base_kw, forms, label):
     """Time one solve per precision form (after a warm-up solve) and recompute the
     residual and the optimality certificate ||A^T r|| / (||A||_F ||r||) in FP64."""
@@ -538,6 +565,8 @@ def main():
                     help="only the batched 32-right-hand-side workload (for profiling)")
     ap.add_argument("--sweep", action="store_true",
                     help="only the gamma/s sweep of the dense and sparse workloads; prints it")
+    ap.add_argument("--cache-ceiling", action="store_true",
+                    help="only the copy rate against the copy's footprint (cache vs HBM)")
     ap.add_argument("--sketch-study", action="store_true",
                     help="only the preconditioner-quality study of the sketch variants")
     args = ap.parse_args()
@@ -557,6 +586,9 @@ def main():
         return
     if args.sweep:
         print(json.dumps({"gamma_s_sweep": sweep_run(P, torch)}), flush=True)
+        return
+    if args.cache_ceiling:
+        print(json.dumps({"cache_ceiling": cache_ceiling(torch)}), flush=True)
         return
     if args.sketch_study:
         print(json.dumps({"sketch_study": sketch_study(P, torch)}), flush=True)
@@ -587,16 +619,21 @@ def main():
     for _ in range(args.warmup):
         one_solve(P, S, At, bt, **kw)
     torch.cuda.synchronize()
-    # only the dominant kernel is bracketed by events in the timed region (its average
-    # launch time feeds the roofline); the other launches run without event records
-    S.set_profiling(True, classes=["lsqr_pass"])
-    iters_sum = 0
+    # only the dominant kernel is bracketed by events, in the last two timed steps (its
+    # average launch time feeds the roofline): an event pair costs ~11 us of device time
+    # per iteration, so the other steps and launches run without event records
+    prof_steps = min(2, args.steps)
+    iters_sum = iters_prof = 0
     infos = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for step in range(args.steps):
+        if step == args.steps - prof_steps:
+            S.set_profiling(True, classes=["lsqr_pass"])
         X, info, rc = one_solve(P, S, At, bt, **kw)
         iters_sum += int(info["iters"])
+        if step >= args.steps - prof_steps:
+            iters_prof += int(info["iters"])
         infos.append(info)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -626,14 +663,15 @@ def main():
     # roofline of the dominant kernel: the fused LSQR pass (A once, u read and written)
     pass_ms, pass_cnt = prof["lsqr_pass"]
     pass_bytes = 8 * n * d + 16 * n
-    pass_avg_ms = pass_ms / max(iters_sum, 1)
+    pass_avg_ms = pass_ms / max(iters_prof, 1)
     achieved = pass_bytes / (pass_avg_ms * 1e-3) / 1e9
     traffic = traffic_for_pass(pass_bytes)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                 "traffic": traffic, "kernel": "k_lsqr_pass<16, 2> (fused u = A z - c u, g = A^T u)",
                 "bytes_per_launch": pass_bytes, "avg_launch_ms": round(pass_avg_ms, 5),
-                "launches_timed": pass_cnt, "lsqr_iterations_timed": iters_sum}
+                "launches_timed": pass_cnt, "lsqr_iterations_timed": iters_prof,
+                "timed_steps_with_events": prof_steps}
     # per kernel class, one solve (profiled apart from the timed steps)
     phases = {kname: {"ms_total": round(v[0], 3), "launches": v[1]}
               for kname, v in prof_all.items() if v[1]}
@@ -691,7 +729,8 @@ def main():
 
     if not args.no_mixed:
         forms = [("fp64", {}), ("fp32", dict(sketch_prec="fp32", qr_prec="fp32")),
-                 ("bf16", dict(sketch_prec="bf16", qr_prec="bf16", it_max=3000))]
+                 ("bf16", dict(sketch_prec="bf16", qr_prec="bf16", it_max=3000)),
+                 ("fp64sketch_fp32qr", dict(sketch_prec="fp64", qr_prec="fp32", it_max=3000))]
         out["mixed_dense_50000x4000"] = mixed_runs(P, torch, At, bt, kw, forms, "dense")
         del At, bt
         torch.cuda.empty_cache()
