@@ -162,7 +162,10 @@ __global__ __launch_bounds__(256) void k_cqr_gram(const T* __restrict__ P, int64
 }
 
 // G = sum of the nch partials: slice q of an entry sums the partials q, q + RSL, ... in
-// ascending order, then the slices are added in ascending order
+// ascending order, then the slices are added in ascending order.  A slice's loads (at most
+// RMAX: nch <= RSL RMAX covers m <= 16384) are issued together, indices clamped, and only
+// the valid ones summed, so the sum costs one memory round trip instead of one per term.
+constexpr int RMAX = 16;
 template <typename T>
 __global__ __launch_bounds__(256) void k_cqr_reduce(const T* __restrict__ Gp, int nch,
                                                     T* __restrict__ G) {
@@ -171,9 +174,16 @@ __global__ __launch_bounds__(256) void k_cqr_reduce(const T* __restrict__ Gp, in
     constexpr int EPB = 256 / RSL;  // entries per workgroup
     const int t = threadIdx.x, el = t % EPB, sl = t / EPB;
     const int e = blockIdx.x * EPB + el;
+    T v[RMAX];
+#pragma unroll
+    for (int u = 0; u < RMAX; ++u) {
+        const int c = sl + RSL * u;
+        v[u] = Gp[(int64_t)(c < nch ? c : nch - 1) * PB * PB + e];
+    }
     T s = 0;
-#pragma unroll 4
-    for (int c = sl; c < nch; c += RSL) s += Gp[(int64_t)c * PB * PB + e];
+#pragma unroll
+    for (int u = 0; u < RMAX; ++u)
+        if (sl + RSL * u < nch) s += v[u];
     part[sl][el] = s;
     __syncthreads();
     if (t < EPB) {
@@ -442,6 +452,7 @@ template <typename T>
 hipError_t cqr_gram_update(T* Ac, int64_t m, int64_t jq, int64_t j0, int nb, const T* V,
                            const T* Tq, const CqrWs& w, hipStream_t st) {
     if (nb < 1 || nb > PB || m - j0 < nb) return hipErrorInvalidValue;
+    if (cqr_num_chunks(m) > RSL * RMAX) return hipErrorInvalidValue;
     const int64_t mr = m - j0;
     const int nch = (int)((mr + GR - 1) / GR);
     const unsigned nred = PB * PB / (256 / RSL);

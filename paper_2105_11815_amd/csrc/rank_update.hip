@@ -204,8 +204,19 @@ __global__ __launch_bounds__(256) void k_project_sum(int64_t M, int K, int nspli
     const int64_t j = e / UT;
     const int q = (int)(e % UT);
     if (q >= K) return;
+    // sixteen partials' loads at a time (indices clamped), summed in ascending order
     T s = 0;
-    for (int z = 0; z < nsplit; ++z) s += P[(int64_t)z * M * UT + e];
+    for (int z0 = 0; z0 < nsplit; z0 += 16) {
+        T v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int z = z0 + u < nsplit ? z0 + u : nsplit - 1;
+            v[u] = P[(int64_t)z * M * UT + e];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            if (z0 + u < nsplit) s += v[u];
+    }
     W[j * ldw + q] = s;
 }
 

@@ -295,8 +295,19 @@ __global__ __launch_bounds__(256) void k_ts_reduce(int64_t M, int64_t N, int spl
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (idx >= M * N) return;
     const int64_t i = idx / N, j = idx - i * N;
+    // sixteen partials' loads at a time (indices clamped), summed in ascending order
     double s = 0.0;
-    for (int z = 0; z < splits; ++z) s += part[(int64_t)z * M * N + idx];
+    for (int z0 = 0; z0 < splits; z0 += 16) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int z = z0 + u < splits ? z0 + u : splits - 1;
+            v[u] = part[(int64_t)z * M * N + idx];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            if (z0 + u < splits) s += v[u];
+    }
     double o = alpha * s;
     if (beta != 0.0) o += beta * C[i * ldc + j];
     C[i * ldc + j] = o;
