@@ -726,6 +726,7 @@ uintptr_t qr_ws_layout(Prec prec, uintptr_t base, int64_t m, int64_t ncols, QrWs
     ws.cqr.W = take(NBP * NBP);
     ws.cqr.tau = ws.tau;
     ws.cqr.flag = (int*)take(1);
+    ws.cqr.one_pass = (int*)take(1);
     ws.nonfinite = (int*)take(1);
     return p;
 }

@@ -41,6 +41,11 @@ constexpr int GR = 64;       // rows per workgroup of the Gram / apply / V2 kern
 constexpr int RSL = 16;      // slices of the partial-sum reduction
 constexpr double EPS_SERIES = 1e-8;  // |G2 - I| below which R2 comes from the series
 constexpr double EPS_FIRST = 1e-11;  // ... from its first-order term alone
+// One CholeskyQR pass leaves Q1 = P R1^-1 orthonormal to about u kappa(R1)^2.  When
+// ||R1||_F ||R1^-1||_F (>= kappa_2(R1)) is at most ONE_PASS_KF in FP64, that is 1e-12 or
+// less, and the second pass (Q1, its Gram matrix, R2) is skipped: the reconstruction then
+// works on Q1's top block P_top R1^-1 and V2 = P(nb:, :) R1^-1 M.
+constexpr double ONE_PASS_KF = 96.0;
 
 // x if keep, else +0.0, without a branch (a select can be turned into a branch around the
 // load, which then waits at once; integer masking keeps the loads together)
@@ -168,8 +173,10 @@ __global__ __launch_bounds__(256) void k_cqr_gram(const T* __restrict__ P, int64
 constexpr int RMAX = 16;
 template <typename T>
 __global__ __launch_bounds__(256) void k_cqr_reduce(const T* __restrict__ Gp, int nch,
-                                                    T* __restrict__ G) {
+                                                    T* __restrict__ G,
+                                                    const int* __restrict__ skip) {
     chain_priority();
+    if (skip && *skip) return;
     __shared__ T part[RSL][256 / RSL];
     constexpr int EPB = 256 / RSL;  // entries per workgroup
     const int t = threadIdx.x, el = t % EPB, sl = t / EPB;
@@ -196,11 +203,13 @@ __global__ __launch_bounds__(256) void k_cqr_reduce(const T* __restrict__ Gp, in
 
 // ---------------------------------------------------------------- kernels
 
-// first Cholesky: G (PB x PB, identity beyond nb) -> R1 and R1^-1 (row-major PB x PB)
+// first Cholesky: G (PB x PB, identity beyond nb) -> R1 and R1^-1 (row-major PB x PB), and
+// the one-pass decision for this panel
 template <typename T>
 __global__ __launch_bounds__(256) void k_cqr_chol1(const T* __restrict__ G, int nb,
                                                    T* __restrict__ R1, T* __restrict__ R1i,
-                                                   int* __restrict__ flag) {
+                                                   int* __restrict__ flag,
+                                                   int* __restrict__ one_pass) {
     chain_priority();
     __shared__ T A[PB][PP];
     __shared__ int bad;
@@ -218,10 +227,33 @@ __global__ __launch_bounds__(256) void k_cqr_chol1(const T* __restrict__ G, int 
     }
     __syncthreads();
     tile_chol(A, t, &bad);
-    for (int o = t; o < PB * PB; o += 256) R1[o] = A[o / PB][o % PB];
+    T nr = 0, ni = 0;  // squared Frobenius norms of R1 and R1^-1 (this thread's entries)
+    for (int o = t; o < PB * PB; o += 256) {
+        const T x = A[o / PB][o % PB];
+        R1[o] = x;
+        nr += x * x;
+    }
     tile_trinv(A, t, false);
-    for (int o = t; o < PB * PB; o += 256) R1i[o] = A[o / PB][o % PB];
-    if (t == 0 && bad) flag[0] = 1;
+    for (int o = t; o < PB * PB; o += 256) {
+        const T x = A[o / PB][o % PB];
+        R1i[o] = x;
+        ni += x * x;
+    }
+    __shared__ T red[2][4];
+    nr = wave_sum(nr);
+    ni = wave_sum(ni);
+    if ((t & 63) == 0) {
+        red[0][t >> 6] = nr;
+        red[1][t >> 6] = ni;
+    }
+    __syncthreads();
+    if (t == 0) {
+        const T kf2 = ((red[0][0] + red[0][1]) + (red[0][2] + red[0][3])) *
+                      ((red[1][0] + red[1][1]) + (red[1][2] + red[1][3]));
+        const bool one = sizeof(T) == 8 && !bad && kf2 <= (T)(ONE_PASS_KF * ONE_PASS_KF);
+        one_pass[0] = one ? 1 : 0;
+        if (bad) flag[0] = 1;
+    }
 }
 
 // Q1 = P R1^-1 over the rows [b GR, (b+1) GR) (column-major, ld ldq) and the Gram partial
@@ -231,8 +263,10 @@ __global__ __launch_bounds__(256) void k_cqr_apply_gram(const T* __restrict__ P,
                                                         int64_t mr, int nb,
                                                         const T* __restrict__ Ri,
                                                         T* __restrict__ Q, int64_t ldq,
-                                                        T* __restrict__ Gp) {
+                                                        T* __restrict__ Gp,
+                                                        const int* __restrict__ one_pass) {
     chain_priority();
+    if (*one_pass) return;
     __shared__ T Xs[PB][PP];
     __shared__ T sh[GR][PP];
     const int t = threadIdx.x;
@@ -257,7 +291,9 @@ __global__ __launch_bounds__(256) void k_cqr_chol2(const T* __restrict__ G, int 
                                                    const T* __restrict__ Q, int64_t ldq,
                                                    T* __restrict__ Pt, int64_t ldp,
                                                    T* __restrict__ tau, T* __restrict__ Mx,
-                                                   T* __restrict__ Tx, int* __restrict__ flag) {
+                                                   T* __restrict__ Tx, int* __restrict__ flag,
+                                                   const T* __restrict__ R1i,
+                                                   const int* __restrict__ one_pass) {
     chain_priority();
     __shared__ T A[PB][PP];  // G2 -> R2 -> R2^-1 -> M
     __shared__ T B[PB][PP];  // R1 -> R = R2 R1
@@ -267,7 +303,31 @@ __global__ __launch_bounds__(256) void k_cqr_chol2(const T* __restrict__ G, int 
     __shared__ int bad;
     const int t = threadIdx.x;
     int off = 0, big = 0, second = 0;
-    {
+    if (*one_pass) {
+        // one CholeskyQR pass: R = R1, "R2^-1" := R1^-1 (so that M below comes out as
+        // -R1^-1 S U'^-1, for V2 = P(nb:, :) M), Qt = P_top R1^-1 from the panel's own top
+        // block (read before it is overwritten at the end)
+        T rv[PB * PB / 256], iv[PB * PB / 256], pv[PB * PB / 256];
+#pragma unroll
+        for (int q = 0; q < PB * PB / 256; ++q) {
+            const int o = t + 256 * q, r = o % PB, c = o / PB;
+            rv[q] = R1[o];
+            iv[q] = R1i[o];
+            pv[q] = Pt[(int64_t)(c < nb ? c : nb - 1) * ldp + (r < nb ? r : nb - 1)];
+        }
+#pragma unroll
+        for (int q = 0; q < PB * PB / 256; ++q) {
+            const int o = t + 256 * q, i = o / PB, j = o % PB;
+            B[i][j] = rv[q];
+            A[i][j] = iv[q];
+            const int r = o % PB, c = o / PB;
+            C[r][c] = keep_or_zero(pv[q], r < nb && c < nb);
+        }
+        if (t == 0) bad = 0;
+        __syncthreads();
+        tile_mma(C, t, [&](int i, int k) { return C[i][k]; }, [&](int k, int j) { return A[k][j]; },
+                 KFullUpper{}, [](int, int, T v) { return v; });
+    } else {
         // all loads first (Q1's top block walked column-major for coalescing; rows and
         // columns beyond nb are clamped and zeroed)
         T gv[PB * PB / 256], rv[PB * PB / 256], qv[PB * PB / 256];
@@ -292,52 +352,52 @@ __global__ __launch_bounds__(256) void k_cqr_chol2(const T* __restrict__ G, int 
             const int r = o % PB, c = o / PB;
             C[r][c] = keep_or_zero(qv[q], r < nb && c < nb);
         }
-    }
-    if (t == 0) bad = 0;
-    off = __syncthreads_or(off);
-    big = __syncthreads_or(big);
-    second = __syncthreads_or(second);
-    if (!second) {
-        // |G2 - I| <= EPS_FIRST: to first order R2 = I + F, R2^-1 = I - F with
-        // F = up(G2 - I); the neglected terms are O(|G2 - I|^2), below 1e-18
-        tile_eval(D, t, [&](int i, int j) {
-            const T e = A[i][j] - (i == j ? (T)1 : (T)0);
-            return i < j ? e : (i == j ? e * (T)0.5 : (T)0);
-        });
-        // R = R1 + F R1
-        tile_mma(B, t, [&](int i, int k) { return D[i][k]; }, [&](int k, int j) { return B[k][j]; },
-                 KFullUpper{}, [&](int i, int j, T v) { return B[i][j] + v; });
-        tile_eval(A, t, [&](int i, int j) { return (i == j ? (T)1 : (T)0) - D[i][j]; });
-    } else if (big) {
-        tile_chol(A, t, &bad);
-        // R = R2 R1 (both upper)
-        tile_mma(B, t, [&](int i, int k) { return A[i][k]; }, [&](int k, int j) { return B[k][j]; },
+        if (t == 0) bad = 0;
+        off = __syncthreads_or(off);
+        big = __syncthreads_or(big);
+        second = __syncthreads_or(second);
+        if (!second) {
+            // |G2 - I| <= EPS_FIRST: to first order R2 = I + F, R2^-1 = I - F with
+            // F = up(G2 - I); the neglected terms are O(|G2 - I|^2), below 1e-18
+            tile_eval(D, t, [&](int i, int j) {
+                const T e = A[i][j] - (i == j ? (T)1 : (T)0);
+                return i < j ? e : (i == j ? e * (T)0.5 : (T)0);
+            });
+            // R = R1 + F R1
+            tile_mma(B, t, [&](int i, int k) { return D[i][k]; }, [&](int k, int j) { return B[k][j]; },
+                     KFullUpper{}, [&](int i, int j, T v) { return B[i][j] + v; });
+            tile_eval(A, t, [&](int i, int j) { return (i == j ? (T)1 : (T)0) - D[i][j]; });
+        } else if (big) {
+            tile_chol(A, t, &bad);
+            // R = R2 R1 (both upper)
+            tile_mma(B, t, [&](int i, int k) { return A[i][k]; }, [&](int k, int j) { return B[k][j]; },
+                     KFullUpper{}, [](int, int, T v) { return v; });
+            tile_trinv(A, t, false);
+        } else {
+            // G2 = I + E with |E| <= EPS_SERIES: R2 = I + F where F + F^T + F^T F = E is solved
+            // by two steps of F <- up(E - F^T F) (up: strict upper part plus half the diagonal),
+            // and R2^-1 = I - F + F^2; both are exact to O(|E|^3), far below rounding
+            auto up = [](int i, int j, T x) { return i < j ? x : (i == j ? x * (T)0.5 : (T)0); };
+            tile_eval(D, t, [&](int i, int j) { return up(i, j, A[i][j] - (i == j ? (T)1 : (T)0)); });
+            tile_mma(A, t, [&](int i, int k) { return D[k][i]; }, [&](int k, int j) { return D[k][j]; },
+                     KFull{}, [&](int i, int j, T v) {
+                         return (i == j ? (T)1 : (T)0) +
+                                up(i, j, A[i][j] - (i == j ? (T)1 : (T)0) - v);
+                     });
+            // R = R2 R1 (both upper)
+            tile_mma(B, t, [&](int i, int k) { return A[i][k]; }, [&](int k, int j) { return B[k][j]; },
+                     KFullUpper{}, [](int, int, T v) { return v; });
+            // R2^-1 = I - F + F F with F = R2 - I
+            tile_mma(A, t, [&](int i, int k) { return A[i][k] - (i == k ? (T)1 : (T)0); },
+                     [&](int k, int j) { return A[k][j] - (k == j ? (T)1 : (T)0); }, KFullUpper{},
+                     [&](int i, int j, T v) {
+                         return (i == j ? (T)1 : (T)0) - (A[i][j] - (i == j ? (T)1 : (T)0)) + v;
+                     });
+        }
+        // Qt = Q1top R2^-1
+        tile_mma(C, t, [&](int i, int k) { return C[i][k]; }, [&](int k, int j) { return A[k][j]; },
                  KFullUpper{}, [](int, int, T v) { return v; });
-        tile_trinv(A, t, false);
-    } else {
-        // G2 = I + E with |E| <= EPS_SERIES: R2 = I + F where F + F^T + F^T F = E is solved
-        // by two steps of F <- up(E - F^T F) (up: strict upper part plus half the diagonal),
-        // and R2^-1 = I - F + F^2; both are exact to O(|E|^3), far below rounding
-        auto up = [](int i, int j, T x) { return i < j ? x : (i == j ? x * (T)0.5 : (T)0); };
-        tile_eval(D, t, [&](int i, int j) { return up(i, j, A[i][j] - (i == j ? (T)1 : (T)0)); });
-        tile_mma(A, t, [&](int i, int k) { return D[k][i]; }, [&](int k, int j) { return D[k][j]; },
-                 KFull{}, [&](int i, int j, T v) {
-                     return (i == j ? (T)1 : (T)0) +
-                            up(i, j, A[i][j] - (i == j ? (T)1 : (T)0) - v);
-                 });
-        // R = R2 R1 (both upper)
-        tile_mma(B, t, [&](int i, int k) { return A[i][k]; }, [&](int k, int j) { return B[k][j]; },
-                 KFullUpper{}, [](int, int, T v) { return v; });
-        // R2^-1 = I - F + F F with F = R2 - I
-        tile_mma(A, t, [&](int i, int k) { return A[i][k] - (i == k ? (T)1 : (T)0); },
-                 [&](int k, int j) { return A[k][j] - (k == j ? (T)1 : (T)0); }, KFullUpper{},
-                 [&](int i, int j, T v) {
-                     return (i == j ? (T)1 : (T)0) - (A[i][j] - (i == j ? (T)1 : (T)0)) + v;
-                 });
-    }
-    // Qt = Q1top R2^-1
-    tile_mma(C, t, [&](int i, int k) { return C[i][k]; }, [&](int k, int j) { return A[k][j]; },
-             KFullUpper{}, [](int, int, T v) { return v; });
+    }  // two passes
     tile_lu_signed(C, sg, t);
     // U'(k, c) = delta_kc - s_c C(k, c) on and above the diagonal; then U'^-1 in place
     tile_eval(D, t, [&](int i, int j) {
@@ -402,7 +462,8 @@ __global__ __launch_bounds__(256) void k_cqr_update_gram(T* __restrict__ Ac, int
     if (blockIdx.x > 0) chunk_gram(Cs, Gp + (int64_t)(blockIdx.x - 1) * PB * PB, t);
 }
 
-// The panel's reflectors: V2 = Q1 M below the top block, L1 (unit lower) in it.  Chunk b
+// The panel's reflectors: V2 = Q1 M below the top block (P R1^-1 M after one pass), L1
+// (unit lower) in it.  Chunk b
 // covers the panel rows [b GR, (b+1) GR): V2 rows go into the panel, the explicit V (unit
 // diagonal, zeros above) into Vout (column-major, ld mr), and with a next panel of nbn
 // columns the partial products V^T C_next of those rows into Gp[b].
@@ -411,7 +472,8 @@ __global__ __launch_bounds__(256) void k_cqr_v2x(const T* __restrict__ Q, int64_
                                                  int nb, const T* __restrict__ Mx,
                                                  T* __restrict__ P, int64_t ldp,
                                                  T* __restrict__ Vout, int nbn,
-                                                 T* __restrict__ Gp) {
+                                                 T* __restrict__ Gp,
+                                                 const int* __restrict__ one_pass) {
     chain_priority();
     __shared__ T Ms[PB][PP];
     __shared__ T Qs[PB][PP];
@@ -419,7 +481,12 @@ __global__ __launch_bounds__(256) void k_cqr_v2x(const T* __restrict__ Q, int64_
     const int t = threadIdx.x;
     const int64_t r0 = (int64_t)blockIdx.x * GR, r1 = std::min<int64_t>(mr, r0 + GR);
     load_tile(Mx, Ms, t);
-    stage_chunk(Q, ldq, r0, r1, nb, Qs, t);
+    // one pass: V2 = P(nb:, :) M with M = -R1^-1 S U'^-1 (rows < nb of the product unused:
+    // the panel's top block, already overwritten, gives L1 below)
+    if (*one_pass)
+        stage_chunk((const T*)P, ldp, r0, r1, nb, Qs, t);
+    else
+        stage_chunk(Q, ldq, r0, r1, nb, Qs, t);
     if (nbn > 0) stage_chunk(P + (int64_t)nb * ldp, ldp, r0, r1, nbn, Cs, t);
     __syncthreads();
     tile_mma(Qs, t, [&](int i, int k) { return Qs[i][k]; }, [&](int k, int j) { return Ms[k][j]; },
@@ -465,7 +532,7 @@ hipError_t cqr_gram_update(T* Ac, int64_t m, int64_t jq, int64_t j0, int nb, con
                            nb, V, Tq, (const T*)w.W, (T*)w.Gp);
     }
     hipLaunchKernelGGL((k_cqr_reduce<T>), dim3(nred), dim3(256), 0, st, (const T*)w.Gp, nch,
-                       (T*)w.G);
+                       (T*)w.G, (const int*)nullptr);
     return hipGetLastError();
 }
 
@@ -483,12 +550,16 @@ hipError_t cqr_factor_panel(T* Ac, int64_t m, int64_t j0, int nb, const CqrWs& w
     T* R1i = (T*)w.R1i;
     const int nch = (int)((mr + GR - 1) / GR);
     const unsigned nred = PB * PB / (256 / RSL);
-    hipLaunchKernelGGL((k_cqr_chol1<T>), dim3(1), dim3(256), 0, st, G, nb, R1, R1i, w.flag);
+    hipLaunchKernelGGL((k_cqr_chol1<T>), dim3(1), dim3(256), 0, st, G, nb, R1, R1i, w.flag,
+                       w.one_pass);
+    // the second pass's kernels return at once when the first Cholesky chose one pass
     hipLaunchKernelGGL((k_cqr_apply_gram<T>), dim3(nch), dim3(256), 0, st, P, m, mr, nb, R1i, Q,
-                       m, Gp);
-    hipLaunchKernelGGL((k_cqr_reduce<T>), dim3(nred), dim3(256), 0, st, Gp, nch, G);
+                       m, Gp, (const int*)w.one_pass);
+    hipLaunchKernelGGL((k_cqr_reduce<T>), dim3(nred), dim3(256), 0, st, Gp, nch, G,
+                       (const int*)w.one_pass);
     hipLaunchKernelGGL((k_cqr_chol2<T>), dim3(1), dim3(256), 0, st, G, nb, R1, Q, m, P, m,
-                       (T*)w.tau + j0, (T*)w.Mx, Tout, w.flag);
+                       (T*)w.tau + j0, (T*)w.Mx, Tout, w.flag, (const T*)R1i,
+                       (const int*)w.one_pass);
     return hipGetLastError();
 }
 
@@ -499,10 +570,11 @@ hipError_t cqr_finish_panel(T* Ac, int64_t m, int64_t j0, int nb, int nbn, const
     const int64_t mr = m - j0;
     const int nch = (int)((mr + GR - 1) / GR);
     hipLaunchKernelGGL((k_cqr_v2x<T>), dim3(nch), dim3(256), 0, st, (const T*)w.Q1, m, mr, nb,
-                       (const T*)w.Mx, Ac + j0 * m + j0, m, Vout, nbn, (T*)w.Gp);
+                       (const T*)w.Mx, Ac + j0 * m + j0, m, Vout, nbn, (T*)w.Gp,
+                       (const int*)w.one_pass);
     if (nbn > 0)
         hipLaunchKernelGGL((k_cqr_reduce<T>), dim3(PB * PB / (256 / RSL)), dim3(256), 0, st,
-                           (const T*)w.Gp, nch, (T*)w.W);
+                           (const T*)w.Gp, nch, (T*)w.W, (const int*)nullptr);
     return hipGetLastError();
 }
 

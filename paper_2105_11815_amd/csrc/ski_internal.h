@@ -218,6 +218,7 @@ struct CqrWs {
     void* W = nullptr;    // V^T C_next of the last finished panel, 64 x 64
     void* tau = nullptr;  // the QR's taus (indexed by global column)
     int* flag = nullptr;  // set to 1 when a panel is too ill-conditioned for CholeskyQR2
+    int* one_pass = nullptr;  // per panel, set by the first Cholesky: 1 when one pass suffices
 };
 int64_t cqr_num_chunks(int64_t m);
 // Gram matrix of the panel [j0, j0+nb) into w.G; with jq >= 0 the previous panel's block

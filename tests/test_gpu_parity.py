@@ -129,6 +129,29 @@ def test_qr_of_sketch_matches_oracle(ski, n, d, m, s, panel):
     S.close()
 
 
+@pytest.mark.parametrize("grade", [0.0, 1.0, 3.0])
+def test_qr_of_graded_columns_matches_oracle(ski, grade):
+    """Columns scaled by 10^(-grade (j mod 16) / 15): grade 0 gives panels whose first
+    Cholesky factor is well conditioned (one CholeskyQR pass, the second skipped on the
+    device), grades 1 and 3 panels whose column norms spread over 10 and 1000 (both passes).
+    R and c against the oracle's Householder QR in either case."""
+    n, d, m, s = 8000, 300, 520, 3
+    _say(f"qr graded columns grade={grade}")
+    rng = np.random.default_rng(77)
+    A = rng.standard_normal((n, d)) * 10.0 ** (-grade * (np.arange(d) % 16) / 15.0)
+    b = rng.standard_normal(n)
+    ref = sk.sketch_dense(A, b, m, s, 41)
+    Rref, cref, _ = lls.factor(ref["SA_aug"], d)
+    S = ski.Solver()
+    S.sketch(dev(A), dev(b), m=m, s=s, seed=41).factor()
+    R, c, Ri = S.get_R()
+    S.close()
+    scale = np.abs(Rref).max()
+    np.testing.assert_allclose(R, Rref, rtol=0, atol=1e-12 * scale * math.sqrt(d))
+    np.testing.assert_allclose(c, cref, rtol=0, atol=1e-12 * np.abs(cref).max() * math.sqrt(d))
+    np.testing.assert_allclose(R @ Ri, np.eye(d), atol=1e-11 * np.linalg.cond(R))
+
+
 def test_qr_falls_back_on_an_ill_conditioned_panel(ski):
     # two nearly equal columns in the first panel: cond(panel) ~ 1e11, beyond what
     # CholeskyQR2 resolves in FP64; the device check must send the factorisation to the

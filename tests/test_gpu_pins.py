@@ -383,3 +383,35 @@ def test_autograd_backward_twice_with_retained_graph(ski):
     assert torch.equal(g1, At.grad)
     with pytest.warns(RuntimeWarning, match="it_max"):
         ski.SkiLstsq.apply(dev(A), dev(B), dict(gamma=1.7, s=3, seed=3, tau_r=1e-14, it_max=2))
+
+
+# ------------------------------------------------------------------ wide problems
+@pytest.mark.parametrize("n,d,gamma,fused", [(12000, 5000, 1.7, True), (16384, 8500, 1.2, False)])
+def test_wide_problems_reach_the_certificate(ski, n, d, gamma, fused):
+    """d = 5000 runs the fused pass with 24 columns per thread (d in 4097..6144); d = 8500
+    is beyond the fused pass (d > 8192) and runs the two-product iteration.  A direct solve
+    at these sizes is out of the tests' reach on the host, so the pin is the optimality
+    certificate recomputed in FP64 against the bound that (TC-lsqr) implies, and LSQR's
+    residual estimate against the recomputed residual."""
+    _say(f"wide problem n={n} d={d} gamma={gamma}")
+    rng = np.random.default_rng(d)
+    A = rng.standard_normal((n, d))
+    A[: n // 5] *= 1e3
+    b = rng.standard_normal(n)
+    S = ski.Solver()
+    S.set_profiling(True)
+    S.sketch(dev(A), dev(b), gamma=gamma, s=3, seed=5, tau_r=1e-10).factor()
+    X, infos, rc = S.solve()
+    prof = S.profile()
+    R = S.get_R()[0]
+    S.close()
+    x = X[:, 0].cpu().numpy()
+    r = b - A @ x
+    anorm = np.linalg.norm(A)
+    cert = np.linalg.norm(A.T @ r) / (anorm * np.linalg.norm(r))
+    bound = 1e-10 * np.linalg.norm(R) * infos[0]["wnorm_est"] / anorm + 1e-13
+    _say(f"  iters {infos[0]['iters']} certificate {cert:.3e} (bound {bound:.3e}), fused-pass "
+         f"launches {prof['lsqr_pass'][1]}")
+    assert rc == 0 and cert <= bound
+    assert abs(infos[0]["rnorm"] - np.linalg.norm(r)) <= 1e-8 * np.linalg.norm(r)
+    assert (prof["lsqr_pass"][1] > 0) == fused
