@@ -19,6 +19,9 @@ lls     -- QR of the sketch, the sketched solution and early exit, LSQR on
            W = A R^-1 with the (TC-lsqr) stopping test, the recovered x
            (Algorithm 1, Steps 2-5), the direct dense reference solve and the
            adjoint (backward) used for differentiation.
+sparse_qr -- the sparse form of Step 2 (Section 6): the pattern of the sketch,
+           the minimum-degree column ordering, the structure of R and the
+           solve on the column-permuted matrix.
 """
 
-from . import philox, sketch, lls  # noqa: F401
+from . import philox, sketch, lls, sparse_qr  # noqa: F401

@@ -35,6 +35,13 @@ Recipes (host numpy Generator(PCG64(1000 + case)) unless stated):
             available): 1% of the entries N(0,1) at uniform positions, plus one
             entry per column so that no column is empty, then columns scaled by
             10^(-6 j/(d-1)) for a condition number near 1e6.
+* very_sparse  n x d CSR with a few stored entries per column (default 40000 x
+            8000, 2 per column): column j holds row j and per_col - 1 further
+            distinct uniform rows, values N(0,1); b ~ N(0,1); no Hadamard,
+            s = 2, gamma = 1.4 (m = 11200).  Stands in for the very sparse
+            matrices of the Florida collection on which the paper's sparse
+            solver relies on a sparse QR of the sketch (such a sketch keeps a
+            few entries per column, and its R stays sparse).
 * semico_sparse  the paper's semi-coherent type [B 0; 0 I_{d/2}] + 1e-8 J with B
             an inco_sparse matrix of (n - d/2) x d/2 (the matrix of the paper's
             s = 1, 2, 3 comparison), as dense float64.
@@ -51,6 +58,8 @@ CASES = {
     "illcond": dict(n=50000, d=7000, s=3, gamma=1.7, m=11900, hadamard=True, case=4),
     "batched": dict(n=20000, d=1000, s=3, gamma=1.7, m=1700, hadamard=True, case=5, k=32),
     "rankdef": dict(n=50000, d=4000, rank=3500, s=3, gamma=1.7, m=6800, hadamard=True, case=6),
+    "very_sparse": dict(n=40000, d=8000, s=2, gamma=1.4, m=11200, hadamard=False, case=9,
+                        per_col=2),
 }
 
 POWER_LAW_ALPHA = 1.6725
@@ -205,3 +214,30 @@ def semico_sparse(n=4000, d=400, case=8):
     A[: n - h, :h] += inco_sparse(n - h, h, case=case)
     A[n - h + np.arange(h), h + np.arange(h)] += 1.0
     return A, np.ones(n)
+
+
+def very_sparse(n=40000, d=8000, per_col=2, case=9):
+    """CSR arrays (row_ptr int64, col int32, val float64) and b ~ N(0,1): column j
+    holds row j and per_col - 1 further distinct rows drawn uniformly."""
+    rng = rng_for(case)
+    rows = np.empty((d, per_col), dtype=np.int64)
+    rows[:, 0] = np.arange(d)
+    if per_col > 1:
+        rows[:, 1:] = rng.integers(0, n, size=(d, per_col - 1))
+        # redraw any row that repeats within its column
+        while True:
+            srt = np.sort(rows, axis=1)
+            bad = (srt[:, 1:] == srt[:, :-1]).any(axis=1)
+            if not bad.any():
+                break
+            idx = np.nonzero(bad)[0]
+            rows[idx, 1:] = rng.integers(0, n, size=(idx.size, per_col - 1))
+    cols = np.repeat(np.arange(d, dtype=np.int64), per_col)
+    row_of = rows.ravel()
+    vals = rng.standard_normal(row_of.size)
+    order = np.lexsort((cols, row_of))
+    row_of, cols, vals = row_of[order], cols[order], vals[order]
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(row_of, minlength=n), out=row_ptr[1:])
+    b = rng.standard_normal(n)
+    return row_ptr, cols.astype(np.int32), vals, b
