@@ -67,7 +67,8 @@ enum ski_qr_panel {
     SKI_QR_HOUSEHOLDER = 1,
     SKI_QR_PIVOTED = 2,
     SKI_QR_PIVOTED_HOUSEHOLDER = 3,
-    SKI_QR_PIVOTED_COD = 4
+    SKI_QR_PIVOTED_COD = 4,
+    SKI_QR_SPARSE = 5
 };
 
 /* The data matrix.  Dense: `a` (n x d, row-major, leading dimension lda >= d).
@@ -131,6 +132,24 @@ typedef struct {
  *                factored by Householder columns; one host synchronisation per panel),
  *                and the sketch is updated from R_12.  SKI_QR_PIVOTED_HOUSEHOLDER: the
  *                same with Householder-column panels only (no per-panel synchronisation).
+ *                SKI_QR_SPARSE (CSR A only, FP64, k <= 32): the sparse form of Step 2 in
+ *                Section 6, S A P = Q R with P a fill-reducing column ordering, and every
+ *                product with R^-1 or R^-T a sparse substitution instead of an explicit
+ *                inverse.  ski_sketch keeps S A sparse (rows of ascending columns, entries
+ *                summed in the dense sketch's order, so equal to it bit for bit).
+ *                ski_factor orders the columns by exact minimum degree on the column graph
+ *                of (SA)^T (SA) (smallest degree first, ties by smallest column index),
+ *                stopping once the smallest degree exceeds 63 - k; the columns left form
+ *                one dense root, placed last in increasing index.  Each eliminated column
+ *                is one front of a multifrontal QR (its rows, and the contribution blocks
+ *                of its children in the elimination tree, factored by Householder
+ *                reflections); the root front is factored by the dense QR above and its
+ *                R^-1 formed explicitly.  R (d x d in position order: upper, row q sparse
+ *                for q below the root) and V-hat = P are returned by ski_get_R and
+ *                ski_get_pivots; ski_get_factor_stats gives the leaf fronts and the root
+ *                size.  No rank detection: rank = d, and the guards rcond and
+ *                rcond_thres/perturb act on the whole diagonal as without pivoting.  The
+ *                ordering and the symbolic structure are computed on the host.
  *                SKI_QR_PIVOTED_COD: the minimal-norm form (the complete orthogonal
  *                decomposition that the factorisation remark allows, with R_12 = 0): the
  *                SKI_QR_PIVOTED factorisation truncated at p, then a QR of the transposed
@@ -268,7 +287,9 @@ int ski_sketch_noalloc(const ski_matrix* A, const double* B, int32_t k, int64_t 
  *   SA: the sketch m x (d+k) row-major, converted to double.
  *   R: d x d row-major (upper triangle, zeros below); c: d x k; Rinv: d x d (after a
  *      pivoted factor: R of the permuted sketch S A P, and Rinv = R_11^-1, p x p; after
- *      SKI_QR_PIVOTED_COD: Rinv = L^-1, p x p, for Rtop^T = Y L). */
+ *      SKI_QR_PIVOTED_COD: Rinv = L^-1, p x p, for Rtop^T = Y L; after SKI_QR_SPARSE: R
+ *      of S A P in position order, c likewise, and Rinv is not formed: SKI_ESTATE if
+ *      Rinv is not NULL).  With SKI_QR_SPARSE, SA is returned dense. */
 /* Kernel timing for measurement (not needed to solve).  ski_set_profiling(h, 1) makes the
  * library record a HIP event pair on the launch stream around every launch of the kernel
  * classes below (clearing earlier totals); ski_get_profile returns, per class, the summed
@@ -279,7 +300,9 @@ int ski_sketch_noalloc(const ski_matrix* A, const double* B, int32_t k, int64_t 
  * hashing gather, by column slabs), 8 hashing gather without the Hadamard mix (dense or
  * CSR), 9 whole QR of the sketch with CholeskyQR2 panels, 10 explicit R^-1, 11 whole QR
  * with column-by-column Householder panels, 12 whole column-pivoted QR (pivot sketch,
- * selection, moves, panels, updates).  ms[] and count[] hold SKI_PROF_CLASSES
+ * selection, moves, panels, updates), 13 sparse sketch (SKI_QR_SPARSE), 14 its symbolic
+ * phase and leaf fronts, 15 its root front (assembly and dense QR); the sparse
+ * factor's triangular solves are timed as class 2.  ms[] and count[] hold SKI_PROF_CLASSES
  * entries.  ski_set_profiling(h, 1) times every class; ski_set_profiling_mask times only
  * the classes whose bit is set (bit c for class c; 0 switches profiling off), which keeps
  * the event records out of the other launches. */
@@ -300,7 +323,9 @@ int ski_get_R(ski_handle h, double* R, double* c, double* Rinv);
 int ski_get_pivots(ski_handle h, int32_t* perm, int64_t* rank);
 /* After ski_factor: stats[0] = rank p, stats[1] = number of 64-column panels,
  * stats[2] = panels that CholeskyQR2 factored in a pivoted factorisation (-1 without
- * pivoting), stats[3] = 1 if the factorisation pivoted.  SKI_ESTATE before ski_factor. */
+ * pivoting), stats[3] = 1 if the factorisation pivoted.  After SKI_QR_SPARSE: stats[1] =
+ * leaf fronts (eliminated columns), stats[2] = root columns, stats[3] = 2.  SKI_ESTATE
+ * before ski_factor. */
 int ski_get_factor_stats(ski_handle h, int64_t stats[4]);
 
 #ifdef __cplusplus

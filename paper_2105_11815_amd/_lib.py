@@ -16,6 +16,7 @@ SKI_DENSE, SKI_DENSE_COLMAJOR, SKI_CSR = 0, 1, 2
 SKI_FP64, SKI_FP32, SKI_BF16 = 0, 1, 2
 SKI_OP_LLS, SKI_OP_NORMAL = 0, 1
 SKI_QR_AUTO, SKI_QR_HOUSEHOLDER, SKI_QR_PIVOTED, SKI_QR_PIVOTED_HOUSEHOLDER, SKI_QR_PIVOTED_COD = 0, 1, 2, 3, 4
+SKI_QR_SPARSE = 5
 SKI_HASH, SKI_HASH_VARIANT, SKI_SAMPLE_ROWS = 0, 1, 2
 
 STATUS_NAMES = {0: "OK", 1: "WNOCONV", 2: "WEARLY", -1: "EINVAL", -2: "ENOMEM",
@@ -28,7 +29,8 @@ EXPORTED = ["ski_create", "ski_destroy", "ski_params_default", "ski_sketch", "sk
             "ski_get_factor_stats", "ski_sketch_noalloc"]
 PROF_CLASSES = 16
 PROF_NAMES = ["lsqr_pass", "pass_reduce", "tri_gemv", "spmv_csr", "spmv_csrT", "lsqr_step",
-              "hash", "wht_gather", "gather", "qr", "trtri", "qr_householder", "qr_pivoted"]
+              "hash", "wht_gather", "gather", "qr", "trtri", "qr_householder", "qr_pivoted",
+              "sparse_sketch", "sparse_fronts", "sparse_root"]
 
 
 class SkiMatrix(C.Structure):

@@ -18,7 +18,7 @@ _PREC = {"fp64": L.SKI_FP64, "fp32": L.SKI_FP32, "bf16": L.SKI_BF16}
 _HASH = {"hash": L.SKI_HASH, "variant": L.SKI_HASH_VARIANT, "sample": L.SKI_SAMPLE_ROWS}
 _PANEL = {"auto": L.SKI_QR_AUTO, "householder": L.SKI_QR_HOUSEHOLDER,
           "pivoted": L.SKI_QR_PIVOTED, "pivoted_householder": L.SKI_QR_PIVOTED_HOUSEHOLDER,
-          "cod": L.SKI_QR_PIVOTED_COD}
+          "cod": L.SKI_QR_PIVOTED_COD, "sparse": L.SKI_QR_SPARSE}
 
 
 class SkiError(RuntimeError):
@@ -276,10 +276,20 @@ class Solver:
         return out
 
     def get_R(self):
-        """(R d x d, c d x k, R^-1); after a pivoted factor R^-1 is R_11^-1 (p x p)."""
+        """(R d x d, c d x k, R^-1); after a pivoted factor R^-1 is R_11^-1 (p x p); after
+        the sparse factor R is in position order and R^-1 (not formed) is None."""
         dm = self.dims()
         R = np.zeros((dm["d"], dm["d"]))
         c = np.zeros((dm["d"], dm["k"]))
+        try:
+            sparse = self.factor_stats()["sparse"]
+        except SkiError:
+            sparse = False
+        if sparse:
+            rc = self._lib.ski_get_R(self._h, R.ctypes.data, c.ctypes.data, None)
+            if rc != L.SKI_OK:
+                self._raise(rc, "ski_get_R")
+            return R, c, None
         Ri = np.zeros(dm["d"] * dm["d"])
         rc = self._lib.ski_get_R(self._h, R.ctypes.data, c.ctypes.data, Ri.ctypes.data)
         if rc != L.SKI_OK:
@@ -291,12 +301,17 @@ class Solver:
         return R, c, Ri[: p * p].reshape(p, p)
 
     def factor_stats(self):
-        """{rank, panels, panels_cqr (-1 without pivoting), pivoted} of the last factor."""
+        """{rank, panels, panels_cqr (-1 without pivoting), pivoted, sparse} of the last
+        factor; after the sparse factor {rank, leaf_fronts, root, sparse=True}."""
         a = np.zeros(4, dtype=np.int64)
         rc = self._lib.ski_get_factor_stats(self._h, a.ctypes.data)
         if rc != L.SKI_OK:
             self._raise(rc, "ski_get_factor_stats")
-        return dict(rank=int(a[0]), panels=int(a[1]), panels_cqr=int(a[2]), pivoted=bool(a[3]))
+        if a[3] == 2:
+            return dict(rank=int(a[0]), leaf_fronts=int(a[1]), root=int(a[2]), pivoted=True,
+                        sparse=True)
+        return dict(rank=int(a[0]), panels=int(a[1]), panels_cqr=int(a[2]), pivoted=bool(a[3]),
+                    sparse=False)
 
     def get_pivots(self):
         """(perm: position j holds column perm[j] of A, rank p) of the last factor."""

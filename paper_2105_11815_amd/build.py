@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libski.so")
-SOURCES = ["hash.hip", "sketch.hip", "gemm.hip", "rank_update.hip", "tsgemm.hip", "qr.hip", "rinv.hip", "qr_panel.hip", "rcpqr.hip", "dht.hip", "lsqr.hip", "ski_api.hip", "ski_noalloc.hip"]
+SOURCES = ["hash.hip", "sketch.hip", "gemm.hip", "rank_update.hip", "tsgemm.hip", "qr.hip", "rinv.hip", "qr_panel.hip", "rcpqr.hip", "dht.hip", "lsqr.hip", "ski_api.hip", "ski_noalloc.hip", "sparse_symbolic.cpp", "sparse_qr.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

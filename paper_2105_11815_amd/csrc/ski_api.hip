@@ -6,11 +6,13 @@
 #include <string.h>
 
 #include <algorithm>
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "lsqr.h"
 #include "ski_internal.h"
+#include "sparse_qr.h"
 
 using namespace ski;
 
@@ -58,6 +60,11 @@ struct ski_handle_s {
     bool pivoted = false;  // the last ski_factor pivoted
     bool cod = false;      // ... and formed the minimal-norm P (d x p in cod_m)
     DevBuf cod_a, cod_m;   // Rtop^T and work, then P = Pi Rtop^T (L^T L)^-1
+    // the sparse QR of the sketch (qr_panel = SKI_QR_SPARSE): its sketch, structure and
+    // factor; sroot holds the dense root front, sptmp the solves' d x k scratch
+    std::unique_ptr<SparseQR> sp;
+    bool sparse = false;  // the last ski_factor was the sparse one
+    DevBuf sroot, sptmp;
     hipStream_t st2 = nullptr;           // second stream of the QR's look-ahead
     hipEvent_t qev[4] = {};
     hipStream_t st3 = nullptr;           // third stream: R^-1 formed during the QR
@@ -138,7 +145,7 @@ constexpr int64_t PASS_WG = 512;  // workgroups of the fused dense LSQR pass
 enum ProfClass {
     PC_PASS = 0, PC_REDUCE = 1, PC_TRIGEMV = 2, PC_SPMV = 3, PC_SPMVT = 4, PC_STEP = 5,
     PC_HASH = 6, PC_WHT = 7, PC_GATHER = 8, PC_QR = 9, PC_TRTRI = 10, PC_QR_HH = 11,
-    PC_QR_PIV = 12
+    PC_QR_PIV = 12, PC_SPARSE_SKETCH = 13, PC_SPARSE_FRONTS = 14, PC_SPARSE_ROOT = 15
 };
 
 hipEvent_t pool_event(ski_handle h) {
@@ -212,7 +219,7 @@ int ski_destroy(ski_handle h) {
                      &h->wp, &h->g, &h->gpart, &h->upart, &h->y, &h->st, &h->cg_r,
                      &h->cg_p, &h->cg_q, &h->t2, &h->dtmp, &h->gemm_ws2, &h->gemm_ws3,
                      &h->piv_part, &h->pivd, &h->Rc, &h->ptmp, &h->cod_a, &h->cod_m,
-                     &h->done_cnt};
+                     &h->done_cnt, &h->sroot, &h->sptmp};
     for (DevBuf* b : all) release(*b);
     if (h->ev_ok)
         for (auto& e : h->ev) (void)hipEventDestroy(e);
@@ -288,8 +295,13 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
     if (akind == SKI_CSR && p->hadamard)
         return fail(h, SKI_EINVAL, "ski_sketch: the Hadamard transform is for dense A only");
     if (p->s < 1 || p->s > 32) return fail(h, SKI_EINVAL, "ski_sketch: need 1 <= s <= 32");
-    if (p->qr_panel < SKI_QR_AUTO || p->qr_panel > SKI_QR_PIVOTED_COD)
+    if (p->qr_panel < SKI_QR_AUTO || p->qr_panel > SKI_QR_SPARSE)
         return fail(h, SKI_EINVAL, "ski_sketch: unknown qr_panel");
+    if (p->qr_panel == SKI_QR_SPARSE &&
+        (akind != SKI_CSR || p->sketch_prec != SKI_FP64 || p->qr_prec != SKI_FP64 || k > 32))
+        return fail(h, SKI_EINVAL,
+                    "ski_sketch: the sparse QR (SKI_QR_SPARSE) needs CSR A, FP64 sketch and QR, "
+                    "and k <= 32");
     if (p->hash_kind < SKI_HASH || p->hash_kind > SKI_SAMPLE_ROWS)
         return fail(h, SKI_EINVAL, "ski_sketch: unknown hash_kind");
     if (p->hash_kind == SKI_SAMPLE_ROWS && p->s != 1)
@@ -356,9 +368,10 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
     SKI_TRY(h, ensure(h->src, nkeys * 4), "alloc");
     SKI_TRY(h, ensure(h->keys, 2 * nch * SORT_CHUNK * 8), "alloc");
     SKI_TRY(h, ensure(h->table, (size_t)nch * m * 4), "alloc");
-    // SA: FP64 in the FP64 form, FP32 in both mixed forms
+    // SA: FP64 in the FP64 form, FP32 in both mixed forms; the sparse QR keeps it sparse
+    const bool sparse = p->qr_panel == SKI_QR_SPARSE;
     const size_t sa_e = qprec == Prec::F64 ? 8 : 4;
-    SKI_TRY(h, ensure(h->SA, (size_t)m * ncols * sa_e), "alloc");
+    if (!sparse) SKI_TRY(h, ensure(h->SA, (size_t)m * ncols * sa_e), "alloc");
     if (h->ev_ok) (void)hipEventRecord(h->ev[0], st);
 
     HashBuffers hb;
@@ -409,10 +422,20 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
                 "gather");
     } else {
         const double scale = hscale;
-        SKI_TRY(h, launch_gather_csr(A->row_ptr, A->col, A->val, B, ldb, d, k,
-                                     P<int32_t>(h->bucket_ptr), P<int32_t>(h->src), m, scale,
-                                     hprec, oprec, h->SA.p, st),
-                "gather csr");
+        if (sparse) {
+            if (!h->sp) h->sp.reset(new (std::nothrow) SparseQR());
+            if (!h->sp) return fail(h, SKI_ENOMEM, "ski_sketch: out of host memory");
+            prof_begin(h, PC_SPARSE_SKETCH, st);
+            SKI_TRY(h, h->sp->sketch(A->row_ptr, A->col, A->val, n, d, B, ldb, k,
+                                     P<int32_t>(h->bucket_ptr), P<int32_t>(h->src), m, scale, st),
+                    "sparse sketch");
+            prof_end(h, st);
+        } else {
+            SKI_TRY(h, launch_gather_csr(A->row_ptr, A->col, A->val, B, ldb, d, k,
+                                         P<int32_t>(h->bucket_ptr), P<int32_t>(h->src), m, scale,
+                                         hprec, oprec, h->SA.p, st),
+                    "gather csr");
+        }
         // CSR of A^T for the transposed products of LSQR
         const int64_t nnz = A->nnz;
         const int64_t tch = hash_num_chunks(nnz);
@@ -491,6 +514,148 @@ int cod_factor(ski_handle h, QrWs& ws, int64_t p, int* hflag, GemmWs& gw, hipStr
     return SKI_OK;
 }
 
+// Step 2 in the sparse form of Section 6: the multifrontal QR of the sparse sketch
+// (sparse_qr.h).  The leaf fronts give the leaf rows of R; the root front, assembled
+// densely, is factored by the dense QR of the sketch (CholeskyQR2 panels, falling back to
+// Householder columns), and its R^-1 is formed explicitly.  The guards of the dense path
+// (rank, perturbation) apply to the whole diagonal.
+int sparse_factor(ski_handle h, hipStream_t st) {
+    const int64_t d = h->d, k = h->k;
+    SparseQR& S = *h->sp;
+    if (h->ev_ok) (void)hipEventRecord(h->ev[2], st);
+    h->factored = false;
+    h->sparse = false;
+    std::string err;
+    prof_begin(h, PC_SPARSE_FRONTS, st);
+    if (!S.analyse((int)(63 - k), st, err)) return fail(h, SKI_EINVAL, "ski_factor: " + err);
+    SKI_TRY(h, S.factor_leaves(st), "leaf fronts");
+    prof_end(h, st);
+    const int64_t nl = S.nleaf(), nr = S.nroot();
+    SKI_TRY(h, ensure(h->c, d * k * 8), "alloc");
+    SKI_TRY(h, ensure(h->dtmp, d * 8), "alloc");
+    SKI_TRY(h, ensure(h->diag_add, d * 8), "alloc");
+    SKI_TRY(h, ensure(h->pivd, d * 4), "alloc");
+    SKI_TRY(h, ensure(h->sptmp, d * std::max<int64_t>(k, 1) * 8), "alloc");
+    SKI_TRY(h, ensure(h->gemm_ws, (size_t)64 << 20), "alloc");
+    if (h->hdiag_n < d) {
+        if (h->hdiag) (void)hipHostFree(h->hdiag);
+        h->hdiag = nullptr;
+        h->hdiag_n = 0;
+        SKI_TRY(h, hipHostMalloc((void**)&h->hdiag, (2 * d + 2) * 8, hipHostMallocDefault),
+                "pinned");
+        h->hdiag_n = d;
+    }
+    int* hflag = (int*)(h->hdiag + 2 * d);
+    int* hnonfinite = (int*)(h->hdiag + 2 * d + 1);
+    SKI_TRY(h, S.leaf_diag(P<double>(h->dtmp), st), "leaf diag");
+    SKI_TRY(h, S.leaf_c(P<double>(h->c), st), "leaf c");
+    SKI_TRY(h, hipMemcpyAsync(hnonfinite, S.nonfinite_dev(), sizeof(int), hipMemcpyDeviceToHost, st),
+            "flag copy");
+    SKI_TRY(h, hipMemcpyAsync(h->pivd.p, S.perm_dev(), d * 4, hipMemcpyDeviceToDevice, st),
+            "perm copy");
+    *hflag = 0;
+    if (nr > 0) {
+        prof_begin(h, PC_SPARSE_ROOT, st);
+        const int64_t rows = S.root_rows_pad(), ncols = nr + k;
+        SKI_TRY(h, ensure(h->sroot, (size_t)rows * ncols * 8), "alloc");
+        SKI_TRY(h, S.assemble_root(P<double>(h->sroot), st), "root assembly");
+        size_t gb = 0;
+        SKI_TRY(h, ensure(h->qr_part, qr_ws_bytes(Prec::F64, rows, ncols, &gb)), "alloc");
+        SKI_TRY(h, ensure(h->gemm_ws, std::max<size_t>(gb, (size_t)64 << 20)), "alloc");
+        SKI_TRY(h, ensure(h->gemm_ws2, std::max<size_t>(gb, (size_t)64 << 20)), "alloc");
+        if (!h->st2) {
+            SKI_TRY(h, hipStreamCreateWithFlags(&h->st2, hipStreamNonBlocking), "stream");
+            for (auto& e : h->qev) SKI_TRY(h, hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+            SKI_TRY(h, hipStreamCreateWithFlags(&h->st3, hipStreamNonBlocking), "stream");
+            for (auto& e : h->rev) SKI_TRY(h, hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+        }
+        SKI_TRY(h, ensure(h->R, nr * nr * 8), "alloc");
+        SKI_TRY(h, ensure(h->Rinv, nr * nr * 8), "alloc");
+        SKI_TRY(h, ensure(h->RinvT, nr * nr * 8), "alloc");
+        SKI_TRY(h, ensure(h->tri_tmp, ((nr + 1) / 2 + 64) * ((nr + 1) / 2 + 64) * 8), "alloc");
+        QrWs ws;
+        qr_ws_carve(Prec::F64, h->qr_part.p, rows, ncols, ws);
+        ws.g.part = h->gemm_ws.p;
+        ws.g.bytes = h->gemm_ws.bytes;
+        ws.g2.part = h->gemm_ws2.p;
+        ws.g2.bytes = h->gemm_ws2.bytes;
+        ws.st2 = h->st2;
+        ws.evF[0] = h->qev[0];
+        ws.evF[1] = h->qev[1];
+        ws.evE[0] = h->qev[2];
+        ws.evE[1] = h->qev[3];
+        for (bool cqr = true;;) {
+            ws.cqr_panels = cqr;
+            SKI_TRY(h, qr_factor(Prec::F64, h->sroot.p, rows, ncols, nr, ws, st), "root qr");
+            SKI_TRY(h, launch_extract_Rc(Prec::F64, ws, rows, nr, k, P<double>(h->R),
+                                         P<double>(h->c) + nl * k, st),
+                    "extract R");
+            if (!cqr) break;
+            SKI_TRY(h, hipMemcpyAsync(hflag, ws.cqr.flag, sizeof(int), hipMemcpyDeviceToHost, st),
+                    "flag copy");
+            SKI_TRY(h, hipStreamSynchronize(st), "sync");
+            if (*hflag == 0) break;
+            cqr = false;  // a panel too ill-conditioned for CholeskyQR2: column by column
+        }
+        SKI_TRY(h, launch_scale_copy(P<double>(h->R), nr, 1, nr + 1, 1.0, P<double>(h->dtmp) + nl,
+                                     1, st),
+                "diag gather");
+        prof_end(h, st);
+    }
+    SKI_TRY(h, hipMemcpyAsync(h->hdiag, h->dtmp.p, d * 8, hipMemcpyDeviceToHost, st), "diag copy");
+    SKI_TRY(h, hipStreamSynchronize(st), "sync");
+    if (*hnonfinite)
+        return fail(h, SKI_EINVAL, "ski_factor: the sketch holds a non-finite entry (A or B is not finite)");
+    const double* Rd = h->hdiag;
+    bool finite = true;
+    for (int64_t i = 0; i < d; ++i) finite = finite && std::isfinite(Rd[i]);
+    if (!finite) return fail(h, SKI_EINVAL, "ski_factor: non-finite R (overflow in the QR)");
+    double amax = 0, amin = INFINITY;
+    for (int64_t i = 0; i < d; ++i) {
+        amax = std::max(amax, fabs(Rd[i]));
+        amin = std::min(amin, fabs(Rd[i]));
+    }
+    h->cond_est = amin > 0 ? amax / amin : INFINITY;
+    if (h->p.rcond > 0) {
+        const double r11 = fabs(Rd[0]);
+        for (int64_t i = 0; i < d; ++i)
+            if (!(r11 > 0) || fabs(Rd[i]) < h->p.rcond * r11) {
+                char buf[200];
+                snprintf(buf, sizeof buf,
+                         "rank guard failed at position %lld: |r_qq| = %.3e < rcond |r_11| "
+                         "(r_11 = %.3e)",
+                         (long long)i, fabs(Rd[i]), r11);
+                return fail(h, SKI_ERANK, buf);
+            }
+    }
+    double* add = h->hdiag + d;
+    const bool pert = h->p.perturb > 0 && h->p.rcond_thres > 0 &&
+                      h->cond_est >= 1.0 / h->p.rcond_thres;
+    for (int64_t i = 0; i < d; ++i) add[i] = pert ? copysign(h->p.perturb, Rd[i]) : 0.0;
+    SKI_TRY(h, hipMemcpyAsync(h->diag_add.p, add, d * 8, hipMemcpyHostToDevice, st), "perturb copy");
+    if (nr > 0) {
+        GemmWs gw;
+        gw.part = h->gemm_ws.p;
+        gw.bytes = h->gemm_ws.bytes;
+        prof_begin(h, PC_TRTRI, st);
+        SKI_TRY(h, trtri_upper(P<double>(h->R), nr, P<double>(h->Rinv), P<double>(h->RinvT),
+                               P<double>(h->diag_add) + nl, P<double>(h->tri_tmp), gw, st),
+                "root inverse");
+        prof_end(h, st);
+    }
+    S.set_root(P<double>(h->Rinv), P<double>(h->RinvT), P<double>(h->diag_add));
+    SKI_TRY(h, S.finish_factor(st), "transposed values");
+    h->sparse = true;
+    h->pivoted = true;  // LSQR works in position order: z and x are scattered by perm
+    h->cod = false;
+    h->rank = d;
+    if (h->ev_ok) (void)hipEventRecord(h->ev[3], st);
+    SKI_TRY(h, hipStreamSynchronize(st), "sync");
+    prof_collect(h);
+    h->factored = true;
+    return SKI_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -499,6 +664,8 @@ int ski_factor(ski_handle h, void* stream) {
     if (!h) return SKI_EINVAL;
     if (!h->sketched) return fail(h, SKI_ESTATE, "ski_factor: call ski_sketch first");
     hipStream_t st = (hipStream_t)stream;
+    if (h->p.qr_panel == SKI_QR_SPARSE) return sparse_factor(h, st);
+    h->sparse = false;
     const int64_t m = h->m, d = h->d, k = h->k, ncols = d + k;
     size_t gb = 0;
     const size_t qrb = qr_ws_bytes(h->qprec, m, ncols, &gb);
@@ -732,6 +899,38 @@ hipError_t tri_products(const double* Mtx, int64_t dp, bool upper, const double*
     return gemm_f64(false, false, dp, k, dp, s, Mtx, dp, x, k, 0.0, y, ldy, gw, st);
 }
 
+// y = s R^-1 x (upper: x in position order, y scattered to column order) or y = s R^-T x
+// (x in column order, y in position order) through the sparse factor: the root block by
+// its explicit inverse, the leaf rows by substitution over the leaf forest
+hipError_t sparse_apply(ski_handle h, bool upper, const double* x, int64_t ldx, double* y,
+                        int64_t ldy, int k, double s, const int32_t* done, GemmWs& gw,
+                        hipStream_t st) {
+    const SparseQR& S = *h->sp;
+    const int64_t nl = S.nleaf(), nr = S.nroot();
+    double* tmp = P<double>(h->sptmp);
+    const double* Ri = P<double>(h->Rinv);
+    const double* RiT = P<double>(h->RinvT);
+    if (upper) {
+        if (nr > 0) {
+            // tmp[nl ..] = R_root^-1 x[nl ..]
+            if (k == 1) {
+                SKI_HIP(launch_tri_gemv(Ri, nr, true, x + nl * ldx, ldx, tmp + nl, 1, 1.0, done, st));
+            } else {
+                if (ldx != k) return hipErrorInvalidValue;
+                SKI_HIP(tri_products(Ri, nr, true, x + nl * ldx, tmp + nl * k, k, k, 1.0, gw, st));
+            }
+        }
+        return S.leaves_upper(x, ldx, tmp, y, ldy, k, s, done, st);
+    }
+    SKI_HIP(S.leaves_lower(x, ldx, tmp, y, ldy, k, s, done, st));
+    if (nr > 0) {
+        // y[nl ..] = s R_root^-T tmp[nl ..]
+        if (k == 1) return launch_tri_gemv(RiT, nr, false, tmp + nl, 1, y + nl * ldy, ldy, s, done, st);
+        return tri_products(RiT, nr, false, tmp + nl * k, y + nl * ldy, ldy, k, s, gw, st);
+    }
+    return hipSuccess;
+}
+
 int alloc_solve_ws(ski_handle h, int k) {
     const int64_t n = h->n, d = h->d;
     SKI_TRY(h, ensure(h->u, n * k * 8), "alloc");
@@ -764,6 +963,7 @@ hipError_t apply_Rinv(ski_handle h, const double* Mtx, bool upper, const double*
                       double s, const int32_t* done, GemmWs& gw, hipStream_t st) {
     const int64_t dp = h->rank;
     if (dp <= 0) return hipSuccess;
+    if (h->sparse) return sparse_apply(h, upper, x, k, y, k, k, s, done, gw, st);
     if (h->cod) {
         // P = cod_m (d x p): upper: y (d x k) = s P x (p x k); lower: y (p x k) = s P^T x
         const double* Pm = (const double*)h->cod_m.p;
@@ -1001,7 +1201,10 @@ int solve_lls(ski_handle h, const double* B, int k, int64_t ldb, double* X, int6
     if (out != SKI_OK) return out;
     // x = R^-1 (c + delta); with pivoting x = V_1 R_11^-1 (c + delta), zero elsewhere
     SKI_TRY(h, launch_final_y(S, dp, k, c, dl, y, st), "final y");
-    if (h->cod) {
+    if (h->sparse) {
+        // x = P R^-1 (c + delta), every row of X written through perm
+        SKI_TRY(h, sparse_apply(h, true, y, k, X, ldx, k, 1.0, nullptr, gw, st), "x");
+    } else if (h->cod) {
         // x = P (c + delta), P = cod_m (d x p)
         if (dp > 0) SKI_TRY(h, apply_P_out(h, y, X, ldx, k, gw, st), "x");
     } else if (h->pivoted) {
@@ -1251,6 +1454,14 @@ int ski_get_SA(ski_handle h, double* SA) {
     if (!h->sketched) return fail(h, SKI_ESTATE, "ski_get_SA: nothing sketched");
     const int64_t cnt = h->m * (h->d + h->k);
     if (hipDeviceSynchronize() != hipSuccess) return fail(h, SKI_EDEVICE, "sync");
+    if (h->p.qr_panel == SKI_QR_SPARSE) {
+        DevBuf tmp;
+        if (ensure(tmp, cnt * 8) != hipSuccess) return fail(h, SKI_ENOMEM, "ski_get_SA: alloc");
+        const bool ok = h->sp->dense_SA(P<double>(tmp), nullptr) == hipSuccess &&
+                        hipMemcpy(SA, tmp.p, cnt * 8, hipMemcpyDeviceToHost) == hipSuccess;
+        release(tmp);
+        return ok ? SKI_OK : fail(h, SKI_EDEVICE, "ski_get_SA: copy");
+    }
     if (h->qprec == Prec::F64) {
         if (hipMemcpy(SA, h->SA.p, cnt * 8, hipMemcpyDeviceToHost) != hipSuccess)
             return fail(h, SKI_EDEVICE, "copy");
@@ -1265,8 +1476,23 @@ int ski_get_SA(ski_handle h, double* SA) {
 
 int ski_get_R(ski_handle h, double* R, double* c, double* Rinv) {
     if (!h) return SKI_EINVAL;
-    if (!h->R.p || !h->sketched) return fail(h, SKI_ESTATE, "ski_get_R: not factored");
     const int64_t d = h->d;
+    if (h->sparse && h->factored) {
+        if (Rinv) return fail(h, SKI_ESTATE, "ski_get_R: the sparse factor forms no R^-1");
+        if (hipDeviceSynchronize() != hipSuccess) return fail(h, SKI_EDEVICE, "sync");
+        if (R) {
+            DevBuf tmp;
+            if (ensure(tmp, d * d * 8) != hipSuccess) return fail(h, SKI_ENOMEM, "ski_get_R: alloc");
+            const bool ok = h->sp->dense_R(P<double>(h->R), P<double>(tmp), nullptr) == hipSuccess &&
+                            hipMemcpy(R, tmp.p, d * d * 8, hipMemcpyDeviceToHost) == hipSuccess;
+            release(tmp);
+            if (!ok) return fail(h, SKI_EDEVICE, "ski_get_R: copy");
+        }
+        if (c && hipMemcpy(c, h->c.p, d * h->k * 8, hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(h, SKI_EDEVICE, "copy");
+        return SKI_OK;
+    }
+    if (!h->R.p || !h->sketched) return fail(h, SKI_ESTATE, "ski_get_R: not factored");
     if (hipDeviceSynchronize() != hipSuccess) return fail(h, SKI_EDEVICE, "sync");
     if (R && hipMemcpy(R, h->R.p, d * d * 8, hipMemcpyDeviceToHost) != hipSuccess)
         return fail(h, SKI_EDEVICE, "copy");
@@ -1282,6 +1508,12 @@ int ski_get_factor_stats(ski_handle h, int64_t stats[4]) {
     if (!h || !stats) return SKI_EINVAL;
     if (!h->factored) return fail(h, SKI_ESTATE, "ski_get_factor_stats: not factored");
     stats[0] = h->rank;
+    if (h->sparse) {
+        stats[1] = h->sp->nleaf();
+        stats[2] = h->sp->nroot();
+        stats[3] = 2;
+        return SKI_OK;
+    }
     stats[1] = (h->d + 63) / 64;
     stats[2] = h->pivoted ? h->panels_cqr : -1;
     stats[3] = h->pivoted ? 1 : 0;

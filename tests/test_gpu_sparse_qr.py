@@ -1,0 +1,224 @@
+"""GPU parity of the sparse QR of the sketch (Section 6, the sparse solver: S A P = Q R with
+a fill-reducing ordering P, and sparse substitution for every product with R^-1), through
+the C interface, against the oracle (oracle/sparse_qr.py).
+
+* The sparse sketch against the oracle's sketch: identical bits.
+* The ordering (integer work) against the oracle's minimum-degree order: identical.
+* R and c against the QR of the oracle's column-permuted sketch, within
+  1e-12 max|R| sqrt(d); R exactly zero outside the oracle's predicted structure.
+* x against the oracle's sparse solve (same sketch, same ordering, same LSQR), and the
+  iteration count within one of the oracle's.
+Cases: leaves only, leaves and a root, root only (with buckets too wide for the sorted
+merge), several right-hand sides, a zero column (perturbed back-solve), a non-finite
+entry, and the 40000 x 8000 very sparse workload against the dense factorisation.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+import workloads
+from oracle import lls, sketch as sk, sparse_qr as sq
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ski():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2105_11815_amd as P
+    return P
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def _csr_arg(rp, ci, va, n, d):
+    return ("csr", dev(rp, torch.int64), dev(ci, torch.int32), dev(va), (n, d))
+
+
+def _inputs(case):
+    n, d, per_col = case["n"], case["d"], case["per_col"]
+    if per_col is None:
+        rp, ci, va, b = workloads.sparse_power_law(n=n, d=d, case=3)
+    else:
+        rp, ci, va, b = workloads.very_sparse(n, d, per_col)
+    k = case["k"]
+    B = b[:, None] if k == 1 else np.random.default_rng(n + d).standard_normal((n, k))
+    return rp, ci, va, B
+
+
+# n, d, nonzeros per column (None: the power-law rows), s, m, k, and what the order gives
+CASES = {
+    "leaves_only": dict(n=2000, d=300, per_col=1, s=3, m=600, k=1),
+    "leaves_and_root": dict(n=3000, d=500, per_col=2, s=2, m=700, k=1),
+    "leaves_root_k2": dict(n=4000, d=600, per_col=3, s=2, m=840, k=2),
+    "root_only_wide_buckets": dict(n=40000, d=100, per_col=None, s=2, m=140, k=1),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_sparse_sketch_order_and_factor_match_oracle(ski, name):
+    c = CASES[name]
+    n, d, s, m, k = c["n"], c["d"], c["s"], c["m"], c["k"]
+    _say(f"sparse factor {name}: n={n} d={d} s={s} m={m} k={k}")
+    rp, ci, va, B = _inputs(c)
+    seed = 11
+    ref = sk.sketch_csr(rp, ci, va, n, d, B, m, s, seed)
+    S = ski.Solver()
+    S.sketch(_csr_arg(rp, ci, va, n, d), dev(B), m=m, s=s, seed=seed, qr_panel="sparse")
+    # the sparse sketch sums in the dense sketch's order: the same bits
+    np.testing.assert_array_equal(S.get_SA(), ref["SA_aug"])
+    S.factor()
+    pats = sq.sa_row_patterns(rp, ci, n, d, m, s, seed)
+    order, root, L = sq.min_degree(pats, d, 63 - k)
+    perm_o, _ = sq.positions(order, root)
+    perm, rank = S.get_pivots()
+    np.testing.assert_array_equal(perm, perm_o)
+    st = S.factor_stats()
+    assert st["sparse"] and rank == d
+    assert (st["leaf_fronts"], st["root"]) == (len(order), len(root))
+    if name == "leaves_only":
+        assert len(root) == 0
+    elif name.startswith("root_only"):
+        assert len(order) == 0
+    else:
+        assert len(order) > 0 and len(root) > 0
+    R, cc, Ri = S.get_R()
+    assert Ri is None
+    Rref, cref = sq.factor(ref["SA_aug"], d, perm_o)
+    # the leaf rows hold nothing outside the predicted structure
+    assert np.all(R[~sq.r_structure(order, root, L, d)] == 0.0)
+    scale = np.abs(Rref).max()
+    np.testing.assert_allclose(R, Rref, rtol=0, atol=1e-12 * scale * math.sqrt(d))
+    np.testing.assert_allclose(cc, cref, rtol=0, atol=1e-12 * np.abs(cref).max() * math.sqrt(d))
+    S.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_sparse_solve_matches_oracle(ski, name):
+    c = CASES[name]
+    n, d, s, m, k = c["n"], c["d"], c["s"], c["m"], c["k"]
+    _say(f"sparse solve {name}: n={n} d={d} s={s} m={m} k={k}")
+    rp, ci, va, B = _inputs(c)
+    A = sp.csr_matrix((va, ci, rp), shape=(n, d))
+    seed = 12
+    tau = 1e-12
+    res = sq.solve(A, B, seed, m=m, s=s, dmax=63 - k, tau_r=tau, tau_a=0.0)
+    S = ski.Solver()
+    S.sketch(_csr_arg(rp, ci, va, n, d), dev(B), m=m, s=s, seed=seed, qr_panel="sparse",
+             tau_r=tau, tau_a=0.0).factor()
+    X, infos, rc = S.solve()
+    S.close()
+    X = X.cpu().numpy()
+    for j in range(k):
+        xr = res["x"][:, j]
+        err = np.linalg.norm(X[:, j] - xr) / np.linalg.norm(xr)
+        _say(f"  column {j}: iters {infos[j]['iters']} (oracle {res['iters'][j]}) rel err {err:.2e}")
+        assert err <= 1e-10
+        assert abs(infos[j]["iters"] - res["iters"][j]) <= 1
+        assert infos[j]["status"] == 0
+
+
+def test_sparse_zero_column_is_perturbed_and_zero(ski):
+    n, d, s, m = 2000, 300, 3, 600
+    rp, ci, va, b = workloads.very_sparse(n, d, 2)
+    A = sp.csr_matrix((va, ci, rp), shape=(n, d)).tolil()
+    A[:, 17] = 0.0
+    A = A.tocsr()
+    A.eliminate_zeros()
+    A.sort_indices()
+    rp, ci, va = A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data
+    _say(f"sparse zero column n={n} d={d}")
+    S = ski.Solver()
+    S.sketch(_csr_arg(rp, ci, va, n, d), dev(b), m=m, s=s, seed=13, qr_panel="sparse",
+             tau_r=1e-12, tau_a=0.0).factor()
+    R, cc, _ = S.get_R()
+    perm, _ = S.get_pivots()
+    q = int(np.nonzero(perm == 17)[0][0])
+    assert np.all(R[q] == 0.0) and np.all(R[:, q] == 0.0)
+    X, infos, rc = S.solve()
+    S.close()
+    x = X[:, 0].cpu().numpy()
+    assert x[17] == 0.0
+    keep = np.arange(d) != 17
+    xd = sla.lstsq(A.toarray()[:, keep], b)[0]
+    assert np.linalg.norm(x[keep] - xd) <= 1e-9 * np.linalg.norm(xd)
+
+
+def test_sparse_nonfinite_entry_is_reported(ski):
+    n, d = 2000, 300
+    rp, ci, va, b = workloads.very_sparse(n, d, 2)
+    va = va.copy()
+    va[123] = np.nan
+    S = ski.Solver()
+    S.sketch(_csr_arg(rp, ci, va, n, d), dev(b), m=600, s=3, seed=14, qr_panel="sparse")
+    with pytest.raises(ski.SkiError) as e:
+        S.factor()
+    assert e.value.code == -1
+    S.close()
+
+
+def test_sparse_repeat_runs_are_bitwise_identical(ski):
+    c = CASES["leaves_and_root"]
+    rp, ci, va, B = _inputs(c)
+    xs = []
+    for _ in range(2):
+        S = ski.Solver()
+        S.sketch(_csr_arg(rp, ci, va, c["n"], c["d"]), dev(B), m=c["m"], s=c["s"], seed=15,
+                 qr_panel="sparse", tau_r=1e-10).factor()
+        X, infos, rc = S.solve()
+        xs.append(X.cpu().numpy().copy())
+        S.close()
+    np.testing.assert_array_equal(xs[0], xs[1])
+
+
+def test_full_size_very_sparse_matches_the_dense_factor(ski):
+    """The 40000 x 8000 very sparse workload: the ordering against the oracle's, and the
+    sparse factorisation against the dense one on the same sketch.  Both preconditioners
+    satisfy R^T R = P^T (SA)^T (SA) P, so A P R_sparse^-1 and A R_dense^-1 differ by an
+    orthogonal factor and LSQR takes the same steps up to rounding."""
+    c = workloads.CASES["very_sparse"]
+    n, d, m, s = c["n"], c["d"], c["m"], c["s"]
+    _say(f"full-size very sparse n={n} d={d} m={m} s={s}")
+    rp, ci, va, b = workloads.very_sparse(n, d, c["per_col"], case=c["case"])
+    A = sp.csr_matrix((va, ci, rp), shape=(n, d))
+    seed = 2009
+    out = {}
+    for form in ("sparse", "auto"):
+        S = ski.Solver()
+        S.sketch(_csr_arg(rp, ci, va, n, d), dev(b), m=m, s=s, seed=seed, qr_panel=form,
+                 tau_r=1e-12, tau_a=0.0).factor()
+        if form == "sparse":
+            perm, _ = S.get_pivots()
+            st = S.factor_stats()
+        X, infos, rc = S.solve()
+        out[form] = (X[:, 0].cpu().numpy(), infos[0]["iters"], rc)
+        S.close()
+    pats = sq.sa_row_patterns(rp, ci, n, d, m, s, seed)
+    order, root, L = sq.min_degree(pats, d, 62)
+    perm_o, _ = sq.positions(order, root)
+    np.testing.assert_array_equal(perm, perm_o)
+    assert (st["leaf_fronts"], st["root"]) == (len(order), len(root))
+    (xs, its, rcs), (xd, itd, rcd) = out["sparse"], out["auto"]
+    err = np.linalg.norm(xs - xd) / np.linalg.norm(xd)
+    r = b - A @ xs
+    cert = np.linalg.norm(A.T @ r) / (sp.linalg.norm(A) * np.linalg.norm(r))
+    _say(f"  leaves {len(order)} root {len(root)}; iters sparse {its} dense {itd}; "
+         f"x difference {err:.2e}; certificate {cert:.2e}")
+    assert rcs == 0 and rcd == 0
+    assert abs(its - itd) <= 1
+    assert err <= 1e-9
+    assert cert <= 1e-10
