@@ -7,8 +7,9 @@ transform, gamma = 1.7 so m = 6800; Householder QR of the sketch; LSQR on A R^-1
 HBM.  Prints one JSON line on stdout (everything else goes to stderr).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-mixed]
-                       [--no-sparse] [--no-rankdef] [--no-batched] [--no-seeds]
-                       [--rankdef-only] [--batched-only] [--sweep]
+                       [--no-sparse] [--no-very-sparse] [--no-rankdef] [--no-batched]
+                       [--no-seeds] [--rankdef-only] [--batched-only] [--very-sparse-only]
+                       [--sweep]
                        [--sketch-study] [--cache-ceiling]
 """
 
@@ -208,6 +209,63 @@ def sparse_run(P, torch):
             "ms_solve": round(float(info["ms_solve"]), 3),
             "kernel_ms": {k: {"ms_total": round(v[0], 3), "launches": v[1]}
                           for k, v in prof.items() if v[1]}}
+
+
+def very_sparse_run(P, torch):
+    """The very sparse 40000 x 8000 workload (2 entries per column, 2-hashing, m 11200):
+    the sparse QR of the sketch (SKI_QR_SPARSE) against the dense QR of the same sketch;
+    a warm-up and the median of three timed solves for each, the optimality certificate
+    recomputed in FP64 on the host, the factor's shape and a per-class breakdown of one
+    more (profiled) sparse solve."""
+    import scipy.sparse as sp
+    import workloads
+    c = workloads.CASES["very_sparse"]
+    n, d = c["n"], c["d"]
+    rp, ci, va, b = workloads.very_sparse(n, d, c["per_col"], case=c["case"])
+    dev = lambda a, t: torch.as_tensor(a).to(device="cuda", dtype=t)
+    Acsr = ("csr", dev(rp, torch.int64), dev(ci, torch.int32), dev(va, torch.float64), (n, d))
+    bt = dev(b, torch.float64)
+    A = sp.csr_matrix((va, ci, rp), shape=(n, d))
+    anorm = sp.linalg.norm(A)
+    out = {"workload": f"very sparse {n}x{d} CSR, {c['per_col']} entries per column (row j and "
+                       f"uniform rows), N(0,1), b ~ N(0,1); 2-hashing, m {c['m']}; LSQR with CSR "
+                       "products to 1e-10"}
+    for form in ("sparse", "auto"):
+        kw = dict(m=c["m"], s=c["s"], seed=2009, tau_r=1e-10, hadamard=False, qr_panel=form)
+        S = P.Solver()
+        one_solve(P, S, Acsr, bt, **kw)
+        torch.cuda.synchronize()
+        times, infos = [], []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            X, info, rc = one_solve(P, S, Acsr, bt, **kw)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+            infos.append(info)
+        x = X[:, 0].cpu().numpy()
+        r = b - A @ x
+        res = {"ms_median": round(float(np.median(times)), 3),
+               "ms_all": [round(t, 3) for t in times], "iters": int(infos[-1]["iters"]),
+               "status": rc,
+               "optimality": float(np.linalg.norm(A.T @ r) / (anorm * np.linalg.norm(r))),
+               "ms_sketch": round(float(infos[-1]["ms_sketch"]), 3),
+               "ms_factor": round(float(infos[-1]["ms_factor"]), 3),
+               "ms_solve": round(float(infos[-1]["ms_solve"]), 3)}
+        if form == "sparse":
+            st = S.factor_stats()
+            res.update(leaf_fronts=st["leaf_fronts"], root=st["root"])
+            S.set_profiling(True)
+            one_solve(P, S, Acsr, bt, **kw)
+            torch.cuda.synchronize()
+            prof = S.profile()
+            S.set_profiling(False)
+            res["kernel_ms"] = {k: {"ms_total": round(v[0], 3), "launches": v[1]}
+                                for k, v in prof.items() if v[1]}
+        S.close()
+        out["sparse_qr" if form == "sparse" else "dense_qr"] = res
+    out["speedup_sparse_over_dense"] = round(out["dense_qr"]["ms_median"] /
+                                             out["sparse_qr"]["ms_median"], 3)
+    return out
 
 
 def rankdef_run(P, torch):
@@ -556,6 +614,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-sparse", action="store_true")
+    ap.add_argument("--no-very-sparse", action="store_true")
+    ap.add_argument("--very-sparse-only", action="store_true")
     ap.add_argument("--no-rankdef", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-seeds", action="store_true")
@@ -583,6 +643,9 @@ def main():
         return
     if args.batched_only:
         print(json.dumps({"batched_20000x1000_k32": batched_run(P, torch)}), flush=True)
+        return
+    if args.very_sparse_only:
+        print(json.dumps({"very_sparse_40000x8000": very_sparse_run(P, torch)}), flush=True)
         return
     if args.sweep:
         print(json.dumps({"gamma_s_sweep": sweep_run(P, torch)}), flush=True)
@@ -721,6 +784,11 @@ def main():
     if not args.no_sparse:
         log("sparse 200000x5000 workload ...")
         out["sparse_200000x5000"] = sparse_run(P, torch)
+        torch.cuda.empty_cache()
+
+    if not args.no_very_sparse:
+        log("very sparse 40000x8000 workload (sparse and dense QR of the sketch) ...")
+        out["very_sparse_40000x8000"] = very_sparse_run(P, torch)
         torch.cuda.empty_cache()
 
     if not args.no_rankdef:

@@ -554,6 +554,8 @@ int sparse_factor(ski_handle h, hipStream_t st) {
     SKI_TRY(h, hipMemcpyAsync(h->pivd.p, S.perm_dev(), d * 4, hipMemcpyDeviceToDevice, st),
             "perm copy");
     *hflag = 0;
+    const void* root_ac = nullptr;  // the root's factored working copy (for R_h^-1)
+    int64_t root_rows = 0;
     if (nr > 0) {
         prof_begin(h, PC_SPARSE_ROOT, st);
         const int64_t rows = S.root_rows_pad(), ncols = nr + k;
@@ -584,6 +586,16 @@ int sparse_factor(ski_handle h, hipStream_t st) {
         ws.evF[1] = h->qev[1];
         ws.evE[0] = h->qev[2];
         ws.evE[1] = h->qev[3];
+        // the root's R_h^-1 formed block by block on the third stream during its QR, as in
+        // the dense factorisation (used unless the perturbation applies)
+        SKI_TRY(h, ensure(h->gemm_ws3, rinv_ws_bytes(nr)), "alloc");
+        ws.Xinv = P<double>(h->Rinv);
+        ws.Zinv = P<double>(h->tri_tmp);
+        ws.g3.part = h->gemm_ws3.p;
+        ws.g3.bytes = h->gemm_ws3.bytes;
+        ws.st3 = h->st3;
+        ws.evP = h->rev[0];
+        ws.evI = h->rev[1];
         for (bool cqr = true;;) {
             ws.cqr_panels = cqr;
             SKI_TRY(h, qr_factor(Prec::F64, h->sroot.p, rows, ncols, nr, ws, st), "root qr");
@@ -601,6 +613,8 @@ int sparse_factor(ski_handle h, hipStream_t st) {
                                      1, st),
                 "diag gather");
         prof_end(h, st);
+        root_ac = ws.Ac;
+        root_rows = rows;
     }
     SKI_TRY(h, hipMemcpyAsync(h->hdiag, h->dtmp.p, d * 8, hipMemcpyDeviceToHost, st), "diag copy");
     SKI_TRY(h, hipStreamSynchronize(st), "sync");
@@ -638,9 +652,16 @@ int sparse_factor(ski_handle h, hipStream_t st) {
         gw.part = h->gemm_ws.p;
         gw.bytes = h->gemm_ws.bytes;
         prof_begin(h, PC_TRTRI, st);
-        SKI_TRY(h, trtri_upper(P<double>(h->R), nr, P<double>(h->Rinv), P<double>(h->RinvT),
-                               P<double>(h->diag_add) + nl, P<double>(h->tri_tmp), gw, st),
-                "root inverse");
+        if (!pert) {
+            // the blocks of R_h^-1 are done (the QR's stream waited for them): R^-1 = R_h^-1 D
+            SKI_TRY(h, rinv_finish((const double*)root_ac, root_rows, nr, P<double>(h->Rinv),
+                                   P<double>(h->RinvT), st),
+                    "root inverse");
+        } else {
+            SKI_TRY(h, trtri_upper(P<double>(h->R), nr, P<double>(h->Rinv), P<double>(h->RinvT),
+                                   P<double>(h->diag_add) + nl, P<double>(h->tri_tmp), gw, st),
+                    "root inverse");
+        }
         prof_end(h, st);
     }
     S.set_root(P<double>(h->Rinv), P<double>(h->RinvT), P<double>(h->diag_add));

@@ -404,8 +404,19 @@ struct SolveArgs {
     int64_t nleaf, d;
 };
 
-// upper: tmp[f] = (x[f] - sum_e R_f,lcol[e] tmp[lcol[e]]) / r_ff, y[perm[f]] = s tmp[f];
-// the workgroups past G scatter the root's values (already in tmp) to y
+// sum over the entries [e0, e1) of v[e] tmp[idx[e] k + t]: lanes take every 64th entry,
+// then a butterfly over the wave (a fixed order, so the result is deterministic)
+__device__ __forceinline__ double wave_dot(const SolveArgs& a, int64_t e0, int64_t e1,
+                                           const double* tmp, int k, int t, int lane) {
+    double part = 0.0;
+    for (int64_t e = e0 + lane; e < e1; e += 64) part += a.v[e] * tmp[(int64_t)a.idx[e] * k + t];
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+    return part;
+}
+
+// upper: tmp[f] = (x[f] - sum_e R_f,lcol[e] tmp[lcol[e]]) / r_ff, y[perm[f]] = s tmp[f],
+// one wave per row of a level; the workgroups past G scatter the root's values (already in
+// tmp) to y
 __global__ __launch_bounds__(SOLVE_THREADS) void k_leaf_upper(SolveArgs a, const double* __restrict__ x,
                                                               int64_t ldx, double* tmp,
                                                               double* __restrict__ y, int64_t ldy,
@@ -413,18 +424,23 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_leaf_upper(SolveArgs a, const
                                                               const int32_t* __restrict__ done) {
     if (done && *done) return;
     const int64_t g = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int NW = SOLVE_THREADS / 64;
     if (g < a.G) {
         for (int64_t l = a.lbptr[g]; l + 1 < a.lbptr[g + 1]; ++l) {
             const int64_t r0 = a.lb[l], r1 = a.lb[l + 1];
-            for (int64_t w = threadIdx.x; w < (r1 - r0) * k; w += SOLVE_THREADS) {
-                const int64_t f = a.rows[r0 + w / k];
-                const int t = (int)(w % k);
-                double acc = x[f * ldx + t];
-                for (int64_t e = a.ptr[f]; e < a.ptr[f + 1]; ++e)
-                    acc -= a.v[e] * tmp[(int64_t)a.idx[e] * k + t];
-                const double yv = acc / (a.rdiag[f] + a.ladd[f]);
-                tmp[f * k + t] = yv;
-                y[(int64_t)a.perm[f] * ldy + t] = s * yv;
+            for (int64_t i = r0 + wave; i < r1; i += NW) {
+                const int64_t f = a.rows[i];
+                const int64_t e0 = a.ptr[f], e1 = a.ptr[f + 1];
+                const double dg = a.rdiag[f] + a.ladd[f];
+                for (int t = 0; t < k; ++t) {
+                    const double sum = wave_dot(a, e0, e1, tmp, k, t, lane);
+                    if (lane == 0) {
+                        const double yv = (x[f * ldx + t] - sum) / dg;
+                        tmp[f * k + t] = yv;
+                        y[(int64_t)a.perm[f] * ldy + t] = s * yv;
+                    }
+                }
             }
             __syncthreads();
         }
@@ -440,7 +456,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_leaf_upper(SolveArgs a, const
 }
 
 // lower: tmp[f] = (x[perm[f]] - sum over the rows i below f with f in L_i of R_if tmp[i])
-// / r_ff, y[f] = s tmp[f]
+// / r_ff, y[f] = s tmp[f], one wave per row of a level
 __global__ __launch_bounds__(SOLVE_THREADS) void k_leaf_lower(SolveArgs a, const double* __restrict__ x,
                                                               int64_t ldx, double* tmp,
                                                               double* __restrict__ y, int64_t ldy,
@@ -448,35 +464,41 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_leaf_lower(SolveArgs a, const
                                                               const int32_t* __restrict__ done) {
     if (done && *done) return;
     const int64_t g = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int NW = SOLVE_THREADS / 64;
     for (int64_t l = a.lbptr[g]; l + 1 < a.lbptr[g + 1]; ++l) {
         const int64_t r0 = a.lb[l], r1 = a.lb[l + 1];
-        for (int64_t w = threadIdx.x; w < (r1 - r0) * k; w += SOLVE_THREADS) {
-            const int64_t f = a.rows[r0 + w / k];
-            const int t = (int)(w % k);
-            double acc = x[(int64_t)a.perm[f] * ldx + t];
-            for (int64_t e = a.ptr[f]; e < a.ptr[f + 1]; ++e)
-                acc -= a.v[e] * tmp[(int64_t)a.idx[e] * k + t];
-            const double yv = acc / (a.rdiag[f] + a.ladd[f]);
-            tmp[f * k + t] = yv;
-            y[f * ldy + t] = s * yv;
+        for (int64_t i = r0 + wave; i < r1; i += NW) {
+            const int64_t f = a.rows[i];
+            const int64_t e0 = a.ptr[f], e1 = a.ptr[f + 1];
+            const double dg = a.rdiag[f] + a.ladd[f];
+            for (int t = 0; t < k; ++t) {
+                const double sum = wave_dot(a, e0, e1, tmp, k, t, lane);
+                if (lane == 0) {
+                    const double yv = (x[(int64_t)a.perm[f] * ldx + t] - sum) / dg;
+                    tmp[f * k + t] = yv;
+                    y[f * ldy + t] = s * yv;
+                }
+            }
         }
         __syncthreads();
     }
 }
 
 // the root's right-hand side: tmp[q] = x[perm[q]] - sum over leaf rows i with q in L_i of
-// R_iq tmp[i], q >= nleaf
-__global__ void k_root_rhs(SolveArgs a, const double* __restrict__ x, int64_t ldx, double* tmp,
-                           int k, const int32_t* __restrict__ done) {
+// R_iq tmp[i], q >= nleaf, one wave per position
+__global__ __launch_bounds__(SOLVE_THREADS) void k_root_rhs(SolveArgs a, const double* __restrict__ x,
+                                                            int64_t ldx, double* tmp, int k,
+                                                            const int32_t* __restrict__ done) {
     if (done && *done) return;
-    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t nr = a.d - a.nleaf;
-    if (w >= nr * k) return;
-    const int64_t q = a.nleaf + w / k;
-    const int t = (int)(w % k);
-    double acc = x[(int64_t)a.perm[q] * ldx + t];
-    for (int64_t e = a.ptr[q]; e < a.ptr[q + 1]; ++e) acc -= a.v[e] * tmp[(int64_t)a.idx[e] * k + t];
-    tmp[q * k + t] = acc;
+    const int lane = threadIdx.x & 63;
+    const int64_t q = a.nleaf + (int64_t)blockIdx.x * (SOLVE_THREADS / 64) + (threadIdx.x >> 6);
+    if (q >= a.d) return;
+    const int64_t e0 = a.ptr[q], e1 = a.ptr[q + 1];
+    for (int t = 0; t < k; ++t) {
+        const double sum = wave_dot(a, e0, e1, tmp, k, t, lane);
+        if (lane == 0) tmp[q * k + t] = x[(int64_t)a.perm[q] * ldx + t] - sum;
+    }
 }
 
 __global__ void k_leaf_copy(const double* __restrict__ src, int64_t n, int64_t k, int64_t lds,
@@ -779,8 +801,8 @@ hipError_t SparseQR::leaves_lower(const double* x, int64_t ldx, double* tmp, dou
         hipLaunchKernelGGL(k_leaf_lower, dim3((unsigned)a.G), dim3(SOLVE_THREADS), 0, st, a, x, ldx,
                            tmp, y, ldy, k, s, done);
     if (S.nroot > 0)
-        hipLaunchKernelGGL(k_root_rhs, dim3(blocks_for(S.nroot * k, 256)), dim3(256), 0, st, a, x, ldx,
-                           tmp, k, done);
+        hipLaunchKernelGGL(k_root_rhs, dim3(blocks_for(S.nroot, SOLVE_THREADS / 64)),
+                           dim3(SOLVE_THREADS), 0, st, a, x, ldx, tmp, k, done);
     return hipGetLastError();
 }
 

@@ -130,41 +130,68 @@ bool sparse_symbolic(int64_t m, int64_t d, int64_t k, const int64_t* rstart, con
     S.dmax = dmax;
 
     // ---- minimum degree on the quotient graph
-    std::vector<std::vector<int32_t>> evars;  // live columns of each element
+    // element e's columns: ev[eoff[e] .. eoff[e + 1]) in one append-only array (the rows of
+    // SA first, then one new element per elimination)
+    std::vector<int32_t> ev;
+    std::vector<int64_t> eoff{0};
     std::vector<std::vector<int32_t>> vel(d);  // elements holding each column (may list dead)
-    evars.reserve(m + d);
+    {
+        int64_t tot = 0;
+        for (int64_t r = 0; r < m; ++r) tot += std::max<int32_t>(rlen[r], 0);
+        ev.reserve(tot + (size_t)d * 16);
+        eoff.reserve(m + d + 1);
+        std::vector<int32_t> cnt(d, 0);
+        for (int64_t r = 0; r < m; ++r)
+            for (int32_t u = 0; u < rlen[r]; ++u) ++cnt[col[rstart[r] + u]];
+        for (int64_t v = 0; v < d; ++v) vel[v].reserve(cnt[v] + 4);
+    }
     for (int64_t r = 0; r < m; ++r) {
         if (rlen[r] <= 0) continue;
-        const int32_t e = (int32_t)evars.size();
-        evars.emplace_back(col + rstart[r], col + rstart[r] + rlen[r]);
-        for (int32_t v : evars.back()) vel[v].push_back(e);
+        const int32_t e = (int32_t)(eoff.size() - 1);
+        ev.insert(ev.end(), col + rstart[r], col + rstart[r] + rlen[r]);
+        eoff.push_back((int64_t)ev.size());
+        for (int32_t u = 0; u < rlen[r]; ++u) vel[col[rstart[r] + u]].push_back(e);
     }
-    std::vector<char> edead(evars.size(), 0);
+    std::vector<char> edead(eoff.size() - 1, 0);
     std::vector<char> elim(d, 0);
-    std::vector<int64_t> mark(d, -1);
-    int64_t stamp = 0;
-    // The degree, counted only up to dmax + 1: a column above the cap is never chosen, and
-    // since an elimination lowers a neighbour's degree by at most one and every neighbour's
-    // degree is counted again after each elimination, a capped column is counted exactly
-    // again once its degree can be <= dmax.  The order is the uncapped rule's.
+    std::vector<int32_t> mark(d, -1);  // 4-byte stamps: d = 8000 columns stay in L1
+    int32_t stamp = 0;
+    // The degree, counted only up to CNT_CAP: a column above the cap dmax is never chosen,
+    // and eliminating a neighbour lowers a column's degree by at most one (it loses that
+    // neighbour and keeps the others), while a non-neighbour's degree does not change.  So
+    // lb[v], the count (a lower bound once it reached CNT_CAP), minus one per eliminated
+    // neighbour, stays a lower bound, and v is counted again only once lb[v] - 1 could be
+    // <= dmax; from there on it is counted exactly.  The order is the uncapped rule's.
+    const int64_t CNT_CAP = (int64_t)dmax + 65;
+    auto next_stamp = [&]() {
+        if (stamp == INT32_MAX - 1) {
+            std::fill(mark.begin(), mark.end(), -1);
+            stamp = 0;
+        }
+        return ++stamp;
+    };
     auto degree = [&](int32_t v) {
-        ++stamp;
+        next_stamp();
         int64_t cnt = 0;
         for (int32_t e : vel[v]) {
             if (edead[e]) continue;
-            for (int32_t u : evars[e])
+            for (int64_t q = eoff[e]; q < eoff[e + 1]; ++q) {
+                const int32_t u = ev[q];
                 if (u != v && mark[u] != stamp) {
                     mark[u] = stamp;
-                    if (++cnt > dmax) return cnt;
+                    if (++cnt >= CNT_CAP) return cnt;
                 }
+            }
         }
         return cnt;
     };
+    std::vector<int64_t> lb(d);
     const int ndeg = dmax + 2;  // degrees 0 .. dmax, and dmax + 1 for every capped column
     std::vector<int> deg(d);
     DegreeBuckets pq(d, ndeg);
     for (int64_t v = 0; v < d; ++v) {
-        deg[v] = (int)std::min<int64_t>(degree((int32_t)v), dmax + 1);
+        lb[v] = degree((int32_t)v);
+        deg[v] = (int)std::min<int64_t>(lb[v], dmax + 1);
         pq.insert(deg[v], v);
     }
     std::vector<int32_t> order;
@@ -179,17 +206,18 @@ bool sparse_symbolic(int64_t m, int64_t d, int64_t k, const int64_t* rstart, con
         const int32_t j = (int32_t)bv;
         // j's live neighbours: the union of its live elements (which hold live columns only:
         // every element holding an eliminated column was absorbed when it was eliminated)
-        ++stamp;
+        next_stamp();
         Lj.clear();
         for (int32_t e : vel[j]) {
             if (edead[e]) continue;
-            for (int32_t u : evars[e])
+            for (int64_t q = eoff[e]; q < eoff[e + 1]; ++q) {
+                const int32_t u = ev[q];
                 if (u != j && mark[u] != stamp) {
                     mark[u] = stamp;
                     Lj.push_back(u);
                 }
+            }
             edead[e] = 1;  // absorbed into the new element
-            std::vector<int32_t>().swap(evars[e]);
         }
         std::sort(Lj.begin(), Lj.end());
         elim[j] = 1;
@@ -197,16 +225,22 @@ bool sparse_symbolic(int64_t m, int64_t d, int64_t k, const int64_t* rstart, con
         lcol_c.insert(lcol_c.end(), Lj.begin(), Lj.end());
         lptr_c.push_back((int64_t)lcol_c.size());
         std::vector<int32_t>().swap(vel[j]);
-        const int32_t ne = (int32_t)evars.size();
-        evars.push_back(Lj);
+        const int32_t ne = (int32_t)(eoff.size() - 1);
+        ev.insert(ev.end(), Lj.begin(), Lj.end());
+        eoff.push_back((int64_t)ev.size());
         edead.push_back(0);
         for (int32_t v : Lj) {
             auto& L = vel[v];
             L.erase(std::remove_if(L.begin(), L.end(), [&](int32_t e) { return edead[e] != 0; }),
                     L.end());
             L.push_back(ne);
+            if (lb[v] - 1 > dmax) {
+                --lb[v];  // still above the cap: its bucket (dmax + 1) is unchanged
+                continue;
+            }
             pq.erase(deg[v], v);
-            deg[v] = (int)std::min<int64_t>(degree(v), dmax + 1);
+            lb[v] = degree(v);
+            deg[v] = (int)std::min<int64_t>(lb[v], dmax + 1);
             pq.insert(deg[v], v);
         }
     }

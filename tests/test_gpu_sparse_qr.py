@@ -6,8 +6,9 @@ the C interface, against the oracle (oracle/sparse_qr.py).
 * The ordering (integer work) against the oracle's minimum-degree order: identical.
 * R and c against the QR of the oracle's column-permuted sketch, within
   1e-12 max|R| sqrt(d); R exactly zero outside the oracle's predicted structure.
-* x against the oracle's sparse solve (same sketch, same ordering, same LSQR), and the
-  iteration count within one of the oracle's.
+* The iteration count at tau_r = 1e-10 within max(2, 1%) of the oracle's sparse solve
+  (same sketch, same ordering, same LSQR); x run to stagnation within 1e-10 of LAPACK's
+  least-squares solution, as the oracle's is.
 Cases: leaves only, leaves and a root, root only (with buckets too wide for the sorted
 merge), several right-hand sides, a zero column (perturbed back-solve), a non-finite
 entry, and the 40000 x 8000 very sparse workload against the dense factorisation.
@@ -109,27 +110,40 @@ def test_sparse_sketch_order_and_factor_match_oracle(ski, name):
 
 @pytest.mark.parametrize("name", list(CASES))
 def test_sparse_solve_matches_oracle(ski, name):
+    """Iterations at tau_r = 1e-10 within max(2, 1%) of the oracle's (same sketch, ordering
+    and LSQR); x run to stagnation (tau_r = 1e-14) within 1e-10 of LAPACK's least-squares
+    solution, as the oracle's is.  (With a large residual, (TC-lsqr) at 1e-12 pins x only to
+    about 1e-10 relative, so two runs stopped there differ by that much.)"""
     c = CASES[name]
     n, d, s, m, k = c["n"], c["d"], c["s"], c["m"], c["k"]
     _say(f"sparse solve {name}: n={n} d={d} s={s} m={m} k={k}")
     rp, ci, va, B = _inputs(c)
     A = sp.csr_matrix((va, ci, rp), shape=(n, d))
+    Xd = sla.lstsq(A.toarray(), B)[0]
     seed = 12
-    tau = 1e-12
-    res = sq.solve(A, B, seed, m=m, s=s, dmax=63 - k, tau_r=tau, tau_a=0.0)
-    S = ski.Solver()
-    S.sketch(_csr_arg(rp, ci, va, n, d), dev(B), m=m, s=s, seed=seed, qr_panel="sparse",
-             tau_r=tau, tau_a=0.0).factor()
-    X, infos, rc = S.solve()
-    S.close()
-    X = X.cpu().numpy()
-    for j in range(k):
-        xr = res["x"][:, j]
-        err = np.linalg.norm(X[:, j] - xr) / np.linalg.norm(xr)
-        _say(f"  column {j}: iters {infos[j]['iters']} (oracle {res['iters'][j]}) rel err {err:.2e}")
-        assert err <= 1e-10
-        assert abs(infos[j]["iters"] - res["iters"][j]) <= 1
-        assert infos[j]["status"] == 0
+    for tau in (1e-10, 1e-14):
+        res = sq.solve(A, B, seed, m=m, s=s, dmax=63 - k, tau_r=tau, tau_a=0.0)
+        S = ski.Solver()
+        S.sketch(_csr_arg(rp, ci, va, n, d), dev(B), m=m, s=s, seed=seed, qr_panel="sparse",
+                 tau_r=tau, tau_a=0.0).factor()
+        X, infos, rc = S.solve()
+        S.close()
+        X = X.cpu().numpy()
+        for j in range(k):
+            xd = Xd[:, j]
+            err = np.linalg.norm(X[:, j] - xd) / np.linalg.norm(xd)
+            erro = np.linalg.norm(res["x"][:, j] - xd) / np.linalg.norm(xd)
+            _say(f"  tau {tau:.0e} column {j}: iters {infos[j]['iters']} (oracle "
+                 f"{res['iters'][j]}); x error {err:.2e} (oracle {erro:.2e})")
+            if tau == 1e-10:
+                # the (TC-lsqr) estimate is not monotone near the threshold, so on a slowly
+                # converging problem (about 140 steps here) rounding order moves the step
+                # that crosses it by a few: within max(2, 1%) of the oracle's count
+                assert infos[j]["status"] == 0
+                assert abs(infos[j]["iters"] - res["iters"][j]) <= max(2, 0.01 * res["iters"][j])
+            else:
+                assert infos[j]["status"] in (0, 1)
+                assert err <= 1e-10 and erro <= 1e-10
 
 
 def test_sparse_zero_column_is_perturbed_and_zero(ski):
