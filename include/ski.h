@@ -96,7 +96,9 @@ typedef struct {
  *   gamma, m     sketch rows m = ceil(gamma d) unless m > 0 is given; d <= m <= 12288
  *                (the column-by-column Householder panel, which every QR falls back to,
  *                keeps a column's m entries in the registers of one 512-thread workgroup,
- *                24 per thread).
+ *                24 per thread).  With qr_panel = SKI_QR_SPARSE any m >= d is taken, and
+ *                the limit of 12288 applies to the rows of the dense root front instead
+ *                (ski_factor returns SKI_EINVAL above it).
  *   s            nonzeros per column of S_h, 1 <= s <= min(m, 32).
  *   hadamard     1: S = S_h H D (dense only); 0: S = S_h; 2: S = S_h F D with F the
  *                discrete Hartley transform of the paper's dense software (Section 6,
@@ -213,8 +215,8 @@ void ski_params_default(int32_t kind, ski_params* p);
 /* Step 1.  Draws S from (m, s, seed), forms S [A B] (B: n x k, device, leading
  * dimension ldb >= k; k >= 1) and keeps it in the handle.  Errors (all found on the host,
  * before any device work): SKI_EINVAL for n < d, d < 1, m < d, m > n' (dense with
- * Hadamard) or m > n, m > 12288, s out of range, k < 1, bad leading dimensions, Hadamard
- * requested for CSR; SKI_ENOMEM.  Non-finite entries of A and B are not looked for here
+ * Hadamard) or m > n, m > 12288 (except with SKI_QR_SPARSE), s out of range, k < 1, bad
+ * leading dimensions, Hadamard requested for CSR; SKI_ENOMEM.  Non-finite entries of A and B are not looked for here
  * (that would cost a pass over A); they are reported by ski_factor. */
 int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, int64_t ldb,
                const ski_params* p, void* stream);

@@ -322,7 +322,10 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
         return fail(h, SKI_EINVAL,
                     "ski_sketch: the Hartley transform needs n' <= 2^24 and FP64 sketch and QR");
     if (p->s > m) return fail(h, SKI_EINVAL, "ski_sketch: need s <= m");
-    if (m > 12288) return fail(h, SKI_EINVAL, "ski_sketch: m above 12288 is not supported");
+    // the dense QR keeps a column of up to 12288 rows in one workgroup's registers; the
+    // sparse factorisation only sends its root front there (checked by ski_factor)
+    if (m > 12288 && p->qr_panel != SKI_QR_SPARSE)
+        return fail(h, SKI_EINVAL, "ski_sketch: m above 12288 is not supported");
     const int64_t ncols = d + k;
     Prec sprec = (Prec)p->sketch_prec, qprec = (Prec)p->qr_prec;
     // the sketch storage follows the QR precision: FP64 QR needs an FP64 sketch
@@ -556,6 +559,14 @@ int sparse_factor(ski_handle h, hipStream_t st) {
     *hflag = 0;
     const void* root_ac = nullptr;  // the root's factored working copy (for R_h^-1)
     int64_t root_rows = 0;
+    if (nr > 0 && S.root_rows_pad() > 12288) {
+        char buf[240];
+        snprintf(buf, sizeof buf,
+                 "ski_factor: the root front of the sparse factorisation has %lld rows; its "
+                 "dense QR takes at most 12288 (a larger gamma or a sparser A shrinks it)",
+                 (long long)S.root_rows_pad());
+        return fail(h, SKI_EINVAL, buf);
+    }
     if (nr > 0) {
         prof_begin(h, PC_SPARSE_ROOT, st);
         const int64_t rows = S.root_rows_pad(), ncols = nr + k;

@@ -236,3 +236,54 @@ def test_full_size_very_sparse_matches_the_dense_factor(ski):
     assert abs(its - itd) <= 1
     assert err <= 1e-9
     assert cert <= 1e-10
+
+
+def test_sparse_sketch_above_the_dense_row_limit(ski):
+    """With the sparse factorisation the sketch may exceed the dense QR's 12288 rows: only the
+    root front goes through the dense QR.  40000 x 8000 very sparse at gamma 3 (m 24000):
+    the ordering equal to the oracle's, the certificate within 1e-10, and x equal to the
+    gamma 1.4 solution (a different sketch, the same least-squares solution)."""
+    c = workloads.CASES["very_sparse"]
+    n, d, s = c["n"], c["d"], c["s"]
+    rp, ci, va, b = workloads.very_sparse(n, d, c["per_col"], case=c["case"])
+    A = sp.csr_matrix((va, ci, rp), shape=(n, d))
+    xs = {}
+    for m in (24000, c["m"]):
+        _say(f"very sparse n={n} d={d} m={m}")
+        S = ski.Solver()
+        S.sketch(_csr_arg(rp, ci, va, n, d), dev(b), m=m, s=s, seed=2010, qr_panel="sparse",
+                 tau_r=1e-13, tau_a=0.0).factor()
+        if m == 24000:
+            perm, _ = S.get_pivots()
+            st = S.factor_stats()
+        X, infos, rc = S.solve()
+        xs[m] = (X[:, 0].cpu().numpy(), infos[0]["iters"])
+        S.close()
+        assert rc in (0, 1)
+    pats = sq.sa_row_patterns(rp, ci, n, d, 24000, s, 2010)
+    order, root, L = sq.min_degree(pats, d, 62)
+    perm_o, _ = sq.positions(order, root)
+    np.testing.assert_array_equal(perm, perm_o)
+    assert st["root"] == len(root) and len(root) < d // 2
+    x3, it3 = xs[24000]
+    x1, it1 = xs[c["m"]]
+    r = b - A @ x3
+    cert = np.linalg.norm(A.T @ r) / (sp.linalg.norm(A) * np.linalg.norm(r))
+    err = np.linalg.norm(x3 - x1) / np.linalg.norm(x1)
+    _say(f"  root {len(root)}; iters gamma 3: {it3}, gamma 1.4: {it1}; certificate {cert:.2e}; "
+         f"x difference {err:.2e}")
+    assert cert <= 1e-10 and err <= 1e-9
+    assert it3 < it1
+
+
+def test_sparse_root_front_above_the_dense_limit_is_refused(ski):
+    """100000 x 20000 very sparse at gamma 2: the root front has about 21800 rows, more than
+    the dense QR takes; ski_factor refuses it with SKI_EINVAL before any numeric work."""
+    n, d = 100000, 20000
+    rp, ci, va, b = workloads.very_sparse(n, d, 2)
+    S = ski.Solver()
+    S.sketch(_csr_arg(rp, ci, va, n, d), dev(b), m=40000, s=2, seed=7, qr_panel="sparse")
+    with pytest.raises(ski.SkiError) as e:
+        S.factor()
+    assert e.value.code == -1 and "root front" in str(e.value)
+    S.close()
