@@ -37,9 +37,14 @@ from . import sketch as sk
 
 def sa_row_patterns(row_ptr, col, n, d, m, s, seed, kind="hash"):
     """Column lists (ascending) of the rows of S_h A for A in CSR form: row b of
-    SA holds column j iff a stored A_ij has row i in bucket b."""
+    SA holds column j iff a stored A_ij has row i in bucket b.  kind "hash" or
+    "variant" (the s-hashing variant, Section 4), or "sample" (row sampling, Section 7:
+    row b of SA is the sampled row of A)."""
     row_ptr = np.asarray(row_ptr, dtype=np.int64)
     col = np.asarray(col, dtype=np.int64)
+    if kind == "sample":
+        picked = sk.sample_rows(m, n, seed)
+        return [sorted(int(c) for c in col[row_ptr[i]:row_ptr[i + 1]]) for i in picked]
     rows, neg = sk.hash_columns(n, m, s, seed, replace=(kind == "variant"))
     pats = [set() for _ in range(m)]
     for i in range(n):

@@ -287,3 +287,98 @@ def test_sparse_root_front_above_the_dense_limit_is_refused(ski):
         S.factor()
     assert e.value.code == -1 and "root front" in str(e.value)
     S.close()
+
+
+@pytest.mark.parametrize("kind", ["variant", "sample"])
+def test_sparse_factor_with_the_other_sketches(ski, kind):
+    """The sparse sketch and ordering under the s-hashing variant (Section 4; a row may land
+    twice in one bucket with both signs) and under row sampling (Section 7): the sketch
+    bit-exact, the ordering equal to the oracle's; with the variant, x against LAPACK."""
+    n, d, per_col = 3000, 500, 2
+    s, m = (3, 700) if kind == "variant" else (1, 1500)
+    rp, ci, va, b = workloads.very_sparse(n, d, per_col)
+    seed = 16
+    ref = sk.sketch_csr(rp, ci, va, n, d, b, m, s, seed, kind=kind)
+    S = ski.Solver()
+    S.sketch(_csr_arg(rp, ci, va, n, d), dev(b), m=m, s=s, seed=seed, qr_panel="sparse",
+             hash_kind=kind, tau_r=1e-14, tau_a=0.0, it_max=2000)
+    np.testing.assert_array_equal(S.get_SA(), ref["SA_aug"])
+    S.factor()
+    pats = sq.sa_row_patterns(rp, ci, n, d, m, s, seed, kind=kind)
+    order, root, L = sq.min_degree(pats, d, 62)
+    perm_o, _ = sq.positions(order, root)
+    perm, _ = S.get_pivots()
+    np.testing.assert_array_equal(perm, perm_o)
+    if kind == "variant":
+        X, infos, rc = S.solve()
+        A = sp.csr_matrix((va, ci, rp), shape=(n, d))
+        xd = sla.lstsq(A.toarray(), b)[0]
+        err = np.linalg.norm(X[:, 0].cpu().numpy() - xd) / np.linalg.norm(xd)
+        _say(f"  variant: iters {infos[0]['iters']} x error {err:.2e}")
+        assert err <= 1e-10
+    S.close()
+
+
+def test_sparse_eight_right_hand_sides(ski):
+    """k = 8: fronts of at most 64 columns leave 55 for A (degree cap 55); every column's x
+    within 1e-10 of LAPACK's."""
+    n, d, per_col, s, m, k = 3000, 500, 2, 2, 700, 8
+    rp, ci, va, _ = workloads.very_sparse(n, d, per_col)
+    B = np.random.default_rng(8).standard_normal((n, k))
+    S = ski.Solver()
+    S.sketch(_csr_arg(rp, ci, va, n, d), dev(B), m=m, s=s, seed=17, qr_panel="sparse",
+             tau_r=1e-14, tau_a=0.0, it_max=2000).factor()
+    pats = sq.sa_row_patterns(rp, ci, n, d, m, s, 17)
+    order, root, L = sq.min_degree(pats, d, 63 - k)
+    perm, _ = S.get_pivots()
+    np.testing.assert_array_equal(perm, sq.positions(order, root)[0])
+    X, infos, rc = S.solve()
+    S.close()
+    A = sp.csr_matrix((va, ci, rp), shape=(n, d))
+    Xd = sla.lstsq(A.toarray(), B)[0]
+    X = X.cpu().numpy()
+    for j in range(k):
+        assert np.linalg.norm(X[:, j] - Xd[:, j]) <= 1e-10 * np.linalg.norm(Xd[:, j])
+
+
+def test_sparse_handle_reused_across_sizes(ski):
+    """One handle: a larger problem, a smaller one, the larger again (buffers grown once and
+    reused, the structure rebuilt each time); each x within 1e-10 of LAPACK's and the
+    second factor's R against the oracle."""
+    big = CASES["leaves_root_k2"]
+    small = CASES["leaves_only"]
+    S = ski.Solver()
+    for c in (big, small, big):
+        n, d, s, m, k = c["n"], c["d"], c["s"], c["m"], c["k"]
+        rp, ci, va, B = _inputs(c)
+        S.sketch(_csr_arg(rp, ci, va, n, d), dev(B), m=m, s=s, seed=18, qr_panel="sparse",
+                 tau_r=1e-14, tau_a=0.0, it_max=2000).factor()
+        if c is small:
+            ref = sk.sketch_csr(rp, ci, va, n, d, B, m, s, 18)
+            pats = sq.sa_row_patterns(rp, ci, n, d, m, s, 18)
+            order, root, L = sq.min_degree(pats, d, 63 - k)
+            perm_o, _ = sq.positions(order, root)
+            R, cc, _ = S.get_R()
+            Rref, cref = sq.factor(ref["SA_aug"], d, perm_o)
+            np.testing.assert_allclose(R, Rref, rtol=0, atol=1e-12 * np.abs(Rref).max() * math.sqrt(d))
+        X, infos, rc = S.solve()
+        A = sp.csr_matrix((va, ci, rp), shape=(n, d))
+        Xd = sla.lstsq(A.toarray(), B)[0]
+        X = X.cpu().numpy()
+        for j in range(k):
+            assert np.linalg.norm(X[:, j] - Xd[:, j]) <= 1e-10 * np.linalg.norm(Xd[:, j])
+    S.close()
+
+
+def test_sparse_rank_guard(ski):
+    """rcond applies to the whole diagonal of the sparse factor, as without pivoting:
+    |r_qq| < rcond |r_11| gives SKI_ERANK."""
+    c = CASES["leaves_and_root"]
+    rp, ci, va, B = _inputs(c)
+    S = ski.Solver()
+    S.sketch(_csr_arg(rp, ci, va, c["n"], c["d"]), dev(B), m=c["m"], s=c["s"], seed=19,
+             qr_panel="sparse", rcond=0.9)
+    with pytest.raises(ski.SkiError) as e:
+        S.factor()
+    assert e.value.code == -4
+    S.close()

@@ -173,3 +173,23 @@ def test_zero_column_gets_zero_row_and_x_zero():
     keep = np.arange(200) != 17
     x = sla.lstsq(A.toarray()[:, keep], b)[0]
     assert np.linalg.norm(res["x"][keep, 0] - x) <= 1e-9 * np.linalg.norm(x)
+
+
+def test_patterns_of_the_other_sketches():
+    # row sampling: each row of SA is one row of A, so the pattern is exactly the nonzeros;
+    # the s-hashing variant: a row drawn twice into one bucket with both signs cancels, so
+    # the pattern holds the nonzeros and, at most, such exact zeros
+    n, d = 3000, 500
+    A, b = _csr(n, d, 2)
+    for kind, s, m in (("sample", 1, 1500), ("variant", 3, 700)):
+        SA = sk.sketch_csr(A.indptr, A.indices, A.data, n, d, b, m, s, 16, kind=kind)["SA_aug"]
+        pats = sq.sa_row_patterns(A.indptr, A.indices, n, d, m, s, 16, kind=kind)
+        P = np.zeros((m, d), dtype=bool)
+        for i, r in enumerate(pats):
+            P[i, r] = True
+        nz = SA[:, :d] != 0
+        assert np.all(P >= nz)
+        if kind == "sample":
+            assert np.array_equal(P, nz)
+        else:
+            assert (P & ~nz).sum() <= 2
