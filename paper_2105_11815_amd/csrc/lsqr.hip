@@ -617,6 +617,7 @@ __device__ __forceinline__ void post_all_done(LsqrState* stt, int k, int32_t* wo
 }
 
 // one step: u_hat holds W v - alpha u (beta2 = its squared norm), wp = R^-T A^T u_hat
+template <int SR>
 __global__ __launch_bounds__(1024) void k_lsqr_step(LsqrState* __restrict__ stt, int64_t d, int k,
                                                     const double* __restrict__ wp,
                                                     double* __restrict__ v, double* __restrict__ h,
@@ -638,15 +639,15 @@ __global__ __launch_bounds__(1024) void k_lsqr_step(LsqrState* __restrict__ stt,
     const double rhobar = S.rhobar, phibar = S.phibar, anorm2_old = S.anorm2;
     const int64_t iters_old = S.iters;
     const double ib = beta > 0 ? 1.0 / beta : 0.0;
-    // d <= STEP_REG * blockDim: each thread's entries are loaded once, all loads issued
-    // together (indices clamped), and stay in registers between the norm and the update; the
+    // d <= SR * blockDim: each thread's entries are loaded once, all loads issued together
+    // (indices clamped), and stay in registers between the norm and the update; the
     // per-thread sums run over the same entries in the same order as the general loops
-    const bool reg = d <= (int64_t)STEP_REG * blockDim.x;
-    double wv[STEP_REG], vv[STEP_REG], hv[STEP_REG], dv[STEP_REG];
+    const bool reg = d <= (int64_t)SR * blockDim.x;
+    double wv[SR], vv[SR], hv[SR], dv[SR];
     double ss = 0;
     if (reg) {
 #pragma unroll
-        for (int u = 0; u < STEP_REG; ++u) {
+        for (int u = 0; u < SR; ++u) {
             const int64_t i = threadIdx.x + (int64_t)u * blockDim.x;
             const int64_t o = (i < d ? i : d - 1) * k + j;
             wv[u] = wp[o];
@@ -655,7 +656,7 @@ __global__ __launch_bounds__(1024) void k_lsqr_step(LsqrState* __restrict__ stt,
             dv[u] = delta[o];
         }
 #pragma unroll
-        for (int u = 0; u < STEP_REG; ++u) {
+        for (int u = 0; u < SR; ++u) {
             const double w = wv[u] * ib - beta * vv[u];
             if (threadIdx.x + (int64_t)u * blockDim.x < d) ss += w * w;
         }
@@ -675,7 +676,7 @@ __global__ __launch_bounds__(1024) void k_lsqr_step(LsqrState* __restrict__ stt,
     const double t1 = phi / rho, t2 = theta / rho;
     if (reg) {
 #pragma unroll
-        for (int u = 0; u < STEP_REG; ++u) {
+        for (int u = 0; u < SR; ++u) {
             const int64_t i = threadIdx.x + (int64_t)u * blockDim.x;
             if (i < d) {
                 const double vn = (wv[u] * ib - beta * vv[u]) * ia;
@@ -1066,8 +1067,15 @@ hipError_t launch_lsqr_init(LsqrState* stt, int64_t d, int k, const double* wp, 
 hipError_t launch_lsqr_step(LsqrState* stt, int64_t d, int k, const double* wp, double* v,
                             double* h, double* delta, double tau_r, int64_t it_max,
                             int32_t* hflag, uint32_t* cnt, hipStream_t st) {
-    hipLaunchKernelGGL(k_lsqr_step, dim3((unsigned)k), dim3(1024), 0, st, stt, d, k, wp, v, h, delta,
-                       tau_r, it_max, hflag, (k > 1 && hflag) ? cnt : nullptr);
+    // 4 entries per thread in registers up to d = 4096, 8 up to 8192 (the same sums: only
+    // the loads are batched differently), a loop beyond
+    uint32_t* c = (k > 1 && hflag) ? cnt : nullptr;
+    if (d > (int64_t)STEP_REG * 1024 && d <= (int64_t)2 * STEP_REG * 1024)
+        hipLaunchKernelGGL(k_lsqr_step<2 * STEP_REG>, dim3((unsigned)k), dim3(1024), 0, st, stt, d, k,
+                           wp, v, h, delta, tau_r, it_max, hflag, c);
+    else
+        hipLaunchKernelGGL(k_lsqr_step<STEP_REG>, dim3((unsigned)k), dim3(1024), 0, st, stt, d, k, wp,
+                           v, h, delta, tau_r, it_max, hflag, c);
     return hipGetLastError();
 }
 

@@ -414,6 +414,40 @@ __device__ __forceinline__ double wave_dot(const SolveArgs& a, int64_t e0, int64
     return part;
 }
 
+// One row of a level, for one right-hand side: what does not depend on earlier levels
+// (the row's index, its entries' columns and values, its diagonal and right-hand side) is
+// loaded before the level's barrier, so that only the values of tmp are read after it.
+// Rows of up to 64 entries are held one entry per lane; longer ones loop.
+struct RowPre {
+    int64_t f, e0, e1;
+    int32_t id;
+    double v, dg, xv;
+};
+
+template <bool UPPER>
+__device__ __forceinline__ void row_pre(const SolveArgs& a, const double* __restrict__ x, int64_t ldx,
+                                        int64_t i, int lane, RowPre& p) {
+    p.f = a.rows[i];
+    p.e0 = a.ptr[p.f];
+    p.e1 = a.ptr[p.f + 1];
+    const int64_t e = p.e0 + lane;
+    const bool has = e < p.e1;
+    p.id = has ? a.idx[e] : 0;
+    p.v = has ? a.v[e] : 0.0;
+    p.dg = a.rdiag[p.f] + a.ladd[p.f];
+    p.xv = UPPER ? x[p.f * ldx] : x[(int64_t)a.perm[p.f] * ldx];
+}
+
+// the row's sum after the barrier (k = 1): the held entry, the rest of a long row, then a
+// butterfly over the wave
+__device__ __forceinline__ double row_sum(const SolveArgs& a, const RowPre& p, const double* tmp,
+                                          int lane) {
+    double part = p.e0 + lane < p.e1 ? p.v * tmp[p.id] : 0.0;
+    for (int64_t e = p.e0 + 64 + lane; e < p.e1; e += 64) part += a.v[e] * tmp[a.idx[e]];
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+    return part;
+}
+
 // upper: tmp[f] = (x[f] - sum_e R_f,lcol[e] tmp[lcol[e]]) / r_ff, y[perm[f]] = s tmp[f],
 // one wave per row of a level; the workgroups past G scatter the root's values (already in
 // tmp) to y
@@ -427,7 +461,30 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_leaf_upper(SolveArgs a, const
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     constexpr int NW = SOLVE_THREADS / 64;
     if (g < a.G) {
-        for (int64_t l = a.lbptr[g]; l + 1 < a.lbptr[g + 1]; ++l) {
+        const int64_t l0 = a.lbptr[g], l1 = a.lbptr[g + 1];
+        if (k == 1) {
+            RowPre p;
+            bool have = l0 + 1 < l1 && a.lb[l0] + wave < a.lb[l0 + 1];
+            if (have) row_pre<true>(a, x, ldx, a.lb[l0] + wave, lane, p);
+            for (int64_t l = l0; l + 1 < l1; ++l) {
+                const int64_t r0 = a.lb[l], r1 = a.lb[l + 1];
+                for (int64_t i = r0 + wave; i < r1; i += NW) {
+                    if (i != r0 + wave) row_pre<true>(a, x, ldx, i, lane, p);
+                    const double sum = row_sum(a, p, tmp, lane);
+                    if (lane == 0) {
+                        const double yv = (p.xv - sum) / p.dg;
+                        tmp[p.f] = yv;
+                        y[(int64_t)a.perm[p.f] * ldy] = s * yv;
+                    }
+                }
+                // the next level's first row, loaded before the barrier
+                have = l + 2 < l1 && a.lb[l + 1] + wave < a.lb[l + 2];
+                if (have) row_pre<true>(a, x, ldx, a.lb[l + 1] + wave, lane, p);
+                __syncthreads();
+            }
+            return;
+        }
+        for (int64_t l = l0; l + 1 < l1; ++l) {
             const int64_t r0 = a.lb[l], r1 = a.lb[l + 1];
             for (int64_t i = r0 + wave; i < r1; i += NW) {
                 const int64_t f = a.rows[i];
@@ -466,7 +523,29 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_leaf_lower(SolveArgs a, const
     const int64_t g = blockIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     constexpr int NW = SOLVE_THREADS / 64;
-    for (int64_t l = a.lbptr[g]; l + 1 < a.lbptr[g + 1]; ++l) {
+    const int64_t l0 = a.lbptr[g], l1 = a.lbptr[g + 1];
+    if (k == 1) {
+        RowPre p;
+        bool have = l0 + 1 < l1 && a.lb[l0] + wave < a.lb[l0 + 1];
+        if (have) row_pre<false>(a, x, ldx, a.lb[l0] + wave, lane, p);
+        for (int64_t l = l0; l + 1 < l1; ++l) {
+            const int64_t r0 = a.lb[l], r1 = a.lb[l + 1];
+            for (int64_t i = r0 + wave; i < r1; i += NW) {
+                if (i != r0 + wave) row_pre<false>(a, x, ldx, i, lane, p);
+                const double sum = row_sum(a, p, tmp, lane);
+                if (lane == 0) {
+                    const double yv = (p.xv - sum) / p.dg;
+                    tmp[p.f] = yv;
+                    y[p.f * ldy] = s * yv;
+                }
+            }
+            have = l + 2 < l1 && a.lb[l + 1] + wave < a.lb[l + 2];
+            if (have) row_pre<false>(a, x, ldx, a.lb[l + 1] + wave, lane, p);
+            __syncthreads();
+        }
+        return;
+    }
+    for (int64_t l = l0; l + 1 < l1; ++l) {
         const int64_t r0 = a.lb[l], r1 = a.lb[l + 1];
         for (int64_t i = r0 + wave; i < r1; i += NW) {
             const int64_t f = a.rows[i];
