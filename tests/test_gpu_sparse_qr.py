@@ -382,3 +382,64 @@ def test_sparse_rank_guard(ski):
         S.factor()
     assert e.value.code == -4
     S.close()
+
+
+def _tall_front_matrix():
+    """1000 x 20: rows 0-899 hold column 0 only, rows 900-999 three of the other columns.
+    Column 0 then meets all 19 others yet is eliminated second, and its leaf front gathers
+    377 rows of the sketch: the front is factored in three chunks of its LDS tile."""
+    rng = np.random.default_rng(21)
+    n, d = 1000, 20
+    rows, cols, vals = [], [], []
+    for i in range(900):
+        rows.append(i)
+        cols.append(0)
+        vals.append(rng.standard_normal())
+    for i in range(900, n):
+        for c in rng.choice(np.arange(1, d), size=3, replace=False):
+            rows.append(i)
+            cols.append(int(c))
+            vals.append(rng.standard_normal())
+    A = sp.csr_matrix((vals, (rows, cols)), shape=(n, d))
+    A.sort_indices()
+    return A, rng.standard_normal(n)
+
+
+@pytest.mark.parametrize("case", ["tall_front", "d1", "d2"])
+def test_sparse_tall_fronts_and_tiny_problems(ski, case):
+    if case == "tall_front":
+        A, b = _tall_front_matrix()
+        m, s = 400, 2
+    else:
+        d = 1 if case == "d1" else 2
+        rng = np.random.default_rng(d)
+        A = sp.csr_matrix(rng.standard_normal((50, d)))
+        b = rng.standard_normal(50)
+        m, s = 3 * d + 1, 2
+    n, d = A.shape
+    rp, ci, va = A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data
+    _say(f"sparse {case}: n={n} d={d} m={m}")
+    ref = sk.sketch_csr(rp, ci, va, n, d, b, m, s, 21)
+    pats = sq.sa_row_patterns(rp, ci, n, d, m, s, 21)
+    order, root, L = sq.min_degree(pats, d, 62)
+    perm_o, pos = sq.positions(order, root)
+    if case == "tall_front":
+        q0 = int(pos[0])
+        first = [min(int(pos[c]) for c in p) for p in pats if p]
+        assert q0 < len(order) and sum(1 for f in first if f == q0) > 256
+    S = ski.Solver()
+    S.sketch(_csr_arg(rp, ci, va, n, d), dev(b), m=m, s=s, seed=21, qr_panel="sparse",
+             tau_r=1e-14, tau_a=0.0, it_max=500).factor()
+    np.testing.assert_array_equal(S.get_SA(), ref["SA_aug"])
+    perm, _ = S.get_pivots()
+    np.testing.assert_array_equal(perm, perm_o)
+    R, cc, _ = S.get_R()
+    Rref, cref = sq.factor(ref["SA_aug"], d, perm_o)
+    scale = np.abs(Rref).max()
+    np.testing.assert_allclose(R, Rref, rtol=0, atol=1e-12 * scale * math.sqrt(d))
+    np.testing.assert_allclose(cc, cref, rtol=0, atol=1e-12 * np.abs(cref).max() * math.sqrt(d))
+    X, infos, rc = S.solve()
+    S.close()
+    xd = sla.lstsq(A.toarray(), b)[0]
+    x = X[:, 0].cpu().numpy()
+    assert np.linalg.norm(x - xd) <= 1e-10 * np.linalg.norm(xd)
