@@ -203,7 +203,7 @@ def test_full_size_very_sparse_matches_the_dense_factor(ski):
     """The 40000 x 8000 very sparse workload: the ordering against the oracle's, and the
     sparse factorisation against the dense one on the same sketch.  Both preconditioners
     satisfy R^T R = P^T (SA)^T (SA) P, so A P R_sparse^-1 and A R_dense^-1 differ by an
-    orthogonal factor and LSQR takes the same steps up to rounding."""
+    orthogonal factor and LSQR takes the same steps up to rounding (within max(2, 1%))."""
     c = workloads.CASES["very_sparse"]
     n, d, m, s = c["n"], c["d"], c["m"], c["s"]
     _say(f"full-size very sparse n={n} d={d} m={m} s={s}")
@@ -233,7 +233,10 @@ def test_full_size_very_sparse_matches_the_dense_factor(ski):
     _say(f"  leaves {len(order)} root {len(root)}; iters sparse {its} dense {itd}; "
          f"x difference {err:.2e}; certificate {cert:.2e}")
     assert rcs == 0 and rcd == 0
-    assert abs(its - itd) <= 1
+    # ~320 steps to 1e-12: the (TC-lsqr) estimate is not monotone near the threshold, and the
+    # two forms' rounding (substitution against the explicit inverse) moves the crossing by a
+    # few steps; within max(2, 1%)
+    assert abs(its - itd) <= max(2, 0.01 * itd)
     assert err <= 1e-9
     assert cert <= 1e-10
 
