@@ -151,7 +151,10 @@ typedef struct {
  *                ski_get_pivots; ski_get_factor_stats gives the leaf fronts and the root
  *                size.  No rank detection: rank = d, and the guards rcond and
  *                rcond_thres/perturb act on the whole diagonal as without pivoting.  The
- *                ordering and the symbolic structure are computed on the host.
+ *                ordering and the symbolic structure are computed on the host.  Non-finite
+ *                entries are found as the fronts are assembled; a sketch row with no entry
+ *                of A carries only B's values and reaches no front, so a non-finite B there
+ *                is reported by ski_solve.
  *                SKI_QR_PIVOTED_COD: the minimal-norm form (the complete orthogonal
  *                decomposition that the factorisation remark allows, with R_12 = 0): the
  *                SKI_QR_PIVOTED factorisation truncated at p, then a QR of the transposed

@@ -552,11 +552,10 @@ int sparse_factor(ski_handle h, hipStream_t st) {
     int* hnonfinite = (int*)(h->hdiag + 2 * d + 1);
     SKI_TRY(h, S.leaf_diag(P<double>(h->dtmp), st), "leaf diag");
     SKI_TRY(h, S.leaf_c(P<double>(h->c), st), "leaf c");
-    SKI_TRY(h, hipMemcpyAsync(hnonfinite, S.nonfinite_dev(), sizeof(int), hipMemcpyDeviceToHost, st),
-            "flag copy");
     SKI_TRY(h, hipMemcpyAsync(h->pivd.p, S.perm_dev(), d * 4, hipMemcpyDeviceToDevice, st),
             "perm copy");
     *hflag = 0;
+    const int* root_nonfinite = nullptr;  // the root QR's own check of its front
     const void* root_ac = nullptr;  // the root's factored working copy (for R_h^-1)
     int64_t root_rows = 0;
     if (nr > 0 && S.root_rows_pad() > 12288) {
@@ -626,10 +625,17 @@ int sparse_factor(ski_handle h, hipStream_t st) {
         prof_end(h, st);
         root_ac = ws.Ac;
         root_rows = rows;
+        root_nonfinite = ws.nonfinite;
     }
+    // the fronts' and the root assembly's non-finite flag (set by both), then the root QR's
+    SKI_TRY(h, hipMemcpyAsync(hnonfinite, S.nonfinite_dev(), sizeof(int), hipMemcpyDeviceToHost, st),
+            "flag copy");
+    if (root_nonfinite)
+        SKI_TRY(h, hipMemcpyAsync(hflag, root_nonfinite, sizeof(int), hipMemcpyDeviceToHost, st),
+                "flag copy");
     SKI_TRY(h, hipMemcpyAsync(h->hdiag, h->dtmp.p, d * 8, hipMemcpyDeviceToHost, st), "diag copy");
     SKI_TRY(h, hipStreamSynchronize(st), "sync");
-    if (*hnonfinite)
+    if (*hnonfinite || (root_nonfinite && *hflag))
         return fail(h, SKI_EINVAL, "ski_factor: the sketch holds a non-finite entry (A or B is not finite)");
     const double* Rd = h->hdiag;
     bool finite = true;

@@ -172,13 +172,23 @@ def test_sparse_zero_column_is_perturbed_and_zero(ski):
     assert np.linalg.norm(x[keep] - xd) <= 1e-9 * np.linalg.norm(xd)
 
 
-def test_sparse_nonfinite_entry_is_reported(ski):
-    n, d = 2000, 300
-    rp, ci, va, b = workloads.very_sparse(n, d, 2)
-    va = va.copy()
-    va[123] = np.nan
+@pytest.mark.parametrize("where", ["leaf", "root", "rhs"])
+def test_sparse_nonfinite_entry_is_reported(ski, where):
+    """A NaN in A reaching a leaf front, a NaN in A on a root-only problem, and an infinity in
+    b: SKI_EINVAL from ski_factor in each case."""
+    if where == "root":
+        rp, ci, va, b = workloads.sparse_power_law(n=40000, d=100, case=3)
+        n, d, m, s = 40000, 100, 140, 2
+    else:
+        n, d, m, s = 2000, 300, 600, 3
+        rp, ci, va, b = workloads.very_sparse(n, d, 2)
+    va, b = va.copy(), b.copy()
+    if where == "rhs":
+        b[5] = np.inf  # row 5 holds column 5's entry: its sketch rows reach a front
+    else:
+        va[123] = np.nan
     S = ski.Solver()
-    S.sketch(_csr_arg(rp, ci, va, n, d), dev(b), m=600, s=3, seed=14, qr_panel="sparse")
+    S.sketch(_csr_arg(rp, ci, va, n, d), dev(b), m=m, s=s, seed=14, qr_panel="sparse")
     with pytest.raises(ski.SkiError) as e:
         S.factor()
     assert e.value.code == -1
