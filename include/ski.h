@@ -24,7 +24,9 @@
  *     pointers; dense matrices are row-major with an explicit leading dimension
  *     (element (i, j) of an n x d matrix at p[i * ld + j]).
  *   - `stream` is a hipStream_t (passed as void*); every call is ordered on it.
- *     ski_sketch is asynchronous.  ski_factor synchronises the stream before it returns
+ *     ski_sketch is asynchronous for dense A; for CSR A it waits once for a device check
+ *     of the CSR structure, and with qr_panel = SKI_QR_SPARSE once more, to size the
+ *     sparse sketch from its entry count.  ski_factor synchronises the stream before it returns
  *     (it reads diag(R) for the rank guard and the perturbation, and the device's checks
  *     of the sketch; with qr_panel = SKI_QR_PIVOTED it also waits once per 64-column panel
  *     for that panel's CholeskyQR2 check).  ski_solve returns after LSQR (or CG) has
@@ -219,8 +221,11 @@ void ski_params_default(int32_t kind, ski_params* p);
  * dimension ldb >= k; k >= 1) and keeps it in the handle.  Errors (all found on the host,
  * before any device work): SKI_EINVAL for n < d, d < 1, m < d, m > n' (dense with
  * Hadamard) or m > n, m > 12288 (except with SKI_QR_SPARSE), s out of range, k < 1, bad
- * leading dimensions, Hadamard requested for CSR; SKI_ENOMEM.  Non-finite entries of A and B are not looked for here
- * (that would cost a pass over A); they are reported by ski_factor. */
+ * leading dimensions, Hadamard requested for CSR; SKI_ENOMEM.  For CSR A, SKI_EINVAL also
+ * when the structure is malformed (row_ptr not rising from 0 to nnz, or a column index
+ * outside [0, d)): a device pass over row_ptr and col checks it before any other work on
+ * A.  Non-finite entries of A and B are not looked for here (that would cost a pass over
+ * the values); they are reported by ski_factor. */
 int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, int64_t ldb,
                const ski_params* p, void* stream);
 
@@ -267,7 +272,9 @@ const char* ski_last_error(ski_handle h);
  * leading dimension d+k; caller-owned device buffer) for the S that (m, s, seed,
  * hadamard, hash_kind) define; the result equals the sketch ski_sketch forms from the
  * same arguments, bit for bit.  A: SKI_DENSE (row-major) or SKI_CSR; B: n x k device
- * (ldb >= k).  hadamard must be 0 or 1; sketch_prec and qr_prec must be SKI_FP64.
+ * (ldb >= k).  hadamard must be 0 or 1; sketch_prec and qr_prec must be SKI_FP64.  A CSR
+ * structure is taken as given (this call never waits, so it cannot check it as ski_sketch
+ * does): with a malformed one the call may read outside the arrays.
  * Scratch: the hash keys, their bucket sort, the D sign bits and the transform's column
  * slab live in one static device array of 64 MiB that the library holds on every GPU it
  * runs on until the process ends (its address is looked up on the first call on each

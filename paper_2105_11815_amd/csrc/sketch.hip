@@ -352,6 +352,30 @@ __global__ __launch_bounds__(64) void k_gather_csr(const int64_t* __restrict__ r
     }
 }
 
+// the structure of a CSR matrix: *bad = 1 unless row_ptr[0] = 0, row_ptr[n] = nnz, the
+// offsets never decrease and every column index lies in [0, d) (every writer writes 1)
+__global__ __launch_bounds__(256) void k_check_csr(const int64_t* __restrict__ row_ptr,
+                                                   const int32_t* __restrict__ col, int64_t n,
+                                                   int64_t d, int64_t nnz, int* __restrict__ bad) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool ok = true;
+    for (int64_t i = t0; i <= n; i += stride) {
+        const int64_t v = row_ptr[i];
+        ok = ok && v >= 0 && v <= nnz;
+        if (i == 0) ok = ok && v == 0;
+        if (i == n)
+            ok = ok && v == nnz;
+        else
+            ok = ok && row_ptr[i + 1] >= v;
+    }
+    for (int64_t e = t0; e < nnz; e += stride) {
+        const int64_t c = col[e];
+        ok = ok && c >= 0 && c < d;
+    }
+    if (!ok) *bad = 1;
+}
+
 }  // namespace
 
 namespace {
@@ -488,6 +512,14 @@ hipError_t launch_gather_plain(const double* A, int64_t lda, const double* B, in
     else
         hipLaunchKernelGGL((k_gather_dense<double, float, float>), grid, dim3(GT), 0, st, A, lda, d,
                            B, ldb, k, bucket_ptr, src, scale, (float*)SA, ncols);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_csr(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t d,
+                            int64_t nnz, int* bad, hipStream_t st) {
+    const int64_t work = std::max<int64_t>(n + 1, nnz);
+    const unsigned g = (unsigned)std::min<int64_t>((work + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_check_csr, dim3(g), dim3(256), 0, st, row_ptr, col, n, d, nnz, bad);
     return hipGetLastError();
 }
 

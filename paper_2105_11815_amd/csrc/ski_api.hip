@@ -52,6 +52,7 @@ struct ski_handle_s {
     DevBuf tkeys, tkeys_tmp, ttable, tp, tpay, ti, tv;
     DevBuf u, t, v, h, delta, z, wp, g, gpart, upart, y, st;
     DevBuf done_cnt;  // arrival counter of the step kernels' status word (zero between steps)
+    DevBuf csr_bad;   // the CSR structure check's flag
     DevBuf cg_r, cg_p, cg_q, t2, dtmp, gemm_ws2, gemm_ws3;
     // column-pivoted factor: workspace, the permutation, compact R_11, p x k staging
     DevBuf piv_part, pivd, Rc, ptmp;
@@ -359,6 +360,21 @@ int ski_sketch(ski_handle h, const ski_matrix* A, const double* B, int32_t k, in
     h->Bsk = B;
     h->ldb = ldb;
     h->sketched = h->factored = false;
+    if (akind == SKI_CSR) {
+        // the structure is checked before any kernel indexes with it
+        int bad = 0;
+        SKI_TRY(h, ensure(h->csr_bad, sizeof(int)), "alloc");
+        SKI_TRY(h, hipMemsetAsync(h->csr_bad.p, 0, sizeof(int), st), "flag init");
+        SKI_TRY(h, launch_check_csr(A->row_ptr, A->col, n, d, A->nnz, P<int>(h->csr_bad), st),
+                "csr check");
+        SKI_TRY(h, hipMemcpyAsync(&bad, h->csr_bad.p, sizeof(int), hipMemcpyDeviceToHost, st),
+                "flag copy");
+        SKI_TRY(h, hipStreamSynchronize(st), "sync");
+        if (bad)
+            return fail(h, SKI_EINVAL,
+                        "ski_sketch: malformed CSR A (row offsets must rise from 0 to nnz and "
+                        "column indices lie in [0, d))");
+    }
 
     const int64_t nhc = npad;  // hashed columns of S_h
     h->ncols_hash = nhc;

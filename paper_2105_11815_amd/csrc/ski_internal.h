@@ -160,6 +160,10 @@ hipError_t launch_colmajor_to_rowmajor(const double* src, int64_t lds, int64_t n
                                        double* dst, hipStream_t st);
 // message of the last failed ski_sketch_noalloc call on this host thread ("" if none)
 const char* noalloc_last_error();
+// *bad = 1 (it is not cleared here) unless row_ptr[0] = 0, row_ptr[n] = nnz, the row offsets
+// never decrease and every column index lies in [0, d); reads row_ptr[0 .. n] and col[0 .. nnz)
+hipError_t launch_check_csr(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t d,
+                            int64_t nnz, int* bad, hipStream_t st);
 hipError_t launch_gather_csr(const int64_t* row_ptr, const int32_t* col, const double* val,
                              const double* B, int64_t ldb, int64_t d, int64_t k,
                              const int32_t* bucket_ptr, const int32_t* src, int64_t m,

@@ -135,6 +135,25 @@ bool sparse_symbolic(int64_t m, int64_t d, int64_t k, const int64_t* rstart, con
     std::vector<int32_t> ev;
     std::vector<int64_t> eoff{0};
     std::vector<std::vector<int32_t>> vel(d);  // elements holding each column (may list dead)
+    // the rows must lie in the value array and hold strictly ascending columns in [0, d)
+    // (the sketch merges equal columns, so only a column index of A outside [0, d) can
+    // break this; it would otherwise index past the arrays below)
+    for (int64_t r = 0; r < m; ++r) {
+        if (rlen[r] <= 0) continue;
+        if (rstart[r] < 0 || rstart[r] + rlen[r] > nvals) {
+            err = "the sketch's row offsets run past its entries";
+            return false;
+        }
+        int64_t prev = -1;
+        for (int32_t u = 0; u < rlen[r]; ++u) {
+            const int64_t c = col[rstart[r] + u];
+            if (c <= prev || c >= d) {
+                err = "a column index of A lies outside [0, d)";
+                return false;
+            }
+            prev = c;
+        }
+    }
     {
         int64_t tot = 0;
         for (int64_t r = 0; r < m; ++r) tot += std::max<int32_t>(rlen[r], 0);

@@ -103,6 +103,46 @@ def test_nonfinite_csr_input_is_rejected(ski):
     lib.ski_destroy(h)
 
 
+@pytest.mark.parametrize("fault", ["col_high", "col_negative", "ptr_decreasing", "ptr_end"])
+def test_malformed_csr_is_rejected_before_device_work(ski, fault):
+    """A column index outside [0, d) or row offsets that do not rise from 0 to nnz: ski_sketch
+    returns SKI_EINVAL from its device check of the structure, before any kernel indexes
+    with it; the handle then refuses to factor, and a well-formed call afterwards works."""
+    from paper_2105_11815_amd import _lib as L
+    lib = L.load()
+    _say(f"malformed CSR: {fault}")
+    n, d = 4000, 50
+    rp, ci, va, b = workloads.sparse_power_law(n=n, d=d, case=3)
+    rp, ci = rp.copy(), ci.copy()
+    if fault == "col_high":
+        ci[len(ci) // 3] = d
+    elif fault == "col_negative":
+        ci[7] = -1
+    elif fault == "ptr_decreasing":
+        rp[100] = rp[101] + 1  # row 100 would start after row 101
+    else:
+        rp[-1] = rp[-1] - 1
+    rpt, cit, vat, bt = dev(rp, torch.int64), dev(ci, torch.int32), dev(va), dev(b)
+    M = L.SkiMatrix(n=n, d=d, kind=L.SKI_CSR, a=None, lda=0, row_ptr=rpt.data_ptr(),
+                    col=cit.data_ptr(), val=vat.data_ptr(), nnz=len(va))
+    p = _params(ski, "csr", s=2, m=80, seed=7)
+    h = C.c_void_p()
+    assert lib.ski_create(C.byref(h)) == L.SKI_OK
+    rc = lib.ski_sketch(h, C.byref(M), C.c_void_p(bt.data_ptr()), 1, 1, C.byref(p), _stream())
+    assert rc == L.SKI_EINVAL
+    assert b"malformed CSR" in lib.ski_last_error(h)
+    assert lib.ski_factor(h, _stream()) == L.SKI_ESTATE
+    # the same handle with the well-formed matrix
+    rp0, ci0, _, _ = workloads.sparse_power_law(n=n, d=d, case=3)
+    rpt, cit = dev(rp0, torch.int64), dev(ci0, torch.int32)
+    M = L.SkiMatrix(n=n, d=d, kind=L.SKI_CSR, a=None, lda=0, row_ptr=rpt.data_ptr(),
+                    col=cit.data_ptr(), val=vat.data_ptr(), nnz=len(va))
+    rc = lib.ski_sketch(h, C.byref(M), C.c_void_p(bt.data_ptr()), 1, 1, C.byref(p), _stream())
+    assert rc == L.SKI_OK, lib.ski_last_error(h)
+    assert lib.ski_factor(h, _stream()) == L.SKI_OK, lib.ski_last_error(h)
+    lib.ski_destroy(h)
+
+
 def test_nonfinite_right_hand_sides_at_solve_and_adjoint(ski):
     """ski_solve with a B that holds an infinity (LLS) or a G that holds a NaN (the adjoint):
     SKI_EINVAL from the first norm of the iteration, with no iterations run on it; the
