@@ -220,7 +220,7 @@ int ski_destroy(ski_handle h) {
                      &h->wp, &h->g, &h->gpart, &h->upart, &h->y, &h->st, &h->cg_r,
                      &h->cg_p, &h->cg_q, &h->t2, &h->dtmp, &h->gemm_ws2, &h->gemm_ws3,
                      &h->piv_part, &h->pivd, &h->Rc, &h->ptmp, &h->cod_a, &h->cod_m,
-                     &h->done_cnt, &h->sroot, &h->sptmp};
+                     &h->done_cnt, &h->csr_bad, &h->sroot, &h->sptmp};
     for (DevBuf* b : all) release(*b);
     if (h->ev_ok)
         for (auto& e : h->ev) (void)hipEventDestroy(e);
