@@ -182,8 +182,10 @@ bool sparse_symbolic(int64_t m, int64_t d, int64_t k, const int64_t* rstart, con
     // neighbour, stays a lower bound, and v is counted again only once lb[v] - 1 could be
     // <= dmax; from there on it is counted exactly.  The order is the uncapped rule's.
     const int64_t CNT_CAP = (int64_t)dmax + 65;
-    auto next_stamp = [&]() {
-        if (stamp == INT32_MAX - 1) {
+    // a fresh stamp; room for `need` more is made first (the marks are cleared when the
+    // stamps would run out), so that the stamps of one elimination stay valid together
+    auto next_stamp = [&](int need = 1) {
+        if (stamp > INT32_MAX - 1 - need) {
             std::fill(mark.begin(), mark.end(), -1);
             stamp = 0;
         }
@@ -202,6 +204,42 @@ bool sparse_symbolic(int64_t m, int64_t d, int64_t k, const int64_t* rstart, con
                 }
             }
         }
+        return cnt;
+    };
+    // the same count for a neighbour v of the column just eliminated, whose members Lj carry
+    // the stamp s0 (v among them), before the new element joins v's list: |Lj| - 1, plus the
+    // members of v's other live elements outside Lj.  Every absorbed element lay inside Lj
+    // and j, so this is v's degree; Lj is marked once per elimination instead of once per
+    // neighbour.  The same pass drops the absorbed elements from v's list, and absorbs any
+    // element found to lie inside Lj: each of its members holds Lj too, so no degree changes.
+    auto degree_after = [&](int32_t v, int32_t s0, int64_t nlj) {
+        const int32_t sv = next_stamp();
+        int64_t cnt = nlj - 1;
+        auto& L = vel[v];
+        size_t w = 0;
+        for (size_t i = 0; i < L.size(); ++i) {
+            const int32_t e = L[i];
+            if (edead[e]) continue;
+            if (cnt >= CNT_CAP) {
+                L[w++] = e;
+                continue;
+            }
+            bool inside = true;
+            for (int64_t q = eoff[e]; q < eoff[e + 1]; ++q) {
+                const int32_t u = ev[q];
+                if (mark[u] == s0) continue;
+                inside = false;
+                if (mark[u] != sv) {
+                    mark[u] = sv;
+                    if (++cnt >= CNT_CAP) break;
+                }
+            }
+            if (inside)
+                edead[e] = 1;
+            else
+                L[w++] = e;
+        }
+        L.resize(w);
         return cnt;
     };
     std::vector<int64_t> lb(d);
@@ -224,15 +262,16 @@ bool sparse_symbolic(int64_t m, int64_t d, int64_t k, const int64_t* rstart, con
         pq.erase(bdeg, bv);
         const int32_t j = (int32_t)bv;
         // j's live neighbours: the union of its live elements (which hold live columns only:
-        // every element holding an eliminated column was absorbed when it was eliminated)
-        next_stamp();
+        // every element holding an eliminated column was absorbed when it was eliminated).
+        // Their stamp s0 stays valid through this elimination: one stamp per neighbour follows.
+        const int32_t s0 = next_stamp(64);
         Lj.clear();
         for (int32_t e : vel[j]) {
             if (edead[e]) continue;
             for (int64_t q = eoff[e]; q < eoff[e + 1]; ++q) {
                 const int32_t u = ev[q];
-                if (u != j && mark[u] != stamp) {
-                    mark[u] = stamp;
+                if (u != j && mark[u] != s0) {
+                    mark[u] = s0;
                     Lj.push_back(u);
                 }
             }
@@ -249,16 +288,16 @@ bool sparse_symbolic(int64_t m, int64_t d, int64_t k, const int64_t* rstart, con
         eoff.push_back((int64_t)ev.size());
         edead.push_back(0);
         for (int32_t v : Lj) {
-            auto& L = vel[v];
-            L.erase(std::remove_if(L.begin(), L.end(), [&](int32_t e) { return edead[e] != 0; }),
-                    L.end());
-            L.push_back(ne);
             if (lb[v] - 1 > dmax) {
-                --lb[v];  // still above the cap: its bucket (dmax + 1) is unchanged
+                // still above the cap: its bucket (dmax + 1) is unchanged, and its list keeps
+                // the absorbed elements until it is counted again (they are skipped)
+                --lb[v];
+                vel[v].push_back(ne);
                 continue;
             }
             pq.erase(deg[v], v);
-            lb[v] = degree(v);
+            lb[v] = degree_after(v, s0, (int64_t)Lj.size());
+            vel[v].push_back(ne);
             deg[v] = (int)std::min<int64_t>(lb[v], dmax + 1);
             pq.insert(deg[v], v);
         }
@@ -286,46 +325,72 @@ bool sparse_symbolic(int64_t m, int64_t d, int64_t k, const int64_t* rstart, con
         const int32_t p = S.parent[q];
         return p < 0 ? -1 : (p < nl ? p : ROOT);
     };
-    // local column of position pq in leaf front f (-1 if absent)
-    auto local_col = [&](int64_t f, int32_t pq) -> int32_t {
-        if (pq == f) return 0;
-        const auto b = S.lcol.begin() + S.lptr[f], e = S.lcol.begin() + S.lptr[f + 1];
-        const auto it = std::lower_bound(b, e, pq);
-        if (it == e || *it != pq) return -1;
-        return (int32_t)(1 + (it - b));
+    // lcmap[pq] = the local column of position pq in the front being visited, -1 elsewhere:
+    // set from a leaf front's columns, used, then cleared (each front costs |L_f| + 1)
+    std::vector<int32_t> lcmap(d, -1);
+    auto map_front = [&](int64_t f, bool on) {
+        lcmap[f] = on ? 0 : -1;
+        for (int64_t e = S.lptr[f]; e < S.lptr[f + 1]; ++e)
+            lcmap[S.lcol[e]] = on ? (int32_t)(1 + (e - S.lptr[f])) : -1;
     };
 
-    // ---- row assignment: each non-empty row of SA goes to the front of its first position
-    std::vector<std::vector<int32_t>> orig(nl + 1);
-    S.ent_lc.assign(nvals, -1);
+    // ---- row assignment: each non-empty row of SA goes to the front of its first position;
+    // the rows of front f, ascending, are orows[optr[f] .. optr[f + 1])
+    std::vector<int32_t> rfront(m, -1);
+    std::vector<int64_t> optr(nl + 2, 0);
     for (int64_t r = 0; r < m; ++r) {
         if (rlen[r] <= 0) continue;
         int32_t first = INT32_MAX;
         for (int32_t u = 0; u < rlen[r]; ++u) first = std::min(first, pos[col[rstart[r] + u]]);
-        const int64_t f = first < nl ? first : ROOT;
-        orig[f].push_back((int32_t)r);
-        for (int32_t u = 0; u < rlen[r]; ++u) {
-            const int32_t pq = pos[col[rstart[r] + u]];
-            const int32_t lc = f == ROOT ? (int32_t)(pq - nl) : local_col(f, pq);
-            if (lc < 0) {
-                err = "internal: a row of the sketch does not fit its front";
-                return false;
-            }
-            S.ent_lc[rstart[r] + u] = lc;
-        }
+        rfront[r] = first < nl ? first : (int32_t)ROOT;
+        ++optr[rfront[r] + 1];
     }
-    // ---- children, front sizes, contribution blocks
-    std::vector<std::vector<int32_t>> kids(nl + 1);
+    for (int64_t f = 0; f <= nl; ++f) optr[f + 1] += optr[f];
+    std::vector<int32_t> orows(optr[nl + 1]);
+    {
+        std::vector<int64_t> fill(optr.begin(), optr.end() - 1);
+        for (int64_t r = 0; r < m; ++r)
+            if (rfront[r] >= 0) orows[fill[rfront[r]]++] = (int32_t)r;
+    }
+    S.ent_lc.assign(nvals, -1);
+    for (int64_t f = 0; f <= nl; ++f) {
+        if (optr[f] == optr[f + 1]) continue;
+        if (f < nl) map_front(f, true);
+        for (int64_t i = optr[f]; i < optr[f + 1]; ++i) {
+            const int32_t r = orows[i];
+            for (int32_t u = 0; u < rlen[r]; ++u) {
+                const int32_t pq = pos[col[rstart[r] + u]];
+                const int32_t lc = f == ROOT ? (int32_t)(pq - nl) : lcmap[pq];
+                if (lc < 0) {
+                    err = "internal: a row of the sketch does not fit its front";
+                    return false;
+                }
+                S.ent_lc[rstart[r] + u] = lc;
+            }
+        }
+        if (f < nl) map_front(f, false);
+    }
+    // ---- children (ascending, kid[kptr[f] .. kptr[f + 1])), front sizes, contribution blocks
+    std::vector<int64_t> kptr(nl + 2, 0);
     for (int64_t q = 0; q < nl; ++q) {
         const int64_t pf = front_of_parent(q);
-        if (pf >= 0) kids[pf].push_back((int32_t)q);
+        if (pf >= 0) ++kptr[pf + 1];
+    }
+    for (int64_t f = 0; f <= nl; ++f) kptr[f + 1] += kptr[f];
+    std::vector<int32_t> kid(kptr[nl + 1]);
+    {
+        std::vector<int64_t> fill(kptr.begin(), kptr.end() - 1);
+        for (int64_t q = 0; q < nl; ++q) {
+            const int64_t pf = front_of_parent(q);
+            if (pf >= 0) kid[fill[pf]++] = (int32_t)q;
+        }
     }
     S.nrows.assign(nl + 1, 0);
     S.cbrows.assign(nl, 0);
     S.cboff.assign(nl, 0);
     for (int64_t q = 0; q <= nl; ++q) {
-        int64_t rows = (int64_t)orig[q].size();
-        for (int32_t c : kids[q]) rows += S.cbrows[c];
+        int64_t rows = optr[q + 1] - optr[q];
+        for (int64_t i = kptr[q]; i < kptr[q + 1]; ++i) rows += S.cbrows[kid[i]];
         if (rows > INT32_MAX) {
             err = "a front holds more than 2^31 rows";
             return false;
@@ -340,31 +405,38 @@ bool sparse_symbolic(int64_t m, int64_t d, int64_t k, const int64_t* rstart, con
     }
     S.root_rows = S.nrows[nl];
     S.src_ptr.assign(nl + 2, 0);
+    S.src_a.reserve(optr[nl + 1] + (size_t)S.cb_total);
     for (int64_t q = 0; q <= nl; ++q) {
-        for (int32_t r : orig[q]) {
-            S.src_a.push_back(r);
+        for (int64_t i = optr[q]; i < optr[q + 1]; ++i) {
+            S.src_a.push_back(orows[i]);
             S.src_b.push_back(-1);
         }
-        for (int32_t c : kids[q])
+        for (int64_t i = kptr[q]; i < kptr[q + 1]; ++i) {
+            const int32_t c = kid[i];
             for (int32_t t = 0; t < S.cbrows[c]; ++t) {
                 S.src_a.push_back(c);
                 S.src_b.push_back(t);
             }
+        }
         S.src_ptr[q + 1] = (int64_t)S.src_a.size();
     }
     // ---- where each child's contribution columns land in its parent
     S.relmap.assign(S.lcol.size(), -1);
-    for (int64_t q = 0; q < nl; ++q) {
-        const int64_t pf = front_of_parent(q);
-        if (pf < 0) continue;
-        for (int64_t e = S.lptr[q]; e < S.lptr[q + 1]; ++e) {
-            const int32_t lc = pf == ROOT ? (int32_t)(S.lcol[e] - nl) : local_col(pf, S.lcol[e]);
-            if (lc < 0) {
-                err = "internal: a contribution column is missing from its parent front";
-                return false;
+    for (int64_t f = 0; f <= nl; ++f) {
+        if (kptr[f] == kptr[f + 1]) continue;
+        if (f < nl) map_front(f, true);
+        for (int64_t i = kptr[f]; i < kptr[f + 1]; ++i) {
+            const int32_t q = kid[i];
+            for (int64_t e = S.lptr[q]; e < S.lptr[q + 1]; ++e) {
+                const int32_t lc = f == ROOT ? (int32_t)(S.lcol[e] - nl) : lcmap[S.lcol[e]];
+                if (lc < 0) {
+                    err = "internal: a contribution column is missing from its parent front";
+                    return false;
+                }
+                S.relmap[e] = lc;
             }
-            S.relmap[e] = lc;
         }
+        if (f < nl) map_front(f, false);
     }
     // ---- heights (factorisation levels), depths, trees
     std::vector<int32_t> height(nl, 0), depth(nl, 0), top(nl, 0);
