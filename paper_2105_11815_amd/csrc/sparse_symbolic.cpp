@@ -192,17 +192,18 @@ bool sparse_symbolic(int64_t m, int64_t d, int64_t k, const int64_t* rstart, con
         return ++stamp;
     };
     auto degree = [&](int32_t v) {
-        next_stamp();
+        const int32_t sv = next_stamp();
+        mark[v] = sv;  // v itself is not counted
         int64_t cnt = 0;
         for (int32_t e : vel[v]) {
             if (edead[e]) continue;
             for (int64_t q = eoff[e]; q < eoff[e + 1]; ++q) {
                 const int32_t u = ev[q];
-                if (u != v && mark[u] != stamp) {
-                    mark[u] = stamp;
-                    if (++cnt >= CNT_CAP) return cnt;
-                }
+                const bool fresh = mark[u] != sv;
+                mark[u] = sv;
+                cnt += fresh;
             }
+            if (cnt >= CNT_CAP) break;  // a lower bound from here (checked per element)
         }
         return cnt;
     };
@@ -224,15 +225,16 @@ bool sparse_symbolic(int64_t m, int64_t d, int64_t k, const int64_t* rstart, con
                 L[w++] = e;
                 continue;
             }
+            // branch-free over the members (their marks follow no pattern); the cap is
+            // checked per element, so the count can pass it by less than one element
             bool inside = true;
             for (int64_t q = eoff[e]; q < eoff[e + 1]; ++q) {
                 const int32_t u = ev[q];
-                if (mark[u] == s0) continue;
-                inside = false;
-                if (mark[u] != sv) {
-                    mark[u] = sv;
-                    if (++cnt >= CNT_CAP) break;
-                }
+                const int32_t mu = mark[u];
+                const bool in_lj = mu == s0, fresh = !in_lj & (mu != sv);
+                inside &= in_lj;
+                mark[u] = fresh ? sv : mu;
+                cnt += fresh;
             }
             if (inside)
                 edead[e] = 1;
