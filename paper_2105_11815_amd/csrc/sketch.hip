@@ -300,51 +300,117 @@ __global__ __launch_bounds__(GT) void k_gather_dense(const TX* __restrict__ X, i
     }
 }
 
-// hashing gather over CSR rows: one wave per (bucket, column range), LDS accumulator
-constexpr int CSR_RANGE = 8192;  // columns per range (64 KiB of FP64 accumulator)
+// hashing gather over CSR rows: one workgroup per (bucket, column range), LDS accumulator.
+// The bucket's entries (its rows of A, then each row's k right-hand-side values, in bucket
+// order) are first staged in LDS, all loads in flight together, GC_STAGE at a time; then
+// one wave adds them row by row into the accumulator (a row's columns are distinct, so
+// each column still receives its terms in bucket order: the sums are the same bits as a
+// sequential loop), and the workgroup writes the range out.
+constexpr int CSR_RANGE = 4096;  // columns per range (32 KiB of FP64 accumulator)
+constexpr int GC_THREADS = 256;
+constexpr int GC_STAGE = 2048;   // entries staged at a time
+constexpr int GC_ROWS = 256;     // bucket rows described at a time
 
 template <typename TAcc, typename TOut>
-__global__ __launch_bounds__(64) void k_gather_csr(const int64_t* __restrict__ row_ptr,
-                                                   const int32_t* __restrict__ col,
-                                                   const double* __restrict__ val,
-                                                   const double* __restrict__ Bx, int64_t ldb,
-                                                   int64_t d, int64_t k,
-                                                   const int32_t* __restrict__ ptr,
-                                                   const int32_t* __restrict__ src, double scale,
-                                                   TOut* __restrict__ out) {
+__global__ __launch_bounds__(GC_THREADS) void k_gather_csr(const int64_t* __restrict__ row_ptr,
+                                                          const int32_t* __restrict__ col,
+                                                          const double* __restrict__ val,
+                                                          const double* __restrict__ Bx,
+                                                          int64_t ldb, int64_t d, int64_t k,
+                                                          const int32_t* __restrict__ ptr,
+                                                          const int32_t* __restrict__ src,
+                                                          double scale, TOut* __restrict__ out) {
     __shared__ TAcc acc[CSR_RANGE];
+    __shared__ int32_t scol[GC_STAGE];   // column - c0, or -1 outside the range
+    __shared__ TAcc sval[GC_STAGE];      // the signed term
+    __shared__ int64_t roff[GC_ROWS + 1];  // flat offsets of the batch's rows
+    __shared__ int64_t rbeg[GC_ROWS];    // row_ptr of each row
+    __shared__ int32_t rlen[GC_ROWS];    // its stored entries
+    __shared__ int32_t rrow[GC_ROWS];    // the row of A, sign in bit 31
+    __shared__ int64_t wsum[GC_THREADS / 64];
     const int64_t j = blockIdx.x;
     const int64_t ncol = d + k;
     const int64_t c0 = (int64_t)blockIdx.y * CSR_RANGE;
     const int64_t c1 = std::min(ncol, c0 + CSR_RANGE);
-    const int lane = threadIdx.x;
-    for (int64_t c = c0 + lane; c < c1; c += 64) acc[c - c0] = 0;
-    __syncthreads();
+    const int t = threadIdx.x, lane = t & 63;
+    for (int64_t c = c0 + t; c < c1; c += GC_THREADS) acc[c - c0] = 0;
     const int32_t p0 = ptr[j], p1 = ptr[j + 1];
-    for (int32_t pp = p0; pp < p1; ++pp) {
-        const int32_t e = src[pp];
-        const int64_t r = (int64_t)((uint32_t)e >> 1);
-        const bool neg = e & 1;
-        const int64_t e0 = row_ptr[r], e1 = row_ptr[r + 1];
-        for (int64_t q = e0 + lane; q < e1; q += 64) {
-            const int64_t c = col[q];
-            if (c >= c0 && c < c1) {
-                TAcc x = (TAcc)val[q];
-                TAcc a = acc[c - c0];
-                acc[c - c0] = neg ? a - x : a + x;
-            }
+    for (int32_t b0 = p0; b0 < p1; b0 += GC_ROWS) {
+        const int nb = (int)std::min<int32_t>(GC_ROWS, p1 - b0);
+        int64_t v = 0;  // this row's entries: stored ones plus k
+        if (t < nb) {
+            const int32_t e = src[b0 + t];
+            const int64_t r = (int64_t)((uint32_t)e >> 1);
+            const int64_t e0 = row_ptr[r];
+            const int32_t len = (int32_t)(row_ptr[r + 1] - e0);
+            rbeg[t] = e0;
+            rlen[t] = len;
+            rrow[t] = (int32_t)r | (int32_t)((uint32_t)(e & 1) << 31);
+            v = (int64_t)len + k;
         }
-        for (int64_t t = lane; t < k; t += 64) {
-            const int64_t c = d + t;
-            if (c >= c0 && c < c1) {
-                TAcc x = (TAcc)Bx[r * ldb + t];
-                TAcc a = acc[c - c0];
-                acc[c - c0] = neg ? a - x : a + x;
-            }
+        // offsets: an inclusive scan in each wave, then the waves' totals in order
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t y = __shfl_up(v, o);
+            if (lane >= o) v += y;
         }
-        __syncthreads();  // single wave: orders this entry's LDS updates before the next
+        if (lane == 63) wsum[t >> 6] = v;
+        __syncthreads();
+        int64_t base = 0;
+        for (int w = 0; w < (t >> 6); ++w) base += wsum[w];
+        if (t < nb) roff[t + 1] = base + v;
+        if (t == 0) roff[0] = 0;
+        __syncthreads();
+        const int64_t tot = roff[nb];
+        for (int64_t x0 = 0; x0 < tot; x0 += GC_STAGE) {
+            const int32_t xn = (int32_t)std::min<int64_t>(GC_STAGE, tot - x0);
+            // stage: entry i lies in the row whose offsets bracket it (binary search)
+            for (int32_t u = t; u < xn; u += GC_THREADS) {
+                const int64_t i = x0 + u;
+                int lo = 0, hi = nb;  // roff[lo] <= i < roff[hi]
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (roff[mid] <= i)
+                        lo = mid;
+                    else
+                        hi = mid;
+                }
+                const int64_t o = i - roff[lo];
+                const int32_t rr = rrow[lo];
+                const int64_t r = rr & 0x7fffffff;
+                int64_t c;
+                double x;
+                if (o < rlen[lo]) {
+                    c = col[rbeg[lo] + o];
+                    x = val[rbeg[lo] + o];
+                } else {
+                    c = d + (o - rlen[lo]);
+                    x = Bx[r * ldb + (o - rlen[lo])];
+                }
+                const bool in = c >= c0 && c < c1;
+                const TAcc xv = (TAcc)x;
+                scol[u] = in ? (int32_t)(c - c0) : -1;
+                sval[u] = rr < 0 ? -xv : xv;
+            }
+            __syncthreads();
+            // add, row by row, on one wave (program order keeps the rows in bucket order)
+            if (t < 64) {
+                for (int i = 0; i < nb; ++i) {
+                    // row i's entries within this chunk, as chunk positions [a, z)
+                    const int64_t a64 = std::max(roff[i], x0) - x0;
+                    const int64_t z64 = std::min(roff[i + 1], x0 + (int64_t)xn) - x0;
+                    if (z64 <= a64) continue;
+                    const int32_t a = (int32_t)a64, z = (int32_t)z64;
+                    for (int32_t u = a + lane; u < z; u += 64) {
+                        const int32_t cc = scol[u];
+                        if (cc >= 0) acc[cc] = acc[cc] + sval[u];
+                    }
+                }
+            }
+            __syncthreads();
+        }
     }
-    for (int64_t c = c0 + lane; c < c1; c += 64) {
+    __syncthreads();
+    for (int64_t c = c0 + t; c < c1; c += GC_THREADS) {
         if constexpr (sizeof(TAcc) == 8)
             out[j * ncol + c] = (TOut)(acc[c - c0] * scale);
         else
@@ -530,13 +596,13 @@ hipError_t launch_gather_csr(const int64_t* row_ptr, const int32_t* col, const d
     const int64_t ncols = d + k;
     dim3 grid((unsigned)m, (unsigned)((ncols + CSR_RANGE - 1) / CSR_RANGE));
     if (prec == Prec::F64 && out == Prec::F64)
-        hipLaunchKernelGGL((k_gather_csr<double, double>), grid, dim3(64), 0, st, row_ptr, col, val,
+        hipLaunchKernelGGL((k_gather_csr<double, double>), grid, dim3(GC_THREADS), 0, st, row_ptr, col, val,
                            B, ldb, d, k, bucket_ptr, src, scale, (double*)SA);
     else if (prec == Prec::F64)
-        hipLaunchKernelGGL((k_gather_csr<double, float>), grid, dim3(64), 0, st, row_ptr, col, val,
+        hipLaunchKernelGGL((k_gather_csr<double, float>), grid, dim3(GC_THREADS), 0, st, row_ptr, col, val,
                            B, ldb, d, k, bucket_ptr, src, scale, (float*)SA);
     else
-        hipLaunchKernelGGL((k_gather_csr<float, float>), grid, dim3(64), 0, st, row_ptr, col, val,
+        hipLaunchKernelGGL((k_gather_csr<float, float>), grid, dim3(GC_THREADS), 0, st, row_ptr, col, val,
                            B, ldb, d, k, bucket_ptr, src, scale, (float*)SA);
     return hipGetLastError();
 }
