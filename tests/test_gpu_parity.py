@@ -85,6 +85,38 @@ def test_csr_sketch_bitexact(ski, n, d, m, s):
     S.close()
 
 
+@pytest.mark.parametrize("n,d,m,s,k", [(30000, 40, 60, 2, 1), (6000, 4500, 4600, 2, 2)])
+def test_csr_sketch_bitexact_batches_chunks_and_ranges(ski, n, d, m, s, k):
+    """The CSR gather's longer paths: buckets of ~1000 rows and ~6600 entries (several row
+    batches and staging chunks), and 4502 columns (two column ranges) with two right-hand
+    sides.  Identical bits to the oracle's bucket-ordered sums."""
+    _say(f"csr sketch n={n} d={d} m={m} s={s} k={k}")
+    rp, ci, va, _ = workloads.sparse_power_law(n=n, d=d, case=3)
+    B = np.random.default_rng(3).standard_normal((n, k))
+    ref = sk.sketch_csr(rp, ci, va, n, d, B, m, s, 77)
+    S = ski.Solver()
+    S.sketch(("csr", dev(rp, torch.int64), dev(ci, torch.int32), dev(va), (n, d)), dev(B),
+             m=m, s=s, seed=77, hadamard=False)
+    np.testing.assert_array_equal(S.get_SA(), ref["SA_aug"])
+    S.close()
+
+
+def test_csr_sketch_in_fp32_against_the_oracle(ski):
+    """The FP32 CSR gather (sketch and QR in FP32): each entry is a float sum of at most
+    ~150 terms taken in bucket order, so ||SA - SA_oracle||_F <= 1e-5 ||SA||_F holds with
+    room (the sum's bound is terms x 2^-24 x sum|terms| per entry)."""
+    n, d, m, s = 5000, 60, 90, 2
+    rp, ci, va, b = workloads.sparse_power_law(n=n, d=d, case=3)
+    ref = sk.sketch_csr(rp, ci, va, n, d, b, m, s, 77)["SA_aug"]
+    S = ski.Solver()
+    S.sketch(("csr", dev(rp, torch.int64), dev(ci, torch.int32), dev(va), (n, d)), dev(b),
+             m=m, s=s, seed=77, hadamard=False, sketch_prec="fp32", qr_prec="fp32")
+    SA = S.get_SA()
+    S.close()
+    assert np.linalg.norm(SA - ref) <= 1e-5 * np.linalg.norm(ref)
+    assert not np.array_equal(SA, ref)  # the FP32 path really ran
+
+
 def test_dense_plain_hashing_matches_oracle(ski):
     n, d, m, s = 3000, 50, 100, 2
     rng = np.random.default_rng(5)
