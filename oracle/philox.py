@@ -4,7 +4,7 @@ and Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC'11).
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 The paper fixes no random number generator; the s-hashing matrix and the sign
-diagonal only have to be drawn independently and uniformly.  This build draws
+diagonal only have to be drawn independently and uniformly.  This library draws
 them from Philox4x64-10 so that the GPU and this oracle can produce the same
 bits independently.  The block function maps a 256-bit counter and a 128-bit
 key to 256 output bits through ten rounds of
