@@ -295,6 +295,32 @@ def test_tiny_workload_x_parity(ski):
     S.close()
 
 
+@pytest.mark.parametrize("d,k,panel", [(1, 1, "auto"), (2, 1, "auto"), (3, 2, "auto"),
+                                       (1, 1, "pivoted"), (2, 3, "pivoted"), (1, 1, "householder")])
+def test_smallest_dense_problems(ski, d, k, panel):
+    """d = 1, 2 and 3 columns (one ragged panel, the smallest LSQR passes and triangular
+    products), one to three right-hand sides, the plain, pivoted and column-by-column
+    factorisations: x against LAPACK's least squares and the oracle's solve."""
+    _say(f"dense d={d} k={k} {panel}")
+    rng = np.random.default_rng(40 + d)
+    n = 300
+    A = rng.standard_normal((n, d))
+    B = rng.standard_normal((n, k))
+    xd = lls.lstsq_direct(A, B)
+    opts = dict(pivoting=True) if panel == "pivoted" else {}
+    Xo, _ = lls.solve(A, B, 2010, s=1, m=16, tau_r=1e-14, **opts)
+    S = ski.Solver()
+    S.sketch(dev(A), dev(B), m=16, s=1, seed=2010, tau_r=1e-14, it_max=200,
+             qr_panel=panel).factor()
+    X, infos, rc = S.solve()
+    S.close()
+    X = X.cpu().numpy()
+    assert rc in (0, 1), rc
+    for j in range(k):
+        assert np.linalg.norm(X[:, j] - xd[:, j]) <= 1e-10 * np.linalg.norm(xd[:, j])
+        assert np.linalg.norm(X[:, j] - Xo[:, j]) <= 1e-10 * np.linalg.norm(Xo[:, j])
+
+
 @pytest.mark.parametrize("tau", [1e-10, 1e-14])
 def test_coherent_dense_x_parity(ski, tau):
     n, d = 6000, 200
