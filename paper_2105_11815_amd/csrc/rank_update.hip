@@ -6,20 +6,28 @@
 // With K <= 64 the update reads and writes C once for 2K flops per entry: it is bound by
 // moving C, not by the matrix cores.  A general GEMM walks K in slices with a barrier and a
 // dependent load round trip per slice and reads C only in its epilogue, so for K = 64 it
-// spends most of its time waiting on memory.  Here a workgroup owns a 64 x 64 tile of C and
-// issues every load it needs at once: the 64 x K block of A and the K x 64 block of B
-// (into LDS, k-major so that each lane's MFMA operand is one conflict-free LDS read) and
-// its own 16 entries of C (straight into registers, in the accumulator layout of the
-// 16x16x4 MFMA).  Then K/4 MFMA steps per 16 x 16 block and one store.  Addresses are
-// clamped into the matrices and the values outside masked to zero, so no load waits
-// behind a branch.  Each output is one fixed-order sum: the result is deterministic.
+// spends most of its time waiting on memory.  Here every load a tile needs is issued at
+// once: the 64 x K block of A (into LDS, k-major so that each lane's MFMA operand is one
+// conflict-free LDS read), this lane's B operands of the K/4 MFMA steps and its 16 entries
+// of C (in the accumulator layout of the 16x16x4 MFMA).  In FP64 a workgroup owns a strip
+// of four 64 x 64 tiles of C along N: A is loaded once for the strip, and the next tile's
+// C is in flight while the current tile's MFMA steps run (B comes from L2); the register
+// budget is two wavefronts per SIMD.  In FP32 a workgroup owns one tile with A and B both
+// in LDS.  Addresses are clamped into the matrices and the values outside masked to zero,
+// so no load waits behind a branch.  Each output is one fixed-order sum: the result is
+// deterministic.
 //
 // The product that precedes the update, W = C V^T (M x K, K <= 64, the reduction over the
 // N rows of the panel), walks N in tiles of 64: a workgroup owns 64 rows of W and one
 // range of N, keeps the next tile's loads in flight while the current tile's 16 MFMA steps
 // run, and writes its partial W; the partials are then summed in ascending range order.
+// In FP64 the number of ranges is chosen so that the grid fills the 512 workgroup slots
+// (two per CU) in as few rounds as possible.
 #include "ski_internal.h"
 #include "tile64.h"
+
+#include <algorithm>
+#include <climits>
 
 namespace ski {
 
@@ -28,12 +36,29 @@ namespace {
 constexpr int UT = 64;        // tile edge (M and N) and the largest K
 constexpr int UP = UT + 1;    // LDS pitch
 
-// ranges of N for W = C V^T: about 640 workgroups in all, and at least 4 tiles per range
-int rank_project_splits(int64_t M, int64_t N) {
+// ranges of N for W = C V^T.  FP32: about 640 workgroups in all, and at least 4 tiles per
+// range.  FP64: the count s (at least 4 tiles per range, partials within 64 MiB) that
+// minimises the rounds of 512 resident workgroups times the tiles per range, so that the
+// last round is not a small remainder.
+int rank_project_splits(int64_t M, int64_t N, size_t elem) {
     const int64_t gx = (M + UT - 1) / UT, tiles = (N + UT - 1) / UT;
-    int64_t s = (640 + gx - 1) / gx;
-    s = std::min<int64_t>(s, std::max<int64_t>(1, tiles / 4));
-    return (int)std::max<int64_t>(1, std::min<int64_t>(s, 64));
+    if (elem != 8) {
+        int64_t s = (640 + gx - 1) / gx;
+        s = std::min<int64_t>(s, std::max<int64_t>(1, tiles / 4));
+        return (int)std::max<int64_t>(1, std::min<int64_t>(s, 64));
+    }
+    const int64_t smax =
+        std::max<int64_t>(1, std::min<int64_t>({64, tiles / 4, ((int64_t)64 << 20) / (M * UT * 8)}));
+    int64_t best = 1, bcost = INT64_MAX;
+    for (int64_t s = 1; s <= smax; ++s) {
+        const int64_t per = (tiles + s - 1) / s, ns = (tiles + per - 1) / per;
+        const int64_t cost = 20 * ((gx * ns + 511) / 512) * per + ns;  // ties: fewer partials
+        if (cost < bcost) {
+            bcost = cost;
+            best = s;
+        }
+    }
+    return (int)best;
 }
 
 template <typename T>
@@ -121,6 +146,115 @@ __global__ __launch_bounds__(256) void k_rank_update(int64_t M, int64_t N, int K
             }
 }
 
+
+// FP64: C tiles per workgroup along N
+constexpr int RU_STRIP = 4;
+
+// C <- C - A B on a strip of RU_STRIP tiles along N (the FP64 form).  The A block goes to
+// LDS once; each tile's B operands are loaded at the tile's start and the next tile's C
+// entries while this tile's MFMA steps run.  The MFMA sequence per output is the one of
+// k_rank_update.
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_rank_update_strip(int64_t M, int64_t N, int K,
+                                                              const T* __restrict__ A,
+                                                              int64_t lda,
+                                                              const T* __restrict__ B,
+                                                              int64_t ldb, T* __restrict__ C,
+                                                              int64_t ldc) {
+    using MF = tile::MF<T>;
+    using A4 = typename MF::A4;
+    __shared__ T At[UT][UP];  // At[q][j] = A(j0 + j, q)
+    const int t = threadIdx.x, l = t & 63, w = t >> 6, li = l & 15, lk = l >> 4;
+    const int64_t j0 = (int64_t)blockIdx.y * UT;
+    const int64_t sbeg = (int64_t)blockIdx.x * UT * RU_STRIP;
+    const int wj = (w >> 1) * 32, wi = (w & 1) * 32;
+    const int ksteps = (K + 3) >> 2;
+    T bf[32], cv0[16], cv1[16];  // B operands of the 16 k-steps (2 blocks each); C entries
+    auto load_b = [&](int64_t i0) {
+#pragma unroll
+        for (int s = 0; s < 16; ++s)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int q = 4 * s + lk;
+                const int64_t ib = std::min<int64_t>(i0 + wi + 16 * b + li, N - 1);
+                bf[2 * s + b] = B[(int64_t)(q < K ? q : K - 1) * ldb + ib];
+            }
+    };
+    auto load_c = [&](int64_t i0, T* cv) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t j = std::min<int64_t>(j0 + wj + 16 * a + MF::row(r, l), M - 1);
+                    const int64_t i = std::min<int64_t>(i0 + wi + 16 * b + li, N - 1);
+                    cv[8 * a + 4 * b + r] = C[j * ldc + i];
+                }
+    };
+    auto update = [&](int64_t i0, const T* cv) {
+        A4 acc[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) acc[a][b] = (A4){0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            if (s < ksteps) {
+                const int q = 4 * s + lk;
+                T af[2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) af[a] = At[q][wj + 16 * a + li];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+                        acc[a][b] = MF::mma(af[a], mask_or_zero(bf[2 * s + b], q < K), acc[a][b]);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t j = j0 + wj + 16 * a + MF::row(r, l);
+                    const int64_t i = i0 + wi + 16 * b + li;
+                    if (j < M && i < N) C[j * ldc + i] = cv[8 * a + 4 * b + r] - acc[a][b][r];
+                }
+    };
+    {
+        T av[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = t + 256 * u;
+            const int r = e >> 6, c = e & 63;  // A: row j0 + r, column c
+            const int64_t ja = std::min<int64_t>(j0 + r, M - 1);
+            av[u] = A[ja * lda + (c < K ? c : K - 1)];
+        }
+        load_b(sbeg);
+        load_c(sbeg, cv0);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = t + 256 * u;
+            const int r = e >> 6, c = e & 63;
+            At[c][r] = mask_or_zero(av[u], c < K);
+        }
+    }
+    __syncthreads();
+    // tiles of the strip inside N (the grid covers N, so there is at least one)
+    const int nt = (int)std::min<int64_t>(RU_STRIP, (N - sbeg + UT - 1) / UT);
+    for (int tt = 0; tt < nt; tt += 2) {  // two tiles per pass: the C buffers alternate
+        const int64_t i0 = sbeg + (int64_t)tt * UT;
+        if (tt + 1 < nt) load_c(i0 + UT, cv1);
+        update(i0, cv0);
+        if (tt + 1 >= nt) break;
+        load_b(i0 + UT);
+        if (tt + 2 < nt) load_c(i0 + 2 * UT, cv0);
+        update(i0 + UT, cv1);
+        if (tt + 2 < nt) load_b(i0 + 2 * UT);
+    }
+}
 
 // W_s = C(j0:j0+64, n-range s) V(:, n-range s)^T: the partial product of range s.
 // C: M x N (ldc), V: K x N (ldv); partial s of W at P + s * M * UT (row-major, ld UT).
@@ -229,8 +363,13 @@ hipError_t launch_rank_update(int64_t M, int64_t N, int K, const T* A, int64_t l
     if (K > UT) return hipErrorInvalidValue;
     const int64_t gx = (N + UT - 1) / UT, gy = (M + UT - 1) / UT;
     if (gy > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_rank_update<T>), dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, st, M,
-                       N, K, A, lda, B, ldb, C, ldc);
+    if constexpr (sizeof(T) == 8) {
+        hipLaunchKernelGGL((k_rank_update_strip<T>), dim3((unsigned)((gx + RU_STRIP - 1) / RU_STRIP),
+                           (unsigned)gy), dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc);
+    } else {
+        hipLaunchKernelGGL((k_rank_update<T>), dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, st,
+                           M, N, K, A, lda, B, ldb, C, ldc);
+    }
     return hipGetLastError();
 }
 
@@ -242,7 +381,7 @@ template hipError_t launch_rank_update<float>(int64_t, int64_t, int, const float
                                               hipStream_t);
 
 size_t rank_project_ws_bytes(int64_t M, int64_t N, size_t elem) {
-    return (size_t)rank_project_splits(M, N) * (size_t)M * UT * elem;
+    return (size_t)rank_project_splits(M, N, elem) * (size_t)M * UT * elem;
 }
 
 template <typename T>
@@ -251,7 +390,7 @@ hipError_t launch_rank_project(int64_t M, int64_t N, int K, const T* C, int64_t 
                                hipStream_t st) {
     if (M <= 0 || K <= 0) return hipSuccess;
     if (K > UT) return hipErrorInvalidValue;
-    int ns = N > 0 ? rank_project_splits(M, N) : 1;
+    int ns = N > 0 ? rank_project_splits(M, N, sizeof(T)) : 1;
     if ((size_t)ns * M * UT * sizeof(T) > ws_bytes) return hipErrorInvalidValue;
     const int64_t tiles = N > 0 ? (N + UT - 1) / UT : 1;
     const int64_t per = (tiles + ns - 1) / ns;  // tiles of N per range
