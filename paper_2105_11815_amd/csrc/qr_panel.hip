@@ -440,24 +440,47 @@ __global__ __launch_bounds__(256) void k_cqr_update_gram(T* __restrict__ Ac, int
                                                          const T* __restrict__ Tq,
                                                          const T* __restrict__ W,
                                                          T* __restrict__ Gp) {
+    using A4 = typename MF<T>::A4;
     chain_priority();
-    __shared__ T Ys[PB][PP];
-    __shared__ T Vs[PB][PP];
-    __shared__ T Cs[PB][PP];
-    const int t = threadIdx.x;
+    // two tiles (66.5 KB in FP64), so that a workgroup fits on a CU beside two workgroups
+    // of the trailing update; V's MFMA operands go straight to registers
+    __shared__ T Ys[PB][PP];  // T, then Y = T^T W
+    __shared__ T Cs[PB][PP];  // W, then the chunk of C
+    const int t = threadIdx.x, l = t & 63, w = t >> 6, li = l & 15, lk = l >> 4;
     const int64_t mq = m - jq;
     const int64_t r0 = (int64_t)blockIdx.x * GR, r1 = std::min<int64_t>(mq, r0 + GR);
-    load_tile(Tq, Vs, t);
+    // this wave's operands of the chunk of V: row r0 + 16 w + li, columns 4 u + lk
+    const int64_t rv = r0 + 16 * w + li;
+    const bool vok = rv < r1;
+    const int64_t rvc = vok ? rv : r1 - 1;
+    T vf[PB / 4];
+#pragma unroll
+    for (int u = 0; u < PB / 4; ++u) vf[u] = V[(int64_t)(4 * u + lk) * mq + rvc];
+    load_tile(Tq, Ys, t);
     load_tile(W, Cs, t);
     __syncthreads();
-    // Y = T^T W (T upper)
-    tile_mma(Ys, t, [&](int i, int k) { return Vs[k][i]; }, [&](int k, int j) { return Cs[k][j]; },
+    // Y = T^T W (T upper), in place
+    tile_mma(Ys, t, [&](int i, int k) { return Ys[k][i]; }, [&](int k, int j) { return Cs[k][j]; },
              KLowerFull{}, [](int, int, T v) { return v; });
-    stage_chunk(V, mq, r0, r1, PB, Vs, t);
     stage_chunk(Ac + j0 * m + jq, m, r0, r1, nb, Cs, t);
     __syncthreads();
-    tile_mma(Cs, t, [&](int i, int k) { return Vs[i][k]; }, [&](int k, int j) { return Ys[k][j]; },
-             KFull{}, [&](int i, int j, T v) { return Cs[i][j] - v; });
+    // C <- C - V Y: wave w owns the tile row w (the MFMA sequence of tile_mma)
+    A4 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        acc[q] = (A4){0, 0, 0, 0};
+#pragma unroll
+        for (int u = 0; u < PB / 4; ++u)
+            acc[q] = MF<T>::mma(keep_or_zero(vf[u], vok), Ys[4 * u + lk][16 * q + li], acc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            T& c = Cs[16 * w + MF<T>::row(r, l)][16 * q + li];
+            c = c - acc[q][r];  // each entry is read and written by its own lane only
+        }
+    __syncthreads();
     store_chunk(Cs, r0, r1, nb, Ac + j0 * m + jq, m, t);
     if (blockIdx.x > 0) chunk_gram(Cs, Gp + (int64_t)(blockIdx.x - 1) * PB * PB, t);
 }
@@ -474,37 +497,69 @@ __global__ __launch_bounds__(256) void k_cqr_v2x(const T* __restrict__ Q, int64_
                                                  T* __restrict__ Vout, int nbn,
                                                  T* __restrict__ Gp,
                                                  const int* __restrict__ one_pass) {
+    using A4 = typename MF<T>::A4;
     chain_priority();
-    __shared__ T Ms[PB][PP];
-    __shared__ T Qs[PB][PP];
-    __shared__ T Cs[PB][PP];
-    const int t = threadIdx.x;
+    // two tiles (66.5 KB in FP64), so that a workgroup fits on a CU beside two workgroups
+    // of the trailing update; the chunk's MFMA operands go straight to registers, and V2
+    // replaces M in its tile once the product is formed
+    __shared__ T Xs[PB][PP];  // M, then V2's chunk
+    __shared__ T Cs[PB][PP];  // the next panel's chunk
+    const int t = threadIdx.x, l = t & 63, w = t >> 6, li = l & 15, lk = l >> 4;
     const int64_t r0 = (int64_t)blockIdx.x * GR, r1 = std::min<int64_t>(mr, r0 + GR);
-    load_tile(Mx, Ms, t);
     // one pass: V2 = P(nb:, :) M with M = -R1^-1 S U'^-1 (rows < nb of the product unused:
-    // the panel's top block, already overwritten, gives L1 below)
-    if (*one_pass)
-        stage_chunk((const T*)P, ldp, r0, r1, nb, Qs, t);
-    else
-        stage_chunk(Q, ldq, r0, r1, nb, Qs, t);
+    // the panel's top block, already overwritten, gives L1 below); else V2 = Q1(nb:, :) M.
+    // This wave's operands: row r0 + 16 w + li of the chunk, columns 4 u + lk.
+    const bool one = *one_pass != 0;
+    const T* src = one ? (const T*)P : Q;
+    const int64_t lds = one ? ldp : ldq;
+    const int64_t ra = r0 + 16 * w + li;
+    const bool aok = ra < r1;
+    const int64_t rac = aok ? ra : r1 - 1;
+    T af[PB / 4];
+#pragma unroll
+    for (int u = 0; u < PB / 4; ++u) {
+        const int c = 4 * u + lk;
+        af[u] = keep_or_zero(src[(int64_t)(c < nb ? c : nb - 1) * lds + rac], aok && c < nb);
+    }
+    load_tile(Mx, Xs, t);
     if (nbn > 0) stage_chunk(P + (int64_t)nb * ldp, ldp, r0, r1, nbn, Cs, t);
     __syncthreads();
-    tile_mma(Qs, t, [&](int i, int k) { return Qs[i][k]; }, [&](int k, int j) { return Ms[k][j]; },
-             KFullUpper{}, [&](int i, int j, T v) {
-                 const int64_t r = r0 + i;
-                 if (r >= r1 || j >= nb) return (T)0;
-                 if (r < nb) return r == j ? (T)1 : (r > j ? P[j * ldp + r] : (T)0);
-                 return v;
-             });
+    // chunk x M (M upper: tile column q needs k < 16 q + 16), wave w owns the tile row w
+    A4 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        acc[q] = (A4){0, 0, 0, 0};
+#pragma unroll
+        for (int u = 0; u < 4 * q + 4; ++u)
+            acc[q] = MF<T>::mma(af[u], Xs[4 * u + lk][16 * q + li], acc[q]);
+    }
+    T vals[16];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = 16 * w + MF<T>::row(r, l), j = 16 * q + li;
+            const int64_t rr = r0 + i;
+            T v = acc[q][r];
+            if (rr >= r1 || j >= nb) v = (T)0;
+            else if (rr < nb) v = rr == j ? (T)1 : (rr > j ? P[j * ldp + rr] : (T)0);
+            vals[4 * q + r] = v;
+        }
+    __syncthreads();  // every wave has read M
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Xs[16 * w + MF<T>::row(r, l)][16 * q + li] = vals[4 * q + r];
+    __syncthreads();
     for (int o = t; o < GR * PB; o += 256) {
         const int rr = o % GR, c = o / GR;
         const int64_t r = r0 + rr;
         if (r < r1 && c < nb) {
-            if (r >= nb) P[c * ldp + r] = Qs[rr][c];
-            Vout[c * mr + r] = Qs[rr][c];
+            if (r >= nb) P[c * ldp + r] = Xs[rr][c];
+            Vout[c * mr + r] = Xs[rr][c];
         }
     }
-    if (nbn > 0) chunk_atb(Qs, Cs, Gp + (int64_t)blockIdx.x * PB * PB, t);
+    if (nbn > 0) chunk_atb(Xs, Cs, Gp + (int64_t)blockIdx.x * PB * PB, t);
 }
 
 __global__ void k_set_flag(int* flag, int v) {
