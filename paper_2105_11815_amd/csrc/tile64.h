@@ -141,6 +141,12 @@ struct KSlice {  // one slice [k0, k1) of k for every tile (the caller masks in 
     int k0, k1;
     __device__ int2 operator()(int, int) const { return make_int2(k0 / 4, k1 / 4); }
 };
+struct KSliceFrom {  // KSlice for the tile columns b >= bmin only (the others: no k-steps)
+    int k0, k1, bmin;
+    __device__ int2 operator()(int, int b) const {
+        return b >= bmin ? make_int2(k0 / 4, k1 / 4) : make_int2(0, 0);
+    }
+};
 struct KFull {
     __device__ int2 operator()(int, int) const { return make_int2(0, PB / 4); }
 };
@@ -185,8 +191,9 @@ __device__ __forceinline__ void tile_chol(T (*A)[PP], int t, int* bad) {
         __syncthreads();
         if (k0 + TB == PB) break;
         const int lo = k0 + TB;
+        // only the tile columns at or right of lo change (j >= i >= lo)
         tile_mma(A, t, [&](int i, int k) { return A[k][i]; }, [&](int k, int j) { return A[k][j]; },
-                 KSlice{k0, k0 + TB},
+                 KSliceFrom{k0, k0 + TB, lo / 16},
                  [&](int i, int j, T v) { return (i >= lo && j >= i) ? A[i][j] - v : A[i][j]; });
     }
     tile_eval(A, t, [&](int i, int j) { return i <= j ? A[i][j] : (T)0; });
@@ -310,8 +317,9 @@ __device__ __forceinline__ void tile_lu_signed(T (*C)[PP], T* sg, int t) {
         __syncthreads();
         if (nt == 0) break;
         const int lo = k0 + TB;
+        // only the tile columns at or right of lo change (j >= lo)
         tile_mma(C, t, [&](int i, int k) { return C[i][k]; }, [&](int k, int j) { return C[k][j]; },
-                 KSlice{k0, k0 + TB},
+                 KSliceFrom{k0, k0 + TB, lo / 16},
                  [&](int i, int j, T v) { return (i >= lo && j >= lo) ? C[i][j] - v : C[i][j]; });
     }
 }
